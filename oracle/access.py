@@ -1,0 +1,218 @@
+"""Symbolic half of the performance prediction of Section 3 -- TEST
+INFRASTRUCTURE ONLY (oracle).
+
+Follows the paper's steps in its order and notation, for the single-kernel loop
+nests the family produces (Section 3.2 restricts itself to those):
+
+Access distance (Section 3.2).  For an operand Op of the kernel, walk from the
+kernel outwards through the surrounding loops with an initially empty set M:
+  1. Op does not vary across the surrounding loop -> stop; the distance is the
+     size of M.
+  2. Op varies across it -> add all kernel operands to M, joined along every
+     loop passed so far (a joined axis becomes ':'), and go up one level.
+  3. The root is reached -> the distance is the size of M (the contraction is
+     assumed to run repeatedly, nothing else in between).
+All operands are distinct tensors here, so |M| is the sum of region sizes.
+
+Setup list (Section 3.2).  Operands sorted by decreasing distance, each followed
+by a remote region [r] so that the sizes to the right of an operand add up to
+its distance; the last operand is followed by a remote region of its own
+distance.  If the list is longer than 5/4 of the cache it is cut from the front
+to exactly that length (a cut remote region shrinks; a cut operand is replaced
+by a remote region of the part that is kept).  Negative remote sizes are
+clamped to 0 and zero-sized remote regions are dropped.
+
+Prefetching (Section 3.3).  Op is prefetched when it varies across the directly
+surrounding loop and that loop indexes Op's first axis, or its second axis while
+the first is kept whole or fits in one cache line.  A prefetched operand gets
+distance 0 and its setup access is limited to one cache line along its first
+axis.  A setup made only of operand accesses is dropped (the repetitions of the
+benchmark already touch every operand).
+
+Prefetch failures (Section 3.4).  Operands prefetched because the innermost
+loop indexes their first axis (line sharing) miss once per cache line, i.e. once
+in every L/e iterations (L line bytes, e element bytes).  A second benchmark
+without their prefetch emulation takes that share of the steady invocations.
+
+First iterations (Section 3.5).  The first iteration of the innermost loop gets
+its own benchmark; an outer loop gets one too when the invocations at which it
+and every loop inside it are in their first iteration exceed 1% of all
+invocations.  Its distances are found by starting the walk at that loop with M
+already holding every operand joined across it and all loops inside it; it uses
+no prefetch emulation.  Invocations at the first iteration of a loop without its
+own class are counted in the nearest inner class that has one.
+
+Readings where the paper leaves a choice: the prefetch distance is 0 (its worked
+example); line failures split only the steady class; a loop nest without loops
+gives every operand distance 0.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+
+@dataclass(frozen=True)
+class Region:
+    tensor: str
+    letters: str
+    fixed: tuple     # per axis: True if fixed by a loop index
+
+
+def region_size(r: Region, joined: set, extents: dict) -> int:
+    n = 1
+    for ch, f in zip(r.letters, r.fixed):
+        if (not f) or ch in joined:
+            n *= int(extents[ch])
+    return n
+
+
+def varies(r: Region, loop: str, joined: set) -> bool:
+    """Does operand r (already joined across ``joined``) depend on ``loop``?"""
+    return any(f and ch == loop and ch not in joined for ch, f in zip(r.letters, r.fixed))
+
+
+def access_distance(op: Region, ops, loops, extents: dict, start: int | None = None,
+                    preset: set | None = None) -> int:
+    """Distance of ``op`` for a kernel nested in ``loops`` (outermost first).
+
+    ``start``/``preset`` implement the first-iteration variant: the walk starts
+    at loop index ``start`` (it and the loops inside it already joined)."""
+    joined = set(preset or ())
+    pos = len(loops) - 1 if start is None else start - 1
+    while pos >= 0:
+        loop = loops[pos]
+        if not varies(op, loop, joined):
+            break                                   # case 1
+        joined.add(loop)                            # case 2
+        pos -= 1
+    # case 1 or case 3 (root)
+    if not joined:
+        return 0
+    return sum(region_size(r, joined, extents) for r in ops)
+
+
+def build_setup(items, cache_elems: float):
+    """items: list of (name, size, distance).  Returns the setup list as
+    [('op', name, size) | ('remote', None, size)], applying the 5/4 cut."""
+    order = sorted(items, key=lambda t: -t[2])
+    seq = []
+    for k, (name, size, d) in enumerate(order):
+        seq.append(["op", name, size])
+        if k + 1 < len(order):
+            r = d - order[k + 1][2] - order[k + 1][1]
+        else:
+            r = d
+        seq.append(["remote", None, max(0, r)])
+    seq = [e for e in seq if not (e[0] == "remote" and e[2] == 0)]
+    limit = 5 * cache_elems / 4
+    total = sum(e[2] for e in seq)
+    if total > limit:
+        kept, acc = [], 0
+        for e in reversed(seq):
+            if acc + e[2] <= limit:
+                kept.append(e)
+                acc += e[2]
+            else:
+                rest = int(limit - acc)
+                if rest > 0:
+                    kept.append(["remote", None, rest])
+                break
+        seq = list(reversed(kept))
+    return [tuple(e) for e in seq]
+
+
+def only_operands(setup) -> bool:
+    return all(e[0] == "op" for e in setup)
+
+
+def prefetch_kind(op: Region, loops, extents: dict, line_elems: int):
+    """None, 'line' (innermost loop indexes the first axis: cache-line sharing)
+    or 'stream' (it indexes the second axis, the first being whole or within
+    one line)."""
+    if not loops:
+        return None
+    inner = loops[-1]
+    if not varies(op, inner, set()):
+        return None
+    if op.letters and op.letters[0] == inner:
+        return "line"
+    if len(op.letters) >= 2 and op.letters[1] == inner:
+        first_whole = not op.fixed[0]
+        first_small = (not op.fixed[0] and int(extents[op.letters[0]]) <= line_elems) or op.fixed[0]
+        if first_whole or first_small:
+            return "stream"
+    return None
+
+
+def prefetch_access_size(op: Region, extents: dict, line_elems: int) -> int:
+    """One cache line along the first axis, everything else of the operand."""
+    n = 1
+    for ax, (ch, f) in enumerate(zip(op.letters, op.fixed)):
+        e = 1 if f else int(extents[ch])
+        if ax == 0:
+            e = min(e, line_elems)
+        n *= e
+    return n
+
+
+@dataclass
+class BenchClass:
+    label: str          # 'steady', 'fail', 'first@<loop>'
+    weight: float       # share of all kernel invocations
+    setup: list         # setup list
+
+
+def predict_classes(ops, loops, extents: dict, cache_elems: float, line_elems: int,
+                    stage: int = 5):
+    """Benchmark classes with their shares of the invocations, for prediction
+    stage 1 (repeated execution) .. 5 (first iterations separate)."""
+    names = [r.tensor for r in ops]
+    sizes = [region_size(r, set(), extents) for r in ops]
+    if stage == 1:
+        return [BenchClass("steady", 1.0, [])]
+    dist = [access_distance(r, ops, loops, extents) for r in ops]
+    kinds = [prefetch_kind(r, loops, extents, line_elems) if stage >= 3 else None for r in ops]
+
+    def setup_with(prefetched):
+        items = []
+        for n, s, d, r, pf in zip(names, sizes, dist, ops, prefetched):
+            if pf:
+                items.append((n, prefetch_access_size(r, extents, line_elems), 0))
+            else:
+                items.append((n, s, d))
+        st = build_setup(items, cache_elems)
+        return [] if only_operands(st) else st
+
+    steady_setup = setup_with([k is not None for k in kinds])
+    classes = []
+    n_inner = int(extents[loops[-1]]) if loops else 1
+    steady_share = 1.0 - (1.0 / n_inner if (stage >= 5 and loops) else 0.0)
+    if stage >= 4 and any(k == "line" for k in kinds):
+        period = line_elems
+        fail_setup = setup_with([k == "stream" for k in kinds])
+        classes.append(BenchClass("steady", steady_share * (period - 1) / period, steady_setup))
+        classes.append(BenchClass("fail", steady_share / period, fail_setup))
+    else:
+        classes.append(BenchClass("steady", steady_share, steady_setup))
+    if stage >= 5 and loops:
+        # share of invocations at which loops[k:] are all in their first iteration
+        n = len(loops)
+        first_share = [0.0] * n
+        for k in range(n):
+            s = 1.0
+            for m in range(k, n):
+                s /= int(extents[loops[m]])
+            first_share[k] = s
+        own = [k for k in range(n) if k == n - 1 or first_share[k] > 0.01]
+        for idx, k in enumerate(sorted(own, reverse=True)):
+            outer = [o for o in own if o < k]
+            nxt = max(outer) if outer else None
+            share = first_share[k] - (first_share[nxt] if nxt is not None else 0.0)
+            preset = set(loops[k:])
+            items = []
+            for nme, s, r in zip(names, sizes, ops):
+                d = access_distance(r, ops, loops, extents, start=k, preset=preset)
+                items.append((nme, s, d))
+            st = build_setup(items, cache_elems)
+            classes.append(BenchClass(f"first@{loops[k]}", share, [] if only_operands(st) else st))
+    return classes

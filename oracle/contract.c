@@ -1,0 +1,182 @@
+/*
+ * Plain FP64 loop-nest tensor contraction -- TEST INFRASTRUCTURE ONLY.
+ *
+ * This file is the oracle: a slow, obviously correct CPU implementation of the
+ * contraction defined in Section 1 ("Tensor Notation") of Peise, Fabregat-Traver
+ * and Bientinesi, "On the Performance Prediction of BLAS-based Tensor
+ * Contractions" (arXiv 1409.8608).  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no code with the GPU
+ * library: it has its own spec parser and its own loops.
+ *
+ * Definition (Section 1): for every free multi-index f of C,
+ *     C[f] = alpha * sum_{k over all contracted indices} A[f_A, k] * B[f_B, k]
+ *            + beta * C_in[f]
+ * Contracted indices appear in both inputs and not in C; free indices appear in
+ * exactly one input and in C.  Element (x_1..x_d) of an operand X lives at
+ * X + sum_m x_m * stride_m (element units).  The paper assumes Fortran order
+ * (first index stride 1); explicit strides generalise that.  The paper's
+ * algorithms accumulate into C ("+="); alpha/beta are the BLAS reading of that,
+ * with the paper's own runs being alpha = 1, beta = 0.
+ *   beta == 0  -> C_in is not read.
+ *   alpha == 0 -> A and B are not read.
+ *
+ * Fixed summation order: the outer odometer runs over C's indices with C's first
+ * index fastest; the inner odometer runs over the contracted indices in the order
+ * they appear in A's spec, first fastest; the accumulator starts at 0.0.
+ * Build with -O2 -ffp-contract=off and without fast-math so the products and sums
+ * are rounded exactly as written.
+ *
+ * mode 1 ("Dot2") accumulates with an error-free TwoSum/TwoProduct pair
+ * (Ogita, Rump, Oishi, "Accurate sum and dot product", SIAM J. Sci. Comput.
+ * 26(6), 2005, Algorithm 5.3), giving a result as if computed in twice the
+ * working precision; it is used to measure GPU error floors free of oracle noise.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#define OR_MAXIDX 16
+
+enum { OR_OK = 0, OR_E_SPEC = 1, OR_E_EXTENT = 2, OR_E_NULL = 3 };
+
+typedef struct {
+    char a[OR_MAXIDX + 1], b[OR_MAXIDX + 1], c[OR_MAXIDX + 1];
+    int na, nb, nc;
+} or_spec;
+
+/* "abc=ai,ibc" -> three index strings.  Whitespace is not allowed. */
+static int or_parse(const char* s, or_spec* p) {
+    const char* eq = strchr(s, '=');
+    if (!eq) return OR_E_SPEC;
+    const char* comma = strchr(eq + 1, ',');
+    if (!comma) return OR_E_SPEC;
+    p->nc = (int)(eq - s);
+    p->na = (int)(comma - eq - 1);
+    p->nb = (int)strlen(comma + 1);
+    if (p->nc > OR_MAXIDX || p->na > OR_MAXIDX || p->nb > OR_MAXIDX) return OR_E_SPEC;
+    memcpy(p->c, s, (size_t)p->nc);          p->c[p->nc] = 0;
+    memcpy(p->a, eq + 1, (size_t)p->na);     p->a[p->na] = 0;
+    memcpy(p->b, comma + 1, (size_t)p->nb);  p->b[p->nb] = 0;
+    const char* all[3] = {p->a, p->b, p->c};
+    for (int t = 0; t < 3; ++t)
+        for (const char* q = all[t]; *q; ++q) {
+            if (*q < 'a' || *q > 'z') return OR_E_SPEC;
+            if (strchr(q + 1, *q)) return OR_E_SPEC;     /* repeated in one operand */
+        }
+    /* every index must be contracted (A and B, not C) or free (one input and C) */
+    for (int t = 0; t < 3; ++t)
+        for (const char* q = all[t]; *q; ++q) {
+            int inA = strchr(p->a, *q) != 0, inB = strchr(p->b, *q) != 0, inC = strchr(p->c, *q) != 0;
+            int contracted = inA && inB && !inC;
+            int free_ = (inA ^ inB) && inC;
+            if (!contracted && !free_) return OR_E_SPEC;
+        }
+    return OR_OK;
+}
+
+static int pos(const char* s, char ch) {
+    const char* q = strchr(s, ch);
+    return q ? (int)(q - s) : -1;
+}
+
+static int64_t extent_of(char ch, const char* idx_chars, const int64_t* extents, int n_idx) {
+    for (int t = 0; t < n_idx; ++t)
+        if (idx_chars[t] == ch) return extents[t];
+    return -1;
+}
+
+/* Returns 0 on success.  Strides are in each operand's own spec order; a NULL
+ * stride array means Fortran-contiguous for that operand. */
+int oracle_contract(const char* spec, const char* idx_chars, const int64_t* extents, int n_idx,
+                    const double* A, const int64_t* strides_A,
+                    const double* B, const int64_t* strides_B,
+                    double* C, const int64_t* strides_C,
+                    double alpha, double beta, int mode) {
+    or_spec p;
+    int rc = or_parse(spec, &p);
+    if (rc) return rc;
+
+    int64_t extA[OR_MAXIDX], extB[OR_MAXIDX], extC[OR_MAXIDX];
+    int64_t sA[OR_MAXIDX], sB[OR_MAXIDX], sC[OR_MAXIDX];
+    const char* names[3] = {p.a, p.b, p.c};
+    int64_t* exts[3] = {extA, extB, extC};
+    int64_t* strs[3] = {sA, sB, sC};
+    const int64_t* given[3] = {strides_A, strides_B, strides_C};
+    int lens[3] = {p.na, p.nb, p.nc};
+    for (int t = 0; t < 3; ++t) {
+        int64_t run = 1;
+        for (int m = 0; m < lens[t]; ++m) {
+            int64_t e = extent_of(names[t][m], idx_chars, extents, n_idx);
+            if (e < 0) return OR_E_EXTENT;
+            exts[t][m] = e;
+            strs[t][m] = given[t] ? given[t][m] : run;
+            run *= e;
+        }
+    }
+
+    /* contracted indices in A's order */
+    char kidx[OR_MAXIDX + 1];
+    int nk = 0;
+    for (int m = 0; m < p.na; ++m)
+        if (pos(p.b, p.a[m]) >= 0) kidx[nk++] = p.a[m];
+    kidx[nk] = 0;
+    int64_t kext[OR_MAXIDX];
+    for (int q = 0; q < nk; ++q) kext[q] = extent_of(kidx[q], idx_chars, extents, n_idx);
+
+    int64_t nC = 1, nK = 1;
+    for (int m = 0; m < p.nc; ++m) nC *= extC[m];
+    for (int q = 0; q < nk; ++q) nK *= kext[q];
+    if (nC == 0) return OR_OK;
+    if (!C) return OR_E_NULL;
+    if (alpha != 0.0 && nK > 0 && (!A || !B)) return OR_E_NULL;
+
+    int64_t ci[OR_MAXIDX], ki[OR_MAXIDX];
+    memset(ci, 0, sizeof ci);
+    for (int64_t f = 0; f < nC; ++f) {
+        /* offset of C[f] and the free parts of A and B */
+        int64_t offC = 0, offA = 0, offB = 0;
+        for (int m = 0; m < p.nc; ++m) {
+            offC += ci[m] * sC[m];
+            int pa = pos(p.a, p.c[m]), pb = pos(p.b, p.c[m]);
+            if (pa >= 0) offA += ci[m] * sA[pa];
+            if (pb >= 0) offB += ci[m] * sB[pb];
+        }
+        double acc = 0.0, comp = 0.0;
+        if (alpha != 0.0) {
+            memset(ki, 0, sizeof ki);
+            for (int64_t k = 0; k < nK; ++k) {
+                int64_t oa = offA, ob = offB;
+                for (int q = 0; q < nk; ++q) {
+                    oa += ki[q] * sA[pos(p.a, kidx[q])];
+                    ob += ki[q] * sB[pos(p.b, kidx[q])];
+                }
+                double x = A[oa], y = B[ob];
+                if (mode == 1) {
+                    /* TwoProduct via fma, TwoSum (Knuth) */
+                    double prod = x * y;
+                    double perr = fma(x, y, -prod);
+                    double s = acc + prod;
+                    double bb = s - acc;
+                    double serr = (acc - (s - bb)) + (prod - bb);
+                    acc = s;
+                    comp += perr + serr;
+                } else {
+                    acc += x * y;
+                }
+                for (int q = 0; q < nk; ++q) {      /* odometer, first index fastest */
+                    if (++ki[q] < kext[q]) break;
+                    ki[q] = 0;
+                }
+            }
+            if (mode == 1) acc = acc + comp;
+        }
+        double out = alpha * acc;
+        if (beta != 0.0) out += beta * C[offC];
+        C[offC] = out;
+        for (int m = 0; m < p.nc; ++m) {
+            if (++ci[m] < extC[m]) break;
+            ci[m] = 0;
+        }
+    }
+    return OR_OK;
+}
