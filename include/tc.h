@@ -1,0 +1,224 @@
+/*
+ * tc.h -- C ABI of the MI355X tensor-contraction library (libtc.so).
+ *
+ * The library computes dense two-operand tensor contractions written in
+ * Einstein notation (Peise, Fabregat-Traver, Bientinesi, "On the Performance
+ * Prediction of BLAS-based Tensor Contractions", arXiv 1409.8608, Section 1,
+ * "Tensor Notation"):
+ *
+ *     C[f] = alpha * sum_k A[f_A, k] * B[f_B, k] + beta * C[f]
+ *
+ * where the contracted indices k appear in both inputs and not in C, and the
+ * free indices f appear in exactly one input and in C.  Every member of the
+ * paper's algorithm family (Section 2: loop nests over sliced indices around a
+ * dot, axpy, gemv, ger or gemm call, with copies where a matrix slice lacks a
+ * contiguous dimension) runs on the GPU, plus one fused direct-contraction
+ * kernel.  The paper's micro-benchmark performance model (Section 3) predicts
+ * which member is fastest.
+ *
+ * Conventions for every entry point
+ *   - All functions return a tc_status; no C++ exception crosses the ABI.
+ *     tc_last_error() returns a thread-local detail string for the last
+ *     failing call on the calling thread.
+ *   - Arguments are validated before any device work, so a failing call leaves
+ *     C untouched.
+ *   - Tensor pointers (A, B, C) are DEVICE pointers (e.g. torch data_ptr()).
+ *     They are borrowed: the caller keeps them alive until the stream work has
+ *     completed.  `stream` is a hipStream_t passed as void*; NULL is the null
+ *     stream.  Asynchronous device faults surface at the caller's next sync.
+ *   - Strides are in ELEMENTS, one per axis in the operand's spec order.  A NULL
+ *     stride array means Fortran order (first axis stride 1), the paper's
+ *     storage.  Input strides must be >= 0 (0 broadcasts); C strides must be
+ *     > 0 and C must not overlap itself.
+ *   - A plan must not be used by two host threads at once; distinct plans are
+ *     independent.
+ */
+#ifndef TC_H
+#define TC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tc_plan_s* tc_plan_t;     /* opaque, owned by the caller until tc_plan_destroy */
+typedef struct tc_batch_s* tc_batch_t;   /* opaque, owned by the caller until tc_batch_destroy */
+
+typedef enum { TC_F64 = 0, TC_F32 = 1 } tc_dtype;   /* storage type of A, B and C */
+
+/* Arithmetic path.  TC_NATIVE computes in the storage type.  TC_BF16X3 splits
+ * each power-of-two scaled slice into three BF16 terms and forms the six
+ * products of order <= 4 on BF16 matrix cores with FP32 accumulation, combined
+ * in FP64 with compensated summation.  TC_FP8X3 does the same with OCP E4M3
+ * terms. */
+typedef enum { TC_NATIVE = 0, TC_BF16X3 = 1, TC_FP8X3 = 2 } tc_compute;
+
+typedef enum {
+    TC_OK = 0,
+    TC_E_SPEC,         /* malformed spec or an index role outside Section 1 */
+    TC_E_EXTENT,       /* missing/negative extent, or element count overflow */
+    TC_E_STRIDE,       /* negative input stride, non-positive or self-overlapping C stride */
+    TC_E_DTYPE,        /* unknown dtype or dtype/compute pair */
+    TC_E_ALIAS,        /* C's address range overlaps A's or B's */
+    TC_E_NULL,         /* NULL pointer where a non-empty tensor or output is needed */
+    TC_E_VARIANT,      /* variant index out of range */
+    TC_E_HIP,          /* a HIP runtime call or kernel launch failed */
+    TC_E_NOMEM,        /* device workspace allocation failed */
+    TC_E_UNSUPPORTED,  /* valid request this build does not execute (reason in tc_last_error) */
+    TC_E_CAPACITY      /* output array too small; *n_out holds the size needed */
+} tc_status;
+
+/* Kernel of a family member (Section 2 kernel list); TC_KERNEL_FUSED is the
+ * library's own direct-contraction kernel (not a paper algorithm). */
+enum { TC_KERNEL_DOT = 0, TC_KERNEL_AXPY = 1, TC_KERNEL_GEMV = 2, TC_KERNEL_GER = 3,
+       TC_KERNEL_GEMM = 4, TC_KERNEL_FUSED = 5 };
+
+#define TC_VARIANT_FUSED (-2)      /* the fused direct-contraction kernel */
+#define TC_VARIANT_PREDICTED (-1)  /* the fastest member according to tc_predict */
+
+/* One family member.  `number` follows the paper's legend numbering (kernel-
+ * major: dot, axpy, gemv, ger, gemm), starting at 1.  `name` is the paper's
+ * name, e.g. "ca-gemv" or "i'c-gemm" (Section 2, footnote on names). */
+typedef struct {
+    char    name[40];
+    int     number;
+    int     kernel;                /* TC_KERNEL_* */
+    char    kept[8];               /* kept (kernel) index letters, NUL-terminated */
+    char    loops[16];             /* sliced index letters, outermost loop first */
+    int     n_copies;
+    char    copy_tensor[4];        /* 'A', 'B' or 'C' for each copy */
+    int     copy_level[4];         /* loop position the copy runs in; -1 before all loops */
+    /* GPU schedule (how the loop nest maps to launches): */
+    int     n_hoisted;             /* leading contracted loops run as separate launch passes */
+    int64_t launches;              /* kernel launches per contraction, copies and prologue included */
+    int64_t invocations;           /* kernel calls of the paper's loop nest (product of loop extents) */
+} tc_variant_info;
+
+/* One entry of a micro-benchmark setup list (Section 3.2): an access to a kernel
+ * operand, or to a remote region of `size` elements. */
+typedef struct {
+    int     kind;                  /* 0 = operand, 1 = remote region */
+    int     tensor;                /* 0 = A, 1 = B, 2 = C (operand entries), -1 for remote */
+    int64_t size;                  /* elements */
+} tc_setup_item;
+
+#define TC_MAX_SETUP 16
+/* One benchmark class of a prediction (Sections 3.4, 3.5): steady state,
+ * prefetch failure or first iteration of a loop, with its share of the kernel
+ * invocations and its setup list. */
+typedef struct {
+    char          label[16];       /* "steady", "fail", "first@<loop>" */
+    double        weight;          /* share of all kernel invocations, sums to 1 */
+    int           n_items;
+    tc_setup_item items[TC_MAX_SETUP];
+} tc_bench_class;
+
+/* Result of tc_predict for one variant. */
+typedef struct {
+    int    variant;                /* 0-based index into the plan's family, or TC_VARIANT_FUSED */
+    double predicted_s;            /* stage-5 prediction (all refinements) */
+    double stage_s[5];             /* predictions of stages 1..5 (Section 3.1 .. 3.5) */
+    double bench_s;                /* time spent measuring this variant's micro-benchmarks */
+    int    n_bench;                /* distinct micro-benchmarks it used */
+} tc_prediction;
+
+/* --- plans ---------------------------------------------------------------- */
+
+/* Build a plan: parse `spec` ("abc=ai,ibc"), classify indices (Section 1),
+ * bind extents and strides, enumerate the algorithm family (Section 2,
+ * Table 1 x loop orders) and map each member to a GPU schedule.  Host work
+ * only; no device memory is touched.
+ *   index_chars/extents: n_index letters and their extents (every letter of
+ *                        the spec must be given; extra letters are an error).
+ *   strides_X: element strides in X's spec order, or NULL for Fortran order.
+ * Errors: TC_E_SPEC, TC_E_EXTENT, TC_E_STRIDE, TC_E_DTYPE, TC_E_NULL. */
+tc_status tc_plan(tc_plan_t* out, const char* spec,
+                  const char* index_chars, const int64_t* extents, int n_index,
+                  const int64_t* strides_A, const int64_t* strides_B, const int64_t* strides_C,
+                  tc_dtype dtype, tc_compute compute);
+
+/* Free a plan and its device workspace.  NULL is accepted. */
+tc_status tc_plan_destroy(tc_plan_t plan);
+
+/* Number of family members of the plan (36 for "abc=ai,ibc"). */
+tc_status tc_variant_count(tc_plan_t plan, int* n);
+
+/* Describe member `variant` (0-based) or TC_VARIANT_FUSED. */
+tc_status tc_variant_get(tc_plan_t plan, int variant, tc_variant_info* out);
+
+/* Select what tc_contract runs: a 0-based member, TC_VARIANT_FUSED (default),
+ * or TC_VARIANT_PREDICTED (requires a prior tc_predict). */
+tc_status tc_set_variant(tc_plan_t plan, int variant);
+
+/* Allocate every device buffer the selected variant needs (copy temporaries,
+ * split buffers, index tables) so that the following tc_contract calls do not
+ * allocate and can be captured in a HIP graph.  tc_contract calls it itself on
+ * first use.  Errors: TC_E_NOMEM, TC_E_HIP. */
+tc_status tc_plan_prepare(tc_plan_t plan);
+
+/* Bytes of device workspace the plan holds now. */
+tc_status tc_plan_workspace(tc_plan_t plan, int64_t* bytes);
+
+/* Run the contraction with the selected variant on `stream`:
+ *     C = alpha * contract(A, B) + beta * C
+ * alpha/beta are rounded to the storage type.  beta == 0: C is not read.
+ * alpha == 0: A and B are not read.  Asynchronous; returns after the launches.
+ * Errors: TC_E_NULL, TC_E_ALIAS, TC_E_UNSUPPORTED, TC_E_HIP, TC_E_NOMEM. */
+tc_status tc_contract(tc_plan_t plan, const void* A, const void* B, void* C,
+                      double alpha, double beta, void* stream);
+
+/* --- performance prediction (Section 3) ----------------------------------- */
+
+/* Access distance, in elements, of kernel operand `tensor` (0 = A, 1 = B,
+ * 2 = C) of member `variant` (Section 3.2).  Host only. */
+tc_status tc_access_distance(tc_plan_t plan, int variant, int tensor, int64_t* out);
+
+/* Benchmark classes of member `variant` at prediction stage `stage` (1 = repeated
+ * execution, 2 = access distances, 3 = prefetching, 4 = prefetch failures,
+ * 5 = first iterations separate), for a cache of `cache_elems` elements and a
+ * line of `line_elems` elements.  Host only.  Errors: TC_E_CAPACITY. */
+tc_status tc_bench_classes(tc_plan_t plan, int variant, int stage, double cache_elems,
+                           int line_elems, tc_bench_class* out, int capacity, int* n_out);
+
+/* Predict the run time of every member (and the fused kernel, last) on the
+ * current device: for each member's benchmark classes, run the GPU
+ * micro-benchmark (setup accesses, then the member's kernel on a sample of its
+ * invocations, 10 repetitions, median) and weight and sum the medians.
+ * Micro-benchmarks shared by several members run once.  Needs scratch device
+ * memory of up to a few hundred MB, freed on return.  Synchronous.
+ * Errors: TC_E_CAPACITY (*n_out = count + 1), TC_E_HIP, TC_E_NOMEM. */
+tc_status tc_predict(tc_plan_t plan, tc_prediction* out, int capacity, int* n_out);
+
+/* --- batches ----------------------------------------------------------------- */
+
+/* Build a batch of n independent contractions (plans stay owned by the caller
+ * and must outlive the batch): work list of tiles ordered longest-first by
+ * predicted cost, uploaded once; the first tc_batch_contract captures the
+ * upload of per-call pointers and one persistent kernel per dtype into a HIP
+ * graph, later calls replay it.  Errors: TC_E_NULL, TC_E_UNSUPPORTED, TC_E_NOMEM. */
+tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n);
+
+/* Autotune the tile shape of every contraction in the batch: candidates are
+ * the `top_k` shapes the cost model ranks best; each is timed on the device and
+ * the fastest kept.  Synchronous. */
+tc_status tc_batch_tune(tc_batch_t batch, int top_k);
+
+/* Run all contractions: C_t = alpha_t * contract(A_t, B_t) + beta_t * C_t.
+ * A, B, C, alpha, beta are host arrays of n entries (device pointers for the
+ * tensors).  With the same pointer arrays as the previous call the captured
+ * graph is replayed as is. */
+tc_status tc_batch_contract(tc_batch_t batch, const void* const* A, const void* const* B,
+                            void* const* C, const double* alpha, const double* beta, void* stream);
+
+/* Free a batch (its graph and device work list).  NULL is accepted. */
+tc_status tc_batch_destroy(tc_batch_t batch);
+
+/* --- errors ------------------------------------------------------------------ */
+const char* tc_status_str(tc_status s);
+const char* tc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TC_H */

@@ -1,0 +1,186 @@
+// Symbolic half of the performance model (Section 3): access distances
+// (Section 3.2), setup lists with the 5/4-cache cut, prefetching (Section 3.3),
+// prefetch failures (Section 3.4) and first-iteration classes (Section 3.5).
+#include <algorithm>
+#include <cmath>
+
+#include "tc_internal.h"
+
+namespace tc {
+
+static bool has(const std::string& s, char ch) { return s.find(ch) != std::string::npos; }
+
+// Elements of operand `op` once joined (made ':') along every loop in `joined`.
+int64_t region_size(const Spec& s, const Operand& op, const std::string& joined) {
+    int64_t n = 1;
+    for (size_t ax = 0; ax < op.letters.size(); ++ax)
+        if (!op.fixed[ax] || has(joined, op.letters[ax])) n *= s.e(op.letters[ax]);
+    return n;
+}
+
+static bool depends(const Operand& op, char loop, const std::string& joined) {
+    for (size_t ax = 0; ax < op.letters.size(); ++ax)
+        if (op.fixed[ax] && op.letters[ax] == loop && !has(joined, loop)) return true;
+    return false;
+}
+
+// Walk outwards from the kernel (or, for a first-iteration class, from loop
+// position `start` with that loop and every loop inside it already joined).
+// Case 1: the operand does not change across the loop -> stop.  Case 2: it does
+// -> join all kernel operands along the loop and go up.  Case 3: root -> stop.
+// The distance is the size of the joined operands (empty set -> 0).
+int64_t access_distance(const Spec& s, const Variant& v, int tensor, int start) {
+    std::string joined;
+    int pos = (int)v.loops.size() - 1;
+    if (start >= 0) {
+        joined = v.loops.substr(start);
+        pos = start - 1;
+    }
+    for (; pos >= 0; --pos) {
+        char loop = v.loops[pos];
+        if (!depends(v.ops[tensor], loop, joined)) break;
+        joined += loop;
+    }
+    if (joined.empty()) return 0;
+    int64_t d = 0;
+    for (int t = 0; t < 3; ++t) d += region_size(s, v.ops[t], joined);
+    return d;
+}
+
+// 1: the innermost loop indexes the operand's first axis (cache-line sharing);
+// 2: it indexes the second axis while the first is whole or within one line.
+int prefetch_kind(const Spec& s, const Variant& v, int tensor, int line_elems) {
+    if (v.loops.empty()) return 0;
+    char inner = v.loops.back();
+    const Operand& op = v.ops[tensor];
+    if (!depends(op, inner, "")) return 0;
+    if (!op.letters.empty() && op.letters[0] == inner) return 1;
+    if (op.letters.size() >= 2 && op.letters[1] == inner) {
+        bool whole = !op.fixed[0];
+        bool small = op.fixed[0] || s.e(op.letters[0]) <= line_elems;
+        if (whole || small) return 2;
+    }
+    return 0;
+}
+
+static int64_t one_line_size(const Spec& s, const Operand& op, int line_elems) {
+    int64_t n = 1;
+    for (size_t ax = 0; ax < op.letters.size(); ++ax) {
+        int64_t e = op.fixed[ax] ? 1 : s.e(op.letters[ax]);
+        if (ax == 0) e = std::min<int64_t>(e, line_elems);
+        n *= e;
+    }
+    return n;
+}
+
+struct Item { int tensor; int64_t size, dist; };
+
+// Operands by decreasing distance, each followed by the remote region that
+// makes the sizes to its right add up to its distance; cut from the front to
+// 5/4 of the cache.  An operands-only list is empty (the repetitions already
+// touch every operand).
+static std::vector<SetupItem> setup_list(std::vector<Item> items, double cache_elems) {
+    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.dist > y.dist; });
+    std::vector<SetupItem> seq;
+    for (size_t k = 0; k < items.size(); ++k) {
+        seq.push_back({0, items[k].tensor, items[k].size});
+        int64_t r = (k + 1 < items.size()) ? items[k].dist - items[k + 1].dist - items[k + 1].size
+                                           : items[k].dist;
+        if (r > 0) seq.push_back({1, -1, r});
+    }
+    double limit = 1.25 * cache_elems;
+    double total = 0;
+    for (auto& e : seq) total += (double)e.size;
+    if (total > limit) {
+        std::vector<SetupItem> kept;
+        double acc = 0;
+        for (auto it = seq.rbegin(); it != seq.rend(); ++it) {
+            if (acc + (double)it->size <= limit) {
+                kept.push_back(*it);
+                acc += (double)it->size;
+            } else {
+                int64_t rest = (int64_t)std::floor(limit - acc);
+                if (rest > 0) kept.push_back({1, -1, rest});
+                break;
+            }
+        }
+        std::reverse(kept.begin(), kept.end());
+        seq = kept;
+    }
+    bool only_ops = std::all_of(seq.begin(), seq.end(), [](const SetupItem& e) { return e.kind == 0; });
+    if (only_ops) seq.clear();
+    return seq;
+}
+
+std::vector<BenchClass> bench_classes(const Spec& s, const Variant& v, int stage,
+                                      double cache_elems, int line_elems) {
+    std::vector<BenchClass> out;
+    if (stage <= 1) {
+        BenchClass c;
+        c.label = "steady";
+        c.weight = 1.0;
+        c.prefetched.assign(3, false);
+        out.push_back(c);
+        return out;
+    }
+    int64_t size[3], dist[3];
+    int kind[3];
+    for (int t = 0; t < 3; ++t) {
+        size[t] = region_size(s, v.ops[t], "");
+        dist[t] = access_distance(s, v, t, -1);
+        kind[t] = stage >= 3 ? prefetch_kind(s, v, t, line_elems) : 0;
+    }
+    auto steady_with = [&](const bool pf[3]) {
+        std::vector<Item> items;
+        for (int t = 0; t < 3; ++t)
+            items.push_back(pf[t] ? Item{t, one_line_size(s, v.ops[t], line_elems), 0}
+                                  : Item{t, size[t], dist[t]});
+        return setup_list(items, cache_elems);
+    };
+    const int L = (int)v.loops.size();
+    double inner_first = (stage >= 5 && L > 0) ? 1.0 / (double)s.e(v.loops[L - 1]) : 0.0;
+    double steady_share = 1.0 - inner_first;
+    bool pf_all[3], pf_stream[3];
+    bool any_line = false;
+    for (int t = 0; t < 3; ++t) {
+        pf_all[t] = kind[t] != 0;
+        pf_stream[t] = kind[t] == 2;
+        any_line = any_line || kind[t] == 1;
+    }
+    if (stage >= 4 && any_line) {
+        double period = (double)line_elems;
+        BenchClass st{"steady", steady_share * (period - 1) / period, steady_with(pf_all), -1,
+                      std::vector<bool>(pf_all, pf_all + 3)};
+        BenchClass fl{"fail", steady_share / period, steady_with(pf_stream), -1,
+                      std::vector<bool>(pf_stream, pf_stream + 3)};
+        out.push_back(st);
+        out.push_back(fl);
+    } else {
+        out.push_back(BenchClass{"steady", steady_share, steady_with(pf_all), -1,
+                                 std::vector<bool>(pf_all, pf_all + 3)});
+    }
+    if (stage >= 5 && L > 0) {
+        // share of invocations at which loops[k..] are all in their first iteration
+        std::vector<double> first(L);
+        for (int k = 0; k < L; ++k) {
+            double f = 1.0;
+            for (int m = k; m < L; ++m) f /= (double)s.e(v.loops[m]);
+            first[k] = f;
+        }
+        std::vector<int> own;
+        for (int k = L - 1; k >= 0; --k)
+            if (k == L - 1 || first[k] > 0.01) own.push_back(k);
+        for (size_t q = 0; q < own.size(); ++q) {
+            int k = own[q];
+            double share = first[k] - (q + 1 < own.size() ? first[own[q + 1]] : 0.0);
+            std::vector<Item> items;
+            for (int t = 0; t < 3; ++t) items.push_back(Item{t, size[t], access_distance(s, v, t, k)});
+            BenchClass c{std::string("first@") + v.loops[k], share, setup_list(items, cache_elems), k,
+                         std::vector<bool>(3, false)};
+            out.push_back(c);
+        }
+    }
+    return out;
+}
+
+}  // namespace tc

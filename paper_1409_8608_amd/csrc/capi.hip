@@ -1,0 +1,545 @@
+// The C ABI: plans, dispatch of tc_contract to the fused kernels or to a family
+// member's launch sequence, and the host-only queries of the performance model.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "plan.h"
+
+using namespace tc;
+
+namespace tc {
+thread_local std::string g_last_error;
+
+tc_status fail(tc_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+tc_status hip_fail(hipError_t e, const char* what) {
+    return fail(TC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Blocked K order for the matrix-core kernel.  Tiles of BK contracted
+// positions are rectangles over the contracted index that is contiguous in A
+// (dA) and the one contiguous in B (dB), so both operands read runs; tiles are
+// ordered with dB's blocks fastest.  Positions are (offA, offB) pairs; a tile
+// that is not full is padded with (-1, -1) entries (zero contributions).
+std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK) {
+    std::vector<int64_t> tab;
+    int nd = (int)kd.size();
+    int64_t K = 1;
+    for (auto& d : kd) K *= d.ext;
+    if (nd == 0 || K == 0) return tab;
+    int dA = -1, dB = -1;
+    for (int d = 0; d < nd; ++d) {
+        if (dA < 0 && kd[d].sA == 1 && kd[d].ext > 1) dA = d;
+        if (dB < 0 && kd[d].sB == 1 && kd[d].ext > 1) dB = d;
+    }
+    std::vector<int64_t> bs(nd, 1);
+    if (dA >= 0 && dB >= 0 && dA != dB) {
+        bs[dA] = std::min<int64_t>(kd[dA].ext, 4);
+        bs[dB] = std::min<int64_t>(kd[dB].ext, BK / bs[dA]);
+    } else {
+        int d = dA >= 0 ? dA : dB >= 0 ? dB : 0;
+        bs[d] = std::min<int64_t>(kd[d].ext, BK);
+    }
+    // block origins: odometer with dB fastest, then dA, then the rest in order
+    std::vector<int> order;
+    if (dB >= 0) order.push_back(dB);
+    if (dA >= 0 && dA != dB) order.push_back(dA);
+    for (int d = 0; d < nd; ++d)
+        if (d != dA && d != dB) order.push_back(d);
+    std::vector<int64_t> nblk(nd);
+    for (int d = 0; d < nd; ++d) nblk[d] = (kd[d].ext + bs[d] - 1) / bs[d];
+    std::vector<int64_t> bi(nd, 0);
+    while (true) {
+        // points inside this block: dA fastest, then dB, then others
+        std::vector<int> inner;
+        if (dA >= 0) inner.push_back(dA);
+        if (dB >= 0 && dB != dA) inner.push_back(dB);
+        for (int d = 0; d < nd; ++d)
+            if (d != dA && d != dB) inner.push_back(d);
+        std::vector<int64_t> li(nd, 0);
+        int cnt = 0;
+        while (true) {
+            bool ok = true;
+            int64_t oa = 0, ob = 0;
+            for (int d = 0; d < nd; ++d) {
+                int64_t x = bi[d] * bs[d] + li[d];
+                if (x >= kd[d].ext) ok = false;
+                oa += x * kd[d].sA;
+                ob += x * kd[d].sB;
+            }
+            if (ok) {
+                tab.push_back(oa);
+                tab.push_back(ob);
+                ++cnt;
+            }
+            int q = 0;
+            for (; q < (int)inner.size(); ++q) {
+                int d = inner[q];
+                if (++li[d] < bs[d]) break;
+                li[d] = 0;
+            }
+            if (q == (int)inner.size()) break;
+        }
+        for (; cnt % BK != 0 || cnt == 0; ++cnt) {
+            tab.push_back(-1);
+            tab.push_back(-1);
+        }
+        int q = 0;
+        for (; q < (int)order.size(); ++q) {
+            int d = order[q];
+            if (++bi[d] < nblk[d]) break;
+            bi[d] = 0;
+        }
+        if (q == (int)order.size()) break;
+    }
+    return tab;
+}
+
+}  // namespace tc
+
+// ---------------------------------------------------------------------------
+static tc_status ensure_device_buffer(void** p, int64_t* cap, int64_t bytes) {
+    if (bytes <= *cap) return TC_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    hipError_t e = hipMalloc(p, (size_t)std::max<int64_t>(bytes, 256));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(TC_E_NOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e));
+    }
+    *cap = std::max<int64_t>(bytes, 256);
+    return TC_OK;
+}
+
+static tc_status upload(void** p, int64_t* cap, const std::vector<int64_t>& v) {
+    int64_t bytes = (int64_t)(v.size() * sizeof(int64_t));
+    tc_status s = ensure_device_buffer(p, cap, bytes);
+    if (s) return s;
+    if (bytes) {
+        hipError_t e = hipMemcpy(*p, v.data(), (size_t)bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy K table");
+    }
+    return TC_OK;
+}
+
+namespace tc {
+
+bool use_stream_kernel(const Spec& s, const GemmView& gv) {
+    return gv.K >= 1 && gv.K <= GT_SMALLK_MAX && gv.m.size() == 1 && gv.m[0].sC == 1;
+}
+
+tc_status prepare_plan(tc_plan_s* p) {
+    const Spec& s = p->spec;
+    bool f64 = s.dtype == TC_F64;
+    int BK = mfma_bk(f64);
+    if (p->selected == TC_VARIANT_FUSED || p->selected == TC_VARIANT_PREDICTED) {
+        if (!use_stream_kernel(s, p->gv) && p->d_ktab == nullptr) {
+            std::vector<int64_t> tab = build_ktab(p->gv.k, BK);
+            p->kpad = (int64_t)tab.size() / 2;
+            tc_status st = upload(&p->d_ktab, &p->ktab_cap, tab);
+            if (st) return st;
+        }
+        if (s.compute != TC_NATIVE) {
+            tc_status st = prepare_split(p);
+            if (st) return st;
+        }
+    }
+    int v = p->selected == TC_VARIANT_PREDICTED ? p->predicted_best : p->selected;
+    if (v >= 0) {
+        VariantPlan& vp = p->vplans[v];
+        if (vp.needs_c_copy) return fail(TC_E_UNSUPPORTED, "member needs a copy of C, not run on the GPU");
+        for (int t = 0; t < 2; ++t) {
+            tc_status st = ensure_device_buffer(&p->d_temp[t], &p->temp_cap[t], vp.temp_elems[t] * s.elem_bytes());
+            if (st) return st;
+        }
+        if (vp.mfma && p->var_ktab_for != v) {
+            std::vector<GtDim> kd;
+            if (vp.body.kb.ext != 1 || vp.body.kb.sA != 0 || vp.body.kb.sB != 0) kd.push_back(vp.body.kb);
+            else kd.push_back(GtDim{1, 0, 0, 0});
+            std::vector<int64_t> tab = build_ktab(kd, BK);
+            p->var_kpad = (int64_t)tab.size() / 2;
+            tc_status st = upload(&p->d_var_ktab, &p->var_ktab_cap, tab);
+            if (st) return st;
+            p->var_ktab_for = v;
+        }
+    }
+    return TC_OK;
+}
+
+static const char* ptr_add(const void* p, int64_t elems, int esize) {
+    return (const char*)p + elems * esize;
+}
+
+// The fused direct contraction: one launch.
+static tc_status run_fused(tc_plan_s* p, const void* A, const void* B, void* C, double alpha,
+                           double beta, hipStream_t st) {
+    const Spec& s = p->spec;
+    const GemmView& gv = p->gv;
+    bool f64 = s.dtype == TC_F64;
+    if (gv.swapped) std::swap(A, B);
+    if (s.compute != TC_NATIVE) return run_split(p, A, B, C, alpha, beta, st);
+    if (use_stream_kernel(s, gv)) {
+        StreamArgs a{};
+        a.A = A; a.B = B; a.C = C;
+        a.M = gv.m[0].ext;
+        a.sAm = gv.m[0].sA;
+        a.N = gv.N;
+        a.n.n = (int)gv.n.size();
+        for (int d = 0; d < a.n.n; ++d) a.n.d[d] = gv.n[d];
+        // contracted positions in odometer order (first index fastest)
+        a.K = (int)gv.K;
+        std::vector<int64_t> idx(gv.k.size(), 0);
+        for (int k = 0; k < a.K; ++k) {
+            int64_t oa = 0, ob = 0;
+            for (size_t d = 0; d < gv.k.size(); ++d) {
+                oa += idx[d] * gv.k[d].sA;
+                ob += idx[d] * gv.k[d].sB;
+            }
+            a.kA[k] = oa;
+            a.kB[k] = ob;
+            for (size_t d = 0; d < gv.k.size(); ++d) {
+                if (++idx[d] < gv.k[d].ext) break;
+                idx[d] = 0;
+            }
+        }
+        a.alpha = alpha;
+        a.beta = beta;
+        stream_shape(f64, a);
+        hipError_t e = launch_stream(f64, a, st);
+        return e == hipSuccess ? TC_OK : hip_fail(e, "stream kernel launch");
+    }
+    MfmaArgs a{};
+    a.A = A; a.B = B; a.C = C;
+    a.m.n = (int)gv.m.size();
+    for (int d = 0; d < a.m.n; ++d) a.m.d[d] = gv.m[d];
+    a.n.n = (int)gv.n.size();
+    for (int d = 0; d < a.n.n; ++d) a.n.d[d] = gv.n[d];
+    a.batch.n = 0;
+    a.pass.n = 0;
+    a.ktab = (const int64_t*)p->d_ktab;
+    a.M = gv.M; a.N = gv.N; a.Kpad = p->kpad;
+    a.nbatch = 1; a.npass = 1;
+    a.alpha = alpha; a.beta = beta;
+    a.mode = 0;
+    mfma_tiles(f64, a);
+    hipError_t e = launch_mfma(f64, a, st);
+    return e == hipSuccess ? TC_OK : hip_fail(e, "mfma kernel launch");
+}
+
+tc_status run_variant(tc_plan_s* p, int v, const void* A, const void* B, void* C, double alpha,
+                      double beta, hipStream_t st) {
+    const Spec& s = p->spec;
+    const VariantPlan& vp = p->vplans[v];
+    bool f64 = s.dtype == TC_F64;
+    int es = s.elem_bytes();
+    hipError_t e;
+    // C := beta*C, then every invocation adds alpha*(kernel result)
+    if (beta != 1.0) {
+        ScaleArgs sa{};
+        sa.C = C;
+        sa.beta = beta;
+        sa.dims.n = 0;
+        sa.total = 1;
+        for (char ch : s.c) {
+            sa.dims.d[sa.dims.n++] = GtDim{s.e(ch), 0, 0, s.stride(2, ch)};
+            sa.total *= s.e(ch);
+        }
+        e = launch_scale(f64, sa, st);
+        if (e != hipSuccess) return hip_fail(e, "scale kernel launch");
+    }
+    const void* X[2] = {A, B};
+    bool copied[2] = {false, false};
+    for (auto& cs : vp.copies) copied[cs.tensor] = true;
+    const int H = (int)vp.hoisted.size();
+    std::vector<int64_t> h(H, 0);
+    int64_t total_passes = 1;
+    for (auto& d : vp.hoisted) total_passes *= d.ext;
+    for (int64_t pass = 0; pass < total_passes; ++pass) {
+        int64_t hA = 0, hB = 0, hC = 0;
+        for (int q = 0; q < H; ++q) {
+            hA += h[q] * vp.hoisted[q].sA;
+            hB += h[q] * vp.hoisted[q].sB;
+            hC += h[q] * vp.hoisted[q].sC;
+        }
+        for (auto& cs : vp.copies) {
+            bool due = true;
+            for (int q = cs.hoist_depth; q < H; ++q)
+                if (h[q] != 0) due = false;
+            if (!due) continue;
+            int64_t src = 0;
+            for (int q = 0; q < cs.hoist_depth; ++q)
+                src += h[q] * (cs.tensor == 0 ? vp.hoisted[q].sA : vp.hoisted[q].sB);
+            CopyArgs ca{};
+            ca.src = ptr_add(X[cs.tensor], src, es);
+            ca.dst = p->d_temp[cs.tensor];
+            ca.dims = cs.dims;
+            ca.total = cs.slice_elems * cs.slots;
+            e = launch_copy(f64, ca, st);
+            if (e != hipSuccess) return hip_fail(e, "copy kernel launch");
+        }
+        const void* a_ptr = copied[0] ? p->d_temp[0] : ptr_add(A, hA, es);
+        const void* b_ptr = copied[1] ? p->d_temp[1] : ptr_add(B, hB, es);
+        void* c_ptr = (void*)ptr_add(C, hC, es);
+        const GtDesc& d = vp.body;
+        if (vp.mfma) {
+            MfmaArgs a{};
+            a.A = a_ptr; a.B = b_ptr; a.C = c_ptr;
+            a.m.n = d.nm;
+            if (d.nm) a.m.d[0] = d.out.d[0];
+            a.n.n = d.nn;
+            if (d.nn) a.n.d[0] = d.out.d[d.nm];
+            a.batch.n = 0;
+            a.nbatch = 1;
+            for (int q = d.nm + d.nn; q < d.out.n; ++q) {
+                a.batch.d[a.batch.n++] = d.out.d[q];
+                a.nbatch *= d.out.d[q].ext;
+            }
+            a.pass = d.pass;
+            a.npass = 1;
+            for (int q = 0; q < d.pass.n; ++q) a.npass *= d.pass.d[q].ext;
+            a.ktab = (const int64_t*)p->d_var_ktab;
+            a.M = d.nm ? d.out.d[0].ext : 1;
+            a.N = d.nn ? d.out.d[d.nm].ext : 1;
+            a.Kpad = p->var_kpad;
+            a.alpha = alpha; a.beta = 1.0;
+            a.mode = 1;
+            mfma_tiles(f64, a);
+            e = launch_mfma(f64, a, st);
+            if (e != hipSuccess) return hip_fail(e, "mfma body launch");
+        } else {
+            SimtArgs a{};
+            a.A = a_ptr; a.B = b_ptr; a.C = c_ptr;
+            a.out = d.out;
+            a.kb = d.kb;
+            a.pass = d.pass;
+            a.total = 1;
+            for (int q = 0; q < d.out.n; ++q) a.total *= d.out.d[q].ext;
+            a.npass = 1;
+            for (int q = 0; q < d.pass.n; ++q) a.npass *= d.pass.d[q].ext;
+            a.alpha = alpha;
+            e = launch_simt(f64, a, st);
+            if (e != hipSuccess) return hip_fail(e, "simt body launch");
+        }
+        for (int q = H - 1; q >= 0; --q) {
+            if (++h[q] < vp.hoisted[q].ext) break;
+            h[q] = 0;
+        }
+    }
+    return TC_OK;
+}
+
+tc_status contract_dispatch(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
+                            hipStream_t st) {
+    const Spec& s = p->spec;
+    bool f64 = s.dtype == TC_F64;
+    int64_t K = 1;
+    for (char ch : s.contracted) K *= s.e(ch);
+    if (s.nC == 0) return TC_OK;
+    if (alpha == 0.0 || K == 0) {
+        ScaleArgs sa{};
+        sa.C = C;
+        sa.beta = beta;
+        sa.total = 1;
+        for (char ch : s.c) {
+            sa.dims.d[sa.dims.n++] = GtDim{s.e(ch), 0, 0, s.stride(2, ch)};
+            sa.total *= s.e(ch);
+        }
+        if (beta == 1.0) return TC_OK;
+        hipError_t e = launch_scale(f64, sa, st);
+        return e == hipSuccess ? TC_OK : hip_fail(e, "scale kernel launch");
+    }
+    int v = p->selected == TC_VARIANT_PREDICTED ? p->predicted_best : p->selected;
+    if (v < 0) return run_fused(p, A, B, C, alpha, beta, st);
+    if (s.compute != TC_NATIVE) return fail(TC_E_UNSUPPORTED, "split precision runs in the fused kernel only");
+    return run_variant(p, v, A, B, C, alpha, beta, st);
+}
+
+}  // namespace tc
+
+// ===========================================================================
+extern "C" {
+
+tc_status tc_plan(tc_plan_t* out, const char* spec, const char* index_chars, const int64_t* extents,
+                  int n_index, const int64_t* strides_A, const int64_t* strides_B,
+                  const int64_t* strides_C, tc_dtype dtype, tc_compute compute) {
+    if (!out) return fail(TC_E_NULL, "out is NULL");
+    *out = nullptr;
+    if (dtype != TC_F64 && dtype != TC_F32) return fail(TC_E_DTYPE, "dtype must be TC_F64 or TC_F32");
+    if (compute != TC_NATIVE && compute != TC_BF16X3 && compute != TC_FP8X3)
+        return fail(TC_E_DTYPE, "unknown compute mode");
+    tc_plan_s* p = new (std::nothrow) tc_plan_s();
+    if (!p) return fail(TC_E_NOMEM, "host allocation");
+    Err err;
+    p->spec.dtype = dtype;
+    p->spec.compute = compute;
+    if (parse_spec(spec, p->spec, err) ||
+        bind_spec(p->spec, index_chars, extents, n_index, strides_A, strides_B, strides_C, err)) {
+        delete p;
+        return fail(err.st, err.msg);
+    }
+    p->fam = enumerate_family(p->spec);
+    p->vplans.reserve(p->fam.size());
+    for (auto& v : p->fam) p->vplans.push_back(plan_variant(p->spec, v));
+    p->gv = gemm_view(p->spec);
+    *out = p;
+    return TC_OK;
+}
+
+tc_status tc_plan_destroy(tc_plan_t p) {
+    if (!p) return TC_OK;
+    release_plan_device(p);
+    delete p;
+    return TC_OK;
+}
+
+tc_status tc_variant_count(tc_plan_t p, int* n) {
+    if (!p || !n) return fail(TC_E_NULL, "NULL argument");
+    *n = (int)p->fam.size();
+    return TC_OK;
+}
+
+tc_status tc_variant_get(tc_plan_t p, int variant, tc_variant_info* out) {
+    if (!p || !out) return fail(TC_E_NULL, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    if (variant == TC_VARIANT_FUSED) {
+        std::snprintf(out->name, sizeof(out->name), "fused");
+        out->number = 0;
+        out->kernel = TC_KERNEL_FUSED;
+        out->launches = 1;
+        out->invocations = 1;
+        return TC_OK;
+    }
+    if (variant < 0 || variant >= (int)p->fam.size()) return fail(TC_E_VARIANT, "variant out of range");
+    const Variant& v = p->fam[variant];
+    std::snprintf(out->name, sizeof(out->name), "%s", v.name.c_str());
+    out->number = v.number;
+    out->kernel = v.kernel;
+    std::snprintf(out->kept, sizeof(out->kept), "%s", v.kept.c_str());
+    std::snprintf(out->loops, sizeof(out->loops), "%s", v.loops.c_str());
+    out->n_copies = (int)std::min<size_t>(4, v.copies.size());
+    for (int c = 0; c < out->n_copies; ++c) {
+        out->copy_tensor[c] = "ABC"[v.copies[c].first];
+        out->copy_level[c] = v.copies[c].second;
+    }
+    out->n_hoisted = v.n_hoisted;
+    out->launches = p->vplans[variant].launches;
+    int64_t inv = 1;
+    for (char ch : v.loops) inv *= p->spec.e(ch);
+    out->invocations = inv;
+    return TC_OK;
+}
+
+tc_status tc_set_variant(tc_plan_t p, int variant) {
+    if (!p) return fail(TC_E_NULL, "plan is NULL");
+    if (variant == TC_VARIANT_PREDICTED) {
+        if (p->predicted_best < -2 || !p->have_prediction)
+            return fail(TC_E_VARIANT, "no prediction yet: call tc_predict first");
+    } else if (variant != TC_VARIANT_FUSED && (variant < 0 || variant >= (int)p->fam.size())) {
+        return fail(TC_E_VARIANT, "variant out of range");
+    }
+    if (variant >= 0 && p->spec.compute != TC_NATIVE)
+        return fail(TC_E_UNSUPPORTED, "split precision runs in the fused kernel only");
+    p->selected = variant;
+    return TC_OK;
+}
+
+tc_status tc_plan_prepare(tc_plan_t p) {
+    if (!p) return fail(TC_E_NULL, "plan is NULL");
+    return prepare_plan(p);
+}
+
+tc_status tc_plan_workspace(tc_plan_t p, int64_t* bytes) {
+    if (!p || !bytes) return fail(TC_E_NULL, "NULL argument");
+    *bytes = p->ktab_cap + p->var_ktab_cap + p->temp_cap[0] + p->temp_cap[1] + p->split_bytes;
+    return TC_OK;
+}
+
+tc_status tc_contract(tc_plan_t p, const void* A, const void* B, void* C, double alpha, double beta,
+                      void* stream) {
+    if (!p) return fail(TC_E_NULL, "plan is NULL");
+    const Spec& s = p->spec;
+    int64_t K = 1;
+    for (char ch : s.contracted) K *= s.e(ch);
+    bool reads_inputs = alpha != 0.0 && K > 0 && s.nC > 0;
+    if (s.nC > 0 && !C) return fail(TC_E_NULL, "C is NULL");
+    if (reads_inputs && ((s.nA > 0 && !A) || (s.nB > 0 && !B))) return fail(TC_E_NULL, "A or B is NULL");
+    int es = s.elem_bytes();
+    auto overlap = [&](const void* x, int64_t span_x, const void* y, int64_t span_y) {
+        if (!x || !y || span_x == 0 || span_y == 0) return false;
+        uintptr_t x0 = (uintptr_t)x, x1 = x0 + (uintptr_t)(span_x * es);
+        uintptr_t y0 = (uintptr_t)y, y1 = y0 + (uintptr_t)(span_y * es);
+        return x0 < y1 && y0 < x1;
+    };
+    if (reads_inputs && (overlap(C, s.spanC, A, s.spanA) || overlap(C, s.spanC, B, s.spanB)))
+        return fail(TC_E_ALIAS, "C overlaps A or B");
+    if (s.nC == 0) return TC_OK;
+    if (std::getenv("TC_FAULT") && std::strcmp(std::getenv("TC_FAULT"), "launch") == 0)
+        return fail(TC_E_HIP, "injected launch failure (TC_FAULT=launch)");
+    tc_status st = prepare_plan(p);
+    if (st) return st;
+    return contract_dispatch(p, A, B, C, alpha, beta, (hipStream_t)stream);
+}
+
+tc_status tc_access_distance(tc_plan_t p, int variant, int tensor, int64_t* out) {
+    if (!p || !out) return fail(TC_E_NULL, "NULL argument");
+    if (variant < 0 || variant >= (int)p->fam.size()) return fail(TC_E_VARIANT, "variant out of range");
+    if (tensor < 0 || tensor > 2) return fail(TC_E_VARIANT, "tensor must be 0, 1 or 2");
+    *out = access_distance(p->spec, p->fam[variant], tensor, -1);
+    return TC_OK;
+}
+
+tc_status tc_bench_classes(tc_plan_t p, int variant, int stage, double cache_elems, int line_elems,
+                           tc_bench_class* out, int capacity, int* n_out) {
+    if (!p || !n_out) return fail(TC_E_NULL, "NULL argument");
+    if (variant < 0 || variant >= (int)p->fam.size()) return fail(TC_E_VARIANT, "variant out of range");
+    if (stage < 1 || stage > 5 || line_elems < 1 || !(cache_elems > 0))
+        return fail(TC_E_UNSUPPORTED, "stage must be 1..5, line and cache positive");
+    std::vector<BenchClass> cls = bench_classes(p->spec, p->fam[variant], stage, cache_elems, line_elems);
+    *n_out = (int)cls.size();
+    if ((int)cls.size() > capacity || (capacity > 0 && !out)) return fail(TC_E_CAPACITY, "capacity too small");
+    for (size_t c = 0; c < cls.size(); ++c) {
+        tc_bench_class& o = out[c];
+        std::memset(&o, 0, sizeof(o));
+        std::snprintf(o.label, sizeof(o.label), "%s", cls[c].label.c_str());
+        o.weight = cls[c].weight;
+        o.n_items = (int)std::min<size_t>(TC_MAX_SETUP, cls[c].setup.size());
+        for (int k = 0; k < o.n_items; ++k) {
+            o.items[k].kind = cls[c].setup[k].kind;
+            o.items[k].tensor = cls[c].setup[k].tensor;
+            o.items[k].size = cls[c].setup[k].size;
+        }
+    }
+    return TC_OK;
+}
+
+const char* tc_status_str(tc_status s) {
+    switch (s) {
+        case TC_OK: return "TC_OK";
+        case TC_E_SPEC: return "TC_E_SPEC";
+        case TC_E_EXTENT: return "TC_E_EXTENT";
+        case TC_E_STRIDE: return "TC_E_STRIDE";
+        case TC_E_DTYPE: return "TC_E_DTYPE";
+        case TC_E_ALIAS: return "TC_E_ALIAS";
+        case TC_E_NULL: return "TC_E_NULL";
+        case TC_E_VARIANT: return "TC_E_VARIANT";
+        case TC_E_HIP: return "TC_E_HIP";
+        case TC_E_NOMEM: return "TC_E_NOMEM";
+        case TC_E_UNSUPPORTED: return "TC_E_UNSUPPORTED";
+        case TC_E_CAPACITY: return "TC_E_CAPACITY";
+    }
+    return "TC_E_UNKNOWN";
+}
+
+const char* tc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,296 @@
+// Matrix-core contraction kernel for gfx950 (FP64 v_mfma_f64_16x16x4f64, FP32
+// v_mfma_f32_16x16x4f32).  It runs the fused direct contraction (one launch,
+// GEMM view M x N x K with arbitrary strides) and the gemm-shaped family
+// members (batch = parallel loops, sequential passes = in-launch contracted
+// loops, each pass reading and writing C).
+//
+// Operand staging: a BM x BK tile of A and a BK x BN tile of B go global ->
+// registers -> LDS, double-buffered, one barrier per K tile.  Each tile is
+// loaded with lanes along whichever index is contiguous in memory (M or K for
+// A, N or K for B), and written to LDS k-major so that the fragment reads of
+// every MFMA are conflict-free rows.  K is walked through a table of (A, B)
+// offset pairs built by the planner in a blocked order in which A's and B's
+// contiguous contracted indices both form runs; that handles any number of
+// contracted indices and permuted strides with one kernel.
+//
+// The MFMA "row" operand is B (rows = n) and the "column" operand is A
+// (columns = m), so each accumulator register holds 16 consecutive m of one n
+// in 16 consecutive lanes:
+// with C's unit stride along m the epilogue stores whole 128-byte (FP64) rows.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "launch.h"
+
+namespace tc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// Accumulator layout of the 16x16x4 forms: lane l, register q holds column
+// l % 16 of row 4*(l/16) + q for FP32, but row (l/16) + 4*q for FP64.
+template <> struct Mfma<double> {
+    typedef d4 acc_t;
+    static __device__ __forceinline__ int row(int lane, int q) { return (lane >> 4) + 4 * q; }
+    static __device__ __forceinline__ acc_t mac(double rowop, double colop, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(rowop, colop, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<float> {
+    typedef f4 acc_t;
+    static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+    static __device__ __forceinline__ acc_t mac(float rowop, float colop, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(rowop, colop, c, 0, 0, 0);
+    }
+};
+
+__device__ __forceinline__ int64_t dm(int64_t& rem, int64_t ext) {
+    if ((uint64_t)rem <= 0xffffffffull && (uint64_t)ext <= 0xffffffffull) {
+        uint32_t r = (uint32_t)rem, e = (uint32_t)ext;
+        uint32_t q = r / e;
+        rem = q;
+        return (int64_t)(r - q * e);
+    }
+    int64_t q = rem / ext, m = rem - q * ext;
+    rem = q;
+    return m;
+}
+
+// offset of linear index `i` within a dimension group, for tensor slot 0 (A),
+// 1 (B) or 2 (C)
+template <int SLOT>
+__device__ __forceinline__ int64_t group_off(const GtDims& g, int64_t i) {
+    int64_t off = 0;
+    for (int d = 0; d < g.n; ++d) {
+        int64_t r = dm(i, g.d[d].ext);
+        off += r * (SLOT == 0 ? g.d[d].sA : SLOT == 1 ? g.d[d].sB : g.d[d].sC);
+    }
+    return off;
+}
+
+// Tiles are handed to XCDs in contiguous ranges: the hardware deals blocks
+// round-robin over the 8 XCDs, so block b runs on XCD b % 8.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
+    const int64_t X = 8;
+    int64_t xcd = b % X, idx = b / X;
+    int64_t per = total / X, rem = total % X;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+template <typename T, int BM, int BN, int BK, bool A_KMAJ, bool B_KMAJ>
+__global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
+    typedef typename Mfma<T>::acc_t acc_t;
+    constexpr int PAD = 4;
+    constexpr int LDA = BM + PAD, LDB = BN + PAD;
+    constexpr int EA = BM * BK / 256, EB = BN * BK / 256;   // elements per thread per tile
+    constexpr int FM = BM / 32, FN = BN / 32;              // 16x16 blocks per wave
+    static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
+    __shared__ T As[2][BK][LDA];
+    __shared__ T Bs[2][BK][LDB];
+
+    const T* __restrict__ Ag = (const T*)a.A;
+    const T* __restrict__ Bg = (const T*)a.B;
+    T* Cg = (T*)a.C;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int wm = wid & 1, wn = wid >> 1;
+
+    const int64_t tile = xcd_tile(blockIdx.x, a.ntiles);
+    int64_t rest = tile;
+    const int64_t mt = rest % a.mt; rest /= a.mt;
+    const int64_t nt = rest % a.nt; rest /= a.nt;
+    const int64_t bt = rest;
+    const int64_t m_base = mt * BM, n_base = nt * BN;
+
+    int64_t bA = 0, bB = 0, bC = 0;
+    {
+        int64_t r = bt;
+        for (int d = 0; d < a.batch.n; ++d) {
+            int64_t q = dm(r, a.batch.d[d].ext);
+            bA += q * a.batch.d[d].sA;
+            bB += q * a.batch.d[d].sB;
+            bC += q * a.batch.d[d].sC;
+        }
+    }
+
+    // per-block offset tables: A/C offsets of the tile's rows (m) and B/C
+    // offsets of its columns (n); -1 marks rows/columns past the edge
+    __shared__ int64_t sAm[BM], sCm[BM], sBn[BN], sCn[BN];
+    for (int i = tid; i < BM; i += 256) {
+        int64_t m = m_base + i;
+        bool ok = m < a.M;
+        sAm[i] = ok ? group_off<0>(a.m, m) : -1;
+        sCm[i] = ok ? group_off<2>(a.m, m) : -1;
+    }
+    for (int i = tid; i < BN; i += 256) {
+        int64_t n = n_base + i;
+        bool ok = n < a.N;
+        sBn[i] = ok ? group_off<1>(a.n, n) : -1;
+        sCn[i] = ok ? group_off<2>(a.n, n) : -1;
+    }
+    __syncthreads();
+
+    const T alpha = (T)a.alpha, beta = (T)a.beta;
+    const int64_t ktiles = a.Kpad / BK;
+
+    int64_t pctr[GT_MAXD];
+    for (int d = 0; d < a.pass.n; ++d) pctr[d] = 0;
+    int64_t pA = 0, pB = 0;
+
+    for (int64_t pass = 0; pass < a.npass; ++pass) {
+        acc_t acc[FN][FM];
+#pragma unroll
+        for (int i = 0; i < FN; ++i)
+#pragma unroll
+            for (int j = 0; j < FM; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+        T ra[EA], rb[EB];
+        // K-table entries of the next tile are fetched one tile ahead, so the
+        // table lookup and the operand load never form a dependent chain inside
+        // one tile.  In K-major loading a thread always handles the same k of
+        // a tile (one entry); in M/N-major loading it handles EA/EB of them.
+        constexpr int TA = A_KMAJ ? 1 : EA, TB = B_KMAJ ? 1 : EB;
+        int64_t tA[TA], tB[TB];
+        auto tload = [&](int64_t kt) {
+            const int64_t* kt0 = a.ktab + 2 * kt * BK;
+#pragma unroll
+            for (int e = 0; e < TA; ++e) tA[e] = kt0[2 * (A_KMAJ ? tid % BK : (tid + 256 * e) / BM)];
+#pragma unroll
+            for (int e = 0; e < TB; ++e) tB[e] = kt0[2 * (B_KMAJ ? tid % BK : (tid + 256 * e) / BN) + 1];
+        };
+        // operand loads with clamped addresses (element (batch, pass, 0, 0) is
+        // always valid) and a select, so no branch sits around a load
+        auto gload = [&]() {
+#pragma unroll
+            for (int e = 0; e < EA; ++e) {
+                const int idx = tid + 256 * e;
+                const int64_t om = sAm[A_KMAJ ? idx / BK : idx % BM];
+                const int64_t ko = tA[A_KMAJ ? 0 : e];
+                const bool ok = (om >= 0) & (ko >= 0);
+                const T v = Ag[bA + pA + (ok ? om + ko : 0)];
+                ra[e] = ok ? v : (T)0;
+            }
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+                const int idx = tid + 256 * e;
+                const int64_t on = sBn[B_KMAJ ? idx / BK : idx % BN];
+                const int64_t ko = tB[B_KMAJ ? 0 : e];
+                const bool ok = (on >= 0) & (ko >= 0);
+                const T v = Bg[bB + pB + (ok ? on + ko : 0)];
+                rb[e] = ok ? v : (T)0;
+            }
+        };
+        auto sstore = [&](int buf) {
+#pragma unroll
+            for (int e = 0; e < EA; ++e) {
+                const int idx = tid + 256 * e;
+                As[buf][A_KMAJ ? idx % BK : idx / BM][A_KMAJ ? idx / BK : idx % BM] = ra[e];
+            }
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+                const int idx = tid + 256 * e;
+                Bs[buf][B_KMAJ ? idx % BK : idx / BN][B_KMAJ ? idx / BK : idx % BN] = rb[e];
+            }
+        };
+
+        if (ktiles > 0) {
+            tload(0);
+            gload();
+            sstore(0);
+            if (ktiles > 1) tload(1);
+        }
+        __syncthreads();
+        for (int64_t kt = 0; kt < ktiles; ++kt) {
+            const int buf = (int)(kt & 1);
+            if (kt + 1 < ktiles) {
+                gload();
+                if (kt + 2 < ktiles) tload(kt + 2);
+            }
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                const int kr = kk + (lane >> 4);
+                T fa[FM], fb[FN];
+#pragma unroll
+                for (int j = 0; j < FM; ++j) fa[j] = As[buf][kr][wm * (BM / 2) + j * 16 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < FN; ++i) fb[i] = Bs[buf][kr][wn * (BN / 2) + i * 16 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < FN; ++i)
+#pragma unroll
+                    for (int j = 0; j < FM; ++j) acc[i][j] = Mfma<T>::mac(fb[i], fa[j], acc[i][j]);
+            }
+            if (kt + 1 < ktiles) sstore(buf ^ 1);
+            __syncthreads();
+        }
+
+        // epilogue: lane holds D[n = row(lane, q)][m = lane % 16] of each block
+#pragma unroll
+        for (int i = 0; i < FN; ++i) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t cn = sCn[wn * (BN / 2) + i * 16 + Mfma<T>::row(lane, q)];
+                if (cn < 0) continue;
+#pragma unroll
+                for (int j = 0; j < FM; ++j) {
+                    const int64_t cm = sCm[wm * (BM / 2) + j * 16 + (lane & 15)];
+                    if (cm < 0) continue;
+                    T* cp = Cg + bC + cn + cm;
+                    T v = alpha * acc[i][j][q];
+                    if (a.mode == 1) v = *cp + v;
+                    else if (a.beta != 0.0) v += beta * (*cp);
+                    *cp = v;
+                }
+            }
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        // next pass (innermost pass loop fastest)
+        for (int d = a.pass.n - 1; d >= 0; --d) {
+            pA += a.pass.d[d].sA;
+            pB += a.pass.d[d].sB;
+            if (++pctr[d] < a.pass.d[d].ext) break;
+            pA -= a.pass.d[d].sA * a.pass.d[d].ext;
+            pB -= a.pass.d[d].sB * a.pass.d[d].ext;
+            pctr[d] = 0;
+        }
+    }
+}
+
+// Tile shape per storage type.  FP64: 128x128x16 (64 accumulators per lane in
+// 16 MFMA blocks per wave); FP32: 128x128x16 as well.
+constexpr int kBM = 128, kBN = 128, kBK = 16;
+
+int mfma_bk(bool) { return kBK; }
+
+void mfma_tiles(bool, MfmaArgs& a) {
+    a.mt = (a.M + kBM - 1) / kBM;
+    a.nt = (a.N + kBN - 1) / kBN;
+    a.ntiles = a.mt * a.nt * a.nbatch;
+}
+
+template <typename T>
+static hipError_t mfma_dispatch(MfmaArgs& a, bool akmaj, bool bkmaj, hipStream_t st) {
+    if (a.ntiles <= 0) return hipSuccess;
+    if (a.ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
+    dim3 g((unsigned)a.ntiles), b(256);
+    if (akmaj && bkmaj) hipLaunchKernelGGL((k_mfma<T, kBM, kBN, kBK, true, true>), g, b, 0, st, a);
+    else if (akmaj) hipLaunchKernelGGL((k_mfma<T, kBM, kBN, kBK, true, false>), g, b, 0, st, a);
+    else if (bkmaj) hipLaunchKernelGGL((k_mfma<T, kBM, kBN, kBK, false, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_mfma<T, kBM, kBN, kBK, false, false>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+// Lanes go along K for an operand whose free group is not unit-stride.
+static bool k_major(const GtDims& g, int slot) {
+    if (g.n == 0) return true;
+    int64_t s = slot == 0 ? g.d[0].sA : g.d[0].sB;
+    return s != 1;
+}
+
+hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st) {
+    bool ak = k_major(a.m, 0), bk = k_major(a.n, 1);
+    return f64 ? mfma_dispatch<double>(a, ak, bk, st) : mfma_dispatch<float>(a, ak, bk, st);
+}
+
+}  // namespace tc

@@ -1,0 +1,35 @@
+// Host-side launchers of the HIP kernels.  All launches are asynchronous on
+// the given stream and return hipSuccess or the launch error.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gett.h"
+
+namespace tc {
+
+// Fused contraction for small contracted extents (K <= GT_SMALLK_MAX): C is
+// streamed along its unit-stride M dimension, A's rows stay in registers.
+hipError_t launch_stream(bool f64, StreamArgs& a, hipStream_t st);
+// Choose threads-per-row and rows-per-block for the streaming kernel.
+void stream_shape(bool f64, StreamArgs& a);
+int64_t stream_grid(bool f64, const StreamArgs& a);
+
+// Family-member bodies with dot/axpy/gemv/ger kernels: one thread per output
+// element of one invocation.
+hipError_t launch_simt(bool f64, SimtArgs& a, hipStream_t st);
+
+// Matrix-core contraction (gemm-shaped members and the fused kernel).
+hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st);
+void mfma_tiles(bool f64, MfmaArgs& a);
+int mfma_bk(bool f64);
+
+// Strided copy (copy statements of the family) and C := beta*C prologue.
+hipError_t launch_copy(bool f64, CopyArgs& a, hipStream_t st);
+hipError_t launch_scale(bool f64, ScaleArgs& a, hipStream_t st);
+
+// Cache set-up for micro-benchmarks: read `n` elements at `p` (touch) and
+// accumulate into a sink so the reads are not removed.
+hipError_t launch_touch(const void* p, int64_t bytes, float* sink, hipStream_t st);
+
+}  // namespace tc

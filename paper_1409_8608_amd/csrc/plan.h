@@ -1,0 +1,52 @@
+// The plan object behind tc_plan_t and the internal entry points that use it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "tc_internal.h"
+
+struct tc_plan_s {
+    tc::Spec spec;
+    std::vector<tc::Variant> fam;
+    std::vector<tc::VariantPlan> vplans;
+    tc::GemmView gv;
+    int selected = TC_VARIANT_FUSED;
+    int predicted_best = TC_VARIANT_FUSED;
+    bool have_prediction = false;
+
+    // device workspace (allocated by prepare, freed by destroy)
+    void* d_ktab = nullptr;          // fused matrix-core K table
+    int64_t ktab_cap = 0, kpad = 0;
+    void* d_var_ktab = nullptr;      // K table of the selected gemm member
+    int64_t var_ktab_cap = 0, var_kpad = 0;
+    int var_ktab_for = -1;
+    void* d_temp[2] = {nullptr, nullptr};   // copy temporaries of A and B
+    int64_t temp_cap[2] = {0, 0};
+    // split-precision buffers (one allocation)
+    void* d_split = nullptr;
+    int64_t split_bytes = 0;
+    int64_t split_layout[16] = {0};
+};
+
+namespace tc {
+extern thread_local std::string g_last_error;
+tc_status fail(tc_status s, const std::string& msg);
+tc_status hip_fail(hipError_t e, const char* what);
+
+std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK);
+bool use_stream_kernel(const Spec& s, const GemmView& gv);
+tc_status prepare_plan(tc_plan_s* p);
+tc_status contract_dispatch(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
+                            hipStream_t st);
+tc_status run_variant(tc_plan_s* p, int v, const void* A, const void* B, void* C, double alpha, double beta,
+                      hipStream_t st);
+
+// split precision (kernels_split.hip)
+tc_status prepare_split(tc_plan_s* p);
+tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
+                    hipStream_t st);
+void release_plan_device(tc_plan_s* p);
+}  // namespace tc

@@ -1,0 +1,121 @@
+// Internal declarations of libtc: host-side planning (spec, family, schedule,
+// symbolic prediction) shared by the C ABI and the kernel launchers.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tc.h"
+#include "gett.h"
+
+namespace tc {
+
+// Error carrier: every internal routine returns a status and fills `msg`.
+struct Err {
+    tc_status st = TC_OK;
+    std::string msg;
+    tc_status set(tc_status s, std::string m) { st = s; msg = std::move(m); return s; }
+};
+
+// ---------------------------------------------------------------------------
+// Contraction spec (Section 1): operand letters and the role of every index.
+struct Spec {
+    std::string a, b, c;            // letters of A, B and C in axis order
+    std::string contracted;         // in A's axis order
+    std::string free_a, free_b;     // in C's axis order
+    std::string base;               // C's letters, then the contracted ones
+    // bound per letter (index by letter - 'a'); stride 0 where the operand lacks it
+    int64_t ext[26] = {0};
+    int64_t sA[26] = {0}, sB[26] = {0}, sC[26] = {0};
+    bool inA[26] = {false}, inB[26] = {false}, inC[26] = {false};
+    tc_dtype dtype = TC_F64;
+    tc_compute compute = TC_NATIVE;
+    int64_t nA = 0, nB = 0, nC = 0;       // element counts (products of extents)
+    int64_t spanA = 0, spanB = 0, spanC = 0; // 1 + largest element offset (0 if empty)
+
+    int64_t e(char ch) const { return ext[ch - 'a']; }
+    int64_t stride(int tensor, char ch) const {
+        int k = ch - 'a';
+        return tensor == 0 ? sA[k] : tensor == 1 ? sB[k] : sC[k];
+    }
+    const std::string& letters(int tensor) const { return tensor == 0 ? a : tensor == 1 ? b : c; }
+    int64_t flops() const;                 // 2 * product of all extents
+    int elem_bytes() const { return dtype == TC_F64 ? 8 : 4; }
+};
+
+tc_status parse_spec(const char* text, Spec& s, Err& err);
+tc_status bind_spec(Spec& s, const char* index_chars, const int64_t* extents, int n_index,
+                    const int64_t* stA, const int64_t* stB, const int64_t* stC, Err& err);
+
+// ---------------------------------------------------------------------------
+// Family member (Section 2).
+struct Operand {
+    int tensor;                       // 0 A, 1 B, 2 C
+    std::string letters;
+    std::vector<bool> fixed;          // per axis: sliced (fixed by a loop)
+};
+
+struct Variant {
+    int number = 0;                   // paper numbering, from 1
+    int kernel = 0;                   // TC_KERNEL_*
+    std::string kept;                 // kernel indices
+    std::string loops;                // sliced indices, outermost first
+    std::vector<std::pair<int, int>> copies;   // (tensor, loop level; -1 = before all loops)
+    std::string name;
+    Operand ops[3];
+    int n_hoisted = 0;                // leading contracted loops -> launch passes
+};
+
+std::vector<Variant> enumerate_family(const Spec& s);
+
+// ---------------------------------------------------------------------------
+// Symbolic prediction (Section 3).
+struct SetupItem { int kind; int tensor; int64_t size; };   // kind 0 op, 1 remote
+struct BenchClass {
+    std::string label;
+    double weight = 0;
+    std::vector<SetupItem> setup;
+    int start = -1;                    // -1 steady/fail; else first-iteration loop position
+    std::vector<bool> prefetched;      // per operand: prefetch emulation used
+};
+
+int64_t region_size(const Spec& s, const Operand& op, const std::string& joined);
+int64_t access_distance(const Spec& s, const Variant& v, int tensor, int start = -1);
+int prefetch_kind(const Spec& s, const Variant& v, int tensor, int line_elems);  // 0 none, 1 line, 2 stream
+std::vector<BenchClass> bench_classes(const Spec& s, const Variant& v, int stage,
+                                      double cache_elems, int line_elems);
+
+// ---------------------------------------------------------------------------
+// GPU schedules.
+//
+// A fused plan is a GEMM view: M = free indices of A, N = free indices of B,
+// K = contracted indices.  Dimensions of a group that are laid out as one
+// (stride[d+1] == stride[d] * ext[d] in every operand holding them) are merged.
+struct GemmView {
+    std::vector<GtDim> m, n, k;       // each group, unit-C-stride dim first where possible
+    bool swapped = false;             // A and B exchanged so that C's unit stride is in M
+    int64_t M = 1, N = 1, K = 1;
+};
+GemmView gemm_view(const Spec& s);
+
+// Launch sequence of one family member.
+struct CopyStep {
+    int tensor;                        // 0 A, 1 B
+    int level;
+    GtDims dims;                       // slice axes then slot axes; src = operand, dst = temp
+    int64_t slice_elems = 0, slots = 1;
+    int hoist_depth = 0;               // hoisted loops the copy's source offset depends on
+};
+struct VariantPlan {
+    GtDesc body;                       // body launch (hoisted-loop offsets added per pass)
+    std::vector<GtDim> hoisted;        // hoisted loops (outermost first): strides into A, B, C
+    std::vector<CopyStep> copies;
+    int64_t temp_elems[2] = {0, 0};    // temp buffer sizes for A and B copies
+    bool mfma = false;                 // gemm body on matrix cores
+    bool needs_c_copy = false;         // unsupported on the GPU
+    int64_t launches = 0;
+};
+VariantPlan plan_variant(const Spec& s, const Variant& v);
+
+}  // namespace tc

@@ -1,0 +1,50 @@
+"""Helpers shared by the GPU tests: move seeded host inputs to the device in
+the plan's layout, run the library, bring C back, compare with the oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def run(plan, A, B, C0=None, alpha=1.0, beta=0.0, dtype="f64"):
+    """Run ``plan`` on host arrays (Fortran order) and return C as float64."""
+    import paper_1409_8608_amd as tc
+    torch = torch_mod()
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    dA = tc.to_device_fortran(A, tdt)
+    dB = tc.to_device_fortran(B, tdt)
+    if C0 is not None:
+        dC = tc.to_device_fortran(C0, tdt)
+    else:
+        dC = tc.empty_fortran(plan.shape("C"), tdt)
+        dC.fill_(float("nan"))             # beta = 0 must not read C
+    plan.contract(dA, dB, dC, alpha, beta)
+    torch.cuda.synchronize()
+    out = dC.double().cpu().numpy()
+    return out
+
+
+def rounded(x, dtype):
+    """Values the device actually sees (FP32 runs round the FP64 draws)."""
+    return x if dtype == "f64" else x.astype(np.float32).astype(np.float64)
+
+
+def check(spec, ext, A, B, got, dtype="f64", C0=None, alpha=1.0, beta=0.0, exact=False, tol=None):
+    Ar, Br = rounded(A, dtype), rounded(B, dtype)
+    Cr = None if C0 is None else np.array(rounded(C0, dtype), order="F")
+    ref = oracle.contract(spec, ext, Ar, Br, C=Cr, alpha=alpha, beta=beta)
+    if exact:
+        np.testing.assert_array_equal(got, ref)
+        return 0.0
+    absAB = oracle.contract(spec, ext, np.abs(Ar), np.abs(Br))
+    err = oracle.normwise_rel_err(got, ref, absAB)
+    if tol is None:
+        tol = 1e-12 if dtype == "f64" else 1e-5
+    assert err <= tol, f"normwise error {err:.3e} > {tol:.1e}"
+    return err

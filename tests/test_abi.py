@@ -1,0 +1,152 @@
+"""CPU tests of the C ABI: the library loads and exports every declared
+symbol, plan validation errors, and the host logic (family enumeration and the
+symbolic prediction steps) against the independent oracle."""
+import os
+import re
+
+import pytest
+
+import oracle
+from oracle import access as ac, family
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+tc = pytest.importorskip("paper_1409_8608_amd")
+
+SPECS = ["abc=ai,ibc", "abc=ija,jbic", "ab=iaj,jbi", "abcd=ai,ibcd", "a=iaj,ji"]
+
+
+def test_exports_every_declared_symbol():
+    with open(os.path.join(ROOT, "include", "tc.h")) as f:
+        text = f.read()
+    declared = set(re.findall(r"\b(tc_[a-z_]+)\s*\(", text))
+    assert len(declared) >= 17
+    for name in declared:
+        assert hasattr(tc.lib, name), name
+    assert set(tc.EXPORTS) == declared
+
+
+@pytest.mark.parametrize("spec,status", [
+    ("abc=ai", "TC_E_SPEC"), ("abc=ai,ib", "TC_E_SPEC"), ("abc=aic,ibc", "TC_E_SPEC"),
+    ("aa=ai,ia", "TC_E_SPEC"), ("abc=aix,ibc", "TC_E_SPEC"), ("aBc=ai,iBc", "TC_E_SPEC"),
+])
+def test_plan_rejects_bad_specs(spec, status):
+    ext = {ch: 2 for ch in set(spec.lower()) if ch.isalpha()}
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_plan(spec, ext)
+    assert e.value.name == status
+
+
+def test_plan_rejects_bad_bindings():
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_plan("abc=ai,ibc", dict(a=2, b=2, c=2))
+    assert e.value.name == "TC_E_EXTENT"
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_plan("abc=ai,ibc", dict(a=2, b=2, c=-1, i=2))
+    assert e.value.name == "TC_E_EXTENT"
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_plan("abc=ai,ibc", dict(a=2 ** 40, b=2 ** 40, c=2 ** 40, i=2))
+    assert e.value.name == "TC_E_EXTENT"
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_plan("abc=ai,ibc", dict(a=4, b=4, c=4, i=2), strides_A=[1, -4])
+    assert e.value.name == "TC_E_STRIDE"
+    with pytest.raises(tc.TcError) as e:   # C aliases itself
+        tc.tc_plan("abc=ai,ibc", dict(a=4, b=4, c=4, i=2), strides_C=[1, 2, 16])
+    assert e.value.name == "TC_E_STRIDE"
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_plan("abc=ai,ibc", dict(a=4, b=4, c=4, i=2), dtype=7)
+    assert e.value.name == "TC_E_DTYPE"
+    h = tc.tc_plan("abc=ai,ibc", dict(a=4, b=4, c=4, i=2))
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_set_variant(h, 36)
+    assert e.value.name == "TC_E_VARIANT"
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_set_variant(h, tc.TC_VARIANT_PREDICTED)
+    assert e.value.name == "TC_E_VARIANT"
+    tc.tc_plan_destroy(h)
+
+
+@pytest.mark.parametrize("spec", SPECS)
+def test_family_matches_oracle(spec):
+    ext = {ch: 3 for ch in set(spec) if ch.isalpha()}
+    h = tc.tc_plan(spec, ext)
+    got = [tc.tc_variant_get(h, v) for v in range(tc.tc_variant_count(h))]
+    want = family.enumerate_family(spec)
+    assert [g["name"] for g in got] == [w.name for w in want]
+    for g, w in zip(got, want):
+        assert g["number"] == w.number and g["kernel"] == w.kernel
+        assert g["loops"] == "".join(w.loops) and sorted(g["kept"]) == sorted(w.kept)
+        assert g["copies"] == [(t, lv) for t, lv in w.copies]
+    tc.tc_plan_destroy(h)
+
+
+def test_family_with_strides_matches_oracle():
+    spec = "abc=ija,jbic"
+    ext = dict(a=4, b=5, c=6, i=2, j=3)
+    sA = [4 * 3, 4, 1]             # A's 'a' axis unit stride
+    h = tc.tc_plan(spec, ext, strides_A=sA)
+    got = [tc.tc_variant_get(h, v) for v in range(tc.tc_variant_count(h))]
+    want = family.enumerate_family(spec, strides={"A": sA})
+    assert [g["name"] for g in got] == [w.name for w in want]
+    tc.tc_plan_destroy(h)
+
+
+def _regions(v):
+    return [ac.Region(o.tensor, o.letters, o.fixed) for o in v.operands]
+
+
+@pytest.mark.parametrize("spec", SPECS)
+@pytest.mark.parametrize("stage", [1, 2, 3, 4, 5])
+def test_symbolic_prediction_matches_oracle(spec, stage):
+    ext = {ch: n for ch, n in zip("abcdij", (400, 30, 20, 12, 8, 6))}
+    ext = {ch: ext[ch] for ch in set(spec) if ch.isalpha()}
+    h = tc.tc_plan(spec, ext)
+    for v in family.enumerate_family(spec):
+        idx = v.number - 1
+        ops = _regions(v)
+        for t, r in enumerate(ops):
+            assert tc.tc_access_distance(h, idx, t) == ac.access_distance(r, ops, v.loops, ext), (v.name, t)
+        for cache, line in ((786432.0, 8), (5000.0, 16)):
+            want = ac.predict_classes(ops, v.loops, ext, cache, line, stage=stage)
+            got = tc.tc_bench_classes(h, idx, stage, cache, line)
+            assert [g["label"] for g in got] == [w.label for w in want], v.name
+            for g, w in zip(got, want):
+                assert abs(g["weight"] - w.weight) < 1e-12, (v.name, g["label"])
+                assert [tuple(e) for e in g["setup"]] == [tuple(e) for e in w.setup], (v.name, g["label"])
+    tc.tc_plan_destroy(h)
+
+
+def test_worked_example_through_abi(golden):
+    g = golden("access_example.json")
+    h = tc.tc_plan(g["spec"], g["extents"])
+    idx = [tc.tc_variant_get(h, v)["name"] for v in range(36)].index(g["variant"])
+    for t, name in enumerate("ABC"):
+        assert tc.tc_access_distance(h, idx, t) == g["distances"][name]
+    st2 = tc.tc_bench_classes(h, idx, 2, g["cache_elems"], g["line_elems"])
+    assert [list(e) for e in st2[0]["setup"]] == g["setup_truncated"]
+    st4 = tc.tc_bench_classes(h, idx, 4, g["cache_elems"], g["line_elems"])
+    assert st4[0]["setup"] == [] and [list(e) for e in st4[1]["setup"]] == g["setup_fail"]
+    tc.tc_plan_destroy(h)
+
+
+def test_schedule_counts():
+    """Launch counts of the GPU schedule: hoisted contracted loops become
+    launch passes, copies run once per pass group."""
+    h = tc.tc_plan("abc=ija,jbic", dict(a=256, b=256, c=256, i=32, j=32))
+    by = {tc.tc_variant_get(h, v)["name"]: tc.tc_variant_get(h, v) for v in range(176)}
+    assert by["i'c-gemm"]["n_hoisted"] == 1 and by["i'c-gemm"]["launches"] == 1 + 32 + 32
+    assert by["ci'-gemm"]["n_hoisted"] == 0 and by["ci'-gemm"]["launches"] == 3
+    assert by["cj'-gemm"]["invocations"] == 256 * 32
+    tc.tc_plan_destroy(h)
+
+
+def test_injected_launch_failure(monkeypatch):
+    """The fault injector turns tc_contract into TC_E_HIP before any device call;
+    the plan stays usable."""
+    monkeypatch.setenv("TC_FAULT", "launch")
+    h = tc.tc_plan("ab=ai,ib", dict(a=2, b=2, i=2))
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_contract(h, 16, 4096, 8192)
+    assert e.value.name == "TC_E_HIP"
+    monkeypatch.delenv("TC_FAULT")
+    assert tc.tc_variant_count(h) == len(family.enumerate_family("ab=ai,ib"))
+    tc.tc_plan_destroy(h)

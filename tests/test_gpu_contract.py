@@ -1,0 +1,171 @@
+"""GPU parity: the fused kernels and every family member against the FP64
+oracle, through the C ABI.  Tolerances: FP64 normwise <= 1e-12, FP32 <= 1e-5
+(against the oracle on the FP32-rounded inputs); integer data bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import check, run
+
+pytestmark = pytest.mark.gpu
+
+tc = pytest.importorskip("paper_1409_8608_amd")
+from paper_1409_8608_amd import workloads as wl  # noqa: E402
+
+
+def _plan(spec, ext, dtype="f64", strides=None, compute="native"):
+    return tc.Plan(spec, ext, dtype=dtype, strides=strides, compute=compute)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fused_smallk_cube(dtype):
+    w = wl.smallk_cube(64, 8)
+    p = _plan(w["spec"], w["ext"], dtype)
+    got = run(p, w["A"], w["B"], dtype=dtype)
+    check(w["spec"], w["ext"], w["A"], w["B"], got, dtype)
+
+
+def test_fused_smallk_integer_exact_and_beta():
+    w = wl.smallk_cube(64, 8, integer=True, with_c=True)
+    p = _plan(w["spec"], w["ext"])
+    got = run(p, w["A"], w["B"], w["C"], alpha=2.0, beta=-0.5)
+    check(w["spec"], w["ext"], w["A"], w["B"], got, C0=w["C"], alpha=2.0, beta=-0.5, exact=True)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", [
+    ("abc=ija,jbic", dict(a=40, b=33, c=7, i=5, j=11)),          # ragged tiles, permuted strides
+    ("ab=iaj,jbi", dict(a=130, b=70, i=9, j=6)),
+    ("abcd=ai,ibcd", dict(a=17, b=5, c=6, d=7, i=40)),            # K > 32: matrix cores
+    ("abc=ai,ibc", dict(a=200, b=9, c=3, i=100)),
+    ("ab=ai,ib", dict(a=129, b=257, i=64)),
+    ("abc=bi,iac", dict(a=64, b=48, c=5, i=33)),                   # C's unit index comes from B
+])
+def test_fused_mfma_shapes(dtype, spec, ext):
+    rng = np.random.default_rng(3)
+    A, B, _ = wl.tensors(spec, ext, rng, "normal")
+    p = _plan(spec, ext, dtype)
+    got = run(p, A, B, dtype=dtype)
+    check(spec, ext, A, B, got, dtype)
+
+
+def test_fused_mfma_integer_exact():
+    spec, ext = "abc=ija,jbic", dict(a=70, b=20, c=9, i=13, j=17)
+    A, B, C = wl.tensors(spec, ext, np.random.default_rng(5), integer=True, with_c=True)
+    for dtype in ("f64", "f32"):
+        p = _plan(spec, ext, dtype)
+        got = run(p, A, B, C, alpha=1.0, beta=2.0, dtype=dtype)
+        check(spec, ext, A, B, got, dtype, C0=C, alpha=1.0, beta=2.0, exact=True)
+
+
+def test_explicit_strides():
+    """Padded, permuted layouts given by strides (same memory, other order)."""
+    torch = pytest.importorskip("torch")
+    spec, ext = "abc=ija,jbic", dict(a=24, b=10, c=6, i=7, j=5)
+    A, B, _ = wl.tensors(spec, ext, np.random.default_rng(8), "normal")
+    ref = oracle.contract(spec, ext, A, B)
+    # A stored as [a][j][i] with padding: strides i=1, j=8, a=8*6
+    sA = [1, 8, 48]
+    bufA = torch.zeros(48 * 24 + 64, dtype=torch.float64, device="cuda")
+    dA = torch.as_strided(bufA, (7, 5, 24), sA)
+    dA.copy_(torch.from_numpy(A))
+    dB = tc.to_device_fortran(B, torch.float64)
+    # C in C-order (last index fastest)
+    sC = [60, 6, 1]
+    dC = torch.full((24 * 60,), float("nan"), dtype=torch.float64, device="cuda")
+    dCv = torch.as_strided(dC, (24, 10, 6), sC)
+    p = _plan(spec, ext, strides=dict(A=sA, C=sC))
+    infos = p.variants()
+    for v in [tc.TC_VARIANT_FUSED] + list(range(0, 176, 7)):
+        p.set_variant(v)
+        dCv.fill_(float("nan"))
+        if v >= 0 and any(t == "C" for t, _ in infos[v]["copies"]):
+            # C's unit-stride index is sliced: the member would copy C in and
+            # out around each call, which the GPU schedule does not run
+            with pytest.raises(tc.TcError) as e:
+                p.contract(dA, dB, dCv, 1.0, 0.0)
+            assert e.value.name == "TC_E_UNSUPPORTED"
+            continue
+        p.contract(dA, dB, dCv, 1.0, 0.0)
+        torch.cuda.synchronize()
+        err = oracle.normwise_rel_err(dCv.cpu().numpy(), ref)
+        assert err <= 1e-12, (v, err)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_every_variant_case_study(dtype):
+    """All 36 members of C_abc = A_ai B_ibc (Section 3 case study, a=b=c=64,
+    i=8) against the oracle; integer data bit-exact."""
+    w = wl.smallk_cube(64, 8, integer=True)
+    p = _plan(w["spec"], w["ext"], dtype)
+    names = [v["name"] for v in p.variants()]
+    assert len(names) == 36
+    for v in range(36):
+        p.set_variant(v)
+        got = run(p, w["A"], w["B"], dtype=dtype)
+        check(w["spec"], w["ext"], w["A"], w["B"], got, dtype, exact=True)
+
+
+def test_every_variant_permuted_small():
+    """All 176 members of C_abc = A_ija B_jbic (Section 4.3 Test 3) with ragged
+    extents; integer data bit-exact, real data within tolerance, alpha/beta."""
+    spec, ext = "abc=ija,jbic", dict(a=19, b=6, c=5, i=4, j=3)
+    A, B, C = wl.tensors(spec, ext, np.random.default_rng(21), integer=True, with_c=True)
+    p = _plan(spec, ext)
+    assert len(p.variants()) == 176
+    for v in range(176):
+        p.set_variant(v)
+        got = run(p, A, B, C, alpha=1.0, beta=-1.0)
+        check(spec, ext, A, B, got, C0=C, alpha=1.0, beta=-1.0, exact=True)
+    Ar, Br, _ = wl.tensors(spec, ext, np.random.default_rng(22), "normal")
+    for v in range(0, 176, 5):
+        p.set_variant(v)
+        got = run(p, Ar, Br)
+        check(spec, ext, Ar, Br, got)
+
+
+def test_every_variant_other_patterns():
+    for spec, ext in [("ab=iaj,jbi", dict(a=9, b=7, i=5, j=3)),
+                      ("abcd=ai,ibcd", dict(a=6, b=3, c=4, d=2, i=5)),
+                      ("a=iaj,ji", dict(a=11, i=6, j=4))]:
+        A, B, _ = wl.tensors(spec, ext, np.random.default_rng(4), integer=True)
+        p = _plan(spec, ext)
+        for v in range(len(p.variants())):
+            p.set_variant(v)
+            got = run(p, A, B)
+            check(spec, ext, A, B, got, exact=True)
+
+
+def test_degenerate_extents():
+    torch = pytest.importorskip("torch")
+    # contracted extent 0: C = beta*C
+    spec, ext = "abc=ai,ibc", dict(a=5, b=4, c=3, i=0)
+    C0 = np.array(np.random.default_rng(1).uniform(-1, 1, (5, 4, 3)), order="F")
+    p = _plan(spec, ext)
+    got = run(p, np.zeros((5, 0), order="F"), np.zeros((0, 4, 3), order="F"), C0, alpha=1.0, beta=3.0)
+    np.testing.assert_array_equal(got, 3.0 * C0)
+    # empty output: no launch, no error
+    p = _plan(spec, dict(a=0, b=4, c=3, i=2))
+    dA = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
+    dB = tc.to_device_fortran(np.zeros((2, 4, 3)), torch.float64)
+    dC = torch.zeros((0, 4, 3), dtype=torch.float64, device="cuda")
+    p.contract(dA, dB, dC)
+    # alpha = 0 reads neither input
+    p = _plan(spec, dict(a=5, b=4, c=3, i=2))
+    dC = tc.to_device_fortran(C0, torch.float64)
+    tc.tc_contract(p.handle, 0, 0, dC.data_ptr(), 0.0, 2.0, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(dC.cpu().numpy(), 2.0 * C0)
+
+
+def test_alias_and_null_errors():
+    torch = pytest.importorskip("torch")
+    spec, ext = "ab=ai,ib", dict(a=8, b=8, i=8)
+    p = _plan(spec, ext)
+    buf = torch.zeros(64 * 3, dtype=torch.float64, device="cuda")
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_contract(p.handle, buf.data_ptr(), buf.data_ptr() + 64 * 8, buf.data_ptr() + 32 * 8)
+    assert e.value.name == "TC_E_ALIAS"
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_contract(p.handle, 0, buf.data_ptr(), buf.data_ptr() + 128 * 8)
+    assert e.value.name == "TC_E_NULL"
