@@ -24,20 +24,20 @@ __device__ __forceinline__ int64_t divmod(int64_t& rem, int64_t ext) {
 }
 
 // ---------------------------------------------------------------------------
-// Fused streaming kernel, K <= KT.  Each thread owns VEC consecutive elements
-// of C's unit-stride M dimension and keeps their A rows (VEC x K) in
-// registers.  A block walks a range of N columns in chunks of R = 256/KT: the
-// block first stages B[:, n] of the chunk's columns and their C offsets in LDS
-// (one element per thread, generic strides decoded once), then every thread
-// computes its VEC outputs of each column from broadcast LDS reads and writes
-// them with one vector store.  Work per output: 2K flops and one 8-byte
-// (FP64) store; A and B are read once.
-template <typename T, int KT, int VEC>
+// Fused streaming kernel for small contracted extents, K <= KT.
+//
+// C is written along its unit-stride M dimension; each thread owns VEC
+// consecutive m and loads their A rows (VEC x K) into registers, then
+// computes R columns n of C (R * rpb columns per block, rpb = 256 / tpr rows
+// of threads) and retires.  Measured on MI355X, a one-shot grid whose blocks
+// each write a few KB and exit streams writes markedly faster than persistent
+// blocks walking long column ranges: the blocks in flight then cover one
+// compact window of C.  Stores are 16-byte non-temporal vector stores.  Work per
+// output: 2K flops, one store; A comes from L2 after its first touch.
+template <typename T, int KT, int VEC, int R>
 __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ A, const T* __restrict__ B,
                                                 T* __restrict__ C, StreamArgs a) {
-    constexpr int R = 256 / KT;
-    __shared__ T Bs[R][KT];
-    __shared__ int64_t Cs[R];
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
     const int tid = threadIdx.x;
     const int tpr = a.tpr;
     const int rpb = 256 / tpr;
@@ -46,73 +46,78 @@ __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ A, const T
     const int64_t mb = blockIdx.x % mblocks;
     const int64_t nb = blockIdx.x / mblocks;
     const int64_t m0 = mb * span + (int64_t)(tid % tpr) * VEC;
+    const bool full = (m0 + VEC <= a.M);
     const T alpha = (T)a.alpha, beta = (T)a.beta;
 
     T av[VEC][KT];
+    const bool avec = full && a.sAm == 1;
 #pragma unroll
-    for (int v = 0; v < VEC; ++v)
+    for (int k = 0; k < KT; ++k) {
+        const bool kok = k < a.K;
+        const T* ap = A + m0 * a.sAm + (kok ? a.kA[k] : 0);
+        if (avec && kok && ((uintptr_t)ap) % (sizeof(T) * VEC) == 0) {
+            vec_t t = *(const vec_t*)ap;
 #pragma unroll
-        for (int k = 0; k < KT; ++k)
-            av[v][k] = (k < a.K && m0 + v < a.M) ? A[(m0 + v) * a.sAm + a.kA[k]] : (T)0;
+            for (int v = 0; v < VEC; ++v) av[v][k] = t[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) av[v][k] = (kok && m0 + v < a.M) ? ap[v * a.sAm] : (T)0;
+        }
+    }
 
-    const int64_t n_lo = nb * a.rows_per_block;
-    const int64_t n_hi = min(a.N, n_lo + a.rows_per_block);
-    const bool full = (m0 + VEC <= a.M);
-    const int lr = tid / tpr;
-    typedef T vec_t __attribute__((ext_vector_type(VEC)));
-    for (int64_t n0 = n_lo; n0 < n_hi; n0 += R) {
-        {   // stage the chunk: thread (r, k) loads B[k, n0 + r]
-            const int r = tid / KT, k = tid % KT;
-            const int64_t n = n0 + r;
-            T v = 0;
-            if (n < n_hi) {
-                int64_t offB = 0, offC = 0;
-                if (a.n.n == 1) {
-                    offB = n * a.n.d[0].sB;
-                    offC = n * a.n.d[0].sC;
-                } else {
-                    int64_t rem = n;
-                    for (int d = 0; d < a.n.n; ++d) {
-                        int64_t q = divmod(rem, a.n.d[d].ext);
-                        offB += q * a.n.d[d].sB;
-                        offC += q * a.n.d[d].sC;
-                    }
-                }
-                if (k < a.K) v = B[offB + a.kB[k]];
-                if (k == 0) Cs[r] = offC;
-            }
-            Bs[r][k] = v;
-        }
-        __syncthreads();
-        const int rows = (int)min<int64_t>(R, n_hi - n0);
-#pragma unroll 2
-        for (int r = lr; r < rows; r += rpb) {
-            T out[VEC];
+    const int64_t n_first = nb * (int64_t)(R * rpb) + tid / tpr;
+    T bv[R][KT];
+    int64_t offC[R];
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                T acc = 0;
-#pragma unroll
-                for (int k = 0; k < KT; ++k) acc += av[v][k] * Bs[r][k];
-                out[v] = alpha * acc;
-            }
-            T* cp = C + Cs[r] + m0;
-            if (a.beta != 0.0) {
-#pragma unroll
-                for (int v = 0; v < VEC; ++v)
-                    if (m0 + v < a.M) out[v] += beta * cp[v];
-            }
-            if (full && (((uintptr_t)cp) % (sizeof(T) * VEC) == 0)) {
-                vec_t val;
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) val[v] = out[v];
-                __builtin_nontemporal_store(val, (vec_t*)cp);
+    for (int q = 0; q < R; ++q) {
+        const int64_t n = n_first + (int64_t)q * rpb;
+        int64_t offB = 0;
+        offC[q] = -1;
+        if (n < a.N) {
+            int64_t oc = 0;
+            if (a.n.n == 1) {
+                offB = n * a.n.d[0].sB;
+                oc = n * a.n.d[0].sC;
             } else {
-#pragma unroll
-                for (int v = 0; v < VEC; ++v)
-                    if (m0 + v < a.M) cp[v] = out[v];
+                int64_t rem = n;
+                for (int d = 0; d < a.n.n; ++d) {
+                    int64_t r = divmod(rem, a.n.d[d].ext);
+                    offB += r * a.n.d[d].sB;
+                    oc += r * a.n.d[d].sC;
+                }
             }
+            offC[q] = oc;
         }
-        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KT; ++k) bv[q][k] = (offC[q] >= 0 && k < a.K) ? B[offB + a.kB[k]] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        if (offC[q] < 0) continue;
+        T out[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            T acc = 0;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) acc += av[v][k] * bv[q][k];
+            out[v] = alpha * acc;
+        }
+        T* cp = C + offC[q] + m0;
+        if (a.beta != 0.0) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+                if (m0 + v < a.M) out[v] += beta * cp[v];
+        }
+        if (full && (((uintptr_t)cp) % (sizeof(T) * VEC) == 0)) {
+            vec_t val;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) val[v] = out[v];
+            __builtin_nontemporal_store(val, (vec_t*)cp);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+                if (m0 + v < a.M) cp[v] = out[v];
+        }
     }
 }
 
@@ -122,17 +127,14 @@ static int next_pow2(int64_t x) {
     return p;
 }
 
+// columns per thread row: four for K <= 8, fewer for larger K (registers)
+static int stream_r(int K) { return K <= 8 ? 4 : K <= 16 ? 2 : 1; }
+
 void stream_shape(bool f64, StreamArgs& a) {
     const int VEC = f64 ? 2 : 4;
     int64_t lanes = (a.M + VEC - 1) / VEC;
     a.tpr = next_pow2(std::max<int64_t>(1, lanes));
-    int rpb = 256 / a.tpr;
-    int64_t span = (int64_t)a.tpr * VEC;
-    int64_t mblocks = (a.M + span - 1) / span;
-    int64_t row_groups = (a.N + rpb - 1) / rpb;
-    const int64_t target = 8192;
-    int64_t per = std::max<int64_t>(1, (row_groups * mblocks + target - 1) / target);
-    a.rows_per_block = per * rpb;
+    a.rows_per_block = (int64_t)stream_r(a.K) * (256 / a.tpr);
 }
 
 int64_t stream_grid(bool f64, const StreamArgs& a) {
@@ -152,10 +154,10 @@ static hipError_t stream_dispatch(StreamArgs& a, hipStream_t st) {
     const T* A = (const T*)a.A;
     const T* B = (const T*)a.B;
     T* C = (T*)a.C;
-    if (a.K <= 4) hipLaunchKernelGGL((k_stream<T, 4, VEC>), g, b, 0, st, A, B, C, a);
-    else if (a.K <= 8) hipLaunchKernelGGL((k_stream<T, 8, VEC>), g, b, 0, st, A, B, C, a);
-    else if (a.K <= 16) hipLaunchKernelGGL((k_stream<T, 16, VEC>), g, b, 0, st, A, B, C, a);
-    else hipLaunchKernelGGL((k_stream<T, 32, VEC>), g, b, 0, st, A, B, C, a);
+    if (a.K <= 4) hipLaunchKernelGGL((k_stream<T, 4, VEC, 4>), g, b, 0, st, A, B, C, a);
+    else if (a.K <= 8) hipLaunchKernelGGL((k_stream<T, 8, VEC, 4>), g, b, 0, st, A, B, C, a);
+    else if (a.K <= 16) hipLaunchKernelGGL((k_stream<T, 16, VEC, 2>), g, b, 0, st, A, B, C, a);
+    else hipLaunchKernelGGL((k_stream<T, 32, VEC, 1>), g, b, 0, st, A, B, C, a);
     return hipGetLastError();
 }
 
