@@ -130,7 +130,51 @@ def forms(args, torch, tc, wl):
                                                    unit="TFLOP/s", frac=round(tfs / peak, 4)))
         del dA, dB, dC
     torch.cuda.empty_cache()
+    # precision: C_ab = A_iaj B_jbi, a=b=4096, i=j=64 (K=4096), per-slice scaled data;
+    # FP64 plain vs split-BF16 (three terms, six products) on the same GPU
+    out.update(precision(args, torch, tc, wl))
     return out
+
+
+def precision(args, torch, tc, wl):
+    import numpy as np
+    import oracle
+    res = {}
+    w = wl.scaled_matrix(4096, 64)
+    fl = 2 * 4096 * 4096 * 64 * 64
+    rng = np.random.default_rng(7)
+    rows = np.sort(rng.choice(4096, 24, replace=False))
+    cols = np.sort(rng.choice(4096, 24, replace=False))
+    ext_s = dict(a=len(rows), b=len(cols), i=64, j=64)
+    ref = oracle.contract(w["spec"], ext_s, np.asfortranarray(w["A"][:, rows, :]),
+                          np.asfortranarray(w["B"][:, cols, :]))
+    dA = tc.to_device_fortran(w["A"], torch.float64)
+    dB = tc.to_device_fortran(w["B"], torch.float64)
+    base_ms = None
+    for name, compute, peak, unit_peak in (("fp64", "native", FP64_PEAK_TFS, "fp64"),
+                                           ("bf16x3", "bf16x3", BF16_PEAK_TFS, "bf16")):
+        plan = tc.Plan(w["spec"], w["ext"], "f64", compute=compute)
+        plan.prepare()
+        dC = tc.empty_fortran(plan.shape("C"), torch.float64)
+        ms, _ = _events_time(lambda: plan.contract(dA, dB, dC), 5, 1, torch)
+        got = dC[torch.as_tensor(rows, device="cuda")][:, torch.as_tensor(cols, device="cuda")].cpu().numpy()
+        err = oracle.normwise_rel_err(got, ref)
+        tfs = fl / (ms * 1e-3) / 1e12
+        executed = fl * (6 if compute == "bf16x3" else 1)
+        rec = dict(workload="C_ab = A_iaj B_jbi, a=b=4096, i=j=64, normal(0,1) x logU[1e-3,1e3] per slice",
+                   ms=round(ms, 4), effective_gflops=round(tfs * 1e3, 1), normwise_err_sampled=err,
+                   roofline=dict(bound="mfma", achieved=round(executed / (ms * 1e-3) / 1e12, 2), peak=peak,
+                                 unit="TFLOP/s", frac=round(executed / (ms * 1e-3) / 1e12 / peak, 4),
+                                 counts="executed MFMA flops (6 products for the split form)"))
+        if base_ms is None:
+            base_ms = ms
+        else:
+            rec["speedup_vs_fp64"] = round(base_ms / ms, 3)
+        res[f"precision_{name}"] = rec
+        del dC
+    del dA, dB
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():

@@ -168,6 +168,15 @@ tc_status tc_plan_workspace(tc_plan_t plan, int64_t* bytes);
 tc_status tc_contract(tc_plan_t plan, const void* A, const void* B, void* C,
                       double alpha, double beta, void* stream);
 
+/* Copy the split terms of the last tc_contract of a TC_BF16X3 plan to host
+ * memory, for bit-exact checks of the quantisation.  side 0 = A, 1 = B.  The
+ * GEMM view of the plan orders rows by the free indices of that side (first
+ * fastest) and columns by the plan's K order.  terms: 3 * rows * kp BF16 bit
+ * patterns (uint16, term-major, row-major), exps: rows power-of-two exponents.
+ * With both pointers NULL only *rows and *kp are filled.  Synchronises the
+ * device.  Errors: TC_E_UNSUPPORTED (no split yet), TC_E_VARIANT (bad side). */
+tc_status tc_split_terms(tc_plan_t plan, int side, void* terms, int32_t* exps, int64_t* rows, int64_t* kp);
+
 /* --- performance prediction (Section 3) ----------------------------------- */
 
 /* Access distance, in elements, of kernel operand `tensor` (0 = A, 1 = B,

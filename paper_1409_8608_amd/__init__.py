@@ -6,7 +6,7 @@ memory and streams.  The functions ``tc_plan``, ``tc_contract``, ... mirror the
 C ABI in ``include/tc.h`` one to one; ``Plan`` and ``Batch`` wrap them.
 
 Importing this package loads libtc.so and raises if it is missing: there is no
-fallback path.  Build it with ``python -m paper_1409_8608_amd.build``.
+fallback path.  Build it with ``python paper_1409_8608_amd/build.py``.
 """
 from __future__ import annotations
 
@@ -26,7 +26,7 @@ TC_MAX_SETUP = 16
 EXPORTS = ("tc_plan", "tc_plan_destroy", "tc_variant_count", "tc_variant_get", "tc_set_variant",
            "tc_plan_prepare", "tc_plan_workspace", "tc_contract", "tc_access_distance", "tc_bench_classes",
            "tc_predict", "tc_batch_create", "tc_batch_tune", "tc_batch_contract", "tc_batch_destroy",
-           "tc_status_str", "tc_last_error")
+           "tc_split_terms", "tc_status_str", "tc_last_error")
 
 
 class TcError(RuntimeError):
@@ -67,7 +67,7 @@ def _load():
         pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libtc.so not found at {LIB_PATH}: build it with "
-                          "`python -m paper_1409_8608_amd.build` (there is no fallback path)")
+                          "`python paper_1409_8608_amd/build.py` (there is no fallback path)")
     lib = ctypes.CDLL(LIB_PATH)
     P, I64P, D = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_double
     sig = {
@@ -89,6 +89,7 @@ def _load():
         "tc_batch_contract": [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                               ctypes.POINTER(D), ctypes.POINTER(D), P],
         "tc_batch_destroy": [P],
+        "tc_split_terms": [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_int32), I64P, I64P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -217,6 +218,19 @@ def tc_batch_contract(h, A_ptrs, B_ptrs, C_ptrs, alphas, betas, stream: int = 0)
 
 def tc_batch_destroy(h):
     _check(lib.tc_batch_destroy(h))
+
+
+def tc_split_terms(h, side: int):
+    """(terms uint16 [3, rows, kp], exponents int32 [rows]) of the last split contraction."""
+    import numpy as np
+    rows, kp = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.tc_split_terms(h, int(side), None, None, ctypes.byref(rows), ctypes.byref(kp)))
+    terms = np.zeros((3, rows.value, kp.value), dtype=np.uint16)
+    exps = np.zeros(rows.value, dtype=np.int32)
+    _check(lib.tc_split_terms(h, int(side), terms.ctypes.data_as(ctypes.c_void_p),
+                              exps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              ctypes.byref(rows), ctypes.byref(kp)))
+    return terms, exps
 
 
 def tc_status_str(s: int) -> str:

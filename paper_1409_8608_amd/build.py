@@ -1,5 +1,6 @@
 """Compile libtc.so for gfx950 in-tree: HIP sources with hipcc, host-only C++
-with g++, linked by hipcc.  Run as ``python -m paper_1409_8608_amd.build``."""
+with g++, linked by hipcc.  Run as ``python paper_1409_8608_amd/build.py`` (by
+path: importing the package would load the library being rebuilt)."""
 from __future__ import annotations
 
 import concurrent.futures as cf

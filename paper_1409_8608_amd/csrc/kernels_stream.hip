@@ -49,51 +49,59 @@ __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ A, const T
     const bool full = (m0 + VEC <= a.M);
     const T alpha = (T)a.alpha, beta = (T)a.beta;
 
+    // A rows of the thread's m, clamped to the last valid m (always a legal
+    // address) and selected to zero past the edge: no branch around a load.
     T av[VEC][KT];
     const bool avec = full && a.sAm == 1;
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
-        const bool kok = k < a.K;
-        const T* ap = A + m0 * a.sAm + (kok ? a.kA[k] : 0);
-        if (avec && kok && ((uintptr_t)ap) % (sizeof(T) * VEC) == 0) {
-            vec_t t = *(const vec_t*)ap;
+        if (k < a.K) {                                   // uniform
+            const T* ap = A + a.kA[k];
+            if (avec && ((uintptr_t)(ap + m0)) % (sizeof(T) * VEC) == 0) {
+                vec_t t = *(const vec_t*)(ap + m0);
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) av[v][k] = t[v];
+                for (int v = 0; v < VEC; ++v) av[v][k] = t[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    const int64_t m = min(m0 + v, a.M - 1);
+                    const T x = ap[m * a.sAm];
+                    av[v][k] = (m0 + v < a.M) ? x : (T)0;
+                }
+            }
         } else {
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) av[v][k] = (kok && m0 + v < a.M) ? ap[v * a.sAm] : (T)0;
+            for (int v = 0; v < VEC; ++v) av[v][k] = (T)0;
         }
     }
 
     const int64_t n_first = nb * (int64_t)(R * rpb) + tid / tpr;
     T bv[R][KT];
     int64_t offC[R];
+    bool nok[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int64_t n = n_first + (int64_t)q * rpb;
-        int64_t offB = 0;
-        offC[q] = -1;
-        if (n < a.N) {
-            int64_t oc = 0;
-            if (a.n.n == 1) {
-                offB = n * a.n.d[0].sB;
-                oc = n * a.n.d[0].sC;
-            } else {
-                int64_t rem = n;
-                for (int d = 0; d < a.n.n; ++d) {
-                    int64_t r = divmod(rem, a.n.d[d].ext);
-                    offB += r * a.n.d[d].sB;
-                    oc += r * a.n.d[d].sC;
-                }
+        nok[q] = n < a.N;
+        const int64_t nn = nok[q] ? n : 0;
+        int64_t offB = 0, oc = 0;
+        if (a.n.n == 1) {
+            offB = nn * a.n.d[0].sB;
+            oc = nn * a.n.d[0].sC;
+        } else {
+            int64_t rem = nn;
+            for (int d = 0; d < a.n.n; ++d) {
+                int64_t r = divmod(rem, a.n.d[d].ext);
+                offB += r * a.n.d[d].sB;
+                oc += r * a.n.d[d].sC;
             }
-            offC[q] = oc;
         }
+        offC[q] = oc;
 #pragma unroll
-        for (int k = 0; k < KT; ++k) bv[q][k] = (offC[q] >= 0 && k < a.K) ? B[offB + a.kB[k]] : (T)0;
+        for (int k = 0; k < KT; ++k) bv[q][k] = (k < a.K) ? B[offB + a.kB[k]] : (T)0;
     }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        if (offC[q] < 0) continue;
         T out[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
@@ -102,6 +110,7 @@ __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ A, const T
             for (int k = 0; k < KT; ++k) acc += av[v][k] * bv[q][k];
             out[v] = alpha * acc;
         }
+        if (!nok[q]) continue;
         T* cp = C + offC[q] + m0;
         if (a.beta != 0.0) {
 #pragma unroll
@@ -118,6 +127,53 @@ __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ A, const T
             for (int v = 0; v < VEC; ++v)
                 if (m0 + v < a.M) cp[v] = out[v];
         }
+    }
+}
+
+// Straight-line form of k_stream for the regular case, chosen by the host when
+// M is a whole number of block spans, A is unit-stride along M, A and C are
+// vector-aligned, N is one dimension and a whole number of block column sets,
+// K equals KT and beta is 0: no guards, no per-element branches.  With WIDE
+// (one M span per block, tpr = 256) the column index depends on the block
+// only, so B[:, n] comes in through scalar loads.
+template <typename T, int KT, int VEC, int R, bool WIDE>
+__global__ __launch_bounds__(256) void k_stream_fast(const T* __restrict__ A, const T* __restrict__ B,
+                                                     T* __restrict__ C, StreamArgs a) {
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
+    const int tid = threadIdx.x;
+    const int tpr = WIDE ? 256 : a.tpr;
+    const int rpb = WIDE ? 1 : 256 / tpr;
+    const int64_t span = (int64_t)tpr * VEC;
+    const int64_t mblocks = a.M / span;
+    const int64_t mb = blockIdx.x % mblocks;
+    const int64_t nb = blockIdx.x / mblocks;
+    const int64_t m0 = mb * span + (int64_t)(tid % tpr) * VEC;
+    const T alpha = (T)a.alpha;
+    T av[VEC][KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+        vec_t t = *(const vec_t*)(A + a.kA[k] + m0);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) av[v][k] = t[v];
+    }
+    const int64_t n_first = nb * (int64_t)(R * rpb) + (WIDE ? 0 : tid / tpr);
+    const int64_t sB = a.n.d[0].sB, sC = a.n.d[0].sC;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int64_t n = n_first + (int64_t)q * rpb;
+        const T* bp = B + n * sB;
+        T bv[KT];
+#pragma unroll
+        for (int k = 0; k < KT; ++k) bv[k] = bp[a.kB[k]];
+        vec_t val;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            T acc = 0;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) acc += av[v][k] * bv[k];
+            val[v] = alpha * acc;
+        }
+        __builtin_nontemporal_store(val, (vec_t*)(C + n * sC + m0));
     }
 }
 
@@ -154,6 +210,28 @@ static hipError_t stream_dispatch(StreamArgs& a, hipStream_t st) {
     const T* A = (const T*)a.A;
     const T* B = (const T*)a.B;
     T* C = (T*)a.C;
+    // the regular case takes the straight-line kernel
+    const int64_t span = (int64_t)a.tpr * VEC;
+    const int Rk = stream_r(a.K);
+    bool fast = a.beta == 0.0 && a.sAm == 1 && a.M % span == 0 && a.n.n == 1 &&
+                a.N % (Rk * (256 / a.tpr)) == 0 && (a.K == 4 || a.K == 8 || a.K == 16 || a.K == 32) &&
+                ((uintptr_t)A) % (sizeof(T) * VEC) == 0 && ((uintptr_t)C) % (sizeof(T) * VEC) == 0 &&
+                a.n.d[0].sC % VEC == 0;
+    for (int k = 0; fast && k < a.K; ++k) fast = a.kA[k] % VEC == 0;
+    if (fast && a.tpr == 256) {
+        if (a.K == 4) hipLaunchKernelGGL((k_stream_fast<T, 4, VEC, 4, true>), g, b, 0, st, A, B, C, a);
+        else if (a.K == 8) hipLaunchKernelGGL((k_stream_fast<T, 8, VEC, 4, true>), g, b, 0, st, A, B, C, a);
+        else if (a.K == 16) hipLaunchKernelGGL((k_stream_fast<T, 16, VEC, 2, true>), g, b, 0, st, A, B, C, a);
+        else hipLaunchKernelGGL((k_stream_fast<T, 32, VEC, 1, true>), g, b, 0, st, A, B, C, a);
+        return hipGetLastError();
+    }
+    if (fast) {
+        if (a.K == 4) hipLaunchKernelGGL((k_stream_fast<T, 4, VEC, 4, false>), g, b, 0, st, A, B, C, a);
+        else if (a.K == 8) hipLaunchKernelGGL((k_stream_fast<T, 8, VEC, 4, false>), g, b, 0, st, A, B, C, a);
+        else if (a.K == 16) hipLaunchKernelGGL((k_stream_fast<T, 16, VEC, 2, false>), g, b, 0, st, A, B, C, a);
+        else hipLaunchKernelGGL((k_stream_fast<T, 32, VEC, 1, false>), g, b, 0, st, A, B, C, a);
+        return hipGetLastError();
+    }
     if (a.K <= 4) hipLaunchKernelGGL((k_stream<T, 4, VEC, 4>), g, b, 0, st, A, B, C, a);
     else if (a.K <= 8) hipLaunchKernelGGL((k_stream<T, 8, VEC, 4>), g, b, 0, st, A, B, C, a);
     else if (a.K <= 16) hipLaunchKernelGGL((k_stream<T, 16, VEC, 2>), g, b, 0, st, A, B, C, a);

@@ -5,11 +5,6 @@
 
 namespace tc {
 
-tc_status prepare_split(tc_plan_s*) { return fail(TC_E_UNSUPPORTED, "split precision not built yet"); }
-tc_status run_split(tc_plan_s*, const void*, const void*, void*, double, double, hipStream_t) {
-    return fail(TC_E_UNSUPPORTED, "split precision not built yet");
-}
-
 void release_plan_device(tc_plan_s* p) {
     void** bufs[] = {&p->d_ktab, &p->d_var_ktab, &p->d_temp[0], &p->d_temp[1], &p->d_split};
     for (void** b : bufs) {

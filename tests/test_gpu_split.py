@@ -1,0 +1,94 @@
+"""GPU parity of the split-BF16 precision form against its oracle (the same
+steps with exact accumulation) and against the plain FP64 contraction."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import split as sp
+from gpu_util import run
+
+pytestmark = pytest.mark.gpu
+tc = pytest.importorskip("paper_1409_8608_amd")
+from paper_1409_8608_amd import workloads as wl  # noqa: E402
+
+
+def _bf16_value(bits):
+    """BF16 bit patterns -> float64 values (upper half of an FP32 pattern)."""
+    return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_integer_exact(dtype):
+    """Small integers are single BF16 terms and every FP32 partial sum is exact:
+    the split form must equal the plain contraction bit for bit."""
+    spec, ext = "abc=ija,jbic", dict(a=70, b=20, c=9, i=13, j=17)
+    A, B, C = wl.tensors(spec, ext, np.random.default_rng(5), integer=True, with_c=True)
+    p = tc.Plan(spec, ext, dtype, compute="bf16x3")
+    got = run(p, A, B, C, alpha=1.0, beta=2.0, dtype=dtype)
+    np.testing.assert_array_equal(got, oracle.contract(spec, ext, A, B, C=np.array(C, order="F"), alpha=1.0, beta=2.0))
+
+
+@pytest.mark.parametrize("spec,ext", [
+    ("ab=iaj,jbi", dict(a=130, b=200, i=24, j=17)),
+    ("abc=ija,jbic", dict(a=40, b=33, c=7, i=5, j=11)),
+    ("abcd=ai,ibcd", dict(a=17, b=5, c=6, d=7, i=300)),
+])
+def test_split_terms_bit_exact_and_result(spec, ext):
+    """The device's exponents and BF16 terms equal the oracle's bit for bit,
+    and the result is within the FP32-accumulation bound of the oracle's
+    exactly accumulated split result, and at FP32 level against FP64."""
+    rng = np.random.default_rng(9)
+    sa, sb, sc = oracle.split_spec(spec)
+    A = np.array(rng.standard_normal([ext[c] for c in sa]), order="F")
+    B = np.array(rng.standard_normal([ext[c] for c in sb]), order="F")
+    # per-slice scales over several binades (free-index slices)
+    fa = [ax for ax, ch in enumerate(sa) if ch in sc]
+    A *= np.exp(rng.uniform(np.log(1e-3), np.log(1e3), [A.shape[ax] if ax in fa else 1 for ax in range(A.ndim)]))
+    p = tc.Plan(spec, ext, "f64", compute="bf16x3")
+    got = run(p, A, B)
+    ref_split = sp.contract_split(spec, ext, A, B)
+    ref = oracle.contract(spec, ext, A, B)
+    absAB = oracle.contract(spec, ext, np.abs(A), np.abs(B))
+    K = int(np.prod([ext[c] for c in sa if c not in sc]))
+    bound = (min(K, 256) + 8) * 2.0 ** -24 + 2.0 ** -22
+    assert np.all(np.abs(got - ref_split) <= bound * absAB)
+    assert oracle.normwise_rel_err(got, ref) <= 1e-5
+    # exponents: one per free multi-index, first free index fastest (the GEMM view's rows)
+    tA, eA = tc.tc_split_terms(p.handle, 0)
+    want_e = sp.slice_exponents(A, sa, "".join(c for c in sa if c in sc))
+    np.testing.assert_array_equal(eA, np.asarray(want_e).ravel(order="F"))
+    # terms: the multiset of values per row must equal the oracle's (the device packs in its K order)
+    TA, _ = sp.split_terms(A, sa, "".join(c for c in sa if c in sc))
+    free_axes = [ax for ax, ch in enumerate(sa) if ch in sc]
+    con_axes = [ax for ax, ch in enumerate(sa) if ch not in sc]
+    for t in range(3):
+        dev = _bf16_value(tA[t])                              # rows x kp (K order + zero padding)
+        ora = np.transpose(TA[t], free_axes + con_axes).reshape(len(eA), -1, order="F") \
+            if len(free_axes) == 1 else None
+        if ora is None:
+            continue
+        for r in range(0, len(eA), max(1, len(eA) // 16)):
+            d = np.sort(dev[r][dev[r] != 0])
+            o = np.sort(ora[r][ora[r] != 0])
+            np.testing.assert_array_equal(d, o)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_scaled_matrix_accuracy(dtype):
+    """The precision workload's shape at reduced size: slices scaled over six
+    decades; FP32-level error against the FP64 contraction."""
+    w = wl.scaled_matrix(n=256, k=16)
+    p = tc.Plan(w["spec"], w["ext"], dtype, compute="bf16x3")
+    got = run(p, w["A"], w["B"], dtype=dtype)
+    Ar = w["A"] if dtype == "f64" else w["A"].astype(np.float32).astype(np.float64)
+    Br = w["B"] if dtype == "f64" else w["B"].astype(np.float32).astype(np.float64)
+    ref = oracle.contract(w["spec"], w["ext"], Ar, Br)
+    err = oracle.normwise_rel_err(got, ref)
+    assert err <= 1e-5, err
+
+
+def test_split_rejects_members():
+    p = tc.Plan("ab=ai,ib", dict(a=8, b=8, i=8), "f64", compute="bf16x3")
+    with pytest.raises(tc.TcError) as e:
+        p.set_variant(0)
+    assert e.value.name == "TC_E_UNSUPPORTED"
