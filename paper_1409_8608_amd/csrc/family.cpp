@@ -178,6 +178,7 @@ VariantPlan plan_variant(const Spec& s, const Variant& v) {
     } else {
         for (char ch : s.c)
             if (has(v.kept, ch)) d.out.d[d.out.n++] = gd(ch);
+        vp.n_body_dims = d.out.n;
     }
     for (int p = L - 1; p >= H; --p)
         if (!has(s.contracted, v.loops[p])) d.out.d[d.out.n++] = gd(v.loops[p]);

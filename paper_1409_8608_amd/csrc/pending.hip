@@ -16,9 +16,6 @@ void release_plan_device(tc_plan_s* p) {
 }  // namespace tc
 
 extern "C" {
-tc_status tc_predict(tc_plan_t, tc_prediction*, int, int*) {
-    return tc::fail(TC_E_UNSUPPORTED, "prediction not built yet");
-}
 tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t*, int) {
     if (out) *out = nullptr;
     return tc::fail(TC_E_UNSUPPORTED, "batches not built yet");

@@ -113,6 +113,7 @@ struct VariantPlan {
     std::vector<CopyStep> copies;
     int64_t temp_elems[2] = {0, 0};    // temp buffer sizes for A and B copies
     bool mfma = false;                 // gemm body on matrix cores
+    int n_body_dims = 0;               // leading out dims that are the kernel's own free indices
     bool needs_c_copy = false;         // unsupported on the GPU
     int64_t launches = 0;
 };

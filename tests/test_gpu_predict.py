@@ -1,0 +1,69 @@
+"""GPU prediction (Section 3 on the device): every member gets a finite
+prediction for each of the five stages, the member picked by the prediction
+computes the right contraction, and the scoring against measured times is
+printed.  Absolute predicted times are not pinned by anything (the paper has
+no GPU numbers); the tests check consistency, the bench reports accuracy."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import check, run
+
+pytestmark = pytest.mark.gpu
+tc = pytest.importorskip("paper_1409_8608_amd")
+from paper_1409_8608_amd import workloads as wl  # noqa: E402
+
+
+def measured_times(plan, dA, dB, dC, reps=5):
+    import torch
+    out = []
+    n = len(plan.variants())
+    for v in list(range(n)) + [tc.TC_VARIANT_FUSED]:
+        plan.set_variant(v)
+        plan.contract(dA, dB, dC)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            s, e = torch.cuda.Event(True), torch.cuda.Event(True)
+            s.record()
+            plan.contract(dA, dB, dC)
+            e.record()
+            torch.cuda.synchronize()
+            ts.append(s.elapsed_time(e) * 1e-3)
+        out.append(float(np.median(ts)))
+    return out
+
+
+def spearman(x, y):
+    rx = np.argsort(np.argsort(x))
+    ry = np.argsort(np.argsort(y))
+    return float(np.corrcoef(rx, ry)[0, 1])
+
+
+@pytest.mark.parametrize("spec,ext", [("abc=ai,ibc", dict(a=64, b=64, c=64, i=8)),
+                                      ("abc=ija,jbic", dict(a=48, b=40, c=24, i=8, j=8))])
+def test_predict_and_select(spec, ext):
+    import torch
+    A, B, _ = wl.tensors(spec, ext, np.random.default_rng(12), "uniform")
+    p = tc.Plan(spec, ext, "f64")
+    preds = p.predict()
+    n = len(p.variants())
+    assert len(preds) == n + 1 and preds[-1]["variant"] == tc.TC_VARIANT_FUSED
+    for q in preds:
+        assert all(np.isfinite(q["stage_s"])) and min(q["stage_s"]) > 0, q
+        assert q["predicted_s"] == q["stage_s"][4]
+    p.set_variant(tc.TC_VARIANT_PREDICTED)
+    got = run(p, A, B)
+    check(spec, ext, A, B, got)
+    dA = tc.to_device_fortran(A, torch.float64)
+    dB = tc.to_device_fortran(B, torch.float64)
+    dC = tc.empty_fortran(p.shape("C"), torch.float64)
+    meas = measured_times(p, dA, dB, dC)
+    pred = [q["predicted_s"] for q in preds]
+    best = int(np.argmin(meas))
+    pick = int(np.argmin(pred))
+    rho = spearman(pred, meas)
+    print(f"\n{spec}: spearman {rho:.3f}; predicted-best measured {meas[pick]*1e6:.1f} us vs best "
+          f"{meas[best]*1e6:.1f} us; stage rho " +
+          " ".join(f"{spearman([q['stage_s'][s] for q in preds], meas):.2f}" for s in range(5)))
+    assert rho > 0.0
