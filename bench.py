@@ -133,7 +133,76 @@ def forms(args, torch, tc, wl):
     # precision: C_ab = A_iaj B_jbi, a=b=4096, i=j=64 (K=4096), per-slice scaled data;
     # FP64 plain vs split-BF16 (three terms, six products) on the same GPU
     out.update(precision(args, torch, tc, wl))
+    for dt in ("f64", "f32"):
+        out[f"batched_{dt}"] = batched(args, torch, tc, wl, dt)
+        print(f"# batched {dt} done", file=sys.stderr, flush=True)
+    if "batched_f32" in out and "batched_f64" in out:
+        out["batched_f32"]["factor_vs_sequential_fp64"] = round(
+            out["batched_f64"]["sequential_ms"] / out["batched_f32"]["batched_tuned_ms"], 3)
     return out
+
+
+def batched(args, torch, tc, wl, dtype):
+    """4096 contractions of the four batch patterns, uneven extents: one
+    tc_contract per member on one stream versus one graph replay (before and
+    after tuning).  Device data from a seeded torch generator (uniform[-1,1])."""
+    import numpy as np
+    import oracle
+    shapes, redraws = wl.batch_shapes(4096)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    es = 8 if dtype == "f64" else 4
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(51)
+    plans, As, Bs, Cs = [], [], [], []
+    flops = bytes_ = 0
+    for it in shapes:
+        p = tc.Plan(it["spec"], it["ext"], dtype)
+        plans.append(p)
+        A = tc.empty_fortran(p.shape("A"), tdt).uniform_(-1, 1, generator=gen)
+        B = tc.empty_fortran(p.shape("B"), tdt).uniform_(-1, 1, generator=gen)
+        C = tc.empty_fortran(p.shape("C"), tdt)
+        As.append(A); Bs.append(B); Cs.append(C)
+        flops += oracle.flops(it["spec"], it["ext"])
+        bytes_ += es * (A.numel() + B.numel() + C.numel())
+    for p in plans:
+        p.prepare()
+
+    def seq():
+        for p, A, B, C in zip(plans, As, Bs, Cs):
+            p.contract(A, B, C)
+    seq_ms, seq_wall = _events_time(seq, 2, 1, torch)
+    batch = tc.Batch(plans)
+    run = lambda: batch.contract(As, Bs, Cs)
+    bat_ms, _ = _events_time(run, 5, 1, torch)
+    t0 = time.perf_counter()
+    batch.tune(2)
+    tune_s = time.perf_counter() - t0
+    tuned_ms, _ = _events_time(run, 5, 1, torch)
+    info = batch.info()
+    # sampled parity of the last replay
+    rng = np.random.default_rng(3)
+    worst = 0.0
+    for t in rng.choice(len(plans), 6, replace=False):
+        it = shapes[t]
+        ref = oracle.contract(it["spec"], it["ext"], As[t].double().cpu().numpy(), Bs[t].double().cpu().numpy())
+        worst = max(worst, oracle.normwise_rel_err(Cs[t].double().cpu().numpy(), ref))
+    peak = FP64_PEAK_TFS if dtype == "f64" else FP32_PEAK_TFS
+    bound_ms = max(flops / (peak * 1e12), bytes_ / (HBM_PEAK_GBS * 1e9)) * 1e3
+    rec = dict(workload="4096 contractions from {abc=ai,ibc; abc=ija,jbic; ab=iaj,jbi; abcd=ai,ibcd}, free extents "
+                        "logU[8,256], contracted logU[4,64], largest operand <= 2^24 elements, uniform[-1,1]",
+               redraws=redraws, gflop=round(flops / 1e9, 2), gbytes=round(bytes_ / 1e9, 2),
+               sequential_ms=round(seq_ms, 3), sequential_wall_ms=round(seq_wall, 3),
+               batched_ms=round(bat_ms, 3), batched_tuned_ms=round(tuned_ms, 3), tune_s=round(tune_s, 2),
+               speedup_vs_sequential=round(seq_ms / tuned_ms, 3), tune_hit_rate=info["tune_hit_rate"],
+               tiles=info["tiles"], groups=info["groups"], normwise_err_sampled_max=worst,
+               gflops=round(flops / (tuned_ms * 1e-3) / 1e9, 1),
+               roofline=dict(bound="max(mfma, hbm)", lower_bound_ms=round(bound_ms, 3),
+                             frac=round(bound_ms / tuned_ms, 4)))
+    del batch, plans, As, Bs, Cs
+    torch.cuda.empty_cache()
+    return rec
+
+
 
 
 def precision(args, torch, tc, wl):

@@ -202,25 +202,39 @@ tc_status tc_predict(tc_plan_t plan, tc_prediction* out, int capacity, int* n_ou
 /* --- batches ----------------------------------------------------------------- */
 
 /* Build a batch of n independent contractions (plans stay owned by the caller
- * and must outlive the batch): work list of tiles ordered longest-first by
- * predicted cost, uploaded once; the first tc_batch_contract captures the
- * upload of per-call pointers and one persistent kernel per dtype into a HIP
- * graph, later calls replay it.  Errors: TC_E_NULL, TC_E_UNSUPPORTED, TC_E_NOMEM. */
+ * and must outlive the batch; each needs the native compute mode, a non-empty
+ * C and a contracted extent > 0).  Every contraction becomes matrix-core tiles
+ * (128x128 outputs, or 64x64 when M or N is at most 64); work lists of
+ * (contraction, tile) pairs, longest tiles first, go to device memory once.
+ * Errors: TC_E_NULL, TC_E_UNSUPPORTED, TC_E_NOMEM. */
 tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n);
 
-/* Autotune the tile shape of every contraction in the batch: candidates are
- * the `top_k` shapes the cost model ranks best; each is timed on the device and
- * the fastest kept.  Synchronous. */
+/* Choose each member's tile shape: an estimate composed from device
+ * micro-benchmarks (one wave of tiles per shape and contracted-length bucket)
+ * ranks the shapes, the best `top_k` are timed on the device one member at a
+ * time and the fastest is kept.  Uses -- and overwrites C with
+ * alpha * contract(A, B) of -- the operands of the previous tc_batch_contract,
+ * which must have been made.  Synchronous.  The share of members whose
+ * estimated-best shape measured within 5% of the best is reported by
+ * tc_batch_info. */
 tc_status tc_batch_tune(tc_batch_t batch, int top_k);
 
 /* Run all contractions: C_t = alpha_t * contract(A_t, B_t) + beta_t * C_t.
  * A, B, C, alpha, beta are host arrays of n entries (device pointers for the
- * tensors).  With the same pointer arrays as the previous call the captured
- * graph is replayed as is. */
+ * tensors, borrowed as in tc_contract; alpha_t must be non-zero).  The first
+ * call (and the first after tc_batch_tune) captures a HIP graph -- pointer
+ * staging from pinned host memory, counter reset, one persistent kernel per
+ * group -- later calls replay it on `stream`.  The call waits for the
+ * previous replay of this batch before restaging pointers.
+ * Errors: TC_E_NULL, TC_E_ALIAS, TC_E_UNSUPPORTED, TC_E_HIP. */
 tc_status tc_batch_contract(tc_batch_t batch, const void* const* A, const void* const* B,
                             void* const* C, const double* alpha, const double* beta, void* stream);
 
-/* Free a batch (its graph and device work list).  NULL is accepted. */
+/* Members, work items (tiles), persistent-kernel groups and the tuner's hit
+ * rate (-1 before tc_batch_tune).  Any pointer may be NULL. */
+tc_status tc_batch_info(tc_batch_t batch, int* n_members, int64_t* n_tiles, int* n_groups, double* tune_hit_rate);
+
+/* Free a batch (its graph, work lists and staging buffers).  NULL is accepted. */
 tc_status tc_batch_destroy(tc_batch_t batch);
 
 /* --- errors ------------------------------------------------------------------ */

@@ -26,7 +26,7 @@ TC_MAX_SETUP = 16
 EXPORTS = ("tc_plan", "tc_plan_destroy", "tc_variant_count", "tc_variant_get", "tc_set_variant",
            "tc_plan_prepare", "tc_plan_workspace", "tc_contract", "tc_access_distance", "tc_bench_classes",
            "tc_predict", "tc_batch_create", "tc_batch_tune", "tc_batch_contract", "tc_batch_destroy",
-           "tc_split_terms", "tc_status_str", "tc_last_error")
+           "tc_batch_info", "tc_split_terms", "tc_status_str", "tc_last_error")
 
 
 class TcError(RuntimeError):
@@ -89,6 +89,8 @@ def _load():
         "tc_batch_contract": [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                               ctypes.POINTER(D), ctypes.POINTER(D), P],
         "tc_batch_destroy": [P],
+        "tc_batch_info": [P, ctypes.POINTER(ctypes.c_int), I64P, ctypes.POINTER(ctypes.c_int),
+                          ctypes.POINTER(ctypes.c_double)],
         "tc_split_terms": [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_int32), I64P, I64P],
     }
     for name, args in sig.items():
@@ -218,6 +220,47 @@ def tc_batch_contract(h, A_ptrs, B_ptrs, C_ptrs, alphas, betas, stream: int = 0)
 
 def tc_batch_destroy(h):
     _check(lib.tc_batch_destroy(h))
+
+
+def tc_batch_info(h) -> dict:
+    n, g = ctypes.c_int(), ctypes.c_int()
+    t = ctypes.c_int64()
+    r = ctypes.c_double()
+    _check(lib.tc_batch_info(h, ctypes.byref(n), ctypes.byref(t), ctypes.byref(g), ctypes.byref(r)))
+    return dict(members=n.value, tiles=t.value, groups=g.value, tune_hit_rate=r.value)
+
+
+class Batch:
+    """Many contractions in one graph launch; ``plans`` must outlive it."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        self.handle = tc_batch_create([p.handle for p in self.plans])
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                lib.tc_batch_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def contract(self, As, Bs, Cs, alphas=None, betas=None, stream=None):
+        import torch
+        n = len(self.plans)
+        alphas = [1.0] * n if alphas is None else alphas
+        betas = [0.0] * n if betas is None else betas
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        tc_batch_contract(self.handle, [x.data_ptr() for x in As], [x.data_ptr() for x in Bs],
+                          [x.data_ptr() for x in Cs], alphas, betas, stream)
+
+    def tune(self, top_k: int = 2):
+        tc_batch_tune(self.handle, top_k)
+
+    def info(self):
+        return tc_batch_info(self.handle)
 
 
 def tc_split_terms(h, side: int):

@@ -156,7 +156,7 @@ tc_status prepare_plan(tc_plan_s* p) {
     }
     int v = p->selected == TC_VARIANT_PREDICTED ? p->predicted_best : p->selected;
     if (v >= 0) {
-        VariantPlan& vp = p->vplans[v];
+        VariantPlan& vp = p->vplans()[v];
         if (vp.needs_c_copy) return fail(TC_E_UNSUPPORTED, "member needs a copy of C, not run on the GPU");
         for (int t = 0; t < 2; ++t) {
             tc_status st = ensure_device_buffer(&p->d_temp[t], &p->temp_cap[t], vp.temp_elems[t] * s.elem_bytes());
@@ -239,7 +239,7 @@ static tc_status run_fused(tc_plan_s* p, const void* A, const void* B, void* C, 
 tc_status run_variant(tc_plan_s* p, int v, const void* A, const void* B, void* C, double alpha,
                       double beta, hipStream_t st) {
     const Spec& s = p->spec;
-    const VariantPlan& vp = p->vplans[v];
+    const VariantPlan& vp = p->vplans()[v];
     bool f64 = s.dtype == TC_F64;
     int es = s.elem_bytes();
     hipError_t e;
@@ -387,9 +387,6 @@ tc_status tc_plan(tc_plan_t* out, const char* spec, const char* index_chars, con
         delete p;
         return fail(err.st, err.msg);
     }
-    p->fam = enumerate_family(p->spec);
-    p->vplans.reserve(p->fam.size());
-    for (auto& v : p->fam) p->vplans.push_back(plan_variant(p->spec, v));
     p->gv = gemm_view(p->spec);
     *out = p;
     return TC_OK;
@@ -404,7 +401,7 @@ tc_status tc_plan_destroy(tc_plan_t p) {
 
 tc_status tc_variant_count(tc_plan_t p, int* n) {
     if (!p || !n) return fail(TC_E_NULL, "NULL argument");
-    *n = (int)p->fam.size();
+    *n = (int)p->fam().size();
     return TC_OK;
 }
 
@@ -419,8 +416,8 @@ tc_status tc_variant_get(tc_plan_t p, int variant, tc_variant_info* out) {
         out->invocations = 1;
         return TC_OK;
     }
-    if (variant < 0 || variant >= (int)p->fam.size()) return fail(TC_E_VARIANT, "variant out of range");
-    const Variant& v = p->fam[variant];
+    if (variant < 0 || variant >= (int)p->fam().size()) return fail(TC_E_VARIANT, "variant out of range");
+    const Variant& v = p->fam()[variant];
     std::snprintf(out->name, sizeof(out->name), "%s", v.name.c_str());
     out->number = v.number;
     out->kernel = v.kernel;
@@ -432,7 +429,7 @@ tc_status tc_variant_get(tc_plan_t p, int variant, tc_variant_info* out) {
         out->copy_level[c] = v.copies[c].second;
     }
     out->n_hoisted = v.n_hoisted;
-    out->launches = p->vplans[variant].launches;
+    out->launches = p->vplans()[variant].launches;
     int64_t inv = 1;
     for (char ch : v.loops) inv *= p->spec.e(ch);
     out->invocations = inv;
@@ -444,7 +441,7 @@ tc_status tc_set_variant(tc_plan_t p, int variant) {
     if (variant == TC_VARIANT_PREDICTED) {
         if (p->predicted_best < -2 || !p->have_prediction)
             return fail(TC_E_VARIANT, "no prediction yet: call tc_predict first");
-    } else if (variant != TC_VARIANT_FUSED && (variant < 0 || variant >= (int)p->fam.size())) {
+    } else if (variant != TC_VARIANT_FUSED && (variant < 0 || variant >= (int)p->fam().size())) {
         return fail(TC_E_VARIANT, "variant out of range");
     }
     if (variant >= 0 && p->spec.compute != TC_NATIVE)
@@ -492,19 +489,19 @@ tc_status tc_contract(tc_plan_t p, const void* A, const void* B, void* C, double
 
 tc_status tc_access_distance(tc_plan_t p, int variant, int tensor, int64_t* out) {
     if (!p || !out) return fail(TC_E_NULL, "NULL argument");
-    if (variant < 0 || variant >= (int)p->fam.size()) return fail(TC_E_VARIANT, "variant out of range");
+    if (variant < 0 || variant >= (int)p->fam().size()) return fail(TC_E_VARIANT, "variant out of range");
     if (tensor < 0 || tensor > 2) return fail(TC_E_VARIANT, "tensor must be 0, 1 or 2");
-    *out = access_distance(p->spec, p->fam[variant], tensor, -1);
+    *out = access_distance(p->spec, p->fam()[variant], tensor, -1);
     return TC_OK;
 }
 
 tc_status tc_bench_classes(tc_plan_t p, int variant, int stage, double cache_elems, int line_elems,
                            tc_bench_class* out, int capacity, int* n_out) {
     if (!p || !n_out) return fail(TC_E_NULL, "NULL argument");
-    if (variant < 0 || variant >= (int)p->fam.size()) return fail(TC_E_VARIANT, "variant out of range");
+    if (variant < 0 || variant >= (int)p->fam().size()) return fail(TC_E_VARIANT, "variant out of range");
     if (stage < 1 || stage > 5 || line_elems < 1 || !(cache_elems > 0))
         return fail(TC_E_UNSUPPORTED, "stage must be 1..5, line and cache positive");
-    std::vector<BenchClass> cls = bench_classes(p->spec, p->fam[variant], stage, cache_elems, line_elems);
+    std::vector<BenchClass> cls = bench_classes(p->spec, p->fam()[variant], stage, cache_elems, line_elems);
     *n_out = (int)cls.size();
     if ((int)cls.size() > capacity || (capacity > 0 && !out)) return fail(TC_E_CAPACITY, "capacity too small");
     for (size_t c = 0; c < cls.size(); ++c) {

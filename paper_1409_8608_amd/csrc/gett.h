@@ -77,6 +77,14 @@ struct MfmaArgs {
     int mode;           // 0: C = alpha*acc + beta*C; 1: per pass C += alpha*acc
 };
 
+// Per-call operands of one batch member.
+struct BatchPtrs {
+    const void* A;
+    const void* B;
+    void* C;
+    double alpha, beta;
+};
+
 struct CopyArgs {
     const void* src;
     void* dst;

@@ -79,8 +79,12 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
     return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
+// One BM x BN output tile (all passes) of the contraction described by `a`,
+// with the operand pointers and scalars given separately (a batch keeps them
+// apart from the static descriptors).  Called by a whole block.
 template <typename T, int BM, int BN, int BK, bool A_KMAJ, bool B_KMAJ>
-__global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
+__device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, const void* Bp, void* Cp,
+                                          double alpha_d, double beta_d, int64_t tile) {
     typedef typename Mfma<T>::acc_t acc_t;
     constexpr int PAD = 4;
     constexpr int LDA = BM + PAD, LDB = BN + PAD;
@@ -90,14 +94,13 @@ __global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
     __shared__ T As[2][BK][LDA];
     __shared__ T Bs[2][BK][LDB];
 
-    const T* __restrict__ Ag = (const T*)a.A;
-    const T* __restrict__ Bg = (const T*)a.B;
-    T* Cg = (T*)a.C;
+    const T* __restrict__ Ag = (const T*)Ap;
+    const T* __restrict__ Bg = (const T*)Bp;
+    T* Cg = (T*)Cp;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     const int wm = wid & 1, wn = wid >> 1;
 
-    const int64_t tile = xcd_tile(blockIdx.x, a.ntiles);
     int64_t rest = tile;
     const int64_t mt = rest % a.mt; rest /= a.mt;
     const int64_t nt = rest % a.nt; rest /= a.nt;
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
     }
     __syncthreads();
 
-    const T alpha = (T)a.alpha, beta = (T)a.beta;
+    const T alpha = (T)alpha_d, beta = (T)beta_d;
     const int64_t ktiles = a.Kpad / BK;
 
     int64_t pctr[GT_MAXD];
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
                     T* cp = Cg + bC + cn + cm;
                     T v = alpha * acc[i][j][q];
                     if (a.mode == 1) v = *cp + v;
-                    else if (a.beta != 0.0) v += beta * (*cp);
+                    else if (beta_d != 0.0) v += beta * (*cp);
                     *cp = v;
                 }
             }
@@ -256,6 +259,32 @@ __global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
         }
     }
 }
+
+template <typename T, int BM, int BN, int BK, bool A_KMAJ, bool B_KMAJ>
+__global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
+    mfma_tile<T, BM, BN, BK, A_KMAJ, B_KMAJ>(a, a.A, a.B, a.C, a.alpha, a.beta, xcd_tile(blockIdx.x, a.ntiles));
+}
+
+// Persistent form for batches: blocks take work items (contraction, tile) off
+// an atomic counter until the list is exhausted, so every block exits once
+// the counter passes nwork.
+template <typename T, int BM, int BN, int BK, bool A_KMAJ, bool B_KMAJ>
+__global__ __launch_bounds__(256) void k_mfma_batch(const MfmaArgs* __restrict__ items,
+                                                    const BatchPtrs* __restrict__ ptrs,
+                                                    const int2* __restrict__ work, int nwork, int* counter) {
+    __shared__ int s_w;
+    for (;;) {
+        if (threadIdx.x == 0) s_w = atomicAdd(counter, 1);
+        __syncthreads();
+        const int w = s_w;
+        if (w >= nwork) break;
+        const int2 wi = work[w];
+        const BatchPtrs& pt = ptrs[wi.x];
+        mfma_tile<T, BM, BN, BK, A_KMAJ, B_KMAJ>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha, pt.beta, wi.y);
+        __syncthreads();   // the tile's LDS tables and s_w are reused by the next item
+    }
+}
+
 
 // Tile shape per storage type.  FP64: 128x128x16 (64 accumulators per lane in
 // 16 MFMA blocks per wave); FP32: 128x128x16 as well.
@@ -291,6 +320,83 @@ static bool k_major(const GtDims& g, int slot) {
 hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st) {
     bool ak = k_major(a.m, 0), bk = k_major(a.n, 1);
     return f64 ? mfma_dispatch<double>(a, ak, bk, st) : mfma_dispatch<float>(a, ak, bk, st);
+}
+
+// ---------------------------------------------------------------------------
+// Batches: tile shapes 0 = 128x128, 1 = 64x64.
+static void shape_dims(int shape, int& bm, int& bn) {
+    bm = shape == 0 ? 128 : 64;
+    bn = bm;
+}
+
+void mfma_tiles_shape(int shape, MfmaArgs& a) {
+    int bm, bn;
+    shape_dims(shape, bm, bn);
+    a.mt = (a.M + bm - 1) / bm;
+    a.nt = (a.N + bn - 1) / bn;
+    a.ntiles = a.mt * a.nt * a.nbatch;
+}
+
+bool mfma_kmajor_a(const MfmaArgs& a) { return k_major(a.m, 0); }
+bool mfma_kmajor_b(const MfmaArgs& a) { return k_major(a.n, 1); }
+
+template <typename T, int BM, int BN>
+static hipError_t batch_dispatch(bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs, const int2* work,
+                                 int nwork, int* counter, int grid, hipStream_t st) {
+    dim3 g(grid), b(256);
+    if (ak && bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, true, true>), g, b, 0, st, items, ptrs, work, nwork, counter);
+    else if (ak) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, true, false>), g, b, 0, st, items, ptrs, work, nwork, counter);
+    else if (bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, false, true>), g, b, 0, st, items, ptrs, work, nwork, counter);
+    else hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, false, false>), g, b, 0, st, items, ptrs, work, nwork, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_batch(bool f64, int shape, bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs,
+                             const int2* work, int nwork, int* counter, int grid, hipStream_t st) {
+    if (nwork <= 0) return hipSuccess;
+    if (f64)
+        return shape == 0 ? batch_dispatch<double, 128, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
+                          : batch_dispatch<double, 64, 64>(ak, bk, items, ptrs, work, nwork, counter, grid, st);
+    return shape == 0 ? batch_dispatch<float, 128, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
+                      : batch_dispatch<float, 64, 64>(ak, bk, items, ptrs, work, nwork, counter, grid, st);
+}
+
+// Resident blocks per CU of the persistent kernel (occupancy query).
+template <typename T, int BM, int BN>
+static int occ_of(bool ak, bool bk) {
+    int n = 0;
+    hipError_t e;
+    if (ak && bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, true, true>, 256, 0);
+    else if (ak) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, true, false>, 256, 0);
+    else if (bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, false, true>, 256, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, false, false>, 256, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+int mfma_batch_occupancy(bool f64, int shape, bool ak, bool bk) {
+    if (f64) return shape == 0 ? occ_of<double, 128, 128>(ak, bk) : occ_of<double, 64, 64>(ak, bk);
+    return shape == 0 ? occ_of<float, 128, 128>(ak, bk) : occ_of<float, 64, 64>(ak, bk);
+}
+
+// One-shot launch with a chosen tile shape (used to time tuning candidates).
+hipError_t launch_mfma_shape(bool f64, int shape, MfmaArgs& a, hipStream_t st) {
+    if (shape == 0) return launch_mfma(f64, a, st);
+    mfma_tiles_shape(1, a);
+    if (a.ntiles <= 0) return hipSuccess;
+    bool ak = k_major(a.m, 0), bk = k_major(a.n, 1);
+    dim3 g((unsigned)a.ntiles), b(256);
+    if (f64) {
+        if (ak && bk) hipLaunchKernelGGL((k_mfma<double, 64, 64, kBK, true, true>), g, b, 0, st, a);
+        else if (ak) hipLaunchKernelGGL((k_mfma<double, 64, 64, kBK, true, false>), g, b, 0, st, a);
+        else if (bk) hipLaunchKernelGGL((k_mfma<double, 64, 64, kBK, false, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_mfma<double, 64, 64, kBK, false, false>), g, b, 0, st, a);
+    } else {
+        if (ak && bk) hipLaunchKernelGGL((k_mfma<float, 64, 64, kBK, true, true>), g, b, 0, st, a);
+        else if (ak) hipLaunchKernelGGL((k_mfma<float, 64, 64, kBK, true, false>), g, b, 0, st, a);
+        else if (bk) hipLaunchKernelGGL((k_mfma<float, 64, 64, kBK, false, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_mfma<float, 64, 64, kBK, false, false>), g, b, 0, st, a);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace tc

@@ -24,6 +24,16 @@ hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st);
 void mfma_tiles(bool f64, MfmaArgs& a);
 int mfma_bk(bool f64);
 
+// Batches: tile shape 0 = 128x128, 1 = 64x64; persistent kernel over a work
+// list of (contraction, tile) pairs taken off an atomic counter.
+void mfma_tiles_shape(int shape, MfmaArgs& a);
+bool mfma_kmajor_a(const MfmaArgs& a);
+bool mfma_kmajor_b(const MfmaArgs& a);
+hipError_t launch_mfma_batch(bool f64, int shape, bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs,
+                             const int2* work, int nwork, int* counter, int grid, hipStream_t st);
+int mfma_batch_occupancy(bool f64, int shape, bool ak, bool bk);
+hipError_t launch_mfma_shape(bool f64, int shape, MfmaArgs& a, hipStream_t st);
+
 // Strided copy (copy statements of the family) and C := beta*C prologue.
 hipError_t launch_copy(bool f64, CopyArgs& a, hipStream_t st);
 hipError_t launch_scale(bool f64, ScaleArgs& a, hipStream_t st);

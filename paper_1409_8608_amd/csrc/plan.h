@@ -10,9 +10,25 @@
 
 struct tc_plan_s {
     tc::Spec spec;
-    std::vector<tc::Variant> fam;
-    std::vector<tc::VariantPlan> vplans;
     tc::GemmView gv;
+    // The algorithm family and each member's GPU schedule are built on first
+    // use: a plan that only runs the fused kernel (a batch member, say) never
+    // pays for enumerating up to a few hundred members.
+    std::vector<tc::Variant>& fam() {
+        build_family();
+        return fam_;
+    }
+    std::vector<tc::VariantPlan>& vplans() {
+        build_family();
+        return vplans_;
+    }
+    void build_family() {
+        if (family_built_) return;
+        fam_ = tc::enumerate_family(spec);
+        vplans_.reserve(fam_.size());
+        for (auto& v : fam_) vplans_.push_back(tc::plan_variant(spec, v));
+        family_built_ = true;
+    }
     int selected = TC_VARIANT_FUSED;
     int predicted_best = TC_VARIANT_FUSED;
     bool have_prediction = false;
@@ -29,6 +45,11 @@ struct tc_plan_s {
     void* d_split = nullptr;
     int64_t split_bytes = 0;
     int64_t split_layout[16] = {0};
+
+private:
+    std::vector<tc::Variant> fam_;
+    std::vector<tc::VariantPlan> vplans_;
+    bool family_built_ = false;
 };
 
 namespace tc {

@@ -196,8 +196,8 @@ static std::string key_of(int v, const GtDesc& d, const std::vector<SetupItem>& 
 static tc_status predict_variant(PredCtx& c, int v, tc_prediction* out) {
     tc_plan_s* p = c.p;
     const Spec& s = p->spec;
-    const Variant& var = p->fam[v];
-    VariantPlan& vp = p->vplans[v];
+    const Variant& var = p->fam()[v];
+    VariantPlan& vp = p->vplans()[v];
     auto t0 = std::chrono::steady_clock::now();
     int measured0 = c.n_measured;
     std::memset(out, 0, sizeof(*out));
@@ -332,7 +332,7 @@ static tc_status predict_fused(PredCtx& c, tc_prediction* out) {
 extern "C" tc_status tc_predict(tc_plan_t p, tc_prediction* out, int capacity, int* n_out) {
     using namespace tc;
     if (!p || !n_out) return fail(TC_E_NULL, "NULL argument");
-    const int count = (int)p->fam.size() + 1;
+    const int count = (int)p->fam().size() + 1;
     *n_out = count;
     if (capacity < count || !out) return fail(TC_E_CAPACITY, "capacity too small");
     if (p->spec.compute != TC_NATIVE) return fail(TC_E_UNSUPPORTED, "prediction covers the native compute mode");
@@ -350,7 +350,7 @@ extern "C" tc_status tc_predict(tc_plan_t p, tc_prediction* out, int capacity, i
     if (!st && hipStreamCreate(&c.st) != hipSuccess) st = fail(TC_E_HIP, "hipStreamCreate");
     int best = -1;
     double best_t = INFINITY;
-    for (int v = 0; v < (int)p->fam.size() && !st; ++v) {
+    for (int v = 0; v < (int)p->fam().size() && !st; ++v) {
         st = predict_variant(c, v, &out[v]);
         if (!st && out[v].predicted_s < best_t) {
             best_t = out[v].predicted_s;

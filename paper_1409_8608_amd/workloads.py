@@ -90,20 +90,22 @@ def _logu_int(rng, lo, hi):
     return int(np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
 
 
-def batch_shapes(count: int = 4096, seed: int = 51, cap_elems: int = 1 << 24):
+def batch_shapes(count: int = 4096, seed: int = 51, cap_elems: int = 1 << 24, free=(8, 256), con=(4, 64)):
     """Patterns uniform over PATTERNS; free extents log-uniform integers in
-    [8, 256], contracted extents in [4, 64]; a draw whose largest operand exceeds
-    `cap_elems` elements is drawn again from the same stream."""
+    `free` ([8, 256]), contracted extents in `con` ([4, 64]); a draw whose
+    largest operand exceeds `cap_elems` elements is drawn again from the same
+    stream."""
     rng = np.random.default_rng(seed)
+    con_rng = con
     out = []
     redraws = 0
     while len(out) < count:
         spec = PATTERNS[int(rng.integers(0, len(PATTERNS)))]
         sa, sb, sc = _split(spec)
-        con = [ch for ch in sa if ch in sb]
+        con_idx = [ch for ch in sa if ch in sb]
         ext = {}
         for ch in sorted(set(sa + sb + sc)):
-            ext[ch] = _logu_int(rng, 4, 64) if ch in con else _logu_int(rng, 8, 256)
+            ext[ch] = _logu_int(rng, *con_rng) if ch in con_idx else _logu_int(rng, *free)
         biggest = max(int(np.prod(_shape(x, ext))) for x in (sa, sb, sc))
         if biggest > cap_elems:
             redraws += 1
