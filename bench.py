@@ -80,8 +80,8 @@ def headline(args, torch, tc, wl):
                              f"fused streaming kernel", spec=spec, extents=ext, seed=w["seed"],
                     flops=flops, algorithmic_bytes=bytes_alg),
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=args.traffic,
-                      kernel="k_stream<double,8,2>"),
+                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
+                      kernel="k_stream_fast<double,8,2,4,true>"),
         finite=ok,
     )
     del dC
@@ -89,24 +89,51 @@ def headline(args, torch, tc, wl):
     return rec, w
 
 
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary, if that summary was taken on the current kernel source (its
+    SHA-256 is recorded in the summary); else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_stream_fast_smallk_cube_1024_counters.md")
+    src = os.path.join(ROOT, "paper_1409_8608_amd", "csrc", "kernels_stream.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel source sha256") != sha:
+        return None
+    try:
+        return float(vals["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(w, seconds):
-    """The oracle as it stands on a slab C[:, :, c0:c0+s] of the workload."""
+    """The oracle as it stands on a slab C[:, :, 0:s] of the workload: one
+    slab times the rate, then one run sized to about `seconds`."""
     import numpy as np
     import oracle
     n, i = w["ext"]["a"], w["ext"]["i"]
-    s = 1
-    while True:
-        ext = dict(a=n, b=n, c=s, i=i)
+
+    def run(s):
         B = np.asfortranarray(w["B"][:, :, :s])
         t0 = time.perf_counter()
-        oracle.contract("abc=ai,ibc", ext, w["A"], B)
-        dt = time.perf_counter() - t0
-        if dt >= seconds or s >= n:
-            break
-        s = min(n, max(s + 1, int(s * min(8.0, 1.2 * seconds / max(dt, 1e-3)))))
+        oracle.contract("abc=ai,ibc", dict(a=n, b=n, c=s, i=i), w["A"], B)
+        return time.perf_counter() - t0
+
+    dt4 = run(4)
+    s = int(max(1, min(n, round(4 * seconds / max(dt4, 1e-6)))))
+    dt = run(s)
     flops = 2 * n * n * s * i
     return dict(value=round(flops / dt / 1e9, 4), unit="GFLOP/s", cores=1, kind="oracle",
-                sample=f"C[:, :, 0:{s}] of the a=b=c={n}, i={i} workload ({flops / 1e9:.2f} GFLOP, {dt:.1f} s)")
+                sample=f"C[:, :, 0:{s}] of the a=b=c={n}, i={i} workload ({flops / 1e9:.2f} GFLOP in {dt:.1f} s, "
+                       "one host core, plain FP64 loop nest)")
 
 
 def forms(args, torch, tc, wl):
@@ -252,11 +279,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--traffic", type=float, default=None,
-                    help="HBM bytes per launch from rocprofv3 counters, when known")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (torch copy_) three times, outside the timed "
+                         "region, so that profiler byte counters can be scaled by a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -268,6 +296,13 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     rec, w = headline(args, torch, tc, wl)
     print(f"# headline done: {rec['value']} GFLOP/s", file=sys.stderr, flush=True)
     if not args.no_forms:
