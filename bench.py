@@ -81,7 +81,7 @@ def headline(args, torch, tc, wl):
                     flops=flops, algorithmic_bytes=bytes_alg),
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
-                      kernel="k_stream_fast<double,8,2,4,true>"),
+                      kernel="k_stream_wave<double,8,2,4,64,false>"),
         finite=ok,
     )
     del dC
@@ -94,7 +94,7 @@ def measured_traffic():
     summary, if that summary was taken on the current kernel source (its
     SHA-256 is recorded in the summary); else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_stream_fast_smallk_cube_1024_counters.md")
+    path = os.path.join(ROOT, "profiles", "k_stream_wave_smallk_cube_1024_counters.md")
     src = os.path.join(ROOT, "paper_1409_8608_amd", "csrc", "kernels_stream.hip")
     try:
         text = open(path).read()
@@ -276,8 +276,8 @@ def precision(args, torch, tc, wl):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")

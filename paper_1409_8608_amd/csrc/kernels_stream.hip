@@ -130,50 +130,90 @@ __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ A, const T
     }
 }
 
-// Straight-line form of k_stream for the regular case, chosen by the host when
-// M is a whole number of block spans, A is unit-stride along M, A and C are
-// vector-aligned, N is one dimension and a whole number of block column sets,
-// K equals KT and beta is 0: no guards, no per-element branches.  With WIDE
-// (one M span per block, tpr = 256) the column index depends on the block
-// only, so B[:, n] comes in through scalar loads.
-template <typename T, int KT, int VEC, int R, bool WIDE>
-__global__ __launch_bounds__(256) void k_stream_fast(const T* __restrict__ A, const T* __restrict__ B,
+// Straight-line form of k_stream for unit-stride, vector-aligned A and C.
+// Each wave covers 64 * VEC consecutive m of one column n: the column index is
+// wave-uniform (readfirstlane; a compile-time zero when one block spans
+// TPR = 256 threads), so everything that depends on n -- the N-dimension
+// decomposition, the B loads, the column guard -- runs on the scalar unit.
+// All R columns' B values are requested before the first FMA, so the block
+// waits for one round of scalar loads, not R; the vector path is a fixed
+// sequence of A loads, FMAs and one 16-byte non-temporal store per column.
+// TPR threads (64, 128 or 256) share one M span of TPR * VEC elements; the
+// host covers the largest multiple of 64 * VEC in M with this kernel and
+// hands the remainder to k_stream.
+template <typename T, int KT, int VEC, int R, int TPR, bool BETA>
+__global__ __launch_bounds__(256) void k_stream_wave(const T* __restrict__ A, const T* __restrict__ B,
                                                      T* __restrict__ C, StreamArgs a) {
+    static_assert(TPR >= 64 && TPR <= 256, "a wave must lie inside one column");
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
+    constexpr int RPB = 256 / TPR;
+    constexpr int SPAN = TPR * VEC;
     const int tid = threadIdx.x;
-    const int tpr = WIDE ? 256 : a.tpr;
-    const int rpb = WIDE ? 1 : 256 / tpr;
-    const int64_t span = (int64_t)tpr * VEC;
-    const int64_t mblocks = a.M / span;
-    const int64_t mb = blockIdx.x % mblocks;
-    const int64_t nb = blockIdx.x / mblocks;
-    const int64_t m0 = mb * span + (int64_t)(tid % tpr) * VEC;
+    const uint32_t mblocks = (uint32_t)(a.M / SPAN);
+    const uint32_t mb = blockIdx.x % mblocks;
+    const uint32_t nb = blockIdx.x / mblocks;
+    const int row = TPR == 256 ? 0 : __builtin_amdgcn_readfirstlane(tid / TPR);
+    const int64_t m0 = (int64_t)mb * SPAN + (tid % TPR) * VEC;
     const T alpha = (T)a.alpha;
+
+    int64_t offB[R], offC[R];
+    bool ok[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int64_t n = ((int64_t)nb * R + q) * RPB + row;
+        ok[q] = n < a.N;
+        const int64_t nn = ok[q] ? n : a.N - 1;
+        if (a.n.n == 1) {
+            offB[q] = nn * a.n.d[0].sB;
+            offC[q] = nn * a.n.d[0].sC;
+        } else {
+            int64_t rem = nn, ob = 0, oc = 0;
+            for (int d = 0; d < a.n.n; ++d) {
+                int64_t r = divmod(rem, a.n.d[d].ext);
+                ob += r * a.n.d[d].sB;
+                oc += r * a.n.d[d].sC;
+            }
+            offB[q] = ob;
+            offC[q] = oc;
+        }
+    }
+    // kA/kB entries K..KT-1 repeat entry K-1 (the host pads them): every load
+    // is in bounds and unconditional, and the padded terms are zeroed by
+    // selects, not branches.
+    T bv[R][KT];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            const T x = B[offB[q] + a.kB[k]];
+            bv[q][k] = (k < a.K) ? x : (T)0;
+        }
     T av[VEC][KT];
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
-        vec_t t = *(const vec_t*)(A + a.kA[k] + m0);
+        const vec_t t = *(const vec_t*)(A + a.kA[k] + m0);
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) av[v][k] = t[v];
+        for (int v = 0; v < VEC; ++v) av[v][k] = (k < a.K) ? t[v] : (T)0;
     }
-    const int64_t n_first = nb * (int64_t)(R * rpb) + (WIDE ? 0 : tid / tpr);
-    const int64_t sB = a.n.d[0].sB, sC = a.n.d[0].sC;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const int64_t n = n_first + (int64_t)q * rpb;
-        const T* bp = B + n * sB;
-        T bv[KT];
-#pragma unroll
-        for (int k = 0; k < KT; ++k) bv[k] = bp[a.kB[k]];
+        if (!ok[q]) break;   // columns grow with q: the rest are past N too
         vec_t val;
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             T acc = 0;
 #pragma unroll
-            for (int k = 0; k < KT; ++k) acc += av[v][k] * bv[k];
+            for (int k = 0; k < KT; ++k) acc += av[v][k] * bv[q][k];
             val[v] = alpha * acc;
         }
-        __builtin_nontemporal_store(val, (vec_t*)(C + n * sC + m0));
+        vec_t* cp = (vec_t*)(C + offC[q] + m0);
+        if (BETA) {
+            const vec_t old = *cp;
+            const T beta = (T)a.beta;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) val[v] += beta * old[v];
+        }
+        __builtin_nontemporal_store(val, cp);
     }
 }
 
@@ -182,6 +222,11 @@ static int next_pow2(int64_t x) {
     while (p < x && p < 256) p <<= 1;
     return p;
 }
+
+// Threads per M span of k_stream_wave.  Measured on MI355X at n^3 outputs,
+// n = 384..1024: one wave per span streams as fast as or faster than 128 or
+// 256 threads per span, and it covers every M that is a multiple of 64 * VEC.
+constexpr int kWaveTpr = 64;
 
 // columns per thread row: four for K <= 8, fewer for larger K (registers)
 static int stream_r(int K) { return K <= 8 ? 4 : K <= 16 ? 2 : 1; }
@@ -201,41 +246,58 @@ int64_t stream_grid(bool f64, const StreamArgs& a) {
     return mblocks * nchunks;
 }
 
+template <typename T, int VEC, bool BETA>
+static void launch_wave(const T* A, const T* B, T* C, const StreamArgs& w, unsigned grid, hipStream_t st) {
+    dim3 g(grid), b(256);
+    if (w.K <= 4) hipLaunchKernelGGL((k_stream_wave<T, 4, VEC, 4, kWaveTpr, BETA>), g, b, 0, st, A, B, C, w);
+    else if (w.K <= 8) hipLaunchKernelGGL((k_stream_wave<T, 8, VEC, 4, kWaveTpr, BETA>), g, b, 0, st, A, B, C, w);
+    else if (w.K <= 16) hipLaunchKernelGGL((k_stream_wave<T, 16, VEC, 2, kWaveTpr, BETA>), g, b, 0, st, A, B, C, w);
+    else hipLaunchKernelGGL((k_stream_wave<T, 32, VEC, 1, kWaveTpr, BETA>), g, b, 0, st, A, B, C, w);
+}
+
+// The largest multiple of one wave span (64 * VEC) in M goes to k_stream_wave
+// when A is unit-stride along M and every A row and C column it touches is
+// 16-byte aligned; k_stream covers the rest of M (and everything else).
 template <typename T, int VEC>
 static hipError_t stream_dispatch(StreamArgs& a, hipStream_t st) {
-    int64_t grid = stream_grid(sizeof(T) == 8, a);
-    if (grid <= 0) return hipSuccess;
-    if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;
-    dim3 g((unsigned)grid), b(256);
+    if (a.M <= 0 || a.N <= 0) return hipSuccess;
     const T* A = (const T*)a.A;
     const T* B = (const T*)a.B;
     T* C = (T*)a.C;
-    // the regular case takes the straight-line kernel
-    const int64_t span = (int64_t)a.tpr * VEC;
-    const int Rk = stream_r(a.K);
-    bool fast = a.beta == 0.0 && a.sAm == 1 && a.M % span == 0 && a.n.n == 1 &&
-                a.N % (Rk * (256 / a.tpr)) == 0 && (a.K == 4 || a.K == 8 || a.K == 16 || a.K == 32) &&
-                ((uintptr_t)A) % (sizeof(T) * VEC) == 0 && ((uintptr_t)C) % (sizeof(T) * VEC) == 0 &&
-                a.n.d[0].sC % VEC == 0;
-    for (int k = 0; fast && k < a.K; ++k) fast = a.kA[k] % VEC == 0;
-    if (fast && a.tpr == 256) {
-        if (a.K == 4) hipLaunchKernelGGL((k_stream_fast<T, 4, VEC, 4, true>), g, b, 0, st, A, B, C, a);
-        else if (a.K == 8) hipLaunchKernelGGL((k_stream_fast<T, 8, VEC, 4, true>), g, b, 0, st, A, B, C, a);
-        else if (a.K == 16) hipLaunchKernelGGL((k_stream_fast<T, 16, VEC, 2, true>), g, b, 0, st, A, B, C, a);
-        else hipLaunchKernelGGL((k_stream_fast<T, 32, VEC, 1, true>), g, b, 0, st, A, B, C, a);
-        return hipGetLastError();
+    constexpr int64_t span = (int64_t)kWaveTpr * VEC;
+    bool wave = a.sAm == 1 && ((uintptr_t)A) % (sizeof(T) * VEC) == 0 && ((uintptr_t)C) % (sizeof(T) * VEC) == 0;
+    for (int d = 0; wave && d < a.n.n; ++d) wave = a.n.d[d].sC % VEC == 0;
+    for (int k = 0; wave && k < a.K; ++k) wave = a.kA[k] % VEC == 0;
+    const int64_t mbulk = wave ? a.M / span * span : 0;
+    if (mbulk > 0) {
+        StreamArgs w = a;
+        w.M = mbulk;
+        for (int k = w.K; k < GT_SMALLK_MAX; ++k) {
+            w.kA[k] = w.kA[w.K - 1];
+            w.kB[k] = w.kB[w.K - 1];
+        }
+        const int64_t cols = (int64_t)(256 / kWaveTpr) * stream_r(a.K);
+        const int64_t grid = (mbulk / span) * ((a.N + cols - 1) / cols);
+        if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;
+        if (a.beta != 0.0) launch_wave<T, VEC, true>(A, B, C, w, (unsigned)grid, st);
+        else launch_wave<T, VEC, false>(A, B, C, w, (unsigned)grid, st);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || mbulk == a.M) return e;
     }
-    if (fast) {
-        if (a.K == 4) hipLaunchKernelGGL((k_stream_fast<T, 4, VEC, 4, false>), g, b, 0, st, A, B, C, a);
-        else if (a.K == 8) hipLaunchKernelGGL((k_stream_fast<T, 8, VEC, 4, false>), g, b, 0, st, A, B, C, a);
-        else if (a.K == 16) hipLaunchKernelGGL((k_stream_fast<T, 16, VEC, 2, false>), g, b, 0, st, A, B, C, a);
-        else hipLaunchKernelGGL((k_stream_fast<T, 32, VEC, 1, false>), g, b, 0, st, A, B, C, a);
-        return hipGetLastError();
-    }
-    if (a.K <= 4) hipLaunchKernelGGL((k_stream<T, 4, VEC, 4>), g, b, 0, st, A, B, C, a);
-    else if (a.K <= 8) hipLaunchKernelGGL((k_stream<T, 8, VEC, 4>), g, b, 0, st, A, B, C, a);
-    else if (a.K <= 16) hipLaunchKernelGGL((k_stream<T, 16, VEC, 2>), g, b, 0, st, A, B, C, a);
-    else hipLaunchKernelGGL((k_stream<T, 32, VEC, 1>), g, b, 0, st, A, B, C, a);
+    StreamArgs t = a;
+    t.A = A + mbulk;   // mbulk > 0 only where A is unit-stride along M
+    t.C = C + mbulk;
+    t.M = a.M - mbulk;
+    stream_shape(sizeof(T) == 8, t);
+    const int64_t grid = stream_grid(sizeof(T) == 8, t);
+    if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;
+    dim3 g((unsigned)grid), b(256);
+    const T* At = (const T*)t.A;
+    T* Ct = (T*)t.C;
+    if (t.K <= 4) hipLaunchKernelGGL((k_stream<T, 4, VEC, 4>), g, b, 0, st, At, B, Ct, t);
+    else if (t.K <= 8) hipLaunchKernelGGL((k_stream<T, 8, VEC, 4>), g, b, 0, st, At, B, Ct, t);
+    else if (t.K <= 16) hipLaunchKernelGGL((k_stream<T, 16, VEC, 2>), g, b, 0, st, At, B, Ct, t);
+    else hipLaunchKernelGGL((k_stream<T, 32, VEC, 1>), g, b, 0, st, At, B, Ct, t);
     return hipGetLastError();
 }
 

@@ -32,6 +32,44 @@ def test_fused_smallk_integer_exact_and_beta():
     check(w["spec"], w["ext"], w["A"], w["B"], got, C0=w["C"], alpha=2.0, beta=-0.5, exact=True)
 
 
+# Streaming shapes: M a whole number of wave spans (128 doubles, 256 floats),
+# M with a tail for the general kernel, N of two dimensions that do not merge,
+# K padded up to the kernel's template size (1, 5, 12), K = 32, odd M (no
+# vector path at all), N not a whole number of block column sets.
+STREAM_SHAPES = [
+    ("abc=ai,ibc", dict(a=384, b=7, c=5, i=8)),
+    ("abc=ai,ibc", dict(a=300, b=9, c=4, i=5)),
+    ("abc=ai,icb", dict(a=256, b=6, c=7, i=12)),
+    ("abc=ai,ibc", dict(a=256, b=3, c=11, i=32)),
+    ("ab=ai,ib", dict(a=1024, b=33, i=1)),
+    ("abc=ai,ibc", dict(a=129, b=5, c=3, i=7)),
+    ("abc=aij,jibc", dict(a=520, b=3, c=5, i=3, j=4)),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", STREAM_SHAPES)
+def test_fused_stream_shapes(dtype, spec, ext):
+    rng = np.random.default_rng(7)
+    A, B, C0 = wl.tensors(spec, ext, rng, "normal", with_c=True)
+    p = _plan(spec, ext, dtype)
+    got = run(p, A, B, dtype=dtype)
+    check(spec, ext, A, B, got, dtype)
+    got = run(p, A, B, C0, alpha=-1.5, beta=0.25, dtype=dtype)
+    check(spec, ext, A, B, got, dtype, C0=C0, alpha=-1.5, beta=0.25)
+
+
+@pytest.mark.parametrize("spec,ext", STREAM_SHAPES[:5])
+def test_fused_stream_integer_exact(spec, ext):
+    A, B, C0 = wl.tensors(spec, ext, np.random.default_rng(8), integer=True, with_c=True)
+    for dtype in ("f64", "f32"):
+        p = _plan(spec, ext, dtype)
+        got = run(p, A, B, dtype=dtype)
+        check(spec, ext, A, B, got, dtype, exact=True)
+        got = run(p, A, B, C0, alpha=2.0, beta=-1.0, dtype=dtype)
+        check(spec, ext, A, B, got, dtype, C0=C0, alpha=2.0, beta=-1.0, exact=True)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("spec,ext", [
     ("abc=ija,jbic", dict(a=40, b=33, c=7, i=5, j=11)),          # ragged tiles, permuted strides

@@ -16,7 +16,7 @@ def _dev(x, dtype):
     return tc.to_device_fortran(x, torch.float64 if dtype == "f64" else torch.float32)
 
 
-@pytest.mark.parametrize("n", [128, 1024])
+@pytest.mark.parametrize("n", [128, 640, 1024])
 def test_smallk_cube_full_size(n):
     """C_abc = A_ai B_ibc, a=b=c=n, i=8, FP64, fused streaming kernel; four
     sampled c-slabs against the oracle."""
