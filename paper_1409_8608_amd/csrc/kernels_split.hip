@@ -5,13 +5,19 @@
 //    of B's).  FP64 absmax over the slice -> exponent e = floor(log2(max)); the
 //    scaled values x = v * 2^-e (exact) are split into three BF16 terms by
 //    round-to-nearest-even, t1 = rn(x), t2 = rn(x - t1), t3 = rn(x - t1 - t2),
-//    and packed K-contiguous ([term][row][Kp], Kp a multiple of 32) in the
-//    K order of the plan's offset table.
+//    in the K order of the plan's offset table.  The terms are written as
+//    ready-made LDS images: for every 128-row tile and 32-wide K stage, one
+//    contiguous 24 KB block [term][row][four 16-byte chunks], the chunks of
+//    each row permuted by xswz so that fragment reads hit distinct banks.
 // 2. k_x3: C tile = sum over the six term products t_A,p t_B,q with p+q <= 4.
-//    The leading product and the five small ones accumulate in two FP32
-//    accumulators over K chunks of 256; after each chunk both are added into an
-//    FP64 running sum with Neumaier compensation.  Epilogue:
-//    C = alpha * 2^(eA + eB) * (sum + comp) + beta * C.
+//    Stages are copied HBM -> LDS by the DMA form of the global load (no
+//    registers in between), three stages in flight.  The leading product
+//    t_A1 t_B1 accumulates in FP32 over K chunks of SPLIT_CHUNK and each chunk
+//    partial is added into an FP64 running sum with Neumaier compensation.
+//    The five small products (each at least 2^-7 below the leading one)
+//    accumulate in one FP32 accumulator over all of K: their rounding stays
+//    below the leading product's chunk error for K up to 2^15.  Epilogue:
+//    C = alpha * 2^(eA + eB) * (sum + comp + small) + beta * C.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,9 +33,22 @@ namespace tc {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int SPLIT_BK = 32;      // contracted positions per MFMA (16x16x32)
-constexpr int SPLIT_CHUNK = 256;  // FP32 accumulation length before the FP64 fold
-constexpr int XBM = 64, XBN = 128;
+constexpr int SPLIT_BK = 32;      // contracted positions per stage (one 16x16x32 MFMA step)
+// FP32 accumulation length of the leading product before it is folded into
+// the FP64 sum: nine K stages, a whole number of turns of the three-stage
+// buffer rotation
+constexpr int SPLIT_CHUNK_TILES = 9;
+constexpr int SPLIT_CHUNK = SPLIT_CHUNK_TILES * 32;
+constexpr int XR = 128;           // rows per panel tile = block tile edge in m and in n
+constexpr int XSTAGE = 3 * XR * SPLIT_BK * 2;   // bytes of one operand stage image (24 KB)
+constexpr int XPIECE = 1024;      // bytes one wave copies per DMA instruction (64 lanes x 16 B)
+constexpr int XWAVES = 4;
+
+// Physical 16-byte chunk of logical chunk c (k = 8c .. 8c+7) of row r inside a
+// stage image.  Rows are 64 bytes, so 16 consecutive rows at one logical chunk
+// would fall on four banks; the permutation spreads any 8 consecutive rows
+// (and any 16 aligned rows) over distinct 16-byte bank groups.
+__host__ __device__ __forceinline__ int xswz(int r, int c) { return c ^ (((r >> 1) ^ (r >> 3)) & 3); }
 
 // Round-to-nearest-even to an 8-bit significand, unbounded exponent (the
 // values stay far inside BF16's range after the per-slice scaling).
@@ -64,11 +83,18 @@ struct SplitArgs {
     GtDims rows;          // the side's free dims (slot selects the stride)
     int slot;             // 0: A side (sA, table column 0); 1: B side (sB, column 1)
     const int64_t* ktab;  // Kp pairs
-    int64_t nrows, Kp, row_stride;   // packed row stride (elements)
-    uint16_t* terms;      // [3][rows_padded][Kp]
-    int64_t term_stride;  // elements between terms
+    int64_t nrows, Kp;
+    uint16_t* panels;     // stage images, see xswz
     int32_t* exps;
 };
+
+// Element offset of (term, row, k) in a side's stage images.
+__host__ __device__ __forceinline__ int64_t panel_off(int64_t row, int64_t k, int term, int64_t Kp) {
+    const int64_t rt = row / XR, kt = k / SPLIT_BK;
+    const int rr = (int)(row % XR), kk = (int)(k % SPLIT_BK);
+    return ((rt * (Kp / SPLIT_BK) + kt) * 3 + term) * (int64_t)(XR * SPLIT_BK) + rr * SPLIT_BK +
+           xswz(rr, kk >> 3) * 8 + (kk & 7);
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_split(SplitArgs a) {
@@ -94,9 +120,7 @@ __global__ __launch_bounds__(256) void k_split(SplitArgs a) {
         e = E - 1;
     }
     if (tid == 0) a.exps[row] = e;
-    uint16_t* t1 = a.terms + row * a.row_stride;
-    uint16_t* t2 = t1 + a.term_stride;
-    uint16_t* t3 = t2 + a.term_stride;
+    constexpr int64_t TS = XR * SPLIT_BK;   // elements between the terms of one stage image
     for (int64_t k = tid; k < a.Kp; k += 256) {
         int64_t o = a.ktab[2 * k + a.slot];
         double x = o >= 0 ? ldexp((double)X[base + o], -e) : 0.0;
@@ -104,16 +128,16 @@ __global__ __launch_bounds__(256) void k_split(SplitArgs a) {
         double rest = x - r1;
         double r2 = rn_bf16(rest);
         double r3 = rn_bf16(rest - r2);
-        t1[k] = bf16_bits(r1);
-        t2[k] = bf16_bits(r2);
-        t3[k] = bf16_bits(r3);
+        uint16_t* t = a.panels + panel_off(row, k, 0, a.Kp);
+        t[0] = bf16_bits(r1);
+        t[TS] = bf16_bits(r2);
+        t[2 * TS] = bf16_bits(r3);
     }
 }
 
 struct X3Args {
-    const uint16_t* tA;   // [3][rowsA][Kp]
-    const uint16_t* tB;   // [3][rowsB][Kp]
-    int64_t tsA, tsB;     // term strides (elements)
+    const uint16_t* tA;   // stage images of A's terms (panel_off layout)
+    const uint16_t* tB;   // stage images of B's terms
     const int32_t* eA;
     const int32_t* eB;
     void* C;
@@ -129,154 +153,194 @@ __device__ __forceinline__ int64_t xcd_tile3(int64_t b, int64_t total) {
     return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// s_waitcnt immediates (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8); a field at its maximum does not wait.
+constexpr int wait_vm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+constexpr int kWaitLgkm0 = 15 | (3 << 14) | (7 << 4);
+
+// One block = 4 waves (one per SIMD) on a 128 (m) x 128 (n) tile; wave
+// (wm, wn) owns 64 m x 64 n, four by four blocks of 16 x 16.  A stage (32 K
+// positions of all three terms of both operands, 48 KB) arrives in LDS by DMA,
+// three stages in flight; each wave copies six 1 KB pieces of each operand per
+// stage.  Work per stage and wave: 96 MFMAs (6 products x 16 blocks) against
+// 24 fragment reads of 16 bytes per lane.
 template <typename T>
 __global__ __launch_bounds__(256) void k_x3(X3Args a) {
-    constexpr int BK = SPLIT_BK;
-    constexpr int LDR = BK + 8;                  // padded row (bf16 elements): 80 bytes
-    constexpr int FM = XBM / 32, FN = XBN / 32;  // 16x16 blocks per wave (wave tile 32 x 64)
-    __shared__ uint16_t sA[2][3][XBM][LDR];
-    __shared__ uint16_t sB[2][3][XBN][LDR];
-    __shared__ int64_t sCm[XBM], sCn[XBN];
-    __shared__ int32_t sEm[XBM], sEn[XBN];
+    constexpr int NV = XSTAGE / 16;               // uint4 per stage image
+    constexpr int PIECES = XSTAGE / XPIECE / XWAVES;   // DMA pieces per wave per operand (6)
+    // One array per stage buffer: the compiler then knows which stage a DMA
+    // writes and which one a fragment read reads, and leaves the younger
+    // stages in flight.
+    __shared__ uint4 sA0[NV], sA1[NV], sA2[NV], sB0[NV], sB1[NV], sB2[NV];
+    __shared__ int64_t sCm[XR], sCn[XR];
+    __shared__ int32_t sEm[XR], sEn[XR];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid & 1, wn = wid >> 1;
-    const int64_t tile = xcd_tile3(blockIdx.x, a.ntiles);
-    const int64_t mt = tile % a.mt, nt = tile / a.mt;
-    const int64_t m_base = mt * XBM, n_base = nt * XBN;
-    for (int i = tid; i < XBM; i += 256) {
-        int64_t m = m_base + i;
+    // tile order: contiguous per XCD, then groups of eight m-tiles sweeping n,
+    // so the blocks resident on one XCD share A and B stage images in its L2
+    const int64_t L = xcd_tile3(blockIdx.x, a.ntiles);
+    constexpr int64_t GM = 8;
+    const int64_t g = L / (GM * a.nt), first = g * GM;
+    const int64_t gm = a.mt - first < GM ? a.mt - first : GM;
+    const int64_t r = L - g * GM * a.nt;
+    const int64_t mt = first + r % gm, nt = r / gm;
+    const int64_t m_base = mt * XR, n_base = nt * XR;
+    for (int i = tid; i < XR; i += 256) {
+        const int64_t m = m_base + i;
         sCm[i] = m < a.M ? grp_off(a.m, m, 2) : -1;
         sEm[i] = m < a.M ? a.eA[m] : 0;
     }
-    for (int i = tid; i < XBN; i += 256) {
-        int64_t n = n_base + i;
+    for (int i = tid; i < XR; i += 256) {
+        const int64_t n = n_base + i;
         sCn[i] = n < a.N ? grp_off(a.n, n, 2) : -1;
         sEn[i] = n < a.N ? a.eB[n] : 0;
     }
+    __syncthreads();
 
-    // global -> LDS: 16-byte pieces, four per row and term
-    constexpr int PA = 3 * XBM * 4 / 256, PB = 3 * XBN * 4 / 256;
-    uint4 ra[PA], rb[PB];
-    auto gload = [&](int64_t kt) {
+    const int64_t ktiles = a.Kp / SPLIT_BK;
+    const char* gA = (const char*)a.tA + mt * ktiles * XSTAGE + lane * 16;
+    const char* gB = (const char*)a.tB + nt * ktiles * XSTAGE + lane * 16;
+    auto dma = [&](int64_t kt, uint4* sa, uint4* sb) {
 #pragma unroll
-        for (int e = 0; e < PA; ++e) {
-            int idx = tid + 256 * e;
-            int piece = idx & 3, row = (idx >> 2) % XBM, term = (idx >> 2) / XBM;
-            const uint16_t* src = a.tA + term * a.tsA + (m_base + row) * a.Kp + kt * BK + piece * 8;
-            ra[e] = *(const uint4*)src;
-        }
-#pragma unroll
-        for (int e = 0; e < PB; ++e) {
-            int idx = tid + 256 * e;
-            int piece = idx & 3, row = (idx >> 2) % XBN, term = (idx >> 2) / XBN;
-            const uint16_t* src = a.tB + term * a.tsB + (n_base + row) * a.Kp + kt * BK + piece * 8;
-            rb[e] = *(const uint4*)src;
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int e = 0; e < PA; ++e) {
-            int idx = tid + 256 * e;
-            int piece = idx & 3, row = (idx >> 2) % XBM, term = (idx >> 2) / XBM;
-            *(uint4*)&sA[buf][term][row][piece * 8] = ra[e];
-        }
-#pragma unroll
-        for (int e = 0; e < PB; ++e) {
-            int idx = tid + 256 * e;
-            int piece = idx & 3, row = (idx >> 2) % XBN, term = (idx >> 2) / XBN;
-            *(uint4*)&sB[buf][term][row][piece * 8] = rb[e];
+        for (int e = 0; e < PIECES; ++e) {
+            const int piece = wid + XWAVES * e;
+            __builtin_amdgcn_global_load_lds(gA + kt * XSTAGE + piece * XPIECE, (lds_void_t*)(sa + piece * 64), 16,
+                                             0, 0);
+            __builtin_amdgcn_global_load_lds(gB + kt * XSTAGE + piece * XPIECE, (lds_void_t*)(sb + piece * 64), 16,
+                                             0, 0);
         }
     };
 
-    f4 big[FN][FM], small[FN][FM];
-    double sum[FN][FM][4], comp[FN][FM][4];
+    // fragment: this lane's 8 consecutive k (logical chunk lane/16) of one row
+    const int r16 = lane & 15, ch = lane >> 4;
+    auto frag = [&](const uint4* st, int term, int row) -> bf8 {
+        const uint4 v = st[(term * XR + row) * 4 + xswz(row, ch)];
+        return __builtin_bit_cast(bf8, v);
+    };
+
+    f4 big[4][4], small[4][4];
+    double sum[4][4][4];
+    float comp[4][4][4];
 #pragma unroll
-    for (int i = 0; i < FN; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < FM; ++j) {
+        for (int j = 0; j < 4; ++j) {
             big[i][j] = f4{0, 0, 0, 0};
             small[i][j] = f4{0, 0, 0, 0};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sum[i][j][q] = comp[i][j][q] = 0.0;
+            for (int q = 0; q < 4; ++q) {
+                sum[i][j][q] = 0.0;
+                comp[i][j][q] = 0.f;
+            }
         }
+
+    // The six products in an order that keeps few fragments live: B term 1
+    // stays, B terms 2 and 3 live only while they are used.  The MFMA row
+    // operand is the B side (n), so a lane holds D[n = 4*(lane/16) + q][m = lane % 16].
+    auto mma = [&](f4 (&acc)[4][4], const bf8 (&fb)[4], const bf8 (&fa)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[i], fa[j], acc[i][j], 0, 0, 0);
+    };
+    auto load_b = [&](const uint4* sb, int t, bf8 (&fb)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fb[i] = frag(sb, t, wn * 64 + i * 16 + r16);
+    };
+    auto load_a = [&](const uint4* sa, int t, bf8 (&fa)[4]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fa[j] = frag(sa, t, wm * 64 + j * 16 + r16);
+    };
+    auto compute = [&](const uint4* sa, const uint4* sb) {
+        // sched_barrier(0) keeps each group in place: the scheduler would
+        // otherwise hoist all fragment reads of the step and run out of
+        // registers
+        bf8 b1[4], bx[4], fa[4];
+        load_b(sb, 0, b1);
+        load_a(sa, 0, fa);
+        load_b(sb, 2, bx);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(big, b1, fa);      // t_A1 t_B1
+        mma(small, bx, fa);    // t_A1 t_B3
+        __builtin_amdgcn_sched_barrier(0);
+        load_b(sb, 1, bx);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(small, bx, fa);    // t_A1 t_B2
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(sa, 1, fa);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(small, b1, fa);    // t_A2 t_B1
+        mma(small, bx, fa);    // t_A2 t_B2
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(sa, 2, fa);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(small, b1, fa);    // t_A3 t_B1
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // chunk partial of the leading product into the running sum, with
+    // Neumaier compensation; the correction is kept in FP32 (it collects
+    // rounding errors of FP64 adds, far below the sum)
     auto fold = [&]() {
 #pragma unroll
-        for (int i = 0; i < FN; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < FM; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    // Neumaier: add the two chunk partials into (sum, comp)
-                    double parts[2] = {(double)small[i][j][q], (double)big[i][j][q]};
-#pragma unroll
-                    for (int p = 0; p < 2; ++p) {
-                        double s = sum[i][j][q], x = parts[p], t = s + x;
-                        comp[i][j][q] += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-                        sum[i][j][q] = t;
-                    }
+                    const double x = (double)big[i][j][q];
+                    const double s0 = sum[i][j][q], t = s0 + x;
+                    const double err = fabs(s0) >= fabs(x) ? (s0 - t) + x : (x - t) + s0;
+                    comp[i][j][q] += (float)err;
+                    sum[i][j][q] = t;
                     big[i][j][q] = 0.f;
-                    small[i][j][q] = 0.f;
                 }
     };
-
-    const int64_t ktiles = a.Kp / BK;
-    const int per_chunk = SPLIT_CHUNK / BK;
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    for (int64_t kt = 0; kt < ktiles; ++kt) {
-        const int buf = (int)(kt & 1);
-        if (kt + 1 < ktiles) gload(kt + 1);
-        // fragments: lane holds 8 consecutive k of row (lane % 16) at k offset 8*(lane/16)
-        bf8 fa[3][FM], fb[3][FN];
-        const int r16 = lane & 15, k8 = (lane >> 4) * 8;
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-#pragma unroll
-            for (int j = 0; j < FM; ++j)
-                fa[t][j] = *(const bf8*)&sA[buf][t][wm * (XBM / 2) + j * 16 + r16][k8];
-#pragma unroll
-            for (int i = 0; i < FN; ++i)
-                fb[t][i] = *(const bf8*)&sB[buf][t][wn * (XBN / 2) + i * 16 + r16][k8];
+    // stage kt sits in (sa, sb); stage kt + 2 goes into (na, nb), the buffers
+    // every wave finished reading in the previous step
+    auto step = [&](int64_t kt, const uint4* sa, const uint4* sb, uint4* na, uint4* nb) {
+        if (kt + 1 < ktiles) __builtin_amdgcn_s_waitcnt(wait_vm(2 * PIECES));   // stage kt landed
+        else __builtin_amdgcn_s_waitcnt(wait_vm(0));
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);   // this wave's reads of the previous stage are done
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (kt + 2 < ktiles) dma(kt + 2, na, nb);
+        compute(sa, sb);
+    };
+    if (ktiles > 0) dma(0, sA0, sB0);
+    if (ktiles > 1) dma(1, sA1, sB1);
+    // chunks start at multiples of three stages, so stage kt always sits in
+    // buffer kt % 3 and every step names its buffers statically
+    for (int64_t c0 = 0; c0 < ktiles; c0 += SPLIT_CHUNK_TILES) {
+#pragma unroll 1
+        for (int u = 0; u < SPLIT_CHUNK_TILES; u += 3) {
+            const int64_t kt = c0 + u;
+            if (kt < ktiles) step(kt, sA0, sB0, sA2, sB2);
+            if (kt + 1 < ktiles) step(kt + 1, sA1, sB1, sA0, sB0);
+            if (kt + 2 < ktiles) step(kt + 2, sA2, sB2, sA1, sB1);
         }
-        // five small products first, then the leading one; row operand = B side (n)
-#pragma unroll
-        for (int pq = 0; pq < 5; ++pq) {
-            const int p = pq == 0 ? 0 : pq == 1 ? 1 : pq == 2 ? 0 : pq == 3 ? 2 : 1;   // A term
-            const int q = pq == 0 ? 1 : pq == 1 ? 0 : pq == 2 ? 2 : pq == 3 ? 0 : 1;   // B term
-#pragma unroll
-            for (int i = 0; i < FN; ++i)
-#pragma unroll
-                for (int j = 0; j < FM; ++j)
-                    small[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[q][i], fa[p][j], small[i][j], 0, 0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < FN; ++i)
-#pragma unroll
-            for (int j = 0; j < FM; ++j)
-                big[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[0][i], fa[0][j], big[i][j], 0, 0, 0);
-        if ((kt + 1) % per_chunk == 0 || kt + 1 == ktiles) fold();
-        if (kt + 1 < ktiles) sstore(buf ^ 1);
-        __syncthreads();
+        fold();
     }
 
-    // epilogue: lane holds D[n = 4*(lane/16) + q][m = lane % 16] of each block
     T* C = (T*)a.C;
     const T beta = (T)a.beta;
 #pragma unroll
-    for (int i = 0; i < FN; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int nl = wn * (XBN / 2) + i * 16 + 4 * (lane >> 4) + q;
+            const int nl = wn * 64 + i * 16 + 4 * (lane >> 4) + q;
             const int64_t cn = sCn[nl];
             if (cn < 0) continue;
 #pragma unroll
-            for (int j = 0; j < FM; ++j) {
-                const int ml = wm * (XBM / 2) + j * 16 + (lane & 15);
+            for (int j = 0; j < 4; ++j) {
+                const int ml = wm * 64 + j * 16 + (lane & 15);
                 const int64_t cm = sCm[ml];
                 if (cm < 0) continue;
-                double v = a.alpha * ldexp(sum[i][j][q] + comp[i][j][q], sEm[ml] + sEn[nl]);
+                const double v = a.alpha * ldexp(sum[i][j][q] + ((double)comp[i][j][q] + (double)small[i][j][q]),
+                                                 sEm[ml] + sEn[nl]);
                 T* cp = C + cn + cm;
                 T out = (T)v;
                 if (a.beta != 0.0) out += beta * (*cp);
@@ -297,7 +361,7 @@ tc_status prepare_split(tc_plan_s* p) {
     const GemmView& gv = p->gv;
     std::vector<int64_t> tab = build_ktab(gv.k, SPLIT_BK);
     int64_t Kp = (int64_t)tab.size() / 2;
-    int64_t RA = round_up(std::max<int64_t>(1, gv.M), XBM), RB = round_up(std::max<int64_t>(1, gv.N), XBN);
+    int64_t RA = round_up(std::max<int64_t>(1, gv.M), XR), RB = round_up(std::max<int64_t>(1, gv.N), XR);
     int64_t off = 0;
     int64_t* L = p->split_layout;
     L[L_KTAB] = off; off += round_up((int64_t)tab.size() * 8, 256);
@@ -312,7 +376,7 @@ tc_status prepare_split(tc_plan_s* p) {
         return fail(TC_E_NOMEM, std::string("hipMalloc split workspace: ") + hipGetErrorString(e));
     }
     p->split_bytes = off;
-    // zero everything once: padded rows of the term buffers stay zero
+    // zero everything once: padded rows of the stage images stay zero
     e = hipMemset(p->d_split, 0, (size_t)off);
     if (e == hipSuccess && !tab.empty())
         e = hipMemcpy((char*)p->d_split + L[L_KTAB], tab.data(), tab.size() * 8, hipMemcpyHostToDevice);
@@ -343,9 +407,7 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
         s.ktab = ktab;
         s.nrows = side == 0 ? gv.M : gv.N;
         s.Kp = Kp;
-        s.row_stride = Kp;
-        s.terms = side == 0 ? tA : tB;
-        s.term_stride = (side == 0 ? RA : RB) * Kp;
+        s.panels = side == 0 ? tA : tB;
         s.exps = side == 0 ? eA : eB;
         if (s.nrows <= 0) continue;
         if (f64) hipLaunchKernelGGL(k_split<double>, dim3((unsigned)s.nrows), dim3(256), 0, st, s);
@@ -355,7 +417,6 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
     }
     X3Args x{};
     x.tA = tA; x.tB = tB;
-    x.tsA = RA * Kp; x.tsB = RB * Kp;
     x.eA = eA; x.eB = eB;
     x.C = C;
     x.m.n = (int)gv.m.size();
@@ -363,9 +424,10 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
     x.n.n = (int)gv.n.size();
     for (int d = 0; d < x.n.n; ++d) x.n.d[d] = gv.n[d];
     x.M = gv.M; x.N = gv.N; x.Kp = Kp;
-    x.mt = RA / XBM; x.nt = RB / XBN;
+    x.mt = RA / XR; x.nt = RB / XR;
     x.ntiles = x.mt * x.nt;
     x.alpha = alpha; x.beta = beta;
+    if (x.ntiles > 0x7fffffff) return fail(TC_E_EXTENT, "too many output tiles for one launch");
     if (f64) hipLaunchKernelGGL(k_x3<double>, dim3((unsigned)x.ntiles), dim3(256), 0, st, x);
     else hipLaunchKernelGGL(k_x3<float>, dim3((unsigned)x.ntiles), dim3(256), 0, st, x);
     e = hipGetLastError();
@@ -391,12 +453,17 @@ extern "C" tc_status tc_split_terms(tc_plan_t p, int side, void* terms, int32_t*
     char* w = (char*)p->d_split;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "synchronize");
-    if (terms)
-        for (int t = 0; t < 3; ++t) {
-            e = hipMemcpy((char*)terms + t * n * Kp * 2, w + L[side == 0 ? L_TA : L_TB] + t * R * Kp * 2,
-                          (size_t)(n * Kp * 2), hipMemcpyDeviceToHost);
-            if (e != hipSuccess) return hip_fail(e, "copy split terms");
-        }
+    if (terms) {
+        // the device keeps stage images; hand back [term][row][Kp]
+        const int64_t elems = 3 * R * Kp;
+        std::vector<uint16_t> img((size_t)elems);
+        e = hipMemcpy(img.data(), w + L[side == 0 ? L_TA : L_TB], (size_t)(elems * 2), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "copy split terms");
+        uint16_t* out = (uint16_t*)terms;
+        for (int t = 0; t < 3; ++t)
+            for (int64_t r = 0; r < n; ++r)
+                for (int64_t k = 0; k < Kp; ++k) out[(t * n + r) * Kp + k] = img[(size_t)panel_off(r, k, t, Kp)];
+    }
     if (exps) {
         e = hipMemcpy(exps, w + L[side == 0 ? L_EA : L_EB], (size_t)(n * 4), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "copy split exponents");

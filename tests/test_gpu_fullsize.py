@@ -5,6 +5,7 @@ import pytest
 
 import oracle
 from oracle import split as sp
+from gpu_util import split_bound
 
 pytestmark = pytest.mark.gpu
 tc = pytest.importorskip("paper_1409_8608_amd")
@@ -77,7 +78,7 @@ def test_scaled_matrix_full_size(compute):
         assert oracle.normwise_rel_err(got, ref) <= 1e-5
         absAB = oracle.contract(w["spec"], ext_s, np.abs(As), np.abs(Bs))
         ref_split = sp.contract_split(w["spec"], ext_s, As, Bs)   # slices are per free index: sampling keeps them
-        bound = (256 + 8) * 2.0 ** -24 + 2.0 ** -22
+        bound = split_bound(64 * 64)
         assert np.all(np.abs(got - ref_split) <= bound * absAB)
 
 

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from oracle import split as sp
-from gpu_util import run
+from gpu_util import split_bound, run
 
 pytestmark = pytest.mark.gpu
 tc = pytest.importorskip("paper_1409_8608_amd")
@@ -50,7 +50,7 @@ def test_split_terms_bit_exact_and_result(spec, ext):
     ref = oracle.contract(spec, ext, A, B)
     absAB = oracle.contract(spec, ext, np.abs(A), np.abs(B))
     K = int(np.prod([ext[c] for c in sa if c not in sc]))
-    bound = (min(K, 256) + 8) * 2.0 ** -24 + 2.0 ** -22
+    bound = split_bound(K)
     assert np.all(np.abs(got - ref_split) <= bound * absAB)
     assert oracle.normwise_rel_err(got, ref) <= 1e-5
     # exponents: one per free multi-index, first free index fastest (the GEMM view's rows)
