@@ -2,7 +2,8 @@
 // v_mfma_f32_16x16x32_bf16).
 //
 // 1. k_split: one block per slice (one row m of A's GEMM view, or one column n
-//    of B's).  FP64 absmax over the slice -> exponent e = floor(log2(max)); the
+//    of B's), reading the slice once.  FP64 absmax over the slice -> exponent
+//    e = floor(log2(max)); the
 //    scaled values x = v * 2^-e (exact) are split into three BF16 terms by
 //    round-to-nearest-even, t1 = rn(x), t2 = rn(x - t1), t3 = rn(x - t1 - t2),
 //    in the K order of the plan's offset table.  The terms are written as
@@ -42,13 +43,22 @@ constexpr int SPLIT_CHUNK = SPLIT_CHUNK_TILES * 32;
 constexpr int XR = 128;           // rows per panel tile = block tile edge in m and in n
 constexpr int XSTAGE = 3 * XR * SPLIT_BK * 2;   // bytes of one operand stage image (24 KB)
 constexpr int XPIECE = 1024;      // bytes one wave copies per DMA instruction (64 lanes x 16 B)
-constexpr int XWAVES = 4;
+// Waves per block along n (two along m): 2 gives four waves of 64 x 64, one
+// per SIMD; 4 gives eight waves of 64 x 32, two per SIMD.  Measured on MI355X
+// at 4096^2 x 4096: eight waves take 8% less time (the second wave on a SIMD
+// covers the first one's fragment-load and barrier waits), at 238 VGPRs.
+constexpr int XWN = 4;
+constexpr int XWAVES = 2 * XWN;
 
 // Physical 16-byte chunk of logical chunk c (k = 8c .. 8c+7) of row r inside a
-// stage image.  Rows are 64 bytes, so 16 consecutive rows at one logical chunk
-// would fall on four banks; the permutation spreads any 8 consecutive rows
-// (and any 16 aligned rows) over distinct 16-byte bank groups.
-__host__ __device__ __forceinline__ int xswz(int r, int c) { return c ^ (((r >> 1) ^ (r >> 3)) & 3); }
+// stage image.  Rows are 64 bytes, so the 16 rows one fragment read touches
+// (rows 16b .. 16b+15 in lanes 0-15, the same rows one chunk further in each
+// next 16 lanes) would fall on few banks.  Measured on MI355X with a
+// read-pattern probe: permuting chunk c of row r by (r >> 1) & 3 makes that
+// read as fast as a linear 1 KB read; other permutations tried (r & 3,
+// (r >> 2) & 3, ((r >> 1) ^ (r >> 3)) & 3, 80-byte padded rows) took 1.55x as
+// long.
+__host__ __device__ __forceinline__ int xswz(int r, int c) { return c ^ ((r >> 1) & 3); }
 
 // Round-to-nearest-even to an 8-bit significand, unbounded exponent (the
 // values stay far inside BF16's range after the per-slice scaling).
@@ -81,9 +91,11 @@ __device__ __forceinline__ int64_t grp_off(const GtDims& g, int64_t i, int slot)
 struct SplitArgs {
     const void* X;
     GtDims rows;          // the side's free dims (slot selects the stride)
-    int slot;             // 0: A side (sA, table column 0); 1: B side (sB, column 1)
-    const int64_t* ktab;  // Kp pairs
+    int slot;             // 0: A side (sA); 1: B side (sB)
+    const int64_t* koff;  // Kp element offsets of the side's operand, -1 for padding
     int64_t nrows, Kp;
+    int64_t Kt;           // positions with table entries (a multiple of 32); Kt .. Kp are zero
+                          // terms that the zeroed workspace already holds
     uint16_t* panels;     // stage images, see xswz
     int32_t* exps;
 };
@@ -96,18 +108,37 @@ __host__ __device__ __forceinline__ int64_t panel_off(int64_t row, int64_t k, in
            xswz(rr, kk >> 3) * 8 + (kk & 7);
 }
 
-template <typename T>
+__device__ __forceinline__ uint32_t pack2(double lo, double hi) {
+    return (uint32_t)bf16_bits(lo) | ((uint32_t)bf16_bits(hi) << 16);
+}
+
+// One block per slice.  Thread t owns the chunks t, t + 256, ... of eight
+// consecutive K positions (CPT of them): it loads their values once, keeps
+// them in registers through the block-wide max, then writes each chunk's three
+// terms as one 16-byte store per term.
+template <typename T, int CPT>
 __global__ __launch_bounds__(256) void k_split(SplitArgs a) {
     __shared__ double red[4];
     const T* X = (const T*)a.X;
     const int64_t row = blockIdx.x;
     const int tid = threadIdx.x;
     const int64_t base = grp_off(a.rows, row, a.slot);
+    const int64_t nch = a.Kt / 8;
+    double v[CPT][8];
     double amax = 0.0;
-    for (int64_t k = tid; k < a.Kp; k += 256) {
-        int64_t o = a.ktab[2 * k + a.slot];
-        double v = o >= 0 ? (double)X[base + o] : 0.0;
-        amax = fmax(amax, fabs(v));
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int64_t ch = tid + 256 * c;
+        const bool in = ch < nch;
+        const int64_t* ko = a.koff + 8 * (in ? ch : 0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t o = ko[e];
+            const bool ok = in && o >= 0;
+            const double x = (double)X[base + (ok ? o : 0)];
+            v[c][e] = ok ? x : 0.0;
+            amax = fmax(amax, fabs(v[c][e]));
+        }
     }
     for (int s = 32; s > 0; s >>= 1) amax = fmax(amax, __shfl_xor(amax, s));
     if ((tid & 63) == 0) red[tid >> 6] = amax;
@@ -121,13 +152,60 @@ __global__ __launch_bounds__(256) void k_split(SplitArgs a) {
     }
     if (tid == 0) a.exps[row] = e;
     constexpr int64_t TS = XR * SPLIT_BK;   // elements between the terms of one stage image
-    for (int64_t k = tid; k < a.Kp; k += 256) {
-        int64_t o = a.ktab[2 * k + a.slot];
-        double x = o >= 0 ? ldexp((double)X[base + o], -e) : 0.0;
-        double r1 = rn_bf16(x);
-        double rest = x - r1;
-        double r2 = rn_bf16(rest);
-        double r3 = rn_bf16(rest - r2);
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int64_t ch = tid + 256 * c;
+        if (ch >= nch) break;
+        double t1[8], t2[8], t3[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double x = ldexp(v[c][q], -e);
+            t1[q] = rn_bf16(x);
+            const double rest = x - t1[q];
+            t2[q] = rn_bf16(rest);
+            t3[q] = rn_bf16(rest - t2[q]);
+        }
+        uint4* out = (uint4*)(a.panels + panel_off(row, 8 * ch, 0, a.Kp));
+        out[0] = make_uint4(pack2(t1[0], t1[1]), pack2(t1[2], t1[3]), pack2(t1[4], t1[5]), pack2(t1[6], t1[7]));
+        out[TS / 8] = make_uint4(pack2(t2[0], t2[1]), pack2(t2[2], t2[3]), pack2(t2[4], t2[5]), pack2(t2[6], t2[7]));
+        out[2 * TS / 8] =
+            make_uint4(pack2(t3[0], t3[1]), pack2(t3[2], t3[3]), pack2(t3[4], t3[5]), pack2(t3[6], t3[7]));
+    }
+}
+
+// Any K: two passes over the slice, the second re-reading it (from cache).
+template <typename T>
+__global__ __launch_bounds__(256) void k_split_long(SplitArgs a) {
+    __shared__ double red[4];
+    const T* X = (const T*)a.X;
+    const int64_t row = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t base = grp_off(a.rows, row, a.slot);
+    double amax = 0.0;
+    for (int64_t k = tid; k < a.Kt; k += 256) {
+        const int64_t o = a.koff[k];
+        const double v = o >= 0 ? (double)X[base + o] : 0.0;
+        amax = fmax(amax, fabs(v));
+    }
+    for (int s = 32; s > 0; s >>= 1) amax = fmax(amax, __shfl_xor(amax, s));
+    if ((tid & 63) == 0) red[tid >> 6] = amax;
+    __syncthreads();
+    amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    int e = 0;
+    if (amax > 0.0) {
+        int E;
+        frexp(amax, &E);
+        e = E - 1;
+    }
+    if (tid == 0) a.exps[row] = e;
+    constexpr int64_t TS = XR * SPLIT_BK;
+    for (int64_t k = tid; k < a.Kt; k += 256) {
+        const int64_t o = a.koff[k];
+        const double x = o >= 0 ? ldexp((double)X[base + o], -e) : 0.0;
+        const double r1 = rn_bf16(x);
+        const double rest = x - r1;
+        const double r2 = rn_bf16(rest);
+        const double r3 = rn_bf16(rest - r2);
         uint16_t* t = a.panels + panel_off(row, k, 0, a.Kp);
         t[0] = bf16_bits(r1);
         t[TS] = bf16_bits(r2);
@@ -160,16 +238,18 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 constexpr int wait_vm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 constexpr int kWaitLgkm0 = 15 | (3 << 14) | (7 << 4);
 
-// One block = 4 waves (one per SIMD) on a 128 (m) x 128 (n) tile; wave
-// (wm, wn) owns 64 m x 64 n, four by four blocks of 16 x 16.  A stage (32 K
-// positions of all three terms of both operands, 48 KB) arrives in LDS by DMA,
-// three stages in flight; each wave copies six 1 KB pieces of each operand per
-// stage.  Work per stage and wave: 96 MFMAs (6 products x 16 blocks) against
-// 24 fragment reads of 16 bytes per lane.
+// One block = 2 x XWN waves on a 128 (m) x 128 (n) tile; wave (wm, wn) owns
+// 64 m x 16*FN n, four by FN blocks of 16 x 16.  A stage (32 K positions of
+// all three terms of both operands, 48 KB) arrives in LDS by DMA, three stages
+// in flight; each wave copies 24 / XWAVES pieces of 1 KB of each operand per
+// stage.  Work per stage and wave: 24 FN MFMAs (6 products x 4 FN blocks)
+// against 12 + 6 FN fragment reads of 16 bytes per lane.
 template <typename T>
-__global__ __launch_bounds__(256) void k_x3(X3Args a) {
+__global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
     constexpr int NV = XSTAGE / 16;               // uint4 per stage image
-    constexpr int PIECES = XSTAGE / XPIECE / XWAVES;   // DMA pieces per wave per operand (6)
+    constexpr int PIECES = XSTAGE / XPIECE / XWAVES;   // DMA pieces per wave per operand
+    constexpr int FN = XR / XWN / 16;                  // n-blocks of 16 per wave
+    constexpr int NT = 64 * XWAVES;                    // threads
     // One array per stage buffer: the compiler then knows which stage a DMA
     // writes and which one a fragment read reads, and leaves the younger
     // stages in flight.
@@ -177,8 +257,9 @@ __global__ __launch_bounds__(256) void k_x3(X3Args a) {
     __shared__ int64_t sCm[XR], sCn[XR];
     __shared__ int32_t sEm[XR], sEn[XR];
 
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int wm = wid & 1, wn = wid >> 1;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar DMA bases
+    const int wm = wid & 1, wn = wid >> 1;   // wave tile 64 (m) x 16*FN (n)
     // tile order: contiguous per XCD, then groups of eight m-tiles sweeping n,
     // so the blocks resident on one XCD share A and B stage images in its L2
     const int64_t L = xcd_tile3(blockIdx.x, a.ntiles);
@@ -188,12 +269,12 @@ __global__ __launch_bounds__(256) void k_x3(X3Args a) {
     const int64_t r = L - g * GM * a.nt;
     const int64_t mt = first + r % gm, nt = r / gm;
     const int64_t m_base = mt * XR, n_base = nt * XR;
-    for (int i = tid; i < XR; i += 256) {
+    for (int i = tid; i < XR; i += NT) {
         const int64_t m = m_base + i;
         sCm[i] = m < a.M ? grp_off(a.m, m, 2) : -1;
         sEm[i] = m < a.M ? a.eA[m] : 0;
     }
-    for (int i = tid; i < XR; i += 256) {
+    for (int i = tid; i < XR; i += NT) {
         const int64_t n = n_base + i;
         sCn[i] = n < a.N ? grp_off(a.n, n, 2) : -1;
         sEn[i] = n < a.N ? a.eB[n] : 0;
@@ -201,16 +282,19 @@ __global__ __launch_bounds__(256) void k_x3(X3Args a) {
     __syncthreads();
 
     const int64_t ktiles = a.Kp / SPLIT_BK;
-    const char* gA = (const char*)a.tA + mt * ktiles * XSTAGE + lane * 16;
-    const char* gB = (const char*)a.tB + nt * ktiles * XSTAGE + lane * 16;
+    // wave-uniform stage bases plus a 32-bit lane offset: the scalar-base form
+    // of the DMA load, with no per-lane 64-bit address arithmetic
+    const char* gA = (const char*)a.tA + mt * ktiles * XSTAGE;
+    const char* gB = (const char*)a.tB + nt * ktiles * XSTAGE;
+    const uint32_t loff = (uint32_t)lane * 16u;
     auto dma = [&](int64_t kt, uint4* sa, uint4* sb) {
 #pragma unroll
         for (int e = 0; e < PIECES; ++e) {
             const int piece = wid + XWAVES * e;
-            __builtin_amdgcn_global_load_lds(gA + kt * XSTAGE + piece * XPIECE, (lds_void_t*)(sa + piece * 64), 16,
-                                             0, 0);
-            __builtin_amdgcn_global_load_lds(gB + kt * XSTAGE + piece * XPIECE, (lds_void_t*)(sb + piece * 64), 16,
-                                             0, 0);
+            const char* ba = gA + kt * XSTAGE + piece * XPIECE;
+            const char* bb = gB + kt * XSTAGE + piece * XPIECE;
+            __builtin_amdgcn_global_load_lds(ba + loff, (lds_void_t*)(sa + piece * 64), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(bb + loff, (lds_void_t*)(sb + piece * 64), 16, 0, 0);
         }
     };
 
@@ -221,11 +305,11 @@ __global__ __launch_bounds__(256) void k_x3(X3Args a) {
         return __builtin_bit_cast(bf8, v);
     };
 
-    f4 big[4][4], small[4][4];
-    double sum[4][4][4];
-    float comp[4][4][4];
+    f4 big[FN][4], small[FN][4];
+    double sum[FN][4][4];
+    float comp[FN][4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FN; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             big[i][j] = f4{0, 0, 0, 0};
@@ -237,47 +321,47 @@ __global__ __launch_bounds__(256) void k_x3(X3Args a) {
             }
         }
 
-    // The six products in an order that keeps few fragments live: B term 1
-    // stays, B terms 2 and 3 live only while they are used.  The MFMA row
-    // operand is the B side (n), so a lane holds D[n = 4*(lane/16) + q][m = lane % 16].
-    auto mma = [&](f4 (&acc)[4][4], const bf8 (&fb)[4], const bf8 (&fa)[4]) {
+    // The MFMA row operand is the B side (n), so a lane holds
+    // D[n = 4*(lane/16) + q][m = lane % 16].
+    auto mma = [&](f4 (&acc)[FN][4], const bf8 (&fb)[FN], const bf8 (&fa)[4]) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FN; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[i], fa[j], acc[i][j], 0, 0, 0);
     };
-    auto load_b = [&](const uint4* sb, int t, bf8 (&fb)[4]) {
+    auto load_b = [&](const uint4* sb, int t, bf8 (&fb)[FN]) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) fb[i] = frag(sb, t, wn * 64 + i * 16 + r16);
+        for (int i = 0; i < FN; ++i) fb[i] = frag(sb, t, wn * (16 * FN) + i * 16 + r16);
     };
     auto load_a = [&](const uint4* sa, int t, bf8 (&fa)[4]) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) fa[j] = frag(sa, t, wm * 64 + j * 16 + r16);
     };
+    // Each group's fragments are requested before the previous group's MFMAs
+    // are issued, so the LDS latency runs under matrix work; sched_barrier(0)
+    // holds this order (the scheduler would otherwise hoist every read of the
+    // step and run out of registers).  Peak live fragments: 48 VGPRs.
     auto compute = [&](const uint4* sa, const uint4* sb) {
-        // sched_barrier(0) keeps each group in place: the scheduler would
-        // otherwise hoist all fragment reads of the step and run out of
-        // registers
-        bf8 b1[4], bx[4], fa[4];
+        bf8 b1[FN], b2[FN], b3[FN], a1[4], a2[4], a3[4];
         load_b(sb, 0, b1);
-        load_a(sa, 0, fa);
-        load_b(sb, 2, bx);
+        load_a(sa, 0, a1);
+        load_b(sb, 2, b3);
         __builtin_amdgcn_sched_barrier(0);
-        mma(big, b1, fa);      // t_A1 t_B1
-        mma(small, bx, fa);    // t_A1 t_B3
+        load_b(sb, 1, b2);
         __builtin_amdgcn_sched_barrier(0);
-        load_b(sb, 1, bx);
+        mma(big, b1, a1);      // t_A1 t_B1
+        mma(small, b3, a1);    // t_A1 t_B3
         __builtin_amdgcn_sched_barrier(0);
-        mma(small, bx, fa);    // t_A1 t_B2
+        load_a(sa, 1, a2);
         __builtin_amdgcn_sched_barrier(0);
-        load_a(sa, 1, fa);
+        mma(small, b2, a1);    // t_A1 t_B2
         __builtin_amdgcn_sched_barrier(0);
-        mma(small, b1, fa);    // t_A2 t_B1
-        mma(small, bx, fa);    // t_A2 t_B2
+        load_a(sa, 2, a3);
         __builtin_amdgcn_sched_barrier(0);
-        load_a(sa, 2, fa);
+        mma(small, b1, a2);    // t_A2 t_B1
+        mma(small, b2, a2);    // t_A2 t_B2
         __builtin_amdgcn_sched_barrier(0);
-        mma(small, b1, fa);    // t_A3 t_B1
+        mma(small, b1, a3);    // t_A3 t_B1
         __builtin_amdgcn_sched_barrier(0);
     };
     // chunk partial of the leading product into the running sum, with
@@ -285,7 +369,7 @@ __global__ __launch_bounds__(256) void k_x3(X3Args a) {
     // rounding errors of FP64 adds, far below the sum)
     auto fold = [&]() {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FN; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -298,40 +382,45 @@ __global__ __launch_bounds__(256) void k_x3(X3Args a) {
                     big[i][j][q] = 0.f;
                 }
     };
-    // stage kt sits in (sa, sb); stage kt + 2 goes into (na, nb), the buffers
-    // every wave finished reading in the previous step
+    // Stage kt sits in (sa, sb); stage kt + 2 goes into (na, nb), the buffers
+    // every wave finished reading in the previous step.  ktiles is a multiple
+    // of three (the host pads K) and every step issues its DMA -- past the end
+    // it reloads the last stage into a buffer nobody reads again -- so each
+    // wait sees the same two stages in flight and every step names its buffers
+    // statically; the compiler can then leave the younger stages in flight.
     auto step = [&](int64_t kt, const uint4* sa, const uint4* sb, uint4* na, uint4* nb) {
-        if (kt + 1 < ktiles) __builtin_amdgcn_s_waitcnt(wait_vm(2 * PIECES));   // stage kt landed
-        else __builtin_amdgcn_s_waitcnt(wait_vm(0));
-        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);   // this wave's reads of the previous stage are done
+        __builtin_amdgcn_s_waitcnt(wait_vm(2 * PIECES));   // stage kt landed (kt + 1 may be in flight)
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);            // this wave's reads of the previous stage are done
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_barrier();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        if (kt + 2 < ktiles) dma(kt + 2, na, nb);
+        dma(kt + 2 < ktiles ? kt + 2 : ktiles - 1, na, nb);
         compute(sa, sb);
     };
-    if (ktiles > 0) dma(0, sA0, sB0);
-    if (ktiles > 1) dma(1, sA1, sB1);
-    // chunks start at multiples of three stages, so stage kt always sits in
-    // buffer kt % 3 and every step names its buffers statically
+    if (ktiles > 0) {
+        dma(0, sA0, sB0);
+        dma(ktiles > 1 ? 1 : 0, sA1, sB1);
+    }
     for (int64_t c0 = 0; c0 < ktiles; c0 += SPLIT_CHUNK_TILES) {
 #pragma unroll 1
         for (int u = 0; u < SPLIT_CHUNK_TILES; u += 3) {
             const int64_t kt = c0 + u;
-            if (kt < ktiles) step(kt, sA0, sB0, sA2, sB2);
-            if (kt + 1 < ktiles) step(kt + 1, sA1, sB1, sA0, sB0);
-            if (kt + 2 < ktiles) step(kt + 2, sA2, sB2, sA1, sB1);
+            if (kt >= ktiles) break;
+            step(kt, sA0, sB0, sA2, sB2);
+            step(kt + 1, sA1, sB1, sA0, sB0);
+            step(kt + 2, sA2, sB2, sA1, sB1);
         }
         fold();
     }
+    __builtin_amdgcn_s_waitcnt(wait_vm(0));   // the trailing reloads land before the block exits
 
     T* C = (T*)a.C;
     const T beta = (T)a.beta;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FN; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int nl = wn * 64 + i * 16 + 4 * (lane >> 4) + q;
+            const int nl = wn * (16 * FN) + i * 16 + 4 * (lane >> 4) + q;
             const int64_t cn = sCn[nl];
             if (cn < 0) continue;
 #pragma unroll
@@ -350,8 +439,9 @@ __global__ __launch_bounds__(256) void k_x3(X3Args a) {
 }
 
 // ---------------------------------------------------------------------------
-// Workspace layout inside p->d_split: ktab | terms A | terms B | exps A | exps B
-enum { L_KTAB = 0, L_TA, L_TB, L_EA, L_EB, L_KP, L_RA, L_RB };
+// Workspace layout inside p->d_split: K offsets of A | of B | terms A | terms B |
+// exps A | exps B
+enum { L_KOA = 0, L_KOB, L_TA, L_TB, L_EA, L_EB, L_KP, L_RA, L_RB, L_KT };
 
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -360,16 +450,25 @@ tc_status prepare_split(tc_plan_s* p) {
     if (p->spec.compute == TC_FP8X3) return fail(TC_E_UNSUPPORTED, "FP8 split terms are not built on the GPU");
     const GemmView& gv = p->gv;
     std::vector<int64_t> tab = build_ktab(gv.k, SPLIT_BK);
-    int64_t Kp = (int64_t)tab.size() / 2;
+    // padded to a whole number of three-stage turns of the product kernel's
+    // buffer rotation; the padding positions (-1) hold zero terms
+    const int64_t Kt = (int64_t)tab.size() / 2;
+    const int64_t Kp = round_up(Kt, 3 * SPLIT_BK);
+    std::vector<int64_t> ko[2] = {std::vector<int64_t>(Kp, -1), std::vector<int64_t>(Kp, -1)};
+    for (int64_t k = 0; k < Kt; ++k) {
+        ko[0][k] = tab[2 * k];
+        ko[1][k] = tab[2 * k + 1];
+    }
     int64_t RA = round_up(std::max<int64_t>(1, gv.M), XR), RB = round_up(std::max<int64_t>(1, gv.N), XR);
     int64_t off = 0;
     int64_t* L = p->split_layout;
-    L[L_KTAB] = off; off += round_up((int64_t)tab.size() * 8, 256);
+    L[L_KOA] = off;  off += round_up(Kp * 8, 256);
+    L[L_KOB] = off;  off += round_up(Kp * 8, 256);
     L[L_TA] = off;   off += round_up(3 * RA * Kp * 2, 256);
     L[L_TB] = off;   off += round_up(3 * RB * Kp * 2, 256);
     L[L_EA] = off;   off += round_up(RA * 4, 256);
     L[L_EB] = off;   off += round_up(RB * 4, 256);
-    L[L_KP] = Kp; L[L_RA] = RA; L[L_RB] = RB;
+    L[L_KP] = Kp; L[L_RA] = RA; L[L_RB] = RB; L[L_KT] = Kt;
     hipError_t e = hipMalloc(&p->d_split, (size_t)std::max<int64_t>(off, 256));
     if (e != hipSuccess) {
         p->d_split = nullptr;
@@ -378,8 +477,9 @@ tc_status prepare_split(tc_plan_s* p) {
     p->split_bytes = off;
     // zero everything once: padded rows of the stage images stay zero
     e = hipMemset(p->d_split, 0, (size_t)off);
-    if (e == hipSuccess && !tab.empty())
-        e = hipMemcpy((char*)p->d_split + L[L_KTAB], tab.data(), tab.size() * 8, hipMemcpyHostToDevice);
+    for (int side = 0; side < 2 && e == hipSuccess && Kp > 0; ++side)
+        e = hipMemcpy((char*)p->d_split + L[side == 0 ? L_KOA : L_KOB], ko[side].data(), (size_t)(Kp * 8),
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "split workspace set-up");
     return TC_OK;
 }
@@ -395,7 +495,6 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
     uint16_t* tB = (uint16_t*)(w + L[L_TB]);
     int32_t* eA = (int32_t*)(w + L[L_EA]);
     int32_t* eB = (int32_t*)(w + L[L_EB]);
-    const int64_t* ktab = (const int64_t*)(w + L[L_KTAB]);
     hipError_t e;
     for (int side = 0; side < 2; ++side) {
         SplitArgs s{};
@@ -404,14 +503,27 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
         s.rows.n = (int)g.size();
         for (int d = 0; d < s.rows.n; ++d) s.rows.d[d] = g[d];
         s.slot = side;
-        s.ktab = ktab;
+        s.koff = (const int64_t*)(w + L[side == 0 ? L_KOA : L_KOB]);
         s.nrows = side == 0 ? gv.M : gv.N;
         s.Kp = Kp;
+        s.Kt = L[L_KT];
         s.panels = side == 0 ? tA : tB;
         s.exps = side == 0 ? eA : eB;
-        if (s.nrows <= 0) continue;
-        if (f64) hipLaunchKernelGGL(k_split<double>, dim3((unsigned)s.nrows), dim3(256), 0, st, s);
-        else hipLaunchKernelGGL(k_split<float>, dim3((unsigned)s.nrows), dim3(256), 0, st, s);
+        if (s.nrows <= 0 || L[L_KT] == 0) continue;   // no K: the exponents stay 0, the terms empty
+        if (s.nrows > 0x7fffffff) return fail(TC_E_EXTENT, "too many slices for one launch");
+        const dim3 grid((unsigned)s.nrows), blk(256);
+        const int64_t nch = s.Kt / 8;   // chunks of eight positions (Kt is a multiple of 32)
+        if (f64) {
+            if (nch <= 256) hipLaunchKernelGGL((k_split<double, 1>), grid, blk, 0, st, s);
+            else if (nch <= 512) hipLaunchKernelGGL((k_split<double, 2>), grid, blk, 0, st, s);
+            else if (nch <= 1024) hipLaunchKernelGGL((k_split<double, 4>), grid, blk, 0, st, s);
+            else hipLaunchKernelGGL(k_split_long<double>, grid, blk, 0, st, s);
+        } else {
+            if (nch <= 256) hipLaunchKernelGGL((k_split<float, 1>), grid, blk, 0, st, s);
+            else if (nch <= 512) hipLaunchKernelGGL((k_split<float, 2>), grid, blk, 0, st, s);
+            else if (nch <= 1024) hipLaunchKernelGGL((k_split<float, 4>), grid, blk, 0, st, s);
+            else hipLaunchKernelGGL(k_split_long<float>, grid, blk, 0, st, s);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "split kernel launch");
     }
@@ -428,8 +540,8 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
     x.ntiles = x.mt * x.nt;
     x.alpha = alpha; x.beta = beta;
     if (x.ntiles > 0x7fffffff) return fail(TC_E_EXTENT, "too many output tiles for one launch");
-    if (f64) hipLaunchKernelGGL(k_x3<double>, dim3((unsigned)x.ntiles), dim3(256), 0, st, x);
-    else hipLaunchKernelGGL(k_x3<float>, dim3((unsigned)x.ntiles), dim3(256), 0, st, x);
+    if (f64) hipLaunchKernelGGL(k_x3<double>, dim3((unsigned)x.ntiles), dim3(64 * XWAVES), 0, st, x);
+    else hipLaunchKernelGGL(k_x3<float>, dim3((unsigned)x.ntiles), dim3(64 * XWAVES), 0, st, x);
     e = hipGetLastError();
     return e == hipSuccess ? TC_OK : hip_fail(e, "split product kernel launch");
 }

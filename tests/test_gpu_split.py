@@ -73,6 +73,27 @@ def test_split_terms_bit_exact_and_result(spec, ext):
             np.testing.assert_array_equal(d, o)
 
 
+@pytest.mark.parametrize("K", [6000, 9000])
+def test_split_long_contraction(K):
+    """Long contracted extents: 4096 < K <= 8192 keeps each slice in
+    registers (four chunks per thread); K > 8192 takes the two-pass form.
+    Per-slice scales over six decades; the device's exponents equal the
+    oracle's, and the result is within the FP32-accumulation bound of the
+    exactly accumulated split oracle."""
+    spec, ext = "ab=ai,ib", dict(a=40, b=70, i=K)
+    rng = np.random.default_rng(K)
+    A = np.array(rng.standard_normal((40, K)) * np.exp(rng.uniform(np.log(1e-3), np.log(1e3), (40, 1))), order="F")
+    B = np.array(rng.standard_normal((K, 70)), order="F")
+    p = tc.Plan(spec, ext, "f64", compute="bf16x3")
+    got = run(p, A, B)
+    ref_split = sp.contract_split(spec, ext, A, B)
+    absAB = oracle.contract(spec, ext, np.abs(A), np.abs(B))
+    assert np.all(np.abs(got - ref_split) <= split_bound(K) * absAB)
+    assert oracle.normwise_rel_err(got, oracle.contract(spec, ext, A, B)) <= 1e-5
+    _, eA = tc.tc_split_terms(p.handle, 0)
+    np.testing.assert_array_equal(eA, np.asarray(sp.slice_exponents(A, "ai", "a")).ravel(order="F"))
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_scaled_matrix_accuracy(dtype):
     """The precision workload's shape at reduced size: slices scaled over six
