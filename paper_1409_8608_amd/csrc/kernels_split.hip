@@ -12,13 +12,11 @@
 //    each row permuted by xswz so that fragment reads hit distinct banks.
 // 2. k_x3: C tile = sum over the six term products t_A,p t_B,q with p+q <= 4.
 //    Stages are copied HBM -> LDS by the DMA form of the global load (no
-//    registers in between), three stages in flight.  The leading product
-//    t_A1 t_B1 accumulates in FP32 over K chunks of SPLIT_CHUNK and each chunk
-//    partial is added into an FP64 running sum with Neumaier compensation.
-//    The five small products (each at least 2^-7 below the leading one)
-//    accumulate in one FP32 accumulator over all of K: their rounding stays
-//    below the leading product's chunk error for K up to 2^15.  Epilogue:
-//    C = alpha * 2^(eA + eB) * (sum + comp + small) + beta * C.
+//    registers in between), double-buffered.  The leading product t_A1 t_B1
+//    and the five small products accumulate in two FP32 accumulators over all
+//    of K (FP32 accumulation, as an FP32 matrix product would); the epilogue
+//    adds the two partials in FP64, which is exact, and unscales:
+//    C = alpha * 2^(eA + eB) * (big + small) + beta * C.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,20 +33,15 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int SPLIT_BK = 32;      // contracted positions per stage (one 16x16x32 MFMA step)
-// FP32 accumulation length of the leading product before it is folded into
-// the FP64 sum: nine K stages, a whole number of turns of the three-stage
-// buffer rotation
-constexpr int SPLIT_CHUNK_TILES = 9;
-constexpr int SPLIT_CHUNK = SPLIT_CHUNK_TILES * 32;
-constexpr int XR = 128;           // rows per panel tile = block tile edge in m and in n
-constexpr int XSTAGE = 3 * XR * SPLIT_BK * 2;   // bytes of one operand stage image (24 KB)
+constexpr int XR = 128;           // rows per stage image (panel row tile)
+constexpr int XSTAGE = 3 * XR * SPLIT_BK * 2;   // bytes of one stage image (24 KB)
 constexpr int XPIECE = 1024;      // bytes one wave copies per DMA instruction (64 lanes x 16 B)
-// Waves per block along n (two along m): 2 gives four waves of 64 x 64, one
-// per SIMD; 4 gives eight waves of 64 x 32, two per SIMD.  Measured on MI355X
-// at 4096^2 x 4096: eight waves take 8% less time (the second wave on a SIMD
-// covers the first one's fragment-load and barrier waits), at 238 VGPRs.
-constexpr int XWN = 4;
-constexpr int XWAVES = 2 * XWN;
+// Product tile: 256 (m) x 128 (n) per block of eight waves, two per SIMD, each
+// wave 64 x 64.  Measured on MI355X at 4096^2 x 4096 against 128 x 128 tiles
+// with eight 64 x 32 waves: a quarter fewer staged bytes and a third fewer
+// fragment reads per flop.
+constexpr int XBM = 2 * XR, XBN = XR;
+constexpr int XWAVES = 8;
 
 // Physical 16-byte chunk of logical chunk c (k = 8c .. 8c+7) of row r inside a
 // stage image.  Rows are 64 bytes, so the 16 rows one fragment read touches
@@ -238,43 +231,43 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 constexpr int wait_vm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 constexpr int kWaitLgkm0 = 15 | (3 << 14) | (7 << 4);
 
-// One block = 2 x XWN waves on a 128 (m) x 128 (n) tile; wave (wm, wn) owns
-// 64 m x 16*FN n, four by FN blocks of 16 x 16.  A stage (32 K positions of
-// all three terms of both operands, 48 KB) arrives in LDS by DMA, three stages
-// in flight; each wave copies 24 / XWAVES pieces of 1 KB of each operand per
-// stage.  Work per stage and wave: 24 FN MFMAs (6 products x 4 FN blocks)
-// against 12 + 6 FN fragment reads of 16 bytes per lane.
+// One block = eight waves on a 256 (m) x 128 (n) tile; wave (wm, wn) owns
+// 64 m x 64 n, four by four blocks of 16 x 16.  A stage (32 K positions of all
+// three terms: two stage images of A, one of B, 72 KB) arrives in LDS by DMA
+// while the previous stage is multiplied; each wave copies six 1 KB pieces of
+// A and three of B per stage.  Work per stage and wave: 96 MFMAs against 24
+// fragment reads of 16 bytes per lane.
 template <typename T>
 __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
-    constexpr int NV = XSTAGE / 16;               // uint4 per stage image
-    constexpr int PIECES = XSTAGE / XPIECE / XWAVES;   // DMA pieces per wave per operand
-    constexpr int FN = XR / XWN / 16;                  // n-blocks of 16 per wave
-    constexpr int NT = 64 * XWAVES;                    // threads
-    // One array per stage buffer: the compiler then knows which stage a DMA
-    // writes and which one a fragment read reads, and leaves the younger
-    // stages in flight.
-    __shared__ uint4 sA0[NV], sA1[NV], sA2[NV], sB0[NV], sB1[NV], sB2[NV];
-    __shared__ int64_t sCm[XR], sCn[XR];
-    __shared__ int32_t sEm[XR], sEn[XR];
+    constexpr int NVA = 2 * XSTAGE / 16, NVB = XSTAGE / 16;   // uint4 per A / B stage
+    constexpr int PA = 2 * XSTAGE / XPIECE / XWAVES;          // DMA pieces per wave: 6 of A
+    constexpr int PB = XSTAGE / XPIECE / XWAVES;              // and 3 of B
+    constexpr int NT = 64 * XWAVES;
+    static_assert(PB * XWAVES * XPIECE == XSTAGE && PA == 2 * PB, "stage pieces");
+    // One array per buffer: every DMA and every fragment read names its
+    // buffer statically.
+    __shared__ uint4 sA0[NVA], sA1[NVA], sB0[NVB], sB1[NVB];
+    __shared__ int64_t sCm[XBM], sCn[XBN];
+    __shared__ int32_t sEm[XBM], sEn[XBN];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar DMA bases
-    const int wm = wid & 1, wn = wid >> 1;   // wave tile 64 (m) x 16*FN (n)
+    const int wm = wid & 3, wn = wid >> 2;
     // tile order: contiguous per XCD, then groups of eight m-tiles sweeping n,
-    // so the blocks resident on one XCD share A and B stage images in its L2
+    // so the blocks resident on one XCD share stage images in its L2
     const int64_t L = xcd_tile3(blockIdx.x, a.ntiles);
     constexpr int64_t GM = 8;
     const int64_t g = L / (GM * a.nt), first = g * GM;
     const int64_t gm = a.mt - first < GM ? a.mt - first : GM;
     const int64_t r = L - g * GM * a.nt;
     const int64_t mt = first + r % gm, nt = r / gm;
-    const int64_t m_base = mt * XR, n_base = nt * XR;
-    for (int i = tid; i < XR; i += NT) {
+    const int64_t m_base = mt * XBM, n_base = nt * XBN;
+    for (int i = tid; i < XBM; i += NT) {
         const int64_t m = m_base + i;
         sCm[i] = m < a.M ? grp_off(a.m, m, 2) : -1;
         sEm[i] = m < a.M ? a.eA[m] : 0;
     }
-    for (int i = tid; i < XR; i += NT) {
+    for (int i = tid; i < XBN; i += NT) {
         const int64_t n = n_base + i;
         sCn[i] = n < a.N ? grp_off(a.n, n, 2) : -1;
         sEn[i] = n < a.N ? a.eB[n] : 0;
@@ -282,19 +275,23 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
     __syncthreads();
 
     const int64_t ktiles = a.Kp / SPLIT_BK;
-    // wave-uniform stage bases plus a 32-bit lane offset: the scalar-base form
-    // of the DMA load, with no per-lane 64-bit address arithmetic
-    const char* gA = (const char*)a.tA + mt * ktiles * XSTAGE;
+    // A's stage kt: the images of row tiles 2 mt and 2 mt + 1; B's: row tile nt
+    const char* gA = (const char*)a.tA + 2 * mt * ktiles * XSTAGE;
     const char* gB = (const char*)a.tB + nt * ktiles * XSTAGE;
     const uint32_t loff = (uint32_t)lane * 16u;
     auto dma = [&](int64_t kt, uint4* sa, uint4* sb) {
 #pragma unroll
-        for (int e = 0; e < PIECES; ++e) {
-            const int piece = wid + XWAVES * e;
-            const char* ba = gA + kt * XSTAGE + piece * XPIECE;
-            const char* bb = gB + kt * XSTAGE + piece * XPIECE;
-            __builtin_amdgcn_global_load_lds(ba + loff, (lds_void_t*)(sa + piece * 64), 16, 0, 0);
-            __builtin_amdgcn_global_load_lds(bb + loff, (lds_void_t*)(sb + piece * 64), 16, 0, 0);
+        for (int e = 0; e < PA; ++e) {
+            const int piece = wid + XWAVES * e;                     // 0 .. 47
+            const int img = e < PA / 2 ? 0 : 1;                     // pieces 0-23: row tile 2 mt
+            const char* src = gA + (img * ktiles + kt) * XSTAGE + (piece - img * (XSTAGE / XPIECE)) * XPIECE;
+            __builtin_amdgcn_global_load_lds(src + loff, (lds_void_t*)(sa + piece * 64), 16, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < PB; ++e) {
+            const int piece = wid + XWAVES * e;                     // 0 .. 23
+            __builtin_amdgcn_global_load_lds(gB + kt * XSTAGE + piece * XPIECE + loff,
+                                             (lds_void_t*)(sb + piece * 64), 16, 0, 0);
         }
     };
 
@@ -304,45 +301,40 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
         const uint4 v = st[(term * XR + row) * 4 + xswz(row, ch)];
         return __builtin_bit_cast(bf8, v);
     };
+    // this wave's m rows lie in image wm / 2 of the A stage
+    const int aimg = (wm >> 1) * (NVA / 2), arow = (wm & 1) * 64;
 
-    f4 big[FN][4], small[FN][4];
-    double sum[FN][4][4];
-    float comp[FN][4][4];
+    f4 big[4][4], small[4][4];
 #pragma unroll
-    for (int i = 0; i < FN; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             big[i][j] = f4{0, 0, 0, 0};
             small[i][j] = f4{0, 0, 0, 0};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                sum[i][j][q] = 0.0;
-                comp[i][j][q] = 0.f;
-            }
         }
 
     // The MFMA row operand is the B side (n), so a lane holds
     // D[n = 4*(lane/16) + q][m = lane % 16].
-    auto mma = [&](f4 (&acc)[FN][4], const bf8 (&fb)[FN], const bf8 (&fa)[4]) {
+    auto mma = [&](f4 (&acc)[4][4], const bf8 (&fb)[4], const bf8 (&fa)[4]) {
 #pragma unroll
-        for (int i = 0; i < FN; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[i], fa[j], acc[i][j], 0, 0, 0);
     };
-    auto load_b = [&](const uint4* sb, int t, bf8 (&fb)[FN]) {
+    auto load_b = [&](const uint4* sb, int t, bf8 (&fb)[4]) {
 #pragma unroll
-        for (int i = 0; i < FN; ++i) fb[i] = frag(sb, t, wn * (16 * FN) + i * 16 + r16);
+        for (int i = 0; i < 4; ++i) fb[i] = frag(sb, t, wn * 64 + i * 16 + r16);
     };
     auto load_a = [&](const uint4* sa, int t, bf8 (&fa)[4]) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) fa[j] = frag(sa, t, wm * 64 + j * 16 + r16);
+        for (int j = 0; j < 4; ++j) fa[j] = frag(sa + aimg, t, arow + j * 16 + r16);
     };
     // Each group's fragments are requested before the previous group's MFMAs
     // are issued, so the LDS latency runs under matrix work; sched_barrier(0)
     // holds this order (the scheduler would otherwise hoist every read of the
-    // step and run out of registers).  Peak live fragments: 48 VGPRs.
+    // step and run out of registers).
     auto compute = [&](const uint4* sa, const uint4* sb) {
-        bf8 b1[FN], b2[FN], b3[FN], a1[4], a2[4], a3[4];
+        bf8 b1[4], b2[4], b3[4], a1[4], a2[4], a3[4];
         load_b(sb, 0, b1);
         load_a(sa, 0, a1);
         load_b(sb, 2, b3);
@@ -364,63 +356,34 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
         mma(small, b1, a3);    // t_A3 t_B1
         __builtin_amdgcn_sched_barrier(0);
     };
-    // chunk partial of the leading product into the running sum, with
-    // Neumaier compensation; the correction is kept in FP32 (it collects
-    // rounding errors of FP64 adds, far below the sum)
-    auto fold = [&]() {
-#pragma unroll
-        for (int i = 0; i < FN; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const double x = (double)big[i][j][q];
-                    const double s0 = sum[i][j][q], t = s0 + x;
-                    const double err = fabs(s0) >= fabs(x) ? (s0 - t) + x : (x - t) + s0;
-                    comp[i][j][q] += (float)err;
-                    sum[i][j][q] = t;
-                    big[i][j][q] = 0.f;
-                }
-    };
-    // Stage kt sits in (sa, sb); stage kt + 2 goes into (na, nb), the buffers
-    // every wave finished reading in the previous step.  ktiles is a multiple
-    // of three (the host pads K) and every step issues its DMA -- past the end
-    // it reloads the last stage into a buffer nobody reads again -- so each
-    // wait sees the same two stages in flight and every step names its buffers
-    // statically; the compiler can then leave the younger stages in flight.
+    // Stage kt sits in (sa, sb); stage kt + 1 goes into (na, nb), which every
+    // wave finished reading in the previous step.  ktiles is even (the host
+    // pads K) and every step issues its DMA -- past the end it reloads the
+    // last stage into the buffer nobody reads again -- so the loop body has no
+    // conditional DMA and names every buffer statically.
     auto step = [&](int64_t kt, const uint4* sa, const uint4* sb, uint4* na, uint4* nb) {
-        __builtin_amdgcn_s_waitcnt(wait_vm(2 * PIECES));   // stage kt landed (kt + 1 may be in flight)
-        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);            // this wave's reads of the previous stage are done
+        __builtin_amdgcn_s_waitcnt(wait_vm(0));    // stage kt landed
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);    // this wave's reads of the previous stage are done
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_barrier();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        dma(kt + 2 < ktiles ? kt + 2 : ktiles - 1, na, nb);
+        dma(kt + 1 < ktiles ? kt + 1 : ktiles - 1, na, nb);
         compute(sa, sb);
     };
-    if (ktiles > 0) {
-        dma(0, sA0, sB0);
-        dma(ktiles > 1 ? 1 : 0, sA1, sB1);
+    if (ktiles > 0) dma(0, sA0, sB0);
+    for (int64_t kt = 0; kt < ktiles; kt += 2) {
+        step(kt, sA0, sB0, sA1, sB1);
+        step(kt + 1, sA1, sB1, sA0, sB0);
     }
-    for (int64_t c0 = 0; c0 < ktiles; c0 += SPLIT_CHUNK_TILES) {
-#pragma unroll 1
-        for (int u = 0; u < SPLIT_CHUNK_TILES; u += 3) {
-            const int64_t kt = c0 + u;
-            if (kt >= ktiles) break;
-            step(kt, sA0, sB0, sA2, sB2);
-            step(kt + 1, sA1, sB1, sA0, sB0);
-            step(kt + 2, sA2, sB2, sA1, sB1);
-        }
-        fold();
-    }
-    __builtin_amdgcn_s_waitcnt(wait_vm(0));   // the trailing reloads land before the block exits
+    __builtin_amdgcn_s_waitcnt(wait_vm(0));   // the trailing reload lands before the block exits
 
     T* C = (T*)a.C;
     const T beta = (T)a.beta;
 #pragma unroll
-    for (int i = 0; i < FN; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int nl = wn * (16 * FN) + i * 16 + 4 * (lane >> 4) + q;
+            const int nl = wn * 64 + i * 16 + 4 * (lane >> 4) + q;
             const int64_t cn = sCn[nl];
             if (cn < 0) continue;
 #pragma unroll
@@ -428,8 +391,8 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
                 const int ml = wm * 64 + j * 16 + (lane & 15);
                 const int64_t cm = sCm[ml];
                 if (cm < 0) continue;
-                const double v = a.alpha * ldexp(sum[i][j][q] + ((double)comp[i][j][q] + (double)small[i][j][q]),
-                                                 sEm[ml] + sEn[nl]);
+                // the two FP32 partials add exactly in FP64
+                const double v = a.alpha * ldexp((double)big[i][j][q] + (double)small[i][j][q], sEm[ml] + sEn[nl]);
                 T* cp = C + cn + cm;
                 T out = (T)v;
                 if (a.beta != 0.0) out += beta * (*cp);
@@ -450,16 +413,16 @@ tc_status prepare_split(tc_plan_s* p) {
     if (p->spec.compute == TC_FP8X3) return fail(TC_E_UNSUPPORTED, "FP8 split terms are not built on the GPU");
     const GemmView& gv = p->gv;
     std::vector<int64_t> tab = build_ktab(gv.k, SPLIT_BK);
-    // padded to a whole number of three-stage turns of the product kernel's
+    // padded to a whole number of two-stage turns of the product kernel's
     // buffer rotation; the padding positions (-1) hold zero terms
     const int64_t Kt = (int64_t)tab.size() / 2;
-    const int64_t Kp = round_up(Kt, 3 * SPLIT_BK);
+    const int64_t Kp = round_up(Kt, 2 * SPLIT_BK);
     std::vector<int64_t> ko[2] = {std::vector<int64_t>(Kp, -1), std::vector<int64_t>(Kp, -1)};
     for (int64_t k = 0; k < Kt; ++k) {
         ko[0][k] = tab[2 * k];
         ko[1][k] = tab[2 * k + 1];
     }
-    int64_t RA = round_up(std::max<int64_t>(1, gv.M), XR), RB = round_up(std::max<int64_t>(1, gv.N), XR);
+    int64_t RA = round_up(std::max<int64_t>(1, gv.M), XBM), RB = round_up(std::max<int64_t>(1, gv.N), XBN);
     int64_t off = 0;
     int64_t* L = p->split_layout;
     L[L_KOA] = off;  off += round_up(Kp * 8, 256);
@@ -536,7 +499,7 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
     x.n.n = (int)gv.n.size();
     for (int d = 0; d < x.n.n; ++d) x.n.d[d] = gv.n[d];
     x.M = gv.M; x.N = gv.N; x.Kp = Kp;
-    x.mt = RA / XR; x.nt = RB / XR;
+    x.mt = RA / XBM; x.nt = RB / XBN;
     x.ntiles = x.mt * x.nt;
     x.alpha = alpha; x.beta = beta;
     if (x.ntiles > 0x7fffffff) return fail(TC_E_EXTENT, "too many output tiles for one launch");
