@@ -25,12 +25,13 @@ tc_status hip_fail(hipError_t e, const char* what) {
     return fail(TC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// Blocked K order for the matrix-core kernel.  Tiles of BK contracted
-// positions are rectangles over the contracted index that is contiguous in A
-// (dA) and the one contiguous in B (dB), so both operands read runs; tiles are
-// ordered with dB's blocks fastest.  Positions are (offA, offB) pairs; a tile
-// that is not full is padded with (-1, -1) entries (zero contributions).
-std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK) {
+// Blocked K order for the matrix-core kernels.  Tiles of BK contracted
+// positions are rectangles, bA positions along the contracted index that is
+// contiguous in A (dA) by BK / bA along the one contiguous in B (dB), so both
+// operands read runs; tiles are ordered with dB's blocks fastest.  Positions
+// are (offA, offB) pairs; a tile that is not full is padded with (-1, -1)
+// entries (zero contributions).
+std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA) {
     std::vector<int64_t> tab;
     int nd = (int)kd.size();
     int64_t K = 1;
@@ -43,7 +44,7 @@ std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK) {
     }
     std::vector<int64_t> bs(nd, 1);
     if (dA >= 0 && dB >= 0 && dA != dB) {
-        bs[dA] = std::min<int64_t>(kd[dA].ext, 4);
+        bs[dA] = std::min<int64_t>(kd[dA].ext, bA);
         bs[dB] = std::min<int64_t>(kd[dB].ext, BK / bs[dA]);
     } else {
         int d = dA >= 0 ? dA : dB >= 0 ? dB : 0;

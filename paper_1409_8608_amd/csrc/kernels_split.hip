@@ -101,6 +101,14 @@ __host__ __device__ __forceinline__ int64_t panel_off(int64_t row, int64_t k, in
            xswz(rr, kk >> 3) * 8 + (kk & 7);
 }
 
+// Block b runs on XCD b % 8; give each XCD a contiguous range of items.
+__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t total) {
+    const int64_t X = 8;
+    int64_t xcd = b % X, idx = b / X;
+    int64_t per = total / X, rem = total % X;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
 __device__ __forceinline__ uint32_t pack2(double lo, double hi) {
     return (uint32_t)bf16_bits(lo) | ((uint32_t)bf16_bits(hi) << 16);
 }
@@ -109,11 +117,13 @@ __device__ __forceinline__ uint32_t pack2(double lo, double hi) {
 // consecutive K positions (CPT of them): it loads their values once, keeps
 // them in registers through the block-wide max, then writes each chunk's three
 // terms as one 16-byte store per term.
-template <typename T, int CPT>
+template <typename T, int CPT, bool VEC>
 __global__ __launch_bounds__(256) void k_split(SplitArgs a) {
     __shared__ double red[4];
     const T* X = (const T*)a.X;
-    const int64_t row = blockIdx.x;
+    // neighbouring slices on one XCD: their stage-image rows share cache
+    // lines, which then fill in one L2
+    const int64_t row = xcd_item(blockIdx.x, a.nrows);
     const int tid = threadIdx.x;
     const int64_t base = grp_off(a.rows, row, a.slot);
     const int64_t nch = a.Kt / 8;
@@ -124,13 +134,32 @@ __global__ __launch_bounds__(256) void k_split(SplitArgs a) {
         const int64_t ch = tid + 256 * c;
         const bool in = ch < nch;
         const int64_t* ko = a.koff + 8 * (in ? ch : 0);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t o = ko[e];
+        if (VEC) {
+            // the host checked: every chunk is eight consecutive, 16-byte
+            // aligned elements (or eight padding entries)
+            typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
+            constexpr int W = 16 / sizeof(T);
+            const int64_t o = ko[0];
             const bool ok = in && o >= 0;
-            const double x = (double)X[base + (ok ? o : 0)];
-            v[c][e] = ok ? x : 0.0;
-            amax = fmax(amax, fabs(v[c][e]));
+            const v16* p = (const v16*)(X + base + (ok ? o : 0));
+#pragma unroll
+            for (int q = 0; q < 8 / W; ++q) {
+                const v16 t = p[q];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    v[c][q * W + w] = ok ? (double)t[w] : 0.0;
+                    amax = fmax(amax, fabs(v[c][q * W + w]));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t o = ko[e];
+                const bool ok = in && o >= 0;
+                const double x = (double)X[base + (ok ? o : 0)];
+                v[c][e] = ok ? x : 0.0;
+                amax = fmax(amax, fabs(v[c][e]));
+            }
         }
     }
     for (int s = 32; s > 0; s >>= 1) amax = fmax(amax, __shfl_xor(amax, s));
@@ -217,12 +246,6 @@ struct X3Args {
     double alpha, beta;
 };
 
-__device__ __forceinline__ int64_t xcd_tile3(int64_t b, int64_t total) {
-    const int64_t X = 8;
-    int64_t xcd = b % X, idx = b / X;
-    int64_t per = total / X, rem = total % X;
-    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-}
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
@@ -255,7 +278,7 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
     const int wm = wid & 3, wn = wid >> 2;
     // tile order: contiguous per XCD, then groups of eight m-tiles sweeping n,
     // so the blocks resident on one XCD share stage images in its L2
-    const int64_t L = xcd_tile3(blockIdx.x, a.ntiles);
+    const int64_t L = xcd_item(blockIdx.x, a.ntiles);
     constexpr int64_t GM = 8;
     const int64_t g = L / (GM * a.nt), first = g * GM;
     const int64_t gm = a.mt - first < GM ? a.mt - first : GM;
@@ -404,7 +427,7 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
 // ---------------------------------------------------------------------------
 // Workspace layout inside p->d_split: K offsets of A | of B | terms A | terms B |
 // exps A | exps B
-enum { L_KOA = 0, L_KOB, L_TA, L_TB, L_EA, L_EB, L_KP, L_RA, L_RB, L_KT };
+enum { L_KOA = 0, L_KOB, L_TA, L_TB, L_EA, L_EB, L_KP, L_RA, L_RB, L_KT, L_VA, L_VB };
 
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -412,7 +435,10 @@ tc_status prepare_split(tc_plan_s* p) {
     if (p->d_split) return TC_OK;
     if (p->spec.compute == TC_FP8X3) return fail(TC_E_UNSUPPORTED, "FP8 split terms are not built on the GPU");
     const GemmView& gv = p->gv;
-    std::vector<int64_t> tab = build_ktab(gv.k, SPLIT_BK);
+    // 8 x 8 blocks: a k_split thread's chunk of eight positions is a run of
+    // eight along A's contiguous index, and the eight chunks of a block read
+    // eight consecutive elements along B's in every load
+    std::vector<int64_t> tab = build_ktab(gv.k, 2 * SPLIT_BK, 8);
     // padded to a whole number of two-stage turns of the product kernel's
     // buffer rotation; the padding positions (-1) hold zero terms
     const int64_t Kt = (int64_t)tab.size() / 2;
@@ -432,6 +458,25 @@ tc_status prepare_split(tc_plan_s* p) {
     L[L_EA] = off;   off += round_up(RA * 4, 256);
     L[L_EB] = off;   off += round_up(RB * 4, 256);
     L[L_KP] = Kp; L[L_RA] = RA; L[L_RB] = RB; L[L_KT] = Kt;
+    // Chunk-vector reads for a side: every chunk of eight positions is eight
+    // consecutive elements (or eight padding entries), starting at an element
+    // offset that, with every row offset, keeps 16-byte alignment (the operand
+    // pointer's own alignment is checked per call).
+    const int64_t W = 16 / p->spec.elem_bytes();
+    for (int side = 0; side < 2; ++side) {
+        bool vec = Kt > 0;
+        for (int64_t c = 0; vec && c < Kt / 8; ++c) {
+            const int64_t o0 = ko[side][8 * c];
+            for (int e = 1; vec && e < 8; ++e) {
+                const int64_t o = ko[side][8 * c + e];
+                vec = o0 < 0 ? o < 0 : o == o0 + e;
+            }
+            vec = vec && (o0 < 0 || o0 % W == 0);
+        }
+        const std::vector<GtDim>& g = side == 0 ? gv.m : gv.n;
+        for (const GtDim& d : g) vec = vec && (side == 0 ? d.sA : d.sB) % W == 0;
+        L[side == 0 ? L_VA : L_VB] = vec ? 1 : 0;
+    }
     hipError_t e = hipMalloc(&p->d_split, (size_t)std::max<int64_t>(off, 256));
     if (e != hipSuccess) {
         p->d_split = nullptr;
@@ -445,6 +490,24 @@ tc_status prepare_split(tc_plan_s* p) {
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "split workspace set-up");
     return TC_OK;
+}
+
+template <typename T>
+static void launch_split(const SplitArgs& s, int64_t nch, bool vec, dim3 grid, dim3 blk, hipStream_t st) {
+    if (nch > 1024) {
+        hipLaunchKernelGGL(k_split_long<T>, grid, blk, 0, st, s);
+        return;
+    }
+    const int cpt = nch <= 256 ? 1 : nch <= 512 ? 2 : 4;
+    if (vec) {
+        if (cpt == 1) hipLaunchKernelGGL((k_split<T, 1, true>), grid, blk, 0, st, s);
+        else if (cpt == 2) hipLaunchKernelGGL((k_split<T, 2, true>), grid, blk, 0, st, s);
+        else hipLaunchKernelGGL((k_split<T, 4, true>), grid, blk, 0, st, s);
+    } else {
+        if (cpt == 1) hipLaunchKernelGGL((k_split<T, 1, false>), grid, blk, 0, st, s);
+        else if (cpt == 2) hipLaunchKernelGGL((k_split<T, 2, false>), grid, blk, 0, st, s);
+        else hipLaunchKernelGGL((k_split<T, 4, false>), grid, blk, 0, st, s);
+    }
 }
 
 tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
@@ -475,18 +538,10 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
         if (s.nrows <= 0 || L[L_KT] == 0) continue;   // no K: the exponents stay 0, the terms empty
         if (s.nrows > 0x7fffffff) return fail(TC_E_EXTENT, "too many slices for one launch");
         const dim3 grid((unsigned)s.nrows), blk(256);
-        const int64_t nch = s.Kt / 8;   // chunks of eight positions (Kt is a multiple of 32)
-        if (f64) {
-            if (nch <= 256) hipLaunchKernelGGL((k_split<double, 1>), grid, blk, 0, st, s);
-            else if (nch <= 512) hipLaunchKernelGGL((k_split<double, 2>), grid, blk, 0, st, s);
-            else if (nch <= 1024) hipLaunchKernelGGL((k_split<double, 4>), grid, blk, 0, st, s);
-            else hipLaunchKernelGGL(k_split_long<double>, grid, blk, 0, st, s);
-        } else {
-            if (nch <= 256) hipLaunchKernelGGL((k_split<float, 1>), grid, blk, 0, st, s);
-            else if (nch <= 512) hipLaunchKernelGGL((k_split<float, 2>), grid, blk, 0, st, s);
-            else if (nch <= 1024) hipLaunchKernelGGL((k_split<float, 4>), grid, blk, 0, st, s);
-            else hipLaunchKernelGGL(k_split_long<float>, grid, blk, 0, st, s);
-        }
+        const int64_t nch = s.Kt / 8;   // chunks of eight positions (Kt is a multiple of 64)
+        const bool vec = L[side == 0 ? L_VA : L_VB] != 0 && ((uintptr_t)s.X) % 16 == 0;
+        if (f64) launch_split<double>(s, nch, vec, grid, blk, st);
+        else launch_split<float>(s, nch, vec, grid, blk, st);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "split kernel launch");
     }

@@ -57,7 +57,7 @@ extern thread_local std::string g_last_error;
 tc_status fail(tc_status s, const std::string& msg);
 tc_status hip_fail(hipError_t e, const char* what);
 
-std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK);
+std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA = 4);
 bool use_stream_kernel(const Spec& s, const GemmView& gv);
 tc_status prepare_plan(tc_plan_s* p);
 tc_status contract_dispatch(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
