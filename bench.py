@@ -247,13 +247,18 @@ def precision(args, torch, tc, wl):
     dA = tc.to_device_fortran(w["A"], torch.float64)
     dB = tc.to_device_fortran(w["B"], torch.float64)
     base_ms = None
-    for name, compute, peak, unit_peak in (("fp64", "native", FP64_PEAK_TFS, "fp64"),
-                                           ("bf16x3", "bf16x3", BF16_PEAK_TFS, "bf16")):
-        plan = tc.Plan(w["spec"], w["ext"], "f64", compute=compute)
+    # FP64 plain, FP32 plain (FP32-rounded inputs, FP32 matrix cores), and the
+    # split-BF16 form on the FP64 inputs; errors against the FP64 oracle
+    for name, dtype, compute, peak in (("fp64", "f64", "native", FP64_PEAK_TFS),
+                                       ("fp32", "f32", "native", FP32_PEAK_TFS),
+                                       ("bf16x3", "f64", "bf16x3", BF16_PEAK_TFS)):
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        xA, xB = (dA, dB) if dtype == "f64" else (dA.to(tdt), dB.to(tdt))
+        plan = tc.Plan(w["spec"], w["ext"], dtype, compute=compute)
         plan.prepare()
-        dC = tc.empty_fortran(plan.shape("C"), torch.float64)
-        ms, _ = _events_time(lambda: plan.contract(dA, dB, dC), 5, 1, torch)
-        got = dC[torch.as_tensor(rows, device="cuda")][:, torch.as_tensor(cols, device="cuda")].cpu().numpy()
+        dC = tc.empty_fortran(plan.shape("C"), tdt)
+        ms, _ = _events_time(lambda: plan.contract(xA, xB, dC), 5, 1, torch)
+        got = dC[torch.as_tensor(rows, device="cuda")][:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
         err = oracle.normwise_rel_err(got, ref)
         tfs = fl / (ms * 1e-3) / 1e12
         executed = fl * (6 if compute == "bf16x3" else 1)
@@ -268,6 +273,8 @@ def precision(args, torch, tc, wl):
             rec["speedup_vs_fp64"] = round(base_ms / ms, 3)
         res[f"precision_{name}"] = rec
         del dC
+        if dtype != "f64":
+            del xA, xB
     del dA, dB
     torch.cuda.empty_cache()
     return res
