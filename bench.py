@@ -30,6 +30,7 @@ METRIC = "contraction GFLOP/s + % roofline (FP64 vs BF16-split vs batched), same
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
+FP8_PEAK_TFS = 5000.0        # MI355X dense FP8 matrix peak (TFLOP/s)
 BF16_PEAK_TFS = 2500.0
 
 
@@ -248,10 +249,12 @@ def precision(args, torch, tc, wl):
     dB = tc.to_device_fortran(w["B"], torch.float64)
     base_ms = None
     # FP64 plain, FP32 plain (FP32-rounded inputs, FP32 matrix cores), and the
-    # split-BF16 form on the FP64 inputs; errors against the FP64 oracle
+    # split-BF16 and split-FP8 forms on the FP64 inputs; errors against the
+    # FP64 oracle
     for name, dtype, compute, peak in (("fp64", "f64", "native", FP64_PEAK_TFS),
                                        ("fp32", "f32", "native", FP32_PEAK_TFS),
-                                       ("bf16x3", "f64", "bf16x3", BF16_PEAK_TFS)):
+                                       ("bf16x3", "f64", "bf16x3", BF16_PEAK_TFS),
+                                       ("fp8x3", "f64", "fp8x3", FP8_PEAK_TFS)):
         tdt = torch.float64 if dtype == "f64" else torch.float32
         xA, xB = (dA, dB) if dtype == "f64" else (dA.to(tdt), dB.to(tdt))
         plan = tc.Plan(w["spec"], w["ext"], dtype, compute=compute)
@@ -261,12 +264,12 @@ def precision(args, torch, tc, wl):
         got = dC[torch.as_tensor(rows, device="cuda")][:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
         err = oracle.normwise_rel_err(got, ref)
         tfs = fl / (ms * 1e-3) / 1e12
-        executed = fl * (6 if compute == "bf16x3" else 1)
+        executed = fl * (6 if compute != "native" else 1)
         rec = dict(workload="C_ab = A_iaj B_jbi, a=b=4096, i=j=64, normal(0,1) x logU[1e-3,1e3] per slice",
                    ms=round(ms, 4), effective_gflops=round(tfs * 1e3, 1), normwise_err_sampled=err,
                    roofline=dict(bound="mfma", achieved=round(executed / (ms * 1e-3) / 1e12, 2), peak=peak,
                                  unit="TFLOP/s", frac=round(executed / (ms * 1e-3) / 1e12 / peak, 4),
-                                 counts="executed MFMA flops (6 products for the split form)"))
+                                 counts="executed MFMA flops (6 products for the split forms)"))
         if base_ms is None:
             base_ms = ms
         else:

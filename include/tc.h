@@ -49,9 +49,11 @@ typedef enum { TC_F64 = 0, TC_F32 = 1 } tc_dtype;   /* storage type of A, B and 
 
 /* Arithmetic path.  TC_NATIVE computes in the storage type.  TC_BF16X3 splits
  * each power-of-two scaled slice into three BF16 terms and forms the six
- * products of order <= 4 on BF16 matrix cores with FP32 accumulation, combined
- * in FP64 with compensated summation.  TC_FP8X3 does the same with OCP E4M3
- * terms. */
+ * products of order <= 4 on BF16 matrix cores with FP32 accumulation (the
+ * leading product and the five smaller ones in two sums, added exactly in FP64
+ * at the end).  TC_FP8X3 does the same with OCP E4M3 terms, term p scaled by
+ * 2^(4(p-1)) to stay in E4M3's normal range, on FP8 matrix cores whose operand
+ * scales undo that factor; at most 8192 contracted positions. */
 typedef enum { TC_NATIVE = 0, TC_BF16X3 = 1, TC_FP8X3 = 2 } tc_compute;
 
 typedef enum {
@@ -168,11 +170,13 @@ tc_status tc_plan_workspace(tc_plan_t plan, int64_t* bytes);
 tc_status tc_contract(tc_plan_t plan, const void* A, const void* B, void* C,
                       double alpha, double beta, void* stream);
 
-/* Copy the split terms of the last tc_contract of a TC_BF16X3 plan to host
- * memory, for bit-exact checks of the quantisation.  side 0 = A, 1 = B.  The
- * GEMM view of the plan orders rows by the free indices of that side (first
- * fastest) and columns by the plan's K order.  terms: 3 * rows * kp BF16 bit
- * patterns (uint16, term-major, row-major), exps: rows power-of-two exponents.
+/* Copy the split terms of the last tc_contract of a TC_BF16X3 or TC_FP8X3
+ * plan to host memory, for bit-exact checks of the quantisation.  side 0 = A,
+ * 1 = B.  The GEMM view of the plan orders rows by the free indices of that
+ * side (first fastest) and columns by the plan's K order.  terms: 3 * rows * kp
+ * elements, term-major, row-major: BF16 bit patterns (uint16) for TC_BF16X3,
+ * E4M3 codes (uint8, term p stored times 2^(4(p-1))) for TC_FP8X3.  exps: rows
+ * power-of-two exponents.
  * With both pointers NULL only *rows and *kp are filled.  Synchronises the
  * device.  Errors: TC_E_UNSUPPORTED (no split yet), TC_E_VARIANT (bad side). */
 tc_status tc_split_terms(tc_plan_t plan, int side, void* terms, int32_t* exps, int64_t* rows, int64_t* kp);

@@ -263,12 +263,14 @@ class Batch:
         return tc_batch_info(self.handle)
 
 
-def tc_split_terms(h, side: int):
-    """(terms uint16 [3, rows, kp], exponents int32 [rows]) of the last split contraction."""
+def tc_split_terms(h, side: int, fp8: bool = False):
+    """(terms [3, rows, kp], exponents int32 [rows]) of the last split contraction:
+    BF16 bit patterns (uint16), or E4M3 codes (uint8) with ``fp8`` for a
+    TC_FP8X3 plan, term p stored scaled by 2^(4(p-1))."""
     import numpy as np
     rows, kp = ctypes.c_int64(), ctypes.c_int64()
     _check(lib.tc_split_terms(h, int(side), None, None, ctypes.byref(rows), ctypes.byref(kp)))
-    terms = np.zeros((3, rows.value, kp.value), dtype=np.uint16)
+    terms = np.zeros((3, rows.value, kp.value), dtype=np.uint8 if fp8 else np.uint16)
     exps = np.zeros(rows.value, dtype=np.int32)
     _check(lib.tc_split_terms(h, int(side), terms.ctypes.data_as(ctypes.c_void_p),
                               exps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),

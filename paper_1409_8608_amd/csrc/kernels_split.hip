@@ -235,6 +235,130 @@ __global__ __launch_bounds__(256) void k_split_long(SplitArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP8 (OCP E4M3) form.  Term p is stored scaled by 2^(4(p-1)) so that it stays
+// in E4M3's normal range; the product kernel undoes the scale through the
+// matrix instruction's per-operand E8M0 scales.  Stage images hold 64 K
+// positions of one byte: [term][128 rows][four 16-byte chunks], the chunks of
+// row r permuted by (r >> 3) & 3 (the fragment reads take 32 consecutive rows
+// per half-wave; an LDS read-pattern probe on MI355X found this permutation as
+// fast as a linear read, where (r >> 1) & 3 took 1.55x and no permutation 2.9x).
+constexpr int F8_BK = 64;
+
+__host__ __device__ __forceinline__ int xswz8(int r, int c) { return c ^ ((r >> 3) & 3); }
+
+__host__ __device__ __forceinline__ int64_t panel_off8(int64_t row, int64_t k, int term, int64_t Kp) {
+    const int64_t rt = row / XR, kt = k / F8_BK;
+    const int rr = (int)(row % XR), kk = (int)(k % F8_BK);
+    return ((rt * (Kp / F8_BK) + kt) * 3 + term) * (int64_t)(XR * F8_BK) + rr * F8_BK +
+           xswz8(rr, kk >> 4) * 16 + (kk & 15);
+}
+
+// Round to nearest even on the E4M3 grid: 4 significant bits, spacing 2^-9
+// below the smallest normal 2^-6, saturating at +-448.
+__device__ __forceinline__ double rn_e4m3(double x) {
+    if (x == 0.0) return x;
+    int E;
+    frexp(x, &E);
+    const int lead = E - 1 > -6 ? E - 1 : -6;
+    const double q = ldexp(rint(ldexp(x, -(lead - 3))), lead - 3);
+    return fmin(fmax(q, -448.0), 448.0);
+}
+
+// E4M3 code of a value already on the grid: sign, 4-bit exponent (bias 7),
+// 3-bit fraction; exponent 0 holds the subnormals m * 2^-9.
+__device__ __forceinline__ uint32_t e4m3_code(double q) {
+    const uint32_t sgn = q < 0.0 ? 0x80u : 0u;
+    const double a = fabs(q);
+    if (a == 0.0) return sgn;
+    int E;
+    const double m = frexp(a, &E);
+    const int e = E - 1 + 7;
+    if (e >= 1) return sgn | ((uint32_t)e << 3) | (uint32_t)((m * 2.0 - 1.0) * 8.0);
+    return sgn | (uint32_t)(a * 512.0);
+}
+
+__device__ __forceinline__ uint32_t pack4_e4m3(const double* t) {
+    return e4m3_code(t[0]) | (e4m3_code(t[1]) << 8) | (e4m3_code(t[2]) << 16) | (e4m3_code(t[3]) << 24);
+}
+
+// One block per slice, like k_split; a thread owns chunks of sixteen positions
+// (one 16-byte chunk of each term image).
+template <typename T, int CPT, bool VEC>
+__global__ __launch_bounds__(256) void k_split8(SplitArgs a) {
+    __shared__ double red[4];
+    const T* X = (const T*)a.X;
+    const int64_t row = xcd_item(blockIdx.x, a.nrows);
+    const int tid = threadIdx.x;
+    const int64_t base = grp_off(a.rows, row, a.slot);
+    const int64_t nch = a.Kt / 16;
+    double v[CPT][16];
+    double amax = 0.0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int64_t ch = tid + 256 * c;
+        const bool in = ch < nch;
+        const int64_t* ko = a.koff + 16 * (in ? ch : 0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (VEC) {
+                typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
+                constexpr int W = 16 / sizeof(T);
+                const int64_t o = ko[8 * h];
+                const bool ok = in && o >= 0;
+                const v16* p = (const v16*)(X + base + (ok ? o : 0));
+#pragma unroll
+                for (int q = 0; q < 8 / W; ++q) {
+                    const v16 t = p[q];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) v[c][8 * h + q * W + w] = ok ? (double)t[w] : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int64_t o = ko[8 * h + e];
+                    const bool ok = in && o >= 0;
+                    const double x = (double)X[base + (ok ? o : 0)];
+                    v[c][8 * h + e] = ok ? x : 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) amax = fmax(amax, fabs(v[c][e]));
+    }
+    for (int s = 32; s > 0; s >>= 1) amax = fmax(amax, __shfl_xor(amax, s));
+    if ((tid & 63) == 0) red[tid >> 6] = amax;
+    __syncthreads();
+    amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    int e = 0;
+    if (amax > 0.0) {
+        int E;
+        frexp(amax, &E);
+        e = E - 1;
+    }
+    if (tid == 0) a.exps[row] = e;
+    constexpr int64_t TS = XR * F8_BK;   // bytes between the terms of one stage image
+    uint8_t* pan = (uint8_t*)a.panels;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int64_t ch = tid + 256 * c;
+        if (ch >= nch) break;
+        double t1[16], t2[16], t3[16];   // t2, t3 as stored: scaled by 2^4 and 2^8
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const double x = ldexp(v[c][q], -e);
+            t1[q] = rn_e4m3(x);
+            const double r1 = x - t1[q];
+            t2[q] = rn_e4m3(ldexp(r1, 4));
+            t3[q] = rn_e4m3(ldexp(r1 - ldexp(t2[q], -4), 8));
+        }
+        uint4* out = (uint4*)(pan + panel_off8(row, 16 * ch, 0, a.Kp));
+        out[0] = make_uint4(pack4_e4m3(t1), pack4_e4m3(t1 + 4), pack4_e4m3(t1 + 8), pack4_e4m3(t1 + 12));
+        out[TS / 16] = make_uint4(pack4_e4m3(t2), pack4_e4m3(t2 + 4), pack4_e4m3(t2 + 8), pack4_e4m3(t2 + 12));
+        out[2 * TS / 16] = make_uint4(pack4_e4m3(t3), pack4_e4m3(t3 + 4), pack4_e4m3(t3 + 8), pack4_e4m3(t3 + 12));
+    }
+}
+
 struct X3Args {
     const uint16_t* tA;   // stage images of A's terms (panel_off layout)
     const uint16_t* tB;   // stage images of B's terms
@@ -424,6 +548,169 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
         }
 }
 
+typedef int i8v __attribute__((ext_vector_type(8)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+// E8M0 scale of term p (0-based): the stored term is 2^(4p) times the true one.
+constexpr int kScale[3] = {127, 123, 119};
+
+// FP8 product kernel: the block and stage structure of k_x3 (256 x 128 tile,
+// eight waves of 64 x 64, double-buffered DMA stages of 72 KB) with 64 K
+// positions per stage and v_mfma_scale_f32_32x32x64_f8f6f4: a wave holds two
+// by two blocks of 32 x 32.  Operand lane l supplies row l % 32 and the 32
+// bytes of K half l / 32; the accumulator holds D[8 (q/4) + 4 (l/32) + q % 4]
+// [l % 32] (both checked with an exact one-wave probe on MI355X).  The
+// instruction's per-operand E8M0 scales undo the terms' 2^(4(p-1)), so the five
+// small products share one FP32 accumulator.  Work per stage and wave: 24
+// MFMAs of 64 x 32 x 32 x 2 flops against 24 fragment reads of 16 bytes.
+template <typename T>
+__global__ __launch_bounds__(64 * XWAVES) void k_x3_8(X3Args a) {
+    constexpr int NVA = 2 * XSTAGE / 16, NVB = XSTAGE / 16;
+    constexpr int PA = 2 * XSTAGE / XPIECE / XWAVES, PB = XSTAGE / XPIECE / XWAVES;
+    constexpr int NT = 64 * XWAVES;
+    __shared__ uint4 sA0[NVA], sA1[NVA], sB0[NVB], sB1[NVB];
+    __shared__ int64_t sCm[XBM], sCn[XBN];
+    __shared__ int32_t sEm[XBM], sEn[XBN];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wid & 3, wn = wid >> 2;
+    const int64_t L = xcd_item(blockIdx.x, a.ntiles);
+    constexpr int64_t GM = 8;
+    const int64_t g = L / (GM * a.nt), first = g * GM;
+    const int64_t gm = a.mt - first < GM ? a.mt - first : GM;
+    const int64_t r = L - g * GM * a.nt;
+    const int64_t mt = first + r % gm, nt = r / gm;
+    const int64_t m_base = mt * XBM, n_base = nt * XBN;
+    for (int i = tid; i < XBM; i += NT) {
+        const int64_t m = m_base + i;
+        sCm[i] = m < a.M ? grp_off(a.m, m, 2) : -1;
+        sEm[i] = m < a.M ? a.eA[m] : 0;
+    }
+    for (int i = tid; i < XBN; i += NT) {
+        const int64_t n = n_base + i;
+        sCn[i] = n < a.N ? grp_off(a.n, n, 2) : -1;
+        sEn[i] = n < a.N ? a.eB[n] : 0;
+    }
+    __syncthreads();
+
+    const int64_t ktiles = a.Kp / F8_BK;
+    const char* gA = (const char*)a.tA + 2 * mt * ktiles * XSTAGE;
+    const char* gB = (const char*)a.tB + nt * ktiles * XSTAGE;
+    const uint32_t loff = (uint32_t)lane * 16u;
+    auto dma = [&](int64_t kt, uint4* sa, uint4* sb) {
+#pragma unroll
+        for (int e = 0; e < PA; ++e) {
+            const int piece = wid + XWAVES * e;
+            const int img = e < PA / 2 ? 0 : 1;
+            const char* src = gA + (img * ktiles + kt) * XSTAGE + (piece - img * (XSTAGE / XPIECE)) * XPIECE;
+            __builtin_amdgcn_global_load_lds(src + loff, (lds_void_t*)(sa + piece * 64), 16, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < PB; ++e) {
+            const int piece = wid + XWAVES * e;
+            __builtin_amdgcn_global_load_lds(gB + kt * XSTAGE + piece * XPIECE + loff,
+                                             (lds_void_t*)(sb + piece * 64), 16, 0, 0);
+        }
+    };
+
+    const int r32 = lane & 31, hk = lane >> 5;
+    auto frag = [&](const uint4* st, int term, int row) -> i8v {
+        const uint4* rp = st + (term * XR + row) * 4;
+        const uint4 lo = rp[xswz8(row, 2 * hk)], hi = rp[xswz8(row, 2 * hk + 1)];
+        i8v v;
+        v[0] = (int)lo.x; v[1] = (int)lo.y; v[2] = (int)lo.z; v[3] = (int)lo.w;
+        v[4] = (int)hi.x; v[5] = (int)hi.y; v[6] = (int)hi.z; v[7] = (int)hi.w;
+        return v;
+    };
+    const int aimg = (wm >> 1) * (NVA / 2), arow = (wm & 1) * 64;
+
+    f16v big[2][2], small[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            big[i][j] = f16v{};
+            small[i][j] = f16v{};
+        }
+    // first operand: the B side (n), second: the A side (m)
+    auto mma = [&](f16v (&acc)[2][2], const i8v (&fb)[2], const i8v (&fa)[2], int sb, int sa) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fb[i], fa[j], acc[i][j], 0, 0, 0, sb, 0, sa);
+    };
+    auto load_b = [&](const uint4* sb, int t, i8v (&fb)[2]) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) fb[i] = frag(sb, t, wn * 64 + i * 32 + r32);
+    };
+    auto load_a = [&](const uint4* sa, int t, i8v (&fa)[2]) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) fa[j] = frag(sa + aimg, t, arow + j * 32 + r32);
+    };
+    auto compute = [&](const uint4* sa, const uint4* sb) {
+        i8v b1[2], b2[2], b3[2], a1[2], a2[2], a3[2];
+        load_b(sb, 0, b1);
+        load_a(sa, 0, a1);
+        load_b(sb, 2, b3);
+        __builtin_amdgcn_sched_barrier(0);
+        load_b(sb, 1, b2);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(big, b1, a1, kScale[0], kScale[0]);      // t_A1 t_B1
+        mma(small, b3, a1, kScale[2], kScale[0]);    // t_A1 t_B3
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(sa, 1, a2);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(small, b2, a1, kScale[1], kScale[0]);    // t_A1 t_B2
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(sa, 2, a3);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(small, b1, a2, kScale[0], kScale[1]);    // t_A2 t_B1
+        mma(small, b2, a2, kScale[1], kScale[1]);    // t_A2 t_B2
+        __builtin_amdgcn_sched_barrier(0);
+        mma(small, b1, a3, kScale[0], kScale[2]);    // t_A3 t_B1
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto step = [&](int64_t kt, const uint4* sa, const uint4* sb, uint4* na, uint4* nb) {
+        __builtin_amdgcn_s_waitcnt(wait_vm(0));
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        dma(kt + 1 < ktiles ? kt + 1 : ktiles - 1, na, nb);
+        compute(sa, sb);
+    };
+    if (ktiles > 0) dma(0, sA0, sB0);
+    for (int64_t kt = 0; kt < ktiles; kt += 2) {
+        step(kt, sA0, sB0, sA1, sB1);
+        step(kt + 1, sA1, sB1, sA0, sB0);
+    }
+    __builtin_amdgcn_s_waitcnt(wait_vm(0));
+
+    T* C = (T*)a.C;
+    const T beta = (T)a.beta;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int nl = wn * 64 + i * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+            const int64_t cn = sCn[nl];
+            if (cn < 0) continue;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int ml = wm * 64 + j * 32 + (lane & 31);
+                const int64_t cm = sCm[ml];
+                if (cm < 0) continue;
+                const double v = a.alpha * ldexp((double)big[i][j][q] + (double)small[i][j][q], sEm[ml] + sEn[nl]);
+                T* cp = C + cn + cm;
+                T out = (T)v;
+                if (a.beta != 0.0) out += beta * (*cp);
+                *cp = out;
+            }
+        }
+}
+
 // ---------------------------------------------------------------------------
 // Workspace layout inside p->d_split: K offsets of A | of B | terms A | terms B |
 // exps A | exps B
@@ -433,7 +720,9 @@ static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 tc_status prepare_split(tc_plan_s* p) {
     if (p->d_split) return TC_OK;
-    if (p->spec.compute == TC_FP8X3) return fail(TC_E_UNSUPPORTED, "FP8 split terms are not built on the GPU");
+    const bool fp8 = p->spec.compute == TC_FP8X3;
+    const int SB = fp8 ? F8_BK : SPLIT_BK;   // K positions per product-kernel stage
+    const int64_t tb = fp8 ? 1 : 2;          // bytes per term element
     const GemmView& gv = p->gv;
     // 8 x 8 blocks: a k_split thread's chunk of eight positions is a run of
     // eight along A's contiguous index, and the eight chunks of a block read
@@ -442,7 +731,7 @@ tc_status prepare_split(tc_plan_s* p) {
     // padded to a whole number of two-stage turns of the product kernel's
     // buffer rotation; the padding positions (-1) hold zero terms
     const int64_t Kt = (int64_t)tab.size() / 2;
-    const int64_t Kp = round_up(Kt, 2 * SPLIT_BK);
+    const int64_t Kp = round_up(Kt, 2 * SB);
     std::vector<int64_t> ko[2] = {std::vector<int64_t>(Kp, -1), std::vector<int64_t>(Kp, -1)};
     for (int64_t k = 0; k < Kt; ++k) {
         ko[0][k] = tab[2 * k];
@@ -453,8 +742,8 @@ tc_status prepare_split(tc_plan_s* p) {
     int64_t* L = p->split_layout;
     L[L_KOA] = off;  off += round_up(Kp * 8, 256);
     L[L_KOB] = off;  off += round_up(Kp * 8, 256);
-    L[L_TA] = off;   off += round_up(3 * RA * Kp * 2, 256);
-    L[L_TB] = off;   off += round_up(3 * RB * Kp * 2, 256);
+    L[L_TA] = off;   off += round_up(3 * RA * Kp * tb, 256);
+    L[L_TB] = off;   off += round_up(3 * RB * Kp * tb, 256);
     L[L_EA] = off;   off += round_up(RA * 4, 256);
     L[L_EB] = off;   off += round_up(RB * 4, 256);
     L[L_KP] = Kp; L[L_RA] = RA; L[L_RB] = RB; L[L_KT] = Kt;
@@ -510,10 +799,27 @@ static void launch_split(const SplitArgs& s, int64_t nch, bool vec, dim3 grid, d
     }
 }
 
+// FP8 terms for up to 8192 contracted positions (k_split8 keeps a slice in
+// registers; longer slices are refused by run_split).
+template <typename T>
+static void launch_split8(const SplitArgs& s, int64_t nch, bool vec, dim3 grid, dim3 blk, hipStream_t st) {
+    const int cpt = nch <= 256 ? 1 : 2;
+    if (vec) {
+        if (cpt == 1) hipLaunchKernelGGL((k_split8<T, 1, true>), grid, blk, 0, st, s);
+        else hipLaunchKernelGGL((k_split8<T, 2, true>), grid, blk, 0, st, s);
+    } else {
+        if (cpt == 1) hipLaunchKernelGGL((k_split8<T, 1, false>), grid, blk, 0, st, s);
+        else hipLaunchKernelGGL((k_split8<T, 2, false>), grid, blk, 0, st, s);
+    }
+}
+
 tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
                     hipStream_t st) {
     const GemmView& gv = p->gv;
     const bool f64 = p->spec.dtype == TC_F64;
+    const bool fp8 = p->spec.compute == TC_FP8X3;
+    if (fp8 && p->split_layout[L_KT] > 8192)
+        return fail(TC_E_UNSUPPORTED, "FP8 split form takes at most 8192 contracted positions");
     const int64_t* L = p->split_layout;
     char* w = (char*)p->d_split;
     const int64_t Kp = L[L_KP], RA = L[L_RA], RB = L[L_RB];
@@ -538,10 +844,16 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
         if (s.nrows <= 0 || L[L_KT] == 0) continue;   // no K: the exponents stay 0, the terms empty
         if (s.nrows > 0x7fffffff) return fail(TC_E_EXTENT, "too many slices for one launch");
         const dim3 grid((unsigned)s.nrows), blk(256);
-        const int64_t nch = s.Kt / 8;   // chunks of eight positions (Kt is a multiple of 64)
         const bool vec = L[side == 0 ? L_VA : L_VB] != 0 && ((uintptr_t)s.X) % 16 == 0;
-        if (f64) launch_split<double>(s, nch, vec, grid, blk, st);
-        else launch_split<float>(s, nch, vec, grid, blk, st);
+        if (fp8) {
+            const int64_t nch = s.Kt / 16;   // chunks of sixteen positions (Kt is a multiple of 64)
+            if (f64) launch_split8<double>(s, nch, vec, grid, blk, st);
+            else launch_split8<float>(s, nch, vec, grid, blk, st);
+        } else {
+            const int64_t nch = s.Kt / 8;    // chunks of eight positions
+            if (f64) launch_split<double>(s, nch, vec, grid, blk, st);
+            else launch_split<float>(s, nch, vec, grid, blk, st);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "split kernel launch");
     }
@@ -558,8 +870,14 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
     x.ntiles = x.mt * x.nt;
     x.alpha = alpha; x.beta = beta;
     if (x.ntiles > 0x7fffffff) return fail(TC_E_EXTENT, "too many output tiles for one launch");
-    if (f64) hipLaunchKernelGGL(k_x3<double>, dim3((unsigned)x.ntiles), dim3(64 * XWAVES), 0, st, x);
-    else hipLaunchKernelGGL(k_x3<float>, dim3((unsigned)x.ntiles), dim3(64 * XWAVES), 0, st, x);
+    const dim3 xg((unsigned)x.ntiles), xb(64 * XWAVES);
+    if (fp8) {
+        if (f64) hipLaunchKernelGGL(k_x3_8<double>, xg, xb, 0, st, x);
+        else hipLaunchKernelGGL(k_x3_8<float>, xg, xb, 0, st, x);
+    } else {
+        if (f64) hipLaunchKernelGGL(k_x3<double>, xg, xb, 0, st, x);
+        else hipLaunchKernelGGL(k_x3<float>, xg, xb, 0, st, x);
+    }
     e = hipGetLastError();
     return e == hipSuccess ? TC_OK : hip_fail(e, "split product kernel launch");
 }
@@ -585,14 +903,18 @@ extern "C" tc_status tc_split_terms(tc_plan_t p, int side, void* terms, int32_t*
     if (e != hipSuccess) return hip_fail(e, "synchronize");
     if (terms) {
         // the device keeps stage images; hand back [term][row][Kp]
-        const int64_t elems = 3 * R * Kp;
-        std::vector<uint16_t> img((size_t)elems);
-        e = hipMemcpy(img.data(), w + L[side == 0 ? L_TA : L_TB], (size_t)(elems * 2), hipMemcpyDeviceToHost);
+        const bool fp8 = p->spec.compute == TC_FP8X3;
+        const int64_t elems = 3 * R * Kp, tb = fp8 ? 1 : 2;
+        std::vector<uint8_t> img((size_t)(elems * tb));
+        e = hipMemcpy(img.data(), w + L[side == 0 ? L_TA : L_TB], (size_t)(elems * tb), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "copy split terms");
-        uint16_t* out = (uint16_t*)terms;
         for (int t = 0; t < 3; ++t)
             for (int64_t r = 0; r < n; ++r)
-                for (int64_t k = 0; k < Kp; ++k) out[(t * n + r) * Kp + k] = img[(size_t)panel_off(r, k, t, Kp)];
+                for (int64_t k = 0; k < Kp; ++k) {
+                    const int64_t o = (t * n + r) * Kp + k;
+                    if (fp8) ((uint8_t*)terms)[o] = img[(size_t)panel_off8(r, k, t, Kp)];
+                    else ((uint16_t*)terms)[o] = ((const uint16_t*)img.data())[(size_t)panel_off(r, k, t, Kp)];
+                }
     }
     if (exps) {
         e = hipMemcpy(exps, w + L[side == 0 ? L_EA : L_EB], (size_t)(n * 4), hipMemcpyDeviceToHost);

@@ -59,3 +59,25 @@ def split_bound(K: int) -> float:
     per position) accumulate in a second FP32 sum: 5 K u 2^-7.  2^-22 covers
     the FP64 combine and the unscaling."""
     return (K + 8) * 2.0 ** -24 + 5 * K * 2.0 ** -31 + 2.0 ** -22
+
+
+def split_bound_fp8(K: int) -> float:
+    """split_bound for OCP E4M3 terms.  The small products are together at
+    most 2^-3 of the leading one per position (each term carries 4 significant
+    bits), so their FP32 sum contributes 5 K u 2^-3.  The FP8 matrix
+    instructions of MI355X add their products with less than FP32 precision:
+    measured on one instruction with random normal-range E4M3 operands, up to
+    880 u of the instruction's sum of |products| (about 2^-14), against about
+    1 u for the BF16 instructions; 2^-12 |A||B| covers it."""
+    return (K + 8) * 2.0 ** -24 + 5 * K * 2.0 ** -27 + 2.0 ** -12
+
+
+def e4m3_value(codes):
+    """Values of OCP E4M3 codes (uint8 array)."""
+    import numpy as np
+    c = np.asarray(codes).astype(np.int64)
+    s = np.where(c & 0x80, -1.0, 1.0)
+    e = (c >> 3) & 15
+    m = (c & 7).astype(np.float64)
+    v = np.where(e == 0, m * 2.0 ** -9, (1.0 + m / 8.0) * np.exp2(e - 7.0))
+    return s * v

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from oracle import split as sp
-from gpu_util import split_bound
+from gpu_util import split_bound, split_bound_fp8
 
 pytestmark = pytest.mark.gpu
 tc = pytest.importorskip("paper_1409_8608_amd")
@@ -53,11 +53,11 @@ def test_permuted_full_size(dtype):
     assert oracle.normwise_rel_err(got, ref) <= (1e-12 if dtype == "f64" else 1e-5)
 
 
-@pytest.mark.parametrize("compute", ["native", "bf16x3"])
+@pytest.mark.parametrize("compute", ["native", "bf16x3", "fp8x3"])
 def test_scaled_matrix_full_size(compute):
-    """C_ab = A_iaj B_jbi, a=b=4096, i=j=64 with per-slice scales: FP64 plain
-    and split-BF16 on sampled rows and columns; the split form also within
-    its bound of the exactly accumulated split oracle."""
+    """C_ab = A_iaj B_jbi, a=b=4096, i=j=64 with per-slice scales: FP64 plain,
+    split-BF16 and split-FP8 on sampled rows and columns; the split forms also
+    within their bounds of the exactly accumulated split oracle."""
     import torch
     w = wl.scaled_matrix(4096, 64)
     p = tc.Plan(w["spec"], w["ext"], "f64", compute=compute)
@@ -75,11 +75,16 @@ def test_scaled_matrix_full_size(compute):
     if compute == "native":
         assert oracle.normwise_rel_err(got, ref) <= 1e-12
     else:
-        assert oracle.normwise_rel_err(got, ref) <= 1e-5
+        kind = "bf16" if compute == "bf16x3" else "fp8"
         absAB = oracle.contract(w["spec"], ext_s, np.abs(As), np.abs(Bs))
-        ref_split = sp.contract_split(w["spec"], ext_s, As, Bs)   # slices are per free index: sampling keeps them
-        bound = split_bound(64 * 64)
+        # slices are per free index, so sampling rows and columns keeps them
+        ref_split = sp.contract_split(w["spec"], ext_s, As, Bs, kind=kind)
+        bound = split_bound(64 * 64) if kind == "bf16" else split_bound_fp8(64 * 64)
         assert np.all(np.abs(got - ref_split) <= bound * absAB)
+        if kind == "bf16":
+            assert oracle.normwise_rel_err(got, ref) <= 1e-5
+        else:
+            assert np.all(np.abs(got - ref) <= 2.0 ** -9 * absAB)
 
 
 def test_batch_full_size_sampled():

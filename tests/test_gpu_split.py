@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from oracle import split as sp
-from gpu_util import split_bound, run
+from gpu_util import e4m3_value, run, split_bound, split_bound_fp8
 
 pytestmark = pytest.mark.gpu
 tc = pytest.importorskip("paper_1409_8608_amd")
@@ -92,6 +92,42 @@ def test_split_long_contraction(K):
     assert oracle.normwise_rel_err(got, oracle.contract(spec, ext, A, B)) <= 1e-5
     _, eA = tc.tc_split_terms(p.handle, 0)
     np.testing.assert_array_equal(eA, np.asarray(sp.slice_exponents(A, "ai", "a")).ravel(order="F"))
+
+
+@pytest.mark.parametrize("spec,ext", [
+    ("ab=iaj,jbi", dict(a=130, b=200, i=24, j=17)),
+    ("abc=ija,jbic", dict(a=40, b=33, c=7, i=5, j=11)),
+    ("ab=ai,ib", dict(a=300, b=140, i=700)),
+])
+def test_fp8_terms_bit_exact_and_result(spec, ext):
+    """FP8 (OCP E4M3) split: exponents equal the oracle's; each row's terms,
+    decoded and unscaled, equal the oracle's as a multiset; the result is
+    within the FP32-accumulation bound of the exactly accumulated FP8 split
+    oracle and within the FP8 split's own 2^-9 of the FP64 contraction."""
+    rng = np.random.default_rng(12)
+    sa, sb, sc = oracle.split_spec(spec)
+    A = np.array(rng.standard_normal([ext[c] for c in sa]), order="F")
+    B = np.array(rng.standard_normal([ext[c] for c in sb]), order="F")
+    fa = [ax for ax, ch in enumerate(sa) if ch in sc]
+    A *= np.exp(rng.uniform(np.log(1e-3), np.log(1e3), [A.shape[ax] if ax in fa else 1 for ax in range(A.ndim)]))
+    p = tc.Plan(spec, ext, "f64", compute="fp8x3")
+    got = run(p, A, B)
+    ref_split = sp.contract_split(spec, ext, A, B, kind="fp8")
+    absAB = oracle.contract(spec, ext, np.abs(A), np.abs(B))
+    K = int(np.prod([ext[c] for c in sa if c not in sc]))
+    assert np.all(np.abs(got - ref_split) <= split_bound_fp8(K) * absAB)
+    assert np.all(np.abs(got - oracle.contract(spec, ext, A, B)) <= 2.0 ** -9 * absAB)
+    tA, eA = tc.tc_split_terms(p.handle, 0, fp8=True)
+    free = "".join(c for c in sa if c in sc)
+    np.testing.assert_array_equal(eA, np.asarray(sp.slice_exponents(A, sa, free)).ravel(order="F"))
+    TA, _ = sp.split_terms(A, sa, free, kind="fp8")
+    con_axes = [ax for ax, ch in enumerate(sa) if ch not in sc]
+    if len(fa) == 1:
+        for t in range(3):
+            dev = e4m3_value(tA[t]) * 2.0 ** (-4 * t)
+            ora = np.transpose(TA[t], fa + con_axes).reshape(len(eA), -1, order="F")
+            for r in range(0, len(eA), max(1, len(eA) // 16)):
+                np.testing.assert_array_equal(np.sort(dev[r][dev[r] != 0]), np.sort(ora[r][ora[r] != 0]))
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
