@@ -7,8 +7,12 @@
 // Operand staging: a BM x BK tile of A and a BK x BN tile of B go global ->
 // registers -> LDS, double-buffered, one barrier per K tile.  Each tile is
 // loaded with lanes along whichever index is contiguous in memory (M or K for
-// A, N or K for B), and written to LDS k-major so that the fragment reads of
-// every MFMA are conflict-free rows.  K is walked through a table of (A, B)
+// A, N or K for B).  In LDS every row (one m of A, one n of B) holds its BK = 16
+// contracted positions contiguously, in 16-byte chunks permuted per row so
+// that fragment reads hit distinct banks.  Within a tile, lane group g = lane
+// / 16 takes positions 4g .. 4g+3 in the four MFMA steps (both operands alike,
+// so every position still meets its partner): a lane reads its fragment for
+// all four steps with one (FP32) or two (FP64) 16-byte reads.  K is walked through a table of (A, B)
 // offset pairs built by the planner in a blocked order in which A's and B's
 // contiguous contracted indices both form runs; that handles any number of
 // contracted indices and permuted strides with one kernel.
@@ -45,6 +49,27 @@ template <> struct Mfma<float> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(rowop, colop, c, 0, 0, 0);
     }
 };
+
+// LDS layout of a staged tile: row r holds positions 0..15 in 16-byte chunks;
+// chunk c sits at c ^ f(r).  Chosen with an LDS read-pattern probe on MI355X
+// for the fragment reads (16 consecutive rows per lane group, one chunk per
+// group for FP32, two for FP64): both run as fast as a linear read, where the
+// unpermuted rows take 1.5x (FP32) and 2.7x (FP64).
+template <typename T> struct TileLds;
+template <> struct TileLds<float> {
+    static constexpr int CE = 4;   // elements per 16-byte chunk
+    static __device__ __forceinline__ int swz(int r, int c) { return c ^ ((r >> 1) & 3); }
+};
+template <> struct TileLds<double> {
+    static constexpr int CE = 2;
+    static __device__ __forceinline__ int swz(int r, int c) { return c ^ ((((r >> 1) & 3) << 1) | ((r >> 3) & 1)); }
+};
+// element (row, k) of a staged tile with BK = 16
+template <typename T>
+__device__ __forceinline__ int tile_at(int r, int k) {
+    constexpr int CE = TileLds<T>::CE;
+    return r * 16 + TileLds<T>::swz(r, k / CE) * CE + (k % CE);
+}
 
 __device__ __forceinline__ int64_t dm(int64_t& rem, int64_t ext) {
     if ((uint64_t)rem <= 0xffffffffull && (uint64_t)ext <= 0xffffffffull) {
@@ -86,13 +111,12 @@ template <typename T, int BM, int BN, int BK, bool A_KMAJ, bool B_KMAJ>
 __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, const void* Bp, void* Cp,
                                           double alpha_d, double beta_d, int64_t tile) {
     typedef typename Mfma<T>::acc_t acc_t;
-    constexpr int PAD = 4;
-    constexpr int LDA = BM + PAD, LDB = BN + PAD;
     constexpr int EA = BM * BK / 256, EB = BN * BK / 256;   // elements per thread per tile
     constexpr int FM = BM / 32, FN = BN / 32;              // 16x16 blocks per wave
     static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
-    __shared__ T As[2][BK][LDA];
-    __shared__ T Bs[2][BK][LDB];
+    static_assert(BK == 16, "the LDS layout holds 16 positions per row");
+    __shared__ __attribute__((aligned(16))) T As[2][BM * BK];
+    __shared__ __attribute__((aligned(16))) T Bs[2][BN * BK];
 
     const T* __restrict__ Ag = (const T*)Ap;
     const T* __restrict__ Bg = (const T*)Bp;
@@ -163,17 +187,23 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
 #pragma unroll
             for (int e = 0; e < TB; ++e) tB[e] = kt0[2 * (B_KMAJ ? tid % BK : (tid + 256 * e) / BN) + 1];
         };
-        // operand loads with clamped addresses (element (batch, pass, 0, 0) is
-        // always valid) and a select, so no branch sits around a load
+        // Operand loads with clamped addresses (element (batch, pass, 0, 0) is
+        // always valid), so no branch sits around a load.  The raw values stay
+        // in registers with a validity mask; padding is zeroed only when the
+        // tile is written to LDS, after the MFMAs of the current tile, so the
+        // loads of the next tile stay in flight meanwhile.
+        uint32_t okA = 0, okB = 0;
         auto gload = [&]() {
+            okA = 0;
+            okB = 0;
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
                 const int idx = tid + 256 * e;
                 const int64_t om = sAm[A_KMAJ ? idx / BK : idx % BM];
                 const int64_t ko = tA[A_KMAJ ? 0 : e];
                 const bool ok = (om >= 0) & (ko >= 0);
-                const T v = Ag[bA + pA + (ok ? om + ko : 0)];
-                ra[e] = ok ? v : (T)0;
+                ra[e] = Ag[bA + pA + (ok ? om + ko : 0)];
+                okA |= (uint32_t)ok << e;
             }
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
@@ -181,20 +211,22 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 const int64_t on = sBn[B_KMAJ ? idx / BK : idx % BN];
                 const int64_t ko = tB[B_KMAJ ? 0 : e];
                 const bool ok = (on >= 0) & (ko >= 0);
-                const T v = Bg[bB + pB + (ok ? on + ko : 0)];
-                rb[e] = ok ? v : (T)0;
+                rb[e] = Bg[bB + pB + (ok ? on + ko : 0)];
+                okB |= (uint32_t)ok << e;
             }
         };
         auto sstore = [&](int buf) {
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
                 const int idx = tid + 256 * e;
-                As[buf][A_KMAJ ? idx % BK : idx / BM][A_KMAJ ? idx / BK : idx % BM] = ra[e];
+                As[buf][tile_at<T>(A_KMAJ ? idx / BK : idx % BM, A_KMAJ ? idx % BK : idx / BM)] =
+                    (okA >> e) & 1 ? ra[e] : (T)0;
             }
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
                 const int idx = tid + 256 * e;
-                Bs[buf][B_KMAJ ? idx % BK : idx / BN][B_KMAJ ? idx / BK : idx % BN] = rb[e];
+                Bs[buf][tile_at<T>(B_KMAJ ? idx / BK : idx % BN, B_KMAJ ? idx % BK : idx / BN)] =
+                    (okB >> e) & 1 ? rb[e] : (T)0;
             }
         };
 
@@ -211,18 +243,33 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 gload();
                 if (kt + 2 < ktiles) tload(kt + 2);
             }
+            {
+                // this lane's positions 4g .. 4g+3 of each fragment row, g = lane / 16
+                typedef T v4 __attribute__((ext_vector_type(4)));
+                constexpr int CE = TileLds<T>::CE;
+                const int g = lane >> 4, r16 = lane & 15;
+                auto frag = [&](const T* tile, int row) -> v4 {
+                    v4 v;
 #pragma unroll
-            for (int kk = 0; kk < BK; kk += 4) {
-                const int kr = kk + (lane >> 4);
-                T fa[FM], fb[FN];
+                    for (int h = 0; h < 4 / CE; ++h) {
+                        typedef T vc __attribute__((ext_vector_type(CE)));
+                        const vc c = *(const vc*)(tile + row * 16 + TileLds<T>::swz(row, (4 * g) / CE + h) * CE);
 #pragma unroll
-                for (int j = 0; j < FM; ++j) fa[j] = As[buf][kr][wm * (BM / 2) + j * 16 + (lane & 15)];
+                        for (int q = 0; q < CE; ++q) v[h * CE + q] = c[q];
+                    }
+                    return v;
+                };
+                v4 fb[FN];
 #pragma unroll
-                for (int i = 0; i < FN; ++i) fb[i] = Bs[buf][kr][wn * (BN / 2) + i * 16 + (lane & 15)];
+                for (int i = 0; i < FN; ++i) fb[i] = frag(Bs[buf], wn * (BN / 2) + i * 16 + r16);
 #pragma unroll
-                for (int i = 0; i < FN; ++i)
+                for (int j = 0; j < FM; ++j) {
+                    const v4 fa = frag(As[buf], wm * (BM / 2) + j * 16 + r16);
 #pragma unroll
-                    for (int j = 0; j < FM; ++j) acc[i][j] = Mfma<T>::mac(fb[i], fa[j], acc[i][j]);
+                    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                        for (int i = 0; i < FN; ++i) acc[i][j] = Mfma<T>::mac(fb[i][s4], fa[s4], acc[i][j]);
+                }
             }
             if (kt + 1 < ktiles) sstore(buf ^ 1);
             __syncthreads();
