@@ -22,6 +22,10 @@ HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-result"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-sign-compare"]
+# Per-file additions.  The matrix-core tile kernels keep MFMA operands and
+# accumulators in ordinary VGPRs: with the default choice the FP64 kernels
+# copied all accumulators between VGPRs and AGPRs on every K tile.
+FILE_FLAGS = {"kernels_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def sources():
@@ -32,7 +36,7 @@ def _compile(src: str) -> str:
     obj = os.path.join(OUT, src + ".o")
     path = os.path.join(CSRC, src)
     if src.endswith(".hip"):
-        cmd = [HIPCC, *HIP_FLAGS, "-c", path, "-o", obj]
+        cmd = [HIPCC, *HIP_FLAGS, *FILE_FLAGS.get(src, []), "-c", path, "-o", obj]
     else:
         cmd = ["g++", *CXX_FLAGS, "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

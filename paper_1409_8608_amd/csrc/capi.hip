@@ -105,6 +105,29 @@ std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA) {
     return tab;
 }
 
+// Bit t set when every run of v table positions starting at a multiple of v
+// is, for operand t (0 = A, 1 = B), either all padding or v consecutive
+// offsets starting at a multiple of v: the matrix-core kernels may then stage
+// that operand's K-major tiles in 16-byte chunks.
+int ktab_vec_flags(const std::vector<int64_t>& tab, int v) {
+    const int64_t n = (int64_t)tab.size() / 2;
+    if (n == 0 || n % v != 0) return 0;
+    int flags = 0;
+    for (int t = 0; t < 2; ++t) {
+        bool ok = true;
+        for (int64_t p = 0; ok && p < n; p += v) {
+            const int64_t o0 = tab[2 * p + t];
+            for (int j = 1; j < v && ok; ++j) {
+                const int64_t o = tab[2 * (p + j) + t];
+                ok = o0 < 0 ? o < 0 : o == o0 + j;
+            }
+            if (o0 >= 0 && o0 % v != 0) ok = false;
+        }
+        if (ok) flags |= 1 << t;
+    }
+    return flags;
+}
+
 }  // namespace tc
 
 // ---------------------------------------------------------------------------
@@ -147,6 +170,7 @@ tc_status prepare_plan(tc_plan_s* p) {
         if (!use_stream_kernel(s, p->gv) && p->d_ktab == nullptr) {
             std::vector<int64_t> tab = build_ktab(p->gv.k, BK);
             p->kpad = (int64_t)tab.size() / 2;
+            p->kvec = ktab_vec_flags(tab, f64 ? 2 : 4);
             tc_status st = upload(&p->d_ktab, &p->ktab_cap, tab);
             if (st) return st;
         }
@@ -169,6 +193,7 @@ tc_status prepare_plan(tc_plan_s* p) {
             else kd.push_back(GtDim{1, 0, 0, 0});
             std::vector<int64_t> tab = build_ktab(kd, BK);
             p->var_kpad = (int64_t)tab.size() / 2;
+            p->var_kvec = ktab_vec_flags(tab, f64 ? 2 : 4);
             tc_status st = upload(&p->d_var_ktab, &p->var_ktab_cap, tab);
             if (st) return st;
             p->var_ktab_for = v;
@@ -228,6 +253,7 @@ static tc_status run_fused(tc_plan_s* p, const void* A, const void* B, void* C, 
     a.batch.n = 0;
     a.pass.n = 0;
     a.ktab = (const int64_t*)p->d_ktab;
+    a.kvec = p->kvec;
     a.M = gv.M; a.N = gv.N; a.Kpad = p->kpad;
     a.nbatch = 1; a.npass = 1;
     a.alpha = alpha; a.beta = beta;
@@ -312,6 +338,7 @@ tc_status run_variant(tc_plan_s* p, int v, const void* A, const void* B, void* C
             a.M = d.nm ? d.out.d[0].ext : 1;
             a.N = d.nn ? d.out.d[d.nm].ext : 1;
             a.Kpad = p->var_kpad;
+            a.kvec = p->var_kvec;
             a.alpha = alpha; a.beta = 1.0;
             a.mode = 1;
             mfma_tiles(f64, a);

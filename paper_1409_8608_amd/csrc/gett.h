@@ -75,6 +75,8 @@ struct MfmaArgs {
     int64_t mt, nt, ntiles;   // tile counts
     double alpha, beta;
     int mode;           // 0: C = alpha*acc + beta*C; 1: per pass C += alpha*acc
+    int kvec;           // bit 0 (A), bit 1 (B): every 16-byte chunk of K-table
+                        // positions is contiguous and aligned in that operand
 };
 
 // Per-call operands of one batch member.

@@ -83,6 +83,10 @@ __device__ __forceinline__ int64_t dm(int64_t& rem, int64_t ext) {
     return m;
 }
 
+// How a thread stages an operand tile: lanes along the free index (M-major),
+// along K one element at a time, or along K in 16-byte chunks.
+enum { LD_MMAJ = 0, LD_KSCAL = 1, LD_KVEC = 2 };
+
 // offset of linear index `i` within a dimension group, for tensor slot 0 (A),
 // 1 (B) or 2 (C)
 template <int SLOT>
@@ -107,11 +111,17 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
 // One BM x BN output tile (all passes) of the contraction described by `a`,
 // with the operand pointers and scalars given separately (a batch keeps them
 // apart from the static descriptors).  Called by a whole block.
-template <typename T, int BM, int BN, int BK, bool A_KMAJ, bool B_KMAJ>
+template <typename T, int BM, int BN, int BK, int AMODE, int BMODE>
 __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, const void* Bp, void* Cp,
                                           double alpha_d, double beta_d, int64_t tile) {
     typedef typename Mfma<T>::acc_t acc_t;
     constexpr int EA = BM * BK / 256, EB = BN * BK / 256;   // elements per thread per tile
+    constexpr bool A_KMAJ = AMODE != LD_MMAJ, B_KMAJ = BMODE != LD_MMAJ;
+    constexpr bool AV = AMODE == LD_KVEC, BV = BMODE == LD_KVEC;
+    constexpr int VEC = 16 / (int)sizeof(T), CPR = BK / VEC;  // chunk width, chunks per row
+    constexpr int CA = EA / VEC, CB = EB / VEC;              // chunks per thread (vector loads)
+    typedef T vT __attribute__((ext_vector_type(VEC)));
+    static_assert(EA % VEC == 0 && EB % VEC == 0 && 256 % CPR == 0, "vector staging shape");
     constexpr int FM = BM / 32, FN = BN / 32;              // 16x16 blocks per wave
     static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
     static_assert(BK == 16, "the LDS layout holds 16 positions per row");
@@ -174,6 +184,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             for (int j = 0; j < FM; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
         T ra[EA], rb[EB];
+        vT va[CA], vb[CB];
         // K-table entries of the next tile are fetched one tile ahead, so the
         // table lookup and the operand load never form a dependent chain inside
         // one tile.  In K-major loading a thread always handles the same k of
@@ -183,9 +194,11 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         auto tload = [&](int64_t kt) {
             const int64_t* kt0 = a.ktab + 2 * kt * BK;
 #pragma unroll
-            for (int e = 0; e < TA; ++e) tA[e] = kt0[2 * (A_KMAJ ? tid % BK : (tid + 256 * e) / BM)];
+            for (int e = 0; e < TA; ++e)
+                tA[e] = kt0[2 * (AV ? VEC * (tid % CPR) : A_KMAJ ? tid % BK : (tid + 256 * e) / BM)];
 #pragma unroll
-            for (int e = 0; e < TB; ++e) tB[e] = kt0[2 * (B_KMAJ ? tid % BK : (tid + 256 * e) / BN) + 1];
+            for (int e = 0; e < TB; ++e)
+                tB[e] = kt0[2 * (BV ? VEC * (tid % CPR) : B_KMAJ ? tid % BK : (tid + 256 * e) / BN) + 1];
         };
         // Operand loads with clamped addresses (element (batch, pass, 0, 0) is
         // always valid), so no branch sits around a load.  The raw values stay
@@ -196,37 +209,74 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         auto gload = [&]() {
             okA = 0;
             okB = 0;
+            if constexpr (AV) {
+                // 16-byte chunks: chunk q = row q / CPR, positions VEC * (q % CPR) ..
 #pragma unroll
-            for (int e = 0; e < EA; ++e) {
-                const int idx = tid + 256 * e;
-                const int64_t om = sAm[A_KMAJ ? idx / BK : idx % BM];
-                const int64_t ko = tA[A_KMAJ ? 0 : e];
-                const bool ok = (om >= 0) & (ko >= 0);
-                ra[e] = Ag[bA + pA + (ok ? om + ko : 0)];
-                okA |= (uint32_t)ok << e;
+                for (int e = 0; e < CA; ++e) {
+                    const int64_t om = sAm[(tid + 256 * e) / CPR];
+                    const bool ok = (om >= 0) & (tA[0] >= 0);
+                    va[e] = *(const vT*)(Ag + bA + pA + (ok ? om + tA[0] : 0));
+                    okA |= (uint32_t)ok << e;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < EA; ++e) {
+                    const int idx = tid + 256 * e;
+                    const int64_t om = sAm[A_KMAJ ? idx / BK : idx % BM];
+                    const int64_t ko = tA[A_KMAJ ? 0 : e];
+                    const bool ok = (om >= 0) & (ko >= 0);
+                    ra[e] = Ag[bA + pA + (ok ? om + ko : 0)];
+                    okA |= (uint32_t)ok << e;
+                }
             }
+            if constexpr (BV) {
 #pragma unroll
-            for (int e = 0; e < EB; ++e) {
-                const int idx = tid + 256 * e;
-                const int64_t on = sBn[B_KMAJ ? idx / BK : idx % BN];
-                const int64_t ko = tB[B_KMAJ ? 0 : e];
-                const bool ok = (on >= 0) & (ko >= 0);
-                rb[e] = Bg[bB + pB + (ok ? on + ko : 0)];
-                okB |= (uint32_t)ok << e;
+                for (int e = 0; e < CB; ++e) {
+                    const int64_t on = sBn[(tid + 256 * e) / CPR];
+                    const bool ok = (on >= 0) & (tB[0] >= 0);
+                    vb[e] = *(const vT*)(Bg + bB + pB + (ok ? on + tB[0] : 0));
+                    okB |= (uint32_t)ok << e;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < EB; ++e) {
+                    const int idx = tid + 256 * e;
+                    const int64_t on = sBn[B_KMAJ ? idx / BK : idx % BN];
+                    const int64_t ko = tB[B_KMAJ ? 0 : e];
+                    const bool ok = (on >= 0) & (ko >= 0);
+                    rb[e] = Bg[bB + pB + (ok ? on + ko : 0)];
+                    okB |= (uint32_t)ok << e;
+                }
             }
         };
         auto sstore = [&](int buf) {
+            if constexpr (AV) {
 #pragma unroll
-            for (int e = 0; e < EA; ++e) {
-                const int idx = tid + 256 * e;
-                As[buf][tile_at<T>(A_KMAJ ? idx / BK : idx % BM, A_KMAJ ? idx % BK : idx / BM)] =
-                    (okA >> e) & 1 ? ra[e] : (T)0;
+                for (int e = 0; e < CA; ++e) {
+                    const int q = tid + 256 * e;
+                    *(vT*)&As[buf][tile_at<T>(q / CPR, VEC * (q % CPR))] = (okA >> e) & 1 ? va[e] : vT(0);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < EA; ++e) {
+                    const int idx = tid + 256 * e;
+                    As[buf][tile_at<T>(A_KMAJ ? idx / BK : idx % BM, A_KMAJ ? idx % BK : idx / BM)] =
+                        (okA >> e) & 1 ? ra[e] : (T)0;
+                }
             }
+            if constexpr (BV) {
 #pragma unroll
-            for (int e = 0; e < EB; ++e) {
-                const int idx = tid + 256 * e;
-                Bs[buf][tile_at<T>(B_KMAJ ? idx / BK : idx % BN, B_KMAJ ? idx % BK : idx / BN)] =
-                    (okB >> e) & 1 ? rb[e] : (T)0;
+                for (int e = 0; e < CB; ++e) {
+                    const int q = tid + 256 * e;
+                    *(vT*)&Bs[buf][tile_at<T>(q / CPR, VEC * (q % CPR))] = (okB >> e) & 1 ? vb[e] : vT(0);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < EB; ++e) {
+                    const int idx = tid + 256 * e;
+                    Bs[buf][tile_at<T>(B_KMAJ ? idx / BK : idx % BN, B_KMAJ ? idx % BK : idx / BN)] =
+                        (okB >> e) & 1 ? rb[e] : (T)0;
+                }
             }
         };
 
@@ -307,15 +357,15 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     }
 }
 
-template <typename T, int BM, int BN, int BK, bool A_KMAJ, bool B_KMAJ>
+template <typename T, int BM, int BN, int BK, int AMODE, int BMODE>
 __global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
-    mfma_tile<T, BM, BN, BK, A_KMAJ, B_KMAJ>(a, a.A, a.B, a.C, a.alpha, a.beta, xcd_tile(blockIdx.x, a.ntiles));
+    mfma_tile<T, BM, BN, BK, AMODE, BMODE>(a, a.A, a.B, a.C, a.alpha, a.beta, xcd_tile(blockIdx.x, a.ntiles));
 }
 
 // Persistent form for batches: blocks take work items (contraction, tile) off
 // an atomic counter until the list is exhausted, so every block exits once
 // the counter passes nwork.
-template <typename T, int BM, int BN, int BK, bool A_KMAJ, bool B_KMAJ>
+template <typename T, int BM, int BN, int BK, int AMODE, int BMODE>
 __global__ __launch_bounds__(256) void k_mfma_batch(const MfmaArgs* __restrict__ items,
                                                     const BatchPtrs* __restrict__ ptrs,
                                                     const int2* __restrict__ work, int nwork, int* counter) {
@@ -327,7 +377,7 @@ __global__ __launch_bounds__(256) void k_mfma_batch(const MfmaArgs* __restrict__
         if (w >= nwork) break;
         const int2 wi = work[w];
         const BatchPtrs& pt = ptrs[wi.x];
-        mfma_tile<T, BM, BN, BK, A_KMAJ, B_KMAJ>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha, pt.beta, wi.y);
+        mfma_tile<T, BM, BN, BK, AMODE, BMODE>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha, pt.beta, wi.y);
         __syncthreads();   // the tile's LDS tables and s_w are reused by the next item
     }
 }
@@ -345,18 +395,6 @@ void mfma_tiles(bool, MfmaArgs& a) {
     a.ntiles = a.mt * a.nt * a.nbatch;
 }
 
-template <typename T>
-static hipError_t mfma_dispatch(MfmaArgs& a, bool akmaj, bool bkmaj, hipStream_t st) {
-    if (a.ntiles <= 0) return hipSuccess;
-    if (a.ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-    dim3 g((unsigned)a.ntiles), b(256);
-    if (akmaj && bkmaj) hipLaunchKernelGGL((k_mfma<T, kBM, kBN, kBK, true, true>), g, b, 0, st, a);
-    else if (akmaj) hipLaunchKernelGGL((k_mfma<T, kBM, kBN, kBK, true, false>), g, b, 0, st, a);
-    else if (bkmaj) hipLaunchKernelGGL((k_mfma<T, kBM, kBN, kBK, false, true>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_mfma<T, kBM, kBN, kBK, false, false>), g, b, 0, st, a);
-    return hipGetLastError();
-}
-
 // Lanes go along K for an operand whose free group is not unit-stride.
 static bool k_major(const GtDims& g, int slot) {
     if (g.n == 0) return true;
@@ -364,13 +402,56 @@ static bool k_major(const GtDims& g, int slot) {
     return s != 1;
 }
 
+// every offset of the group is a multiple of v elements
+static bool group_aligned(const GtDims& g, int slot, int64_t v) {
+    for (int d = 0; d < g.n; ++d) {
+        int64_t s = slot == 0 ? g.d[d].sA : g.d[d].sB;
+        if (g.d[d].ext > 1 && s % v != 0) return false;
+    }
+    return true;
+}
+
+// Load mode of operand `slot` (0 = A over the M group, 1 = B over N):
+// 16-byte chunk loads when lanes run along K, the K table's chunks are
+// contiguous and aligned (flag from the planner), every row, batch and pass
+// offset is a multiple of the chunk and the base pointer is 16-byte aligned.
+static int load_mode(const MfmaArgs& a, bool f64, int slot) {
+    const GtDims& g = slot == 0 ? a.m : a.n;
+    if (!k_major(g, slot)) return LD_MMAJ;
+    const int64_t v = f64 ? 2 : 4;
+    const void* base = slot == 0 ? a.A : a.B;
+    bool vec = ((a.kvec >> slot) & 1) && group_aligned(g, slot, v) && group_aligned(a.batch, slot, v) &&
+               group_aligned(a.pass, slot, v) && ((uintptr_t)base % 16 == 0);
+    return vec ? LD_KVEC : LD_KSCAL;
+}
+
+template <typename T, int BM, int BN>
+static hipError_t tile_dispatch(const MfmaArgs& a, int am, int bm, hipStream_t st) {
+    if (a.ntiles <= 0) return hipSuccess;
+    if (a.ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
+    dim3 g((unsigned)a.ntiles), b(256);
+    switch (am * 3 + bm) {
+        case 0: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 0, 0>), g, b, 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 0, 1>), g, b, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 0, 2>), g, b, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 1, 0>), g, b, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 1, 1>), g, b, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 1, 2>), g, b, 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 2, 0>), g, b, 0, st, a); break;
+        case 7: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 2, 1>), g, b, 0, st, a); break;
+        default: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 2, 2>), g, b, 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st) {
-    bool ak = k_major(a.m, 0), bk = k_major(a.n, 1);
-    return f64 ? mfma_dispatch<double>(a, ak, bk, st) : mfma_dispatch<float>(a, ak, bk, st);
+    int am = load_mode(a, f64, 0), bm = load_mode(a, f64, 1);
+    return f64 ? tile_dispatch<double, kBM, kBN>(a, am, bm, st) : tile_dispatch<float, kBM, kBN>(a, am, bm, st);
 }
 
 // ---------------------------------------------------------------------------
-// Batches: tile shapes 0 = 128x128, 1 = 64x64.
+// Batches: tile shapes 0 = 128x128, 1 = 64x64.  Batch members use the scalar
+// load modes (their K tables are not checked for chunk contiguity).
 static void shape_dims(int shape, int& bm, int& bn) {
     bm = shape == 0 ? 128 : 64;
     bn = bm;
@@ -391,10 +472,10 @@ template <typename T, int BM, int BN>
 static hipError_t batch_dispatch(bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs, const int2* work,
                                  int nwork, int* counter, int grid, hipStream_t st) {
     dim3 g(grid), b(256);
-    if (ak && bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, true, true>), g, b, 0, st, items, ptrs, work, nwork, counter);
-    else if (ak) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, true, false>), g, b, 0, st, items, ptrs, work, nwork, counter);
-    else if (bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, false, true>), g, b, 0, st, items, ptrs, work, nwork, counter);
-    else hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, false, false>), g, b, 0, st, items, ptrs, work, nwork, counter);
+    if (ak && bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 1>), g, b, 0, st, items, ptrs, work, nwork, counter);
+    else if (ak) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 0>), g, b, 0, st, items, ptrs, work, nwork, counter);
+    else if (bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 1>), g, b, 0, st, items, ptrs, work, nwork, counter);
+    else hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 0>), g, b, 0, st, items, ptrs, work, nwork, counter);
     return hipGetLastError();
 }
 
@@ -413,10 +494,10 @@ template <typename T, int BM, int BN>
 static int occ_of(bool ak, bool bk) {
     int n = 0;
     hipError_t e;
-    if (ak && bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, true, true>, 256, 0);
-    else if (ak) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, true, false>, 256, 0);
-    else if (bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, false, true>, 256, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, false, false>, 256, 0);
+    if (ak && bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 1, 1>, 256, 0);
+    else if (ak) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 1, 0>, 256, 0);
+    else if (bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 0, 1>, 256, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 0, 0>, 256, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
@@ -429,21 +510,8 @@ int mfma_batch_occupancy(bool f64, int shape, bool ak, bool bk) {
 hipError_t launch_mfma_shape(bool f64, int shape, MfmaArgs& a, hipStream_t st) {
     if (shape == 0) return launch_mfma(f64, a, st);
     mfma_tiles_shape(1, a);
-    if (a.ntiles <= 0) return hipSuccess;
-    bool ak = k_major(a.m, 0), bk = k_major(a.n, 1);
-    dim3 g((unsigned)a.ntiles), b(256);
-    if (f64) {
-        if (ak && bk) hipLaunchKernelGGL((k_mfma<double, 64, 64, kBK, true, true>), g, b, 0, st, a);
-        else if (ak) hipLaunchKernelGGL((k_mfma<double, 64, 64, kBK, true, false>), g, b, 0, st, a);
-        else if (bk) hipLaunchKernelGGL((k_mfma<double, 64, 64, kBK, false, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((k_mfma<double, 64, 64, kBK, false, false>), g, b, 0, st, a);
-    } else {
-        if (ak && bk) hipLaunchKernelGGL((k_mfma<float, 64, 64, kBK, true, true>), g, b, 0, st, a);
-        else if (ak) hipLaunchKernelGGL((k_mfma<float, 64, 64, kBK, true, false>), g, b, 0, st, a);
-        else if (bk) hipLaunchKernelGGL((k_mfma<float, 64, 64, kBK, false, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((k_mfma<float, 64, 64, kBK, false, false>), g, b, 0, st, a);
-    }
-    return hipGetLastError();
+    int am = load_mode(a, f64, 0), bm = load_mode(a, f64, 1);
+    return f64 ? tile_dispatch<double, 64, 64>(a, am, bm, st) : tile_dispatch<float, 64, 64>(a, am, bm, st);
 }
 
 }  // namespace tc

@@ -36,8 +36,10 @@ struct tc_plan_s {
     // device workspace (allocated by prepare, freed by destroy)
     void* d_ktab = nullptr;          // fused matrix-core K table
     int64_t ktab_cap = 0, kpad = 0;
+    int kvec = 0;                    // chunk flags of d_ktab (MfmaArgs::kvec)
     void* d_var_ktab = nullptr;      // K table of the selected gemm member
     int64_t var_ktab_cap = 0, var_kpad = 0;
+    int var_kvec = 0;
     int var_ktab_for = -1;
     void* d_temp[2] = {nullptr, nullptr};   // copy temporaries of A and B
     int64_t temp_cap[2] = {0, 0};
@@ -58,6 +60,7 @@ tc_status fail(tc_status s, const std::string& msg);
 tc_status hip_fail(hipError_t e, const char* what);
 
 std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA = 4);
+int ktab_vec_flags(const std::vector<int64_t>& tab, int v);
 bool use_stream_kernel(const Spec& s, const GemmView& gv);
 tc_status prepare_plan(tc_plan_s* p);
 tc_status contract_dispatch(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,

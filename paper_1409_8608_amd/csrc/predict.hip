@@ -106,6 +106,7 @@ static hipError_t launch_body(PredCtx& c, const VariantPlan& vp, const GtDesc& d
         a.M = d.nm ? d.out.d[0].ext : 1;
         a.N = d.nn ? d.out.d[d.nm].ext : 1;
         a.Kpad = p->var_kpad;
+        a.kvec = p->var_kvec;
         a.alpha = 1.0; a.beta = 1.0;
         a.mode = 1;
         mfma_tiles(f64, a);

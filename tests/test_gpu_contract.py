@@ -87,6 +87,53 @@ def test_fused_mfma_shapes(dtype, spec, ext):
     check(spec, ext, A, B, got, dtype)
 
 
+# Operand staging modes of the matrix-core kernel: 16-byte K chunks where the
+# K table's chunks are contiguous and every row offset is a chunk multiple,
+# single elements otherwise.  Ragged M/N tiles, K padded inside a tile (i=20),
+# a K extent that splits a chunk (i=22: element loads), a row stride that is a
+# multiple of 2 but not 4 (FP64 chunks, FP32 elements), two contracted indices.
+MFMA_CHUNK_SHAPES = [
+    ("abc=ija,jbic", dict(a=40, b=36, c=7, i=8, j=12)),
+    ("ab=ia,ib", dict(a=100, b=50, i=20)),
+    ("ab=ia,ib", dict(a=64, b=70, i=22)),
+    ("ab=ia,ib", dict(a=90, b=33, i=18)),
+    ("ab=iaj,jbi", dict(a=130, b=70, i=8, j=8)),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", MFMA_CHUNK_SHAPES)
+def test_fused_mfma_chunk_loads(dtype, spec, ext):
+    rng = np.random.default_rng(13)
+    A, B, C0 = wl.tensors(spec, ext, rng, "normal", with_c=True)
+    p = _plan(spec, ext, dtype)
+    got = run(p, A, B, dtype=dtype)
+    check(spec, ext, A, B, got, dtype)
+    got = run(p, A, B, C0, alpha=0.5, beta=-2.0, dtype=dtype)
+    check(spec, ext, A, B, got, dtype, C0=C0, alpha=0.5, beta=-2.0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fused_mfma_unaligned_base(dtype):
+    """Operands that start one element past a 16-byte boundary take the
+    element loads; same result as the aligned call."""
+    torch = pytest.importorskip("torch")
+    spec, ext = "ab=ia,ib", dict(a=100, b=50, i=20)
+    A, B, _ = wl.tensors(spec, ext, np.random.default_rng(14), "normal")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    p = _plan(spec, ext, dtype)
+    bufA = torch.zeros(A.size + 1, dtype=tdt, device="cuda")
+    bufB = torch.zeros(B.size + 1, dtype=tdt, device="cuda")
+    dA = torch.as_strided(bufA, A.shape, (1, A.shape[0]), 1)
+    dB = torch.as_strided(bufB, B.shape, (1, B.shape[0]), 1)
+    dA.copy_(torch.from_numpy(A))
+    dB.copy_(torch.from_numpy(B))
+    dC = tc.empty_fortran(p.shape("C"), tdt).fill_(float("nan"))
+    p.contract(dA, dB, dC)
+    torch.cuda.synchronize()
+    check(spec, ext, A, B, dC.double().cpu().numpy(), dtype)
+
+
 def test_fused_mfma_integer_exact():
     spec, ext = "abc=ija,jbic", dict(a=70, b=20, c=9, i=13, j=17)
     A, B, C = wl.tensors(spec, ext, np.random.default_rng(5), integer=True, with_c=True)
