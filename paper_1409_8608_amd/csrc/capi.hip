@@ -28,10 +28,13 @@ tc_status hip_fail(hipError_t e, const char* what) {
 // Blocked K order for the matrix-core kernels.  Tiles of BK contracted
 // positions are rectangles, bA positions along the contracted index that is
 // contiguous in A (dA) by BK / bA along the one contiguous in B (dB), so both
-// operands read runs; tiles are ordered with dB's blocks fastest.  Positions
-// are (offA, offB) pairs; a tile that is not full is padded with (-1, -1)
-// entries (zero contributions).
-std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA) {
+// operands read runs.  Blocks are walked with one of dA, dB fastest
+// (`a_first`), in super-blocks of G blocks along each of them (G = 0: the
+// whole extent), then the other contracted indices in order: an operand whose
+// contiguous index walks fastest reuses each cache line on consecutive tiles,
+// the other one every G tiles.  Positions are (offA, offB) pairs; a tile that
+// is not full is padded with (-1, -1) entries (zero contributions).
+std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA, bool a_first, int G) {
     std::vector<int64_t> tab;
     int nd = (int)kd.size();
     int64_t K = 1;
@@ -50,57 +53,70 @@ std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA) {
         int d = dA >= 0 ? dA : dB >= 0 ? dB : 0;
         bs[d] = std::min<int64_t>(kd[d].ext, BK);
     }
-    // block origins: odometer with dB fastest, then dA, then the rest in order
-    std::vector<int> order;
-    if (dB >= 0) order.push_back(dB);
-    if (dA >= 0 && dA != dB) order.push_back(dA);
-    for (int d = 0; d < nd; ++d)
-        if (d != dA && d != dB) order.push_back(d);
     std::vector<int64_t> nblk(nd);
     for (int d = 0; d < nd; ++d) nblk[d] = (kd[d].ext + bs[d] - 1) / bs[d];
-    std::vector<int64_t> bi(nd, 0);
+    // Walk digits: (dim, weight, range).  Block index along d = sum of its
+    // digits times weights; a combination past nblk[d] is skipped.
+    struct Digit { int d; int64_t w, n; };
+    std::vector<Digit> dig;
+    int f = a_first ? dA : dB, s = a_first ? dB : dA;
+    if (s == f) s = -1;
+    auto gsz = [&](int d) { return G > 0 ? std::min<int64_t>(G, nblk[d]) : nblk[d]; };
+    if (f >= 0) dig.push_back({f, 1, gsz(f)});
+    if (s >= 0) dig.push_back({s, 1, gsz(s)});
+    if (f >= 0) dig.push_back({f, gsz(f), (nblk[f] + gsz(f) - 1) / gsz(f)});
+    if (s >= 0) dig.push_back({s, gsz(s), (nblk[s] + gsz(s) - 1) / gsz(s)});
+    for (int d = 0; d < nd; ++d)
+        if (d != dA && d != dB) dig.push_back({d, 1, nblk[d]});
+    // points inside a block: dA fastest, then dB, then the others
+    std::vector<int> inner;
+    if (dA >= 0) inner.push_back(dA);
+    if (dB >= 0 && dB != dA) inner.push_back(dB);
+    for (int d = 0; d < nd; ++d)
+        if (d != dA && d != dB) inner.push_back(d);
+    std::vector<int64_t> dv(dig.size(), 0), bi(nd);
     while (true) {
-        // points inside this block: dA fastest, then dB, then others
-        std::vector<int> inner;
-        if (dA >= 0) inner.push_back(dA);
-        if (dB >= 0 && dB != dA) inner.push_back(dB);
+        std::fill(bi.begin(), bi.end(), 0);
+        for (size_t q = 0; q < dig.size(); ++q) bi[dig[q].d] += dv[q] * dig[q].w;
+        bool inside = true;
         for (int d = 0; d < nd; ++d)
-            if (d != dA && d != dB) inner.push_back(d);
-        std::vector<int64_t> li(nd, 0);
-        int cnt = 0;
-        while (true) {
-            bool ok = true;
-            int64_t oa = 0, ob = 0;
-            for (int d = 0; d < nd; ++d) {
-                int64_t x = bi[d] * bs[d] + li[d];
-                if (x >= kd[d].ext) ok = false;
-                oa += x * kd[d].sA;
-                ob += x * kd[d].sB;
+            if (bi[d] >= nblk[d]) inside = false;
+        if (inside) {
+            std::vector<int64_t> li(nd, 0);
+            int cnt = 0;
+            while (true) {
+                bool ok = true;
+                int64_t oa = 0, ob = 0;
+                for (int d = 0; d < nd; ++d) {
+                    int64_t x = bi[d] * bs[d] + li[d];
+                    if (x >= kd[d].ext) ok = false;
+                    oa += x * kd[d].sA;
+                    ob += x * kd[d].sB;
+                }
+                if (ok) {
+                    tab.push_back(oa);
+                    tab.push_back(ob);
+                    ++cnt;
+                }
+                int q = 0;
+                for (; q < (int)inner.size(); ++q) {
+                    int d = inner[q];
+                    if (++li[d] < bs[d]) break;
+                    li[d] = 0;
+                }
+                if (q == (int)inner.size()) break;
             }
-            if (ok) {
-                tab.push_back(oa);
-                tab.push_back(ob);
-                ++cnt;
+            for (; cnt % BK != 0 || cnt == 0; ++cnt) {
+                tab.push_back(-1);
+                tab.push_back(-1);
             }
-            int q = 0;
-            for (; q < (int)inner.size(); ++q) {
-                int d = inner[q];
-                if (++li[d] < bs[d]) break;
-                li[d] = 0;
-            }
-            if (q == (int)inner.size()) break;
         }
-        for (; cnt % BK != 0 || cnt == 0; ++cnt) {
-            tab.push_back(-1);
-            tab.push_back(-1);
+        size_t q = 0;
+        for (; q < dig.size(); ++q) {
+            if (++dv[q] < dig[q].n) break;
+            dv[q] = 0;
         }
-        int q = 0;
-        for (; q < (int)order.size(); ++q) {
-            int d = order[q];
-            if (++bi[d] < nblk[d]) break;
-            bi[d] = 0;
-        }
-        if (q == (int)order.size()) break;
+        if (q == dig.size()) break;
     }
     return tab;
 }
@@ -168,7 +184,7 @@ tc_status prepare_plan(tc_plan_s* p) {
     int BK = mfma_bk(f64);
     if (p->selected == TC_VARIANT_FUSED || p->selected == TC_VARIANT_PREDICTED) {
         if (!use_stream_kernel(s, p->gv) && p->d_ktab == nullptr) {
-            std::vector<int64_t> tab = build_ktab(p->gv.k, BK);
+            std::vector<int64_t> tab = build_ktab(p->gv.k, BK, 4, mfma_a_first(p->gv.M, p->gv.N), 4);
             p->kpad = (int64_t)tab.size() / 2;
             p->kvec = ktab_vec_flags(tab, f64 ? 2 : 4);
             tc_status st = upload(&p->d_ktab, &p->ktab_cap, tab);

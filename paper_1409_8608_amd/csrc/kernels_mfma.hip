@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "launch.h"
 
@@ -183,12 +184,18 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
 #pragma unroll
             for (int j = 0; j < FM; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-        T ra[EA], rb[EB];
-        vT va[CA], vb[CB];
-        // K-table entries of the next tile are fetched one tile ahead, so the
-        // table lookup and the operand load never form a dependent chain inside
-        // one tile.  In K-major loading a thread always handles the same k of
-        // a tile (one entry); in M/N-major loading it handles EA/EB of them.
+        // Register slots for operand tiles in flight: tile kt + NS - 1 is
+        // loaded while tile kt is multiplied, so a load has NS - 1 tiles of
+        // MFMA time to arrive.  FP32 keeps two tiles in flight (its MFMAs take
+        // half as long per tile as FP64's), FP64 one.
+        constexpr int NS = sizeof(T) == 4 ? 3 : 2;
+        T ra[NS - 1][EA], rb[NS - 1][EB];
+        vT va[NS - 1][CA], vb[NS - 1][CB];
+        uint32_t okA[NS - 1], okB[NS - 1];
+        // K-table entries of a tile are fetched one tile before its operands,
+        // so the table lookup and the operand load never form a dependent
+        // chain.  In K-major loading a thread always handles the same k of a
+        // tile (one entry); in M/N-major loading it handles EA/EB of them.
         constexpr int TA = A_KMAJ ? 1 : EA, TB = B_KMAJ ? 1 : EB;
         int64_t tA[TA], tB[TB];
         auto tload = [&](int64_t kt) {
@@ -203,20 +210,18 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         // Operand loads with clamped addresses (element (batch, pass, 0, 0) is
         // always valid), so no branch sits around a load.  The raw values stay
         // in registers with a validity mask; padding is zeroed only when the
-        // tile is written to LDS, after the MFMAs of the current tile, so the
-        // loads of the next tile stay in flight meanwhile.
-        uint32_t okA = 0, okB = 0;
-        auto gload = [&]() {
-            okA = 0;
-            okB = 0;
+        // tile is written to LDS, so the loads stay in flight until then.
+        auto gload = [&](auto slot_c) {
+            constexpr int sl = decltype(slot_c)::value;
+            uint32_t ma = 0, mb = 0;
             if constexpr (AV) {
                 // 16-byte chunks: chunk q = row q / CPR, positions VEC * (q % CPR) ..
 #pragma unroll
                 for (int e = 0; e < CA; ++e) {
                     const int64_t om = sAm[(tid + 256 * e) / CPR];
                     const bool ok = (om >= 0) & (tA[0] >= 0);
-                    va[e] = *(const vT*)(Ag + bA + pA + (ok ? om + tA[0] : 0));
-                    okA |= (uint32_t)ok << e;
+                    va[sl][e] = *(const vT*)(Ag + bA + pA + (ok ? om + tA[0] : 0));
+                    ma |= (uint32_t)ok << e;
                 }
             } else {
 #pragma unroll
@@ -225,8 +230,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                     const int64_t om = sAm[A_KMAJ ? idx / BK : idx % BM];
                     const int64_t ko = tA[A_KMAJ ? 0 : e];
                     const bool ok = (om >= 0) & (ko >= 0);
-                    ra[e] = Ag[bA + pA + (ok ? om + ko : 0)];
-                    okA |= (uint32_t)ok << e;
+                    ra[sl][e] = Ag[bA + pA + (ok ? om + ko : 0)];
+                    ma |= (uint32_t)ok << e;
                 }
             }
             if constexpr (BV) {
@@ -234,8 +239,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 for (int e = 0; e < CB; ++e) {
                     const int64_t on = sBn[(tid + 256 * e) / CPR];
                     const bool ok = (on >= 0) & (tB[0] >= 0);
-                    vb[e] = *(const vT*)(Bg + bB + pB + (ok ? on + tB[0] : 0));
-                    okB |= (uint32_t)ok << e;
+                    vb[sl][e] = *(const vT*)(Bg + bB + pB + (ok ? on + tB[0] : 0));
+                    mb |= (uint32_t)ok << e;
                 }
             } else {
 #pragma unroll
@@ -244,85 +249,108 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                     const int64_t on = sBn[B_KMAJ ? idx / BK : idx % BN];
                     const int64_t ko = tB[B_KMAJ ? 0 : e];
                     const bool ok = (on >= 0) & (ko >= 0);
-                    rb[e] = Bg[bB + pB + (ok ? on + ko : 0)];
-                    okB |= (uint32_t)ok << e;
+                    rb[sl][e] = Bg[bB + pB + (ok ? on + ko : 0)];
+                    mb |= (uint32_t)ok << e;
                 }
             }
+            okA[sl] = ma;
+            okB[sl] = mb;
         };
-        auto sstore = [&](int buf) {
+        auto sstore = [&](int buf, auto slot_c) {
+            constexpr int sl = decltype(slot_c)::value;
             if constexpr (AV) {
 #pragma unroll
                 for (int e = 0; e < CA; ++e) {
                     const int q = tid + 256 * e;
-                    *(vT*)&As[buf][tile_at<T>(q / CPR, VEC * (q % CPR))] = (okA >> e) & 1 ? va[e] : vT(0);
+                    *(vT*)&As[buf][tile_at<T>(q / CPR, VEC * (q % CPR))] = (okA[sl] >> e) & 1 ? va[sl][e] : vT(0);
                 }
             } else {
 #pragma unroll
                 for (int e = 0; e < EA; ++e) {
                     const int idx = tid + 256 * e;
                     As[buf][tile_at<T>(A_KMAJ ? idx / BK : idx % BM, A_KMAJ ? idx % BK : idx / BM)] =
-                        (okA >> e) & 1 ? ra[e] : (T)0;
+                        (okA[sl] >> e) & 1 ? ra[sl][e] : (T)0;
                 }
             }
             if constexpr (BV) {
 #pragma unroll
                 for (int e = 0; e < CB; ++e) {
                     const int q = tid + 256 * e;
-                    *(vT*)&Bs[buf][tile_at<T>(q / CPR, VEC * (q % CPR))] = (okB >> e) & 1 ? vb[e] : vT(0);
+                    *(vT*)&Bs[buf][tile_at<T>(q / CPR, VEC * (q % CPR))] = (okB[sl] >> e) & 1 ? vb[sl][e] : vT(0);
                 }
             } else {
 #pragma unroll
                 for (int e = 0; e < EB; ++e) {
                     const int idx = tid + 256 * e;
                     Bs[buf][tile_at<T>(B_KMAJ ? idx / BK : idx % BN, B_KMAJ ? idx % BK : idx / BN)] =
-                        (okB >> e) & 1 ? rb[e] : (T)0;
+                        (okB[sl] >> e) & 1 ? rb[sl][e] : (T)0;
                 }
             }
         };
+        auto compute = [&](int buf) {
+            // this lane's positions 4g .. 4g+3 of each fragment row, g = lane / 16
+            typedef T v4 __attribute__((ext_vector_type(4)));
+            constexpr int CE = TileLds<T>::CE;
+            const int g = lane >> 4, r16 = lane & 15;
+            auto frag = [&](const T* tile, int row) -> v4 {
+                v4 v;
+#pragma unroll
+                for (int h = 0; h < 4 / CE; ++h) {
+                    typedef T vc __attribute__((ext_vector_type(CE)));
+                    const vc c = *(const vc*)(tile + row * 16 + TileLds<T>::swz(row, (4 * g) / CE + h) * CE);
+#pragma unroll
+                    for (int q = 0; q < CE; ++q) v[h * CE + q] = c[q];
+                }
+                return v;
+            };
+            v4 fb[FN];
+#pragma unroll
+            for (int i = 0; i < FN; ++i) fb[i] = frag(Bs[buf], wn * (BN / 2) + i * 16 + r16);
+#pragma unroll
+            for (int j = 0; j < FM; ++j) {
+                const v4 fa = frag(As[buf], wm * (BM / 2) + j * 16 + r16);
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                    for (int i = 0; i < FN; ++i) acc[i][j] = Mfma<T>::mac(fb[i][s4], fa[s4], acc[i][j]);
+            }
+        };
+        typedef std::integral_constant<int, 0> S0;
+        typedef std::integral_constant<int, NS - 2> SL;   // slot 1 (FP32) or 0 (FP64)
 
+        // prologue: tile 0 to LDS, tiles 1 .. NS-2 in registers, table of the
+        // next tile to load
         if (ktiles > 0) {
             tload(0);
-            gload();
-            sstore(0);
-            if (ktiles > 1) tload(1);
+            gload(S0{});
+            sstore(0, S0{});
         }
+        if (NS == 3 && ktiles > 1) {
+            tload(1);
+            gload(SL{});
+        }
+        if (ktiles > NS - 1) tload(NS - 1);
         __syncthreads();
-        for (int64_t kt = 0; kt < ktiles; ++kt) {
+        // one K tile: load tile kt + NS - 1 into the slot that tile kt + 1
+        // does not use, multiply tile kt, store tile kt + 1 from its slot
+        auto step = [&](int64_t kt, auto ld_c, auto st_c) {
             const int buf = (int)(kt & 1);
-            if (kt + 1 < ktiles) {
-                gload();
-                if (kt + 2 < ktiles) tload(kt + 2);
+            if (kt + NS - 1 < ktiles) {
+                gload(ld_c);
+                if (kt + NS < ktiles) tload(kt + NS);
             }
-            {
-                // this lane's positions 4g .. 4g+3 of each fragment row, g = lane / 16
-                typedef T v4 __attribute__((ext_vector_type(4)));
-                constexpr int CE = TileLds<T>::CE;
-                const int g = lane >> 4, r16 = lane & 15;
-                auto frag = [&](const T* tile, int row) -> v4 {
-                    v4 v;
-#pragma unroll
-                    for (int h = 0; h < 4 / CE; ++h) {
-                        typedef T vc __attribute__((ext_vector_type(CE)));
-                        const vc c = *(const vc*)(tile + row * 16 + TileLds<T>::swz(row, (4 * g) / CE + h) * CE);
-#pragma unroll
-                        for (int q = 0; q < CE; ++q) v[h * CE + q] = c[q];
-                    }
-                    return v;
-                };
-                v4 fb[FN];
-#pragma unroll
-                for (int i = 0; i < FN; ++i) fb[i] = frag(Bs[buf], wn * (BN / 2) + i * 16 + r16);
-#pragma unroll
-                for (int j = 0; j < FM; ++j) {
-                    const v4 fa = frag(As[buf], wm * (BM / 2) + j * 16 + r16);
-#pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-                        for (int i = 0; i < FN; ++i) acc[i][j] = Mfma<T>::mac(fb[i][s4], fa[s4], acc[i][j]);
-                }
-            }
-            if (kt + 1 < ktiles) sstore(buf ^ 1);
+            compute(buf);
+            if (kt + 1 < ktiles) sstore(buf ^ 1, st_c);
             __syncthreads();
+        };
+        if constexpr (NS == 3) {
+            // slots alternate: tile t sits in slot t % 2
+            for (int64_t kt = 0; kt < ktiles; kt += 2) {
+                step(kt, S0{}, SL{});
+                if (kt + 1 < ktiles) step(kt + 1, SL{}, S0{});
+            }
+        } else {
+            for (int64_t kt = 0; kt < ktiles; ++kt) step(kt, S0{}, S0{});
         }
 
         // epilogue: lane holds D[n = row(lane, q)][m = lane % 16] of each block
@@ -393,6 +421,18 @@ void mfma_tiles(bool, MfmaArgs& a) {
     a.mt = (a.M + kBM - 1) / kBM;
     a.nt = (a.N + kBN - 1) / kBN;
     a.ntiles = a.mt * a.nt * a.nbatch;
+}
+
+// K-table walk for a fused M x N launch.  Tiles are dealt to the 8 XCDs in
+// contiguous ranges with m tiles fastest, so the blocks resident on one XCD
+// (at most about 64) span min(mt, R) m tiles and R / mt n tiles.  The operand
+// with more distinct rows in that set walks its contiguous contracted index
+// fastest (its cache lines are reused on consecutive K tiles); the other
+// reuses its lines every 4 tiles (super-blocks of 4 blocks).
+bool mfma_a_first(int64_t M, int64_t N) {
+    const int64_t mt = (M + kBM - 1) / kBM, nt = (N + kBN - 1) / kBN;
+    const int64_t R = std::max<int64_t>(1, std::min<int64_t>((mt * nt + 7) / 8, 64));
+    return std::min(mt, R) * kBM > (R + mt - 1) / mt * kBN;
 }
 
 // Lanes go along K for an operand whose free group is not unit-stride.

@@ -23,6 +23,7 @@ hipError_t launch_simt(bool f64, SimtArgs& a, hipStream_t st);
 hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st);
 void mfma_tiles(bool f64, MfmaArgs& a);
 int mfma_bk(bool f64);
+bool mfma_a_first(int64_t M, int64_t N);
 
 // Batches: tile shape 0 = 128x128, 1 = 64x64; persistent kernel over a work
 // list of (contraction, tile) pairs taken off an atomic counter.

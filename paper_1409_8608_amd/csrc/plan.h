@@ -59,7 +59,7 @@ extern thread_local std::string g_last_error;
 tc_status fail(tc_status s, const std::string& msg);
 tc_status hip_fail(hipError_t e, const char* what);
 
-std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA = 4);
+std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA = 4, bool a_first = false, int G = 0);
 int ktab_vec_flags(const std::vector<int64_t>& tab, int v);
 bool use_stream_kernel(const Spec& s, const GemmView& gv);
 tc_status prepare_plan(tc_plan_s* p);
