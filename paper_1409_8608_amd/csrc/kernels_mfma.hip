@@ -84,6 +84,11 @@ __device__ __forceinline__ int64_t dm(int64_t& rem, int64_t ext) {
     return m;
 }
 
+// s_waitcnt immediate that waits for LDS/scalar-memory traffic only (gfx9
+// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8; a field at its
+// maximum does not wait).
+constexpr int kWaitLgkm0 = 15 | (3 << 14) | (7 << 4);
+
 // How a thread stages an operand tile: lanes along the free index (M-major),
 // along K one element at a time, or along K in 16-byte chunks.
 enum { LD_MMAJ = 0, LD_KSCAL = 1, LD_KVEC = 2 };
@@ -192,35 +197,37 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         T ra[NS - 1][EA], rb[NS - 1][EB];
         vT va[NS - 1][CA], vb[NS - 1][CB];
         uint32_t okA[NS - 1], okB[NS - 1];
-        // K-table entries of a tile are fetched one tile before its operands,
-        // so the table lookup and the operand load never form a dependent
-        // chain.  In K-major loading a thread always handles the same k of a
-        // tile (one entry); in M/N-major loading it handles EA/EB of them.
+        // K-table entries of a tile are fetched one step before its operands
+        // (two table slots, tile t in slot t % 2), and in each step before the
+        // operand loads: waiting for a table then never waits for operand
+        // loads still in flight.  In K-major loading a thread always handles
+        // the same k of a tile (one entry); in M/N-major loading EA/EB.
         constexpr int TA = A_KMAJ ? 1 : EA, TB = B_KMAJ ? 1 : EB;
-        int64_t tA[TA], tB[TB];
-        auto tload = [&](int64_t kt) {
+        int64_t tA[2][TA], tB[2][TB];
+        auto tload = [&](int64_t kt, auto ts_c) {
+            constexpr int ts = decltype(ts_c)::value;
             const int64_t* kt0 = a.ktab + 2 * kt * BK;
 #pragma unroll
             for (int e = 0; e < TA; ++e)
-                tA[e] = kt0[2 * (AV ? VEC * (tid % CPR) : A_KMAJ ? tid % BK : (tid + 256 * e) / BM)];
+                tA[ts][e] = kt0[2 * (AV ? VEC * (tid % CPR) : A_KMAJ ? tid % BK : (tid + 256 * e) / BM)];
 #pragma unroll
             for (int e = 0; e < TB; ++e)
-                tB[e] = kt0[2 * (BV ? VEC * (tid % CPR) : B_KMAJ ? tid % BK : (tid + 256 * e) / BN) + 1];
+                tB[ts][e] = kt0[2 * (BV ? VEC * (tid % CPR) : B_KMAJ ? tid % BK : (tid + 256 * e) / BN) + 1];
         };
         // Operand loads with clamped addresses (element (batch, pass, 0, 0) is
         // always valid), so no branch sits around a load.  The raw values stay
         // in registers with a validity mask; padding is zeroed only when the
         // tile is written to LDS, so the loads stay in flight until then.
-        auto gload = [&](auto slot_c) {
-            constexpr int sl = decltype(slot_c)::value;
+        auto gload = [&](auto slot_c, auto ts_c, bool live) {
+            constexpr int sl = decltype(slot_c)::value, ts = decltype(ts_c)::value;
             uint32_t ma = 0, mb = 0;
             if constexpr (AV) {
                 // 16-byte chunks: chunk q = row q / CPR, positions VEC * (q % CPR) ..
 #pragma unroll
                 for (int e = 0; e < CA; ++e) {
                     const int64_t om = sAm[(tid + 256 * e) / CPR];
-                    const bool ok = (om >= 0) & (tA[0] >= 0);
-                    va[sl][e] = *(const vT*)(Ag + bA + pA + (ok ? om + tA[0] : 0));
+                    const bool ok = (om >= 0) & (tA[ts][0] >= 0) & live;
+                    va[sl][e] = *(const vT*)(Ag + bA + pA + (ok ? om + tA[ts][0] : 0));
                     ma |= (uint32_t)ok << e;
                 }
             } else {
@@ -228,8 +235,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 for (int e = 0; e < EA; ++e) {
                     const int idx = tid + 256 * e;
                     const int64_t om = sAm[A_KMAJ ? idx / BK : idx % BM];
-                    const int64_t ko = tA[A_KMAJ ? 0 : e];
-                    const bool ok = (om >= 0) & (ko >= 0);
+                    const int64_t ko = tA[ts][A_KMAJ ? 0 : e];
+                    const bool ok = (om >= 0) & (ko >= 0) & live;
                     ra[sl][e] = Ag[bA + pA + (ok ? om + ko : 0)];
                     ma |= (uint32_t)ok << e;
                 }
@@ -238,8 +245,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
 #pragma unroll
                 for (int e = 0; e < CB; ++e) {
                     const int64_t on = sBn[(tid + 256 * e) / CPR];
-                    const bool ok = (on >= 0) & (tB[0] >= 0);
-                    vb[sl][e] = *(const vT*)(Bg + bB + pB + (ok ? on + tB[0] : 0));
+                    const bool ok = (on >= 0) & (tB[ts][0] >= 0) & live;
+                    vb[sl][e] = *(const vT*)(Bg + bB + pB + (ok ? on + tB[ts][0] : 0));
                     mb |= (uint32_t)ok << e;
                 }
             } else {
@@ -247,8 +254,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 for (int e = 0; e < EB; ++e) {
                     const int idx = tid + 256 * e;
                     const int64_t on = sBn[B_KMAJ ? idx / BK : idx % BN];
-                    const int64_t ko = tB[B_KMAJ ? 0 : e];
-                    const bool ok = (on >= 0) & (ko >= 0);
+                    const int64_t ko = tB[ts][B_KMAJ ? 0 : e];
+                    const bool ok = (on >= 0) & (ko >= 0) & live;
                     rb[sl][e] = Bg[bB + pB + (ok ? on + ko : 0)];
                     mb |= (uint32_t)ok << e;
                 }
@@ -316,41 +323,60 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             }
         };
         typedef std::integral_constant<int, 0> S0;
+        typedef std::integral_constant<int, 1> S1;
         typedef std::integral_constant<int, NS - 2> SL;   // slot 1 (FP32) or 0 (FP64)
 
         // prologue: tile 0 to LDS, tiles 1 .. NS-2 in registers, table of the
         // next tile to load
         if (ktiles > 0) {
-            tload(0);
-            gload(S0{});
+            const int64_t last = ktiles - 1;
+            // Loads leave the prologue in the order a step leaves them (the
+            // table of tile NS - 1, then the operands of tile 1 for FP32), so
+            // the wait counts at the loop entry match the steady state.
+            tload(0, S0{});
+            gload(S0{}, S0{}, true);
             sstore(0, S0{});
-        }
-        if (NS == 3 && ktiles > 1) {
-            tload(1);
-            gload(SL{});
-        }
-        if (ktiles > NS - 1) tload(NS - 1);
-        __syncthreads();
-        // one K tile: load tile kt + NS - 1 into the slot that tile kt + 1
-        // does not use, multiply tile kt, store tile kt + 1 from its slot
-        auto step = [&](int64_t kt, auto ld_c, auto st_c) {
-            const int buf = (int)(kt & 1);
-            if (kt + NS - 1 < ktiles) {
-                gload(ld_c);
-                if (kt + NS < ktiles) tload(kt + NS);
+            tload(std::min<int64_t>(1, last), S1{});
+            if (NS == 3) {
+                tload(std::min<int64_t>(2, last), S0{});
+                gload(SL{}, S1{}, ktiles > 1);
             }
-            compute(buf);
-            if (kt + 1 < ktiles) sstore(buf ^ 1, st_c);
-            __syncthreads();
-        };
-        if constexpr (NS == 3) {
-            // slots alternate: tile t sits in slot t % 2
-            for (int64_t kt = 0; kt < ktiles; kt += 2) {
-                step(kt, S0{}, SL{});
-                if (kt + 1 < ktiles) step(kt + 1, SL{}, S0{});
+            __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            // One K tile: load tile kt + NS - 1 into the slot that tile kt + 1
+            // does not use, multiply tile kt, store tile kt + 1 from its slot.
+            // The loads are issued on every step (past the last tile all
+            // lanes read element 0 and the values are dropped) and the barrier
+            // waits for LDS traffic only, so the compiler's wait counting
+            // keeps the loads of later tiles in flight across steps.
+            // Step parity p = kt % 2 is a compile-time constant (steps come
+            // in pairs), so every slot index below is too.
+            auto step = [&](int64_t kt, auto p_c) {
+                constexpr int p = decltype(p_c)::value;
+                tload(std::min<int64_t>(kt + NS, last), std::integral_constant<int, (p + NS) % 2>{});
+                gload(std::integral_constant<int, NS == 3 ? p : 0>{}, std::integral_constant<int, (p + NS - 1) % 2>{},
+                      kt + NS - 1 < ktiles);
+                // FP64: keep the loads ahead of the MFMAs (under its register
+                // pressure the scheduler sinks them next to their LDS stores,
+                // leaving no time to arrive); FP32 spreads them among the
+                // MFMAs by itself, which measures faster
+                if constexpr (NS == 2) __builtin_amdgcn_sched_barrier(0);
+                compute(p);
+                if (kt + 1 < ktiles) sstore(p ^ 1, std::integral_constant<int, NS == 3 ? 1 - p : 0>{});
+                __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __builtin_amdgcn_s_barrier();
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            };
+            // operand slots: tile t in slot t % 2 (FP32), slot 0 (FP64)
+            int64_t kt = 0;
+            for (; kt + 1 < ktiles; kt += 2) {
+                step(kt, S0{});
+                step(kt + 1, S1{});
             }
-        } else {
-            for (int64_t kt = 0; kt < ktiles; ++kt) step(kt, S0{}, S0{});
+            if (kt < ktiles) step(kt, S0{});
         }
 
         // epilogue: lane holds D[n = row(lane, q)][m = lane % 16] of each block
