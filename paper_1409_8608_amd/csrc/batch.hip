@@ -1,7 +1,7 @@
 // Batches: many independent contractions in one HIP graph.
 //
 // tc_batch_create turns every contraction into matrix-core tiles of a chosen
-// shape (128x128 or 64x64 outputs), writes one static descriptor per
+// shape (128x128, 64x64 or 32x128 outputs), writes one static descriptor per
 // contraction to device memory and builds work lists of (contraction, tile)
 // pairs, one per (storage type, tile shape, operand layout) group, ordered
 // longest-first by the estimated cost of a tile (contracted length x tile
@@ -106,7 +106,7 @@ static tc_status build_groups(tc_batch_s* b) {
         const bool ak = mfma_kmajor_a(a), bk = mfma_kmajor_b(a);
         const int sh = b->shape[c];
         mfma_tiles_shape(sh, a);
-        const int key = (f64 ? 8 : 0) | (sh << 2) | (ak ? 2 : 0) | (bk ? 1 : 0);
+        const int key = (f64 ? 16 : 0) | (sh << 2) | (ak ? 2 : 0) | (bk ? 1 : 0);   // sh in 0..3
         if (!gid.count(key)) {
             gid[key] = (int)b->groups.size();
             BatchGroup g;
@@ -117,8 +117,7 @@ static tc_status build_groups(tc_batch_s* b) {
             b->groups.push_back(g);
             lists.emplace_back();
         }
-        const int bm = sh == 0 ? 128 : 64;
-        const int64_t cost = a.Kpad * bm * bm;
+        const int64_t cost = a.Kpad * (sh == 0 ? 128 * 128 : sh == 1 ? 64 * 64 : 32 * 128);
         for (int64_t t = 0; t < a.ntiles; ++t) lists[gid[key]].push_back({cost, int2{c, (int)t}});
     }
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
@@ -167,7 +166,9 @@ static tc_status capture(tc_batch_s* b) {
     return TC_OK;
 }
 
-static int default_shape(const MfmaArgs& a) { return (a.M <= 64 || a.N <= 64) ? 1 : 0; }
+constexpr int kShapes = 3;   // tile shapes 128x128, 64x64, 32x128
+
+static int default_shape(const MfmaArgs& a) { return a.M <= 32 ? 2 : (a.M <= 64 || a.N <= 64) ? 1 : 0; }
 
 }  // namespace tc
 
@@ -343,7 +344,7 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
     };
     std::map<std::string, std::pair<int64_t, int>> rep;   // key -> (tiles, member)
     for (int c = 0; c < n; ++c)
-        for (int sh = 0; sh < 2; ++sh) {
+        for (int sh = 0; sh < kShapes; ++sh) {
             MfmaArgs a = b->items[c];
             mfma_tiles_shape(sh, a);
             std::string key = std::to_string(b->plans[c]->spec.dtype) + "/" + std::to_string(sh) + "/" +
@@ -360,7 +361,7 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
     int hits = 0;
     for (int c = 0; c < n && e == hipSuccess; ++c) {
         std::vector<std::pair<double, int>> cand;
-        for (int sh = 0; sh < 2; ++sh) {
+        for (int sh = 0; sh < kShapes; ++sh) {
             MfmaArgs a = b->items[c];
             mfma_tiles_shape(sh, a);
             std::string key = std::to_string(b->plans[c]->spec.dtype) + "/" + std::to_string(sh) + "/" +
@@ -371,7 +372,7 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
         int seed_pick = cand[0].second;
         double best_t = INFINITY;
         int best = seed_pick;
-        std::vector<double> meas(2, INFINITY);
+        std::vector<double> meas(kShapes, INFINITY);
         for (int q = 0; q < (int)cand.size() && q < std::max(top_k, 2); ++q) {
             double t;
             e = time_one(c, cand[q].second, &t);
@@ -382,7 +383,7 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
                 best = cand[q].second;
             }
         }
-        double truly_best = std::min(meas[0], meas[1]);
+        double truly_best = *std::min_element(meas.begin(), meas.end());
         if (meas[seed_pick] <= 1.05 * truly_best) ++hits;
         b->shape[c] = best;
     }

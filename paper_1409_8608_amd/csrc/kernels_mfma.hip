@@ -84,10 +84,21 @@ __device__ __forceinline__ int64_t dm(int64_t& rem, int64_t ext) {
     return m;
 }
 
+
 // s_waitcnt immediate that waits for LDS/scalar-memory traffic only (gfx9
 // encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8; a field at its
 // maximum does not wait).
 constexpr int kWaitLgkm0 = 15 | (3 << 14) | (7 << 4);
+
+// Block barrier for LDS hand-offs: this wave's LDS traffic is complete, then
+// s_barrier.  Unlike __syncthreads it does not wait for outstanding global
+// loads and stores, which stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 // How a thread stages an operand tile: lanes along the free index (M-major),
 // along K one element at a time, or along K in 16-byte chunks.
@@ -127,8 +138,10 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     constexpr int VEC = 16 / (int)sizeof(T), CPR = BK / VEC;  // chunk width, chunks per row
     constexpr int CA = EA / VEC, CB = EB / VEC;              // chunks per thread (vector loads)
     typedef T vT __attribute__((ext_vector_type(VEC)));
-    static_assert(EA % VEC == 0 && EB % VEC == 0 && 256 % CPR == 0, "vector staging shape");
-    constexpr int FM = BM / 32, FN = BN / 32;              // 16x16 blocks per wave
+    static_assert((!AV || EA % VEC == 0) && (!BV || EB % VEC == 0) && 256 % CPR == 0, "vector staging shape");
+    // four waves, 2 x 2 over the tile, or 1 x 4 along n for tiles of 32 rows
+    constexpr int WM = BM >= 64 ? 2 : 1, WN = 4 / WM;
+    constexpr int FM = BM / WM / 16, FN = BN / WN / 16;    // 16x16 blocks per wave
     static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
     static_assert(BK == 16, "the LDS layout holds 16 positions per row");
     __shared__ __attribute__((aligned(16))) T As[2][BM * BK];
@@ -139,11 +152,11 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     T* Cg = (T*)Cp;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    const int wm = wid & 1, wn = wid >> 1;
+    const int wm = wid % WM, wn = wid / WM;
 
     int64_t rest = tile;
-    const int64_t mt = rest % a.mt; rest /= a.mt;
-    const int64_t nt = rest % a.nt; rest /= a.nt;
+    const int64_t mt = dm(rest, a.mt);
+    const int64_t nt = dm(rest, a.nt);
     const int64_t bt = rest;
     const int64_t m_base = mt * BM, n_base = nt * BN;
 
@@ -173,7 +186,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         sBn[i] = ok ? group_off<1>(a.n, n) : -1;
         sCn[i] = ok ? group_off<2>(a.n, n) : -1;
     }
-    __syncthreads();
+    lds_barrier();
 
     const T alpha = (T)alpha_d, beta = (T)beta_d;
     const int64_t ktiles = a.Kpad / BK;
@@ -312,10 +325,10 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             };
             v4 fb[FN];
 #pragma unroll
-            for (int i = 0; i < FN; ++i) fb[i] = frag(Bs[buf], wn * (BN / 2) + i * 16 + r16);
+            for (int i = 0; i < FN; ++i) fb[i] = frag(Bs[buf], wn * (BN / WN) + i * 16 + r16);
 #pragma unroll
             for (int j = 0; j < FM; ++j) {
-                const v4 fa = frag(As[buf], wm * (BM / 2) + j * 16 + r16);
+                const v4 fa = frag(As[buf], wm * (BM / WM) + j * 16 + r16);
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
@@ -341,10 +354,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 tload(std::min<int64_t>(2, last), S0{});
                 gload(SL{}, S1{}, ktiles > 1);
             }
-            __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            __builtin_amdgcn_s_barrier();
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            lds_barrier();
             // One K tile: load tile kt + NS - 1 into the slot that tile kt + 1
             // does not use, multiply tile kt, store tile kt + 1 from its slot.
             // The loads are issued on every step (past the last tile all
@@ -365,10 +375,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 if constexpr (NS == 2) __builtin_amdgcn_sched_barrier(0);
                 compute(p);
                 if (kt + 1 < ktiles) sstore(p ^ 1, std::integral_constant<int, NS == 3 ? 1 - p : 0>{});
-                __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                __builtin_amdgcn_s_barrier();
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                lds_barrier();
             };
             // operand slots: tile t in slot t % 2 (FP32), slot 0 (FP64)
             int64_t kt = 0;
@@ -384,11 +391,11 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         for (int i = 0; i < FN; ++i) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t cn = sCn[wn * (BN / 2) + i * 16 + Mfma<T>::row(lane, q)];
+                const int64_t cn = sCn[wn * (BN / WN) + i * 16 + Mfma<T>::row(lane, q)];
                 if (cn < 0) continue;
 #pragma unroll
                 for (int j = 0; j < FM; ++j) {
-                    const int64_t cm = sCm[wm * (BM / 2) + j * 16 + (lane & 15)];
+                    const int64_t cm = sCm[wm * (BM / WM) + j * 16 + (lane & 15)];
                     if (cm < 0) continue;
                     T* cp = Cg + bC + cn + cm;
                     T v = alpha * acc[i][j][q];
@@ -416,23 +423,29 @@ __global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
     mfma_tile<T, BM, BN, BK, AMODE, BMODE>(a, a.A, a.B, a.C, a.alpha, a.beta, xcd_tile(blockIdx.x, a.ntiles));
 }
 
-// Persistent form for batches: blocks take work items (contraction, tile) off
-// an atomic counter until the list is exhausted, so every block exits once
-// the counter passes nwork.
+// Persistent form for batches: blocks take runs of `chunk` consecutive work
+// items (contraction, tile) off an atomic counter until the list is
+// exhausted, so every block exits once the counter passes nwork.  Claiming a
+// run per atomic keeps the single counter from serialising the many small
+// tiles of a large batch.
 template <typename T, int BM, int BN, int BK, int AMODE, int BMODE>
 __global__ __launch_bounds__(256) void k_mfma_batch(const MfmaArgs* __restrict__ items,
                                                     const BatchPtrs* __restrict__ ptrs,
-                                                    const int2* __restrict__ work, int nwork, int* counter) {
+                                                    const int2* __restrict__ work, int nwork, int chunk,
+                                                    int* counter) {
     __shared__ int s_w;
     for (;;) {
-        if (threadIdx.x == 0) s_w = atomicAdd(counter, 1);
-        __syncthreads();
-        const int w = s_w;
-        if (w >= nwork) break;
-        const int2 wi = work[w];
-        const BatchPtrs& pt = ptrs[wi.x];
-        mfma_tile<T, BM, BN, BK, AMODE, BMODE>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha, pt.beta, wi.y);
-        __syncthreads();   // the tile's LDS tables and s_w are reused by the next item
+        if (threadIdx.x == 0) s_w = atomicAdd(counter, chunk);
+        lds_barrier();
+        const int w0 = s_w;
+        if (w0 >= nwork) break;
+        const int w1 = min(w0, nwork - chunk) + chunk;
+        for (int w = w0; w < w1; ++w) {
+            const int2 wi = work[w];
+            const BatchPtrs& pt = ptrs[wi.x];
+            mfma_tile<T, BM, BN, BK, AMODE, BMODE>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha, pt.beta, wi.y);
+            lds_barrier();   // the tile's LDS tables and s_w are reused by the next item
+        }
     }
 }
 
@@ -491,21 +504,30 @@ static int load_mode(const MfmaArgs& a, bool f64, int slot) {
     return vec ? LD_KVEC : LD_KSCAL;
 }
 
+// Chunk loads need a whole number of 16-byte chunks per thread; a tile side
+// too small for that stages element by element.
+template <typename T, int ROWS>
+constexpr int fit_mode(int m) {
+    return (m == LD_KVEC && (ROWS * kBK / 256) % (16 / (int)sizeof(T)) != 0) ? LD_KSCAL : m;
+}
+
 template <typename T, int BM, int BN>
 static hipError_t tile_dispatch(const MfmaArgs& a, int am, int bm, hipStream_t st) {
     if (a.ntiles <= 0) return hipSuccess;
     if (a.ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
     dim3 g((unsigned)a.ntiles), b(256);
+    constexpr int A0 = fit_mode<T, BM>(0), A1 = fit_mode<T, BM>(1), A2 = fit_mode<T, BM>(2);
+    constexpr int B0 = fit_mode<T, BN>(0), B1 = fit_mode<T, BN>(1), B2 = fit_mode<T, BN>(2);
     switch (am * 3 + bm) {
-        case 0: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 0, 0>), g, b, 0, st, a); break;
-        case 1: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 0, 1>), g, b, 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 0, 2>), g, b, 0, st, a); break;
-        case 3: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 1, 0>), g, b, 0, st, a); break;
-        case 4: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 1, 1>), g, b, 0, st, a); break;
-        case 5: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 1, 2>), g, b, 0, st, a); break;
-        case 6: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 2, 0>), g, b, 0, st, a); break;
-        case 7: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 2, 1>), g, b, 0, st, a); break;
-        default: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, 2, 2>), g, b, 0, st, a); break;
+        case 0: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B0>), g, b, 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B1>), g, b, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B2>), g, b, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B0>), g, b, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B1>), g, b, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B2>), g, b, 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B0>), g, b, 0, st, a); break;
+        case 7: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B1>), g, b, 0, st, a); break;
+        default: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B2>), g, b, 0, st, a); break;
     }
     return hipGetLastError();
 }
@@ -516,11 +538,12 @@ hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Batches: tile shapes 0 = 128x128, 1 = 64x64.  Batch members use the scalar
-// load modes (their K tables are not checked for chunk contiguity).
+// Batches: tile shapes 0 = 128x128, 1 = 64x64, 2 = 32x128 (m x n; for
+// contractions with few rows).  Batch members use the scalar load modes
+// (their K tables are not checked for chunk contiguity).
 static void shape_dims(int shape, int& bm, int& bn) {
-    bm = shape == 0 ? 128 : 64;
-    bn = bm;
+    bm = shape == 0 ? 128 : shape == 1 ? 64 : 32;
+    bn = shape == 0 ? 128 : shape == 1 ? 64 : 128;
 }
 
 void mfma_tiles_shape(int shape, MfmaArgs& a) {
@@ -538,10 +561,13 @@ template <typename T, int BM, int BN>
 static hipError_t batch_dispatch(bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs, const int2* work,
                                  int nwork, int* counter, int grid, hipStream_t st) {
     dim3 g(grid), b(256);
-    if (ak && bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 1>), g, b, 0, st, items, ptrs, work, nwork, counter);
-    else if (ak) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 0>), g, b, 0, st, items, ptrs, work, nwork, counter);
-    else if (bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 1>), g, b, 0, st, items, ptrs, work, nwork, counter);
-    else hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 0>), g, b, 0, st, items, ptrs, work, nwork, counter);
+    // runs of up to 16 items when the list is long (at least about 64 runs
+    // per block); short lists of costly tiles keep single items for balance
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)nwork / ((int64_t)grid * 64)));
+    if (ak && bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 1>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+    else if (ak) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 0>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+    else if (bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 1>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+    else hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 0>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
     return hipGetLastError();
 }
 
@@ -549,10 +575,12 @@ hipError_t launch_mfma_batch(bool f64, int shape, bool ak, bool bk, const MfmaAr
                              const int2* work, int nwork, int* counter, int grid, hipStream_t st) {
     if (nwork <= 0) return hipSuccess;
     if (f64)
-        return shape == 0 ? batch_dispatch<double, 128, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
-                          : batch_dispatch<double, 64, 64>(ak, bk, items, ptrs, work, nwork, counter, grid, st);
-    return shape == 0 ? batch_dispatch<float, 128, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
-                      : batch_dispatch<float, 64, 64>(ak, bk, items, ptrs, work, nwork, counter, grid, st);
+        return shape == 0   ? batch_dispatch<double, 128, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
+               : shape == 1 ? batch_dispatch<double, 64, 64>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
+                            : batch_dispatch<double, 32, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st);
+    return shape == 0   ? batch_dispatch<float, 128, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
+           : shape == 1 ? batch_dispatch<float, 64, 64>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
+                        : batch_dispatch<float, 32, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st);
 }
 
 // Resident blocks per CU of the persistent kernel (occupancy query).
@@ -568,16 +596,21 @@ static int occ_of(bool ak, bool bk) {
 }
 
 int mfma_batch_occupancy(bool f64, int shape, bool ak, bool bk) {
-    if (f64) return shape == 0 ? occ_of<double, 128, 128>(ak, bk) : occ_of<double, 64, 64>(ak, bk);
-    return shape == 0 ? occ_of<float, 128, 128>(ak, bk) : occ_of<float, 64, 64>(ak, bk);
+    if (f64)
+        return shape == 0 ? occ_of<double, 128, 128>(ak, bk)
+                          : shape == 1 ? occ_of<double, 64, 64>(ak, bk) : occ_of<double, 32, 128>(ak, bk);
+    return shape == 0 ? occ_of<float, 128, 128>(ak, bk)
+                      : shape == 1 ? occ_of<float, 64, 64>(ak, bk) : occ_of<float, 32, 128>(ak, bk);
 }
 
 // One-shot launch with a chosen tile shape (used to time tuning candidates).
 hipError_t launch_mfma_shape(bool f64, int shape, MfmaArgs& a, hipStream_t st) {
     if (shape == 0) return launch_mfma(f64, a, st);
-    mfma_tiles_shape(1, a);
+    mfma_tiles_shape(shape, a);
     int am = load_mode(a, f64, 0), bm = load_mode(a, f64, 1);
-    return f64 ? tile_dispatch<double, 64, 64>(a, am, bm, st) : tile_dispatch<float, 64, 64>(a, am, bm, st);
+    if (shape == 1)
+        return f64 ? tile_dispatch<double, 64, 64>(a, am, bm, st) : tile_dispatch<float, 64, 64>(a, am, bm, st);
+    return f64 ? tile_dispatch<double, 32, 128>(a, am, bm, st) : tile_dispatch<float, 32, 128>(a, am, bm, st);
 }
 
 }  // namespace tc
