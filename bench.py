@@ -137,19 +137,24 @@ def cpu_baseline(w, seconds):
                        "one host core, plain FP64 loop nest)")
 
 
+FORMS = ("permuted", "precision", "batched")
+
+
 def forms(args, torch, tc, wl):
     """Other forms of the metric on the same GPU (short runs)."""
     out = {}
     import numpy as np
+    chosen = FORMS if args.forms == "all" else tuple(args.forms.split(","))
     # FP64 / FP32 fused permuted contraction, C_abc = A_ija B_jbic (256^3, 32^2)
     w = wl.permuted(256, 32)
-    for dt, tdt, peak in (("f64", torch.float64, FP64_PEAK_TFS), ("f32", torch.float32, FP32_PEAK_TFS)):
+    for dt, tdt, peak in ((("f64", torch.float64, FP64_PEAK_TFS), ("f32", torch.float32, FP32_PEAK_TFS))
+                          if "permuted" in chosen else ()):
         plan = tc.Plan(w["spec"], w["ext"], dt)
         plan.prepare()
         dA = tc.to_device_fortran(w["A"], tdt)
         dB = tc.to_device_fortran(w["B"], tdt)
         dC = tc.empty_fortran(plan.shape("C"), tdt)
-        ms, _ = _events_time(lambda: plan.contract(dA, dB, dC), max(3, args.steps // 4), 2, torch)
+        ms, _ = _events_time(lambda: plan.contract(dA, dB, dC), max(3, args.steps // 4), max(2, args.warmup // 2), torch)
         fl = 2 * 256 ** 3 * 32 * 32
         tfs = fl / (ms * 1e-3) / 1e12
         out[f"permuted_{dt}"] = dict(workload="C_abc = A_ija B_jbic, a=b=c=256, i=j=32, normal(0,1)",
@@ -160,8 +165,9 @@ def forms(args, torch, tc, wl):
     torch.cuda.empty_cache()
     # precision: C_ab = A_iaj B_jbi, a=b=4096, i=j=64 (K=4096), per-slice scaled data;
     # FP64 plain vs split-BF16 (three terms, six products) on the same GPU
-    out.update(precision(args, torch, tc, wl))
-    for dt in ("f64", "f32"):
+    if "precision" in chosen:
+        out.update(precision(args, torch, tc, wl))
+    for dt in (("f64", "f32") if "batched" in chosen else ()):
         out[f"batched_{dt}"] = batched(args, torch, tc, wl, dt)
         print(f"# batched {dt} done", file=sys.stderr, flush=True)
     if "batched_f32" in out and "batched_f64" in out:
@@ -201,11 +207,11 @@ def batched(args, torch, tc, wl, dtype):
     seq_ms, seq_wall = _events_time(seq, 2, 1, torch)
     batch = tc.Batch(plans)
     run = lambda: batch.contract(As, Bs, Cs)
-    bat_ms, _ = _events_time(run, 5, 1, torch)
+    bat_ms, _ = _events_time(run, 5, 3, torch)
     t0 = time.perf_counter()
     batch.tune(2)
     tune_s = time.perf_counter() - t0
-    tuned_ms, _ = _events_time(run, 5, 1, torch)
+    tuned_ms, _ = _events_time(run, 5, 3, torch)
     info = batch.info()
     # sampled parity of the last replay
     rng = np.random.default_rng(3)
@@ -260,7 +266,7 @@ def precision(args, torch, tc, wl):
         plan = tc.Plan(w["spec"], w["ext"], dtype, compute=compute)
         plan.prepare()
         dC = tc.empty_fortran(plan.shape("C"), tdt)
-        ms, _ = _events_time(lambda: plan.contract(xA, xB, dC), 5, 1, torch)
+        ms, _ = _events_time(lambda: plan.contract(xA, xB, dC), 10, max(1, args.warmup // 5), torch)
         got = dC[torch.as_tensor(rows, device="cuda")][:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
         err = oracle.normwise_rel_err(got, ref)
         tfs = fl / (ms * 1e-3) / 1e12
@@ -292,10 +298,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--forms", default="all",
+                    help="comma list of the other forms to run: " + ", ".join(FORMS) + " (default all)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (torch copy_) three times, outside the timed "
                          "region, so that profiler byte counters can be scaled by a kernel of known traffic")
     args = ap.parse_args()
+    if args.forms != "all" and any(f not in FORMS for f in args.forms.split(",")):
+        print(f"--forms takes a comma list of {', '.join(FORMS)}", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(see the sharding paragraph of DESIGN.md)", file=sys.stderr)
