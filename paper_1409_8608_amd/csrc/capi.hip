@@ -189,6 +189,13 @@ tc_status prepare_plan(tc_plan_s* p) {
             p->kvec = ktab_vec_flags(tab, f64 ? 2 : 4);
             tc_status st = upload(&p->d_ktab, &p->ktab_cap, tab);
             if (st) return st;
+            int64_t ws = 0;
+            p->kslices = s.compute == TC_NATIVE ? mfma_split_plan(f64, p->gv.M, p->gv.N, p->kpad, &p->kslice_tiles, &ws)
+                                                : 1;
+            if (p->kslices > 1) {
+                st = ensure_device_buffer(&p->d_splitk, &p->splitk_cap, ws);
+                if (st) return st;
+            }
         }
         if (s.compute != TC_NATIVE) {
             tc_status st = prepare_split(p);
@@ -270,6 +277,11 @@ static tc_status run_fused(tc_plan_s* p, const void* A, const void* B, void* C, 
     a.pass.n = 0;
     a.ktab = (const int64_t*)p->d_ktab;
     a.kvec = p->kvec;
+    if (p->kslices > 1) {
+        a.ws = p->d_splitk;
+        a.kslices = p->kslices;
+        a.kslice_tiles = p->kslice_tiles;
+    }
     a.M = gv.M; a.N = gv.N; a.Kpad = p->kpad;
     a.nbatch = 1; a.npass = 1;
     a.alpha = alpha; a.beta = beta;

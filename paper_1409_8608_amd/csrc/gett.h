@@ -77,6 +77,11 @@ struct MfmaArgs {
     int mode;           // 0: C = alpha*acc + beta*C; 1: per pass C += alpha*acc
     int kvec;           // bit 0 (A), bit 1 (B): every 16-byte chunk of K-table
                         // positions is contiguous and aligned in that operand
+    // split K (fused launches with few output tiles): kslices > 1 slices of
+    // kslice_tiles K tiles each; every (slice, tile) block writes its raw
+    // accumulators to ws, [slice][tile][n][m], and a reduction kernel forms C
+    void* ws;
+    int64_t kslices, kslice_tiles;
 };
 
 // Per-call operands of one batch member.

@@ -130,7 +130,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
 // apart from the static descriptors).  Called by a whole block.
 template <typename T, int BM, int BN, int BK, int AMODE, int BMODE>
 __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, const void* Bp, void* Cp,
-                                          double alpha_d, double beta_d, int64_t tile) {
+                                          double alpha_d, double beta_d, int64_t tile, int64_t slice) {
     typedef typename Mfma<T>::acc_t acc_t;
     constexpr int EA = BM * BK / 256, EB = BN * BK / 256;   // elements per thread per tile
     constexpr bool A_KMAJ = AMODE != LD_MMAJ, B_KMAJ = BMODE != LD_MMAJ;
@@ -189,7 +189,13 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     lds_barrier();
 
     const T alpha = (T)alpha_d, beta = (T)beta_d;
-    const int64_t ktiles = a.Kpad / BK;
+    // this block's K tiles: all of them, or one slice when K is split
+    int64_t ktiles = a.Kpad / BK, k_first = 0;
+    if (a.kslices > 1) {
+        k_first = slice * a.kslice_tiles;
+        ktiles = std::max<int64_t>(0, std::min<int64_t>(a.kslice_tiles, ktiles - k_first));
+    }
+    const int64_t* __restrict__ ktab0 = a.ktab + 2 * k_first * BK;
 
     int64_t pctr[GT_MAXD];
     for (int d = 0; d < a.pass.n; ++d) pctr[d] = 0;
@@ -219,7 +225,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         int64_t tA[2][TA], tB[2][TB];
         auto tload = [&](int64_t kt, auto ts_c) {
             constexpr int ts = decltype(ts_c)::value;
-            const int64_t* kt0 = a.ktab + 2 * kt * BK;
+            const int64_t* kt0 = ktab0 + 2 * kt * BK;
 #pragma unroll
             for (int e = 0; e < TA; ++e)
                 tA[ts][e] = kt0[2 * (AV ? VEC * (tid % CPR) : A_KMAJ ? tid % BK : (tid + 256 * e) / BM)];
@@ -387,6 +393,20 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         }
 
         // epilogue: lane holds D[n = row(lane, q)][m = lane % 16] of each block
+        if (a.kslices > 1) {
+            // split K: raw partial tile to the workspace (rows and columns past
+            // the edge hold zeros and are never read)
+            T* wsp = (T*)a.ws + (slice * a.ntiles + tile) * (int64_t)(BM * BN);
+#pragma unroll
+            for (int i = 0; i < FN; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int j = 0; j < FM; ++j)
+                        wsp[(wn * (BN / WN) + i * 16 + Mfma<T>::row(lane, q)) * BM + wm * (BM / WM) + j * 16 +
+                            (lane & 15)] = acc[i][j][q];
+            continue;   // a split launch has one pass
+        }
 #pragma unroll
         for (int i = 0; i < FN; ++i) {
 #pragma unroll
@@ -420,8 +440,33 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
 
 template <typename T, int BM, int BN, int BK, int AMODE, int BMODE>
 __global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
-    mfma_tile<T, BM, BN, BK, AMODE, BMODE>(a, a.A, a.B, a.C, a.alpha, a.beta, xcd_tile(blockIdx.x, a.ntiles));
+    const int64_t S = a.kslices > 1 ? a.kslices : 1;
+    const int64_t t = xcd_tile(blockIdx.x, a.ntiles * S);
+    mfma_tile<T, BM, BN, BK, AMODE, BMODE>(a, a.A, a.B, a.C, a.alpha, a.beta, t % a.ntiles, t / a.ntiles);
 }
+
+// Split-K reduction: output (m, n) is the sum of its slices' partials, in
+// slice order, then C = alpha * sum + beta * C.
+template <typename T, int BM, int BN>
+__global__ __launch_bounds__(256) void k_splitk_reduce(MfmaArgs a) {
+    const T alpha = (T)a.alpha, beta = (T)a.beta;
+    const T* __restrict__ ws = (const T*)a.ws;
+    T* C = (T*)a.C;
+    const int64_t total = a.M * a.N, sstride = a.ntiles * (int64_t)(BM * BN);
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = idx % a.M, n = idx / a.M;
+        const int64_t tile = (n / BN) * a.mt + m / BM;
+        const T* p = ws + tile * (int64_t)(BM * BN) + (n % BN) * BM + m % BM;
+        T sum = 0;
+        for (int64_t s = 0; s < a.kslices; ++s) sum += p[s * sstride];
+        T* cp = C + group_off<2>(a.m, m) + group_off<2>(a.n, n);
+        T v = alpha * sum;
+        if (a.beta != 0.0) v += beta * (*cp);
+        *cp = v;
+    }
+}
+
 
 // Persistent form for batches: blocks take runs of `chunk` consecutive work
 // items (contraction, tile) off an atomic counter until the list is
@@ -443,7 +488,7 @@ __global__ __launch_bounds__(256) void k_mfma_batch(const MfmaArgs* __restrict__
         for (int w = w0; w < w1; ++w) {
             const int2 wi = work[w];
             const BatchPtrs& pt = ptrs[wi.x];
-            mfma_tile<T, BM, BN, BK, AMODE, BMODE>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha, pt.beta, wi.y);
+            mfma_tile<T, BM, BN, BK, AMODE, BMODE>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha, pt.beta, wi.y, 0);
             lds_barrier();   // the tile's LDS tables and s_w are reused by the next item
         }
     }
@@ -513,9 +558,10 @@ constexpr int fit_mode(int m) {
 
 template <typename T, int BM, int BN>
 static hipError_t tile_dispatch(const MfmaArgs& a, int am, int bm, hipStream_t st) {
+    const int64_t S = a.kslices > 1 ? a.kslices : 1;
     if (a.ntiles <= 0) return hipSuccess;
-    if (a.ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-    dim3 g((unsigned)a.ntiles), b(256);
+    if (a.ntiles * S > 0x7fffffff) return hipErrorInvalidConfiguration;
+    dim3 g((unsigned)(a.ntiles * S)), b(256);
     constexpr int A0 = fit_mode<T, BM>(0), A1 = fit_mode<T, BM>(1), A2 = fit_mode<T, BM>(2);
     constexpr int B0 = fit_mode<T, BN>(0), B1 = fit_mode<T, BN>(1), B2 = fit_mode<T, BN>(2);
     switch (am * 3 + bm) {
@@ -534,7 +580,37 @@ static hipError_t tile_dispatch(const MfmaArgs& a, int am, int bm, hipStream_t s
 
 hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st) {
     int am = load_mode(a, f64, 0), bm = load_mode(a, f64, 1);
-    return f64 ? tile_dispatch<double, kBM, kBN>(a, am, bm, st) : tile_dispatch<float, kBM, kBN>(a, am, bm, st);
+    hipError_t e = f64 ? tile_dispatch<double, kBM, kBN>(a, am, bm, st) : tile_dispatch<float, kBM, kBN>(a, am, bm, st);
+    if (e != hipSuccess || a.kslices <= 1 || a.ntiles <= 0) return e;
+    if (a.nbatch != 1 || a.npass != 1 || a.mode != 0 || !a.ws) return hipErrorInvalidValue;
+    const int64_t total = a.M * a.N;
+    dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536))), b(256);
+    if (f64) hipLaunchKernelGGL((k_splitk_reduce<double, kBM, kBN>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_splitk_reduce<float, kBM, kBN>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+// Split-K choice for a fused M x N x Kpad launch (one batch, one pass): none
+// while the output tiles fill about two waves of resident blocks, or when K is
+// short; else enough slices of at least 8 K tiles to fill them, with the
+// workspace (slices x tiles x 128 x 128 elements) at most 64 MiB.  Returns the
+// slice count and sets the tiles per slice and the workspace bytes.
+int64_t mfma_split_plan(bool f64, int64_t M, int64_t N, int64_t Kpad, int64_t* slice_tiles, int64_t* ws_bytes) {
+    const int64_t ntiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    const int64_t ktiles = Kpad / kBK;
+    const int64_t fill = f64 ? 256 : 512;   // resident blocks of the two tile kernels on 256 CUs
+    const int64_t esize = f64 ? 8 : 4;
+    *slice_tiles = ktiles;
+    *ws_bytes = 0;
+    if (ntiles <= 0 || ntiles >= fill || ktiles < 16) return 1;
+    int64_t S = std::min<int64_t>((2 * fill + ntiles - 1) / ntiles, ktiles / 8);
+    S = std::min<int64_t>(S, (64LL << 20) / (ntiles * kBM * kBN * esize));
+    if (S < 2) return 1;
+    const int64_t per = (ktiles + S - 1) / S;
+    S = (ktiles + per - 1) / per;
+    *slice_tiles = per;
+    *ws_bytes = S * ntiles * kBM * kBN * esize;
+    return S;
 }
 
 // ---------------------------------------------------------------------------

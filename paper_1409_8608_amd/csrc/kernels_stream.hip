@@ -350,16 +350,80 @@ __global__ __launch_bounds__(256) void k_simt(SimtArgs a) {
     }
 }
 
+// The same body with G lanes per output element, for long kernels (dot or
+// gemv rows of many elements) with few outputs per launch: the lanes of a
+// group take every G-th term of the kernel's sum, an xor-shuffle tree adds the
+// G partial sums, and the group's first lane updates C.  Invocations of one
+// output still run in order.
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_simt_group(SimtArgs a) {
+    const T* __restrict__ A = (const T*)a.A;
+    const T* __restrict__ B = (const T*)a.B;
+    T* C = (T*)a.C;
+    const T alpha = (T)a.alpha;
+    const int l = threadIdx.x % G;
+    const int64_t gstride = (int64_t)gridDim.x * (blockDim.x / G);
+    for (int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; idx < a.total; idx += gstride) {
+        int64_t rem = idx, oA = 0, oB = 0, oC = 0;
+        for (int d = 0; d < a.out.n; ++d) {
+            int64_t r = divmod(rem, a.out.d[d].ext);
+            oA += r * a.out.d[d].sA;
+            oB += r * a.out.d[d].sB;
+            oC += r * a.out.d[d].sC;
+        }
+        int64_t ctr[GT_MAXD];
+        for (int d = 0; d < a.pass.n; ++d) ctr[d] = 0;
+        int64_t pA = 0, pB = 0;
+        for (int64_t p = 0; p < a.npass; ++p) {
+            T acc = 0;
+            const T* ap = A + oA + pA;
+            const T* bp = B + oB + pB;
+            for (int64_t k = l; k < a.kb.ext; k += G) acc += ap[k * a.kb.sA] * bp[k * a.kb.sB];
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+            if (l == 0) {
+                T c = C[oC];
+                C[oC] = c + alpha * acc;
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);   // next invocation re-reads C
+            for (int d = a.pass.n - 1; d >= 0; --d) {  // innermost pass loop fastest
+                pA += a.pass.d[d].sA;
+                pB += a.pass.d[d].sB;
+                if (++ctr[d] < a.pass.d[d].ext) break;
+                pA -= a.pass.d[d].sA * a.pass.d[d].ext;
+                pB -= a.pass.d[d].sB * a.pass.d[d].ext;
+                ctr[d] = 0;
+            }
+        }
+    }
+}
+
 static unsigned grid_for(int64_t total, int64_t cap = 65536) {
     int64_t g = (total + 255) / 256;
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
+// Lanes per output: one while the outputs alone fill the device (about 2^18
+// threads), else as many as the kernel length uses (8 or 64).
+int simt_group(int64_t total, int64_t klen) {
+    if (total >= (1 << 18) || klen < 16) return 1;
+    return (klen >= 128 && total * 64 <= (1LL << 22)) ? 64 : 8;
+}
+
 hipError_t launch_simt(bool f64, SimtArgs& a, hipStream_t st) {
     if (a.total <= 0 || a.npass <= 0) return hipSuccess;
-    dim3 g(grid_for(a.total, 1 << 20)), b(256);
-    if (f64) hipLaunchKernelGGL(k_simt<double>, g, b, 0, st, a);
-    else hipLaunchKernelGGL(k_simt<float>, g, b, 0, st, a);
+    const int G = simt_group(a.total, a.kb.ext);
+    dim3 g(grid_for(a.total * G, 1 << 20)), b(256);
+    if (G == 64) {
+        if (f64) hipLaunchKernelGGL((k_simt_group<double, 64>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_simt_group<float, 64>), g, b, 0, st, a);
+    } else if (G == 8) {
+        if (f64) hipLaunchKernelGGL((k_simt_group<double, 8>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_simt_group<float, 8>), g, b, 0, st, a);
+    } else {
+        if (f64) hipLaunchKernelGGL(k_simt<double>, g, b, 0, st, a);
+        else hipLaunchKernelGGL(k_simt<float>, g, b, 0, st, a);
+    }
     return hipGetLastError();
 }
 

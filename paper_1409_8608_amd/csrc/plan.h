@@ -37,6 +37,8 @@ struct tc_plan_s {
     void* d_ktab = nullptr;          // fused matrix-core K table
     int64_t ktab_cap = 0, kpad = 0;
     int kvec = 0;                    // chunk flags of d_ktab (MfmaArgs::kvec)
+    void* d_splitk = nullptr;        // split-K partial tiles of the fused kernel
+    int64_t splitk_cap = 0, kslices = 1, kslice_tiles = 0;
     void* d_var_ktab = nullptr;      // K table of the selected gemm member
     int64_t var_ktab_cap = 0, var_kpad = 0;
     int var_kvec = 0;

@@ -134,6 +134,65 @@ def test_fused_mfma_unaligned_base(dtype):
     check(spec, ext, A, B, dC.double().cpu().numpy(), dtype)
 
 
+# Split K: few output tiles and a long contraction (the paper's Test 2,
+# C_a = A_iaj B_ji, and a small matrix product with K in the thousands): the
+# fused kernel splits K over blocks and sums the slices in a fixed order.
+# K values not a multiple of 16 leave padding in the last tile.
+SPLITK_SHAPES = [
+    ("a=iaj,ji", dict(a=100, i=120, j=90)),
+    ("ab=ia,ib", dict(a=150, b=130, i=5000)),
+    ("a=iaj,ji", dict(a=300, i=64, j=201)),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", SPLITK_SHAPES)
+def test_fused_split_k(dtype, spec, ext):
+    rng = np.random.default_rng(17)
+    A, B, C0 = wl.tensors(spec, ext, rng, "normal", with_c=True)
+    p = _plan(spec, ext, dtype)
+    got = run(p, A, B, dtype=dtype)
+    check(spec, ext, A, B, got, dtype)
+    got = run(p, A, B, C0, alpha=0.5, beta=-1.5, dtype=dtype)
+    check(spec, ext, A, B, got, dtype, C0=C0, alpha=0.5, beta=-1.5)
+
+
+def test_fused_split_k_integer_exact():
+    spec, ext = "a=iaj,ji", dict(a=100, i=120, j=90)
+    A, B, C = wl.tensors(spec, ext, np.random.default_rng(21), integer=True, with_c=True)
+    for dtype in ("f64", "f32"):
+        p = _plan(spec, ext, dtype)
+        got = run(p, A, B, C, alpha=1.0, beta=-1.0, dtype=dtype)
+        check(spec, ext, A, B, got, dtype, C0=C, alpha=1.0, beta=-1.0, exact=True)
+
+
+# Family members with long kernels and few outputs (the paper's Test 2): the
+# member body gives each output 8 lanes (length 40) or 64 lanes (length 130).
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [40, 130])
+def test_test2_members_long_kernels(dtype, n):
+    import torch
+    spec, ext = "a=iaj,ji", dict(a=n, i=n, j=17)
+    rng = np.random.default_rng(n)
+    A, B, C0 = wl.tensors(spec, ext, rng, "normal", with_c=True)
+    p = _plan(spec, ext, dtype)
+    assert len(p.variants()) == 8
+    for v in range(8):
+        p.set_variant(v)
+        got = run(p, A, B, C0, alpha=2.0, beta=0.5, dtype=dtype)
+        check(spec, ext, A, B, got, dtype, C0=C0, alpha=2.0, beta=0.5)
+
+
+def test_test2_members_integer_exact():
+    spec, ext = "a=iaj,ji", dict(a=130, i=130, j=9)
+    A, B, C = wl.tensors(spec, ext, np.random.default_rng(23), integer=True, with_c=True)
+    p = _plan(spec, ext)
+    for v in range(8):
+        p.set_variant(v)
+        got = run(p, A, B, C, alpha=1.0, beta=2.0)
+        check(spec, ext, A, B, got, C0=C, alpha=1.0, beta=2.0, exact=True)
+
+
 def test_fused_mfma_integer_exact():
     spec, ext = "abc=ija,jbic", dict(a=70, b=20, c=9, i=13, j=17)
     A, B, C = wl.tensors(spec, ext, np.random.default_rng(5), integer=True, with_c=True)
