@@ -4,8 +4,10 @@
 //
 // Reading for the GPU.  A member's kernel invocations run many at a time, so a
 // micro-benchmark times one launch of the member's body over a SAMPLE of its
-// invocations (the first ones in schedule order, about 2^19 outputs worth, or
-// the whole launch if smaller), preceded by the class's setup list: operand
+// invocations (the first ones in schedule order, enough to fill the device:
+// about 2^19 outputs worth for one-thread-per-output bodies, 2^25 for
+// matrix-core bodies, or the whole launch if smaller), preceded by the class's
+// setup list: operand
 // regions are touched in list order and every remote region is a distinct
 // piece of a scratch buffer, so after the setup the caches hold what the
 // setup list says.  Ten repetitions, median (Sections 3.1, 3.2).  A class's
@@ -220,7 +222,10 @@ static tc_status predict_variant(PredCtx& c, int v, tc_prediction* out) {
     const void* opB = copied[1] ? p->d_temp[1] : c.B;
 
     GtDesc d;
-    const int64_t target = (int64_t)1 << 19;
+    // The sample must fill the device, or scaling it up overstates the time:
+    // 2^19 outputs are 2048 blocks of the one-thread-per-output bodies, and
+    // 2^25 outputs about 2048 tiles of 128 x 128 for matrix-core bodies.
+    const int64_t target = vp.mfma ? ((int64_t)1 << 25) : ((int64_t)1 << 19);
     double frac = sample_desc(vp, d, target);
     int64_t hoisted = 1;
     for (auto& h : vp.hoisted) hoisted *= h.ext;
