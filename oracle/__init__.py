@@ -5,7 +5,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 imports nothing from the GPU library: the two share no code.
 
 Contents
-  contract.c    plain FP64 loop nest (Section 1, Tensor Notation), own parser
+  contract.c    plain FP64 loop nest (Section 1, Tensor Notation), own parser;
+                batch indices (in A, B and C) and trace indices (one input
+                only) read as the same sum over every index absent from C
   family.py     the algorithm family of Section 2 (Table 1 rules x loop orders)
   interp.py     executes each family member as the paper's loops of BLAS calls
   access.py     the symbolic prediction steps of Section 3 (access distance,

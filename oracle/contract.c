@@ -12,7 +12,11 @@
  *     C[f] = alpha * sum_{k over all contracted indices} A[f_A, k] * B[f_B, k]
  *            + beta * C_in[f]
  * Contracted indices appear in both inputs and not in C; free indices appear in
- * exactly one input and in C.  Element (x_1..x_d) of an operand X lives at
+ * exactly one input and in C.  Two index classes the paper does not define are
+ * read as the same sum over every index absent from C: a batch index (in A, B
+ * and C) is a free index of both inputs, so each of its values is an ordinary
+ * contraction of slices; a trace index (in one input only) is summed with the
+ * other input constant along it.  Element (x_1..x_d) of an operand X lives at
  * X + sum_m x_m * stride_m (element units).  The paper assumes Fortran order
  * (first index stride 1); explicit strides generalise that.  The paper's
  * algorithms accumulate into C ("+="); alpha/beta are the BLAS reading of that,
@@ -21,8 +25,9 @@
  *   alpha == 0 -> A and B are not read.
  *
  * Fixed summation order: the outer odometer runs over C's indices with C's first
- * index fastest; the inner odometer runs over the contracted indices in the order
- * they appear in A's spec, first fastest; the accumulator starts at 0.0.
+ * index fastest; the inner odometer runs over the summed indices (those not in
+ * C) in the order they appear in A's spec, then B's indices that are in neither
+ * A nor C, first fastest; the accumulator starts at 0.0.
  * Build with -O2 -ffp-contract=off and without fast-math so the products and sums
  * are rounded exactly as written.
  *
@@ -63,14 +68,11 @@ static int or_parse(const char* s, or_spec* p) {
             if (*q < 'a' || *q > 'z') return OR_E_SPEC;
             if (strchr(q + 1, *q)) return OR_E_SPEC;     /* repeated in one operand */
         }
-    /* every index must be contracted (A and B, not C) or free (one input and C) */
-    for (int t = 0; t < 3; ++t)
-        for (const char* q = all[t]; *q; ++q) {
-            int inA = strchr(p->a, *q) != 0, inB = strchr(p->b, *q) != 0, inC = strchr(p->c, *q) != 0;
-            int contracted = inA && inB && !inC;
-            int free_ = (inA ^ inB) && inC;
-            if (!contracted && !free_) return OR_E_SPEC;
-        }
+    /* every index of C must come from an input; any index of an input is allowed:
+     * contracted (A and B), free (one input and C), batch (A, B and C) or trace
+     * (one input only) */
+    for (const char* q = p->c; *q; ++q)
+        if (!strchr(p->a, *q) && !strchr(p->b, *q)) return OR_E_SPEC;
     return OR_OK;
 }
 
@@ -114,13 +116,15 @@ int oracle_contract(const char* spec, const char* idx_chars, const int64_t* exte
         }
     }
 
-    /* contracted indices in A's order */
-    char kidx[OR_MAXIDX + 1];
+    /* summed indices (not in C): A's in A's order, then B's own */
+    char kidx[2 * OR_MAXIDX + 1];
     int nk = 0;
     for (int m = 0; m < p.na; ++m)
-        if (pos(p.b, p.a[m]) >= 0) kidx[nk++] = p.a[m];
+        if (pos(p.c, p.a[m]) < 0) kidx[nk++] = p.a[m];
+    for (int m = 0; m < p.nb; ++m)
+        if (pos(p.c, p.b[m]) < 0 && pos(p.a, p.b[m]) < 0) kidx[nk++] = p.b[m];
     kidx[nk] = 0;
-    int64_t kext[OR_MAXIDX];
+    int64_t kext[2 * OR_MAXIDX];
     for (int q = 0; q < nk; ++q) kext[q] = extent_of(kidx[q], idx_chars, extents, n_idx);
 
     int64_t nC = 1, nK = 1;
@@ -130,7 +134,7 @@ int oracle_contract(const char* spec, const char* idx_chars, const int64_t* exte
     if (!C) return OR_E_NULL;
     if (alpha != 0.0 && nK > 0 && (!A || !B)) return OR_E_NULL;
 
-    int64_t ci[OR_MAXIDX], ki[OR_MAXIDX];
+    int64_t ci[OR_MAXIDX], ki[2 * OR_MAXIDX];
     memset(ci, 0, sizeof ci);
     for (int64_t f = 0; f < nC; ++f) {
         /* offset of C[f] and the free parts of A and B */
@@ -147,8 +151,9 @@ int oracle_contract(const char* spec, const char* idx_chars, const int64_t* exte
             for (int64_t k = 0; k < nK; ++k) {
                 int64_t oa = offA, ob = offB;
                 for (int q = 0; q < nk; ++q) {
-                    oa += ki[q] * sA[pos(p.a, kidx[q])];
-                    ob += ki[q] * sB[pos(p.b, kidx[q])];
+                    int pa = pos(p.a, kidx[q]), pb = pos(p.b, kidx[q]);
+                    if (pa >= 0) oa += ki[q] * sA[pa];   /* a trace index of B leaves A fixed */
+                    if (pb >= 0) ob += ki[q] * sB[pb];
                 }
                 double x = A[oa], y = B[ob];
                 if (mode == 1) {

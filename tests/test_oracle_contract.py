@@ -167,7 +167,7 @@ def test_zero_extents():
     assert out.shape == (0, 2, 2)
 
 
-@pytest.mark.parametrize("bad", ["abc=ai,ib", "abc=aai,ibc", "ab=ai,ibc", "abc=ai", "aBc=ai,iBc", "abcx=ai,ibc"])
+@pytest.mark.parametrize("bad", ["abc=ai,ib", "abc=aai,ibc", "abc=ai", "aBc=ai,iBc", "abcx=ai,ibc"])
 def test_rejects_malformed_specs(bad):
     ext = dict(a=2, b=2, c=2, i=2, x=2, B=2)
     sa, sb, sc = (bad.split("=")[1].split(",") + [""])[:2] + [bad.split("=")[0]]
@@ -216,3 +216,69 @@ def test_error_metrics():
     assert abs(oracle.normwise_rel_err(C + np.array([0.3, 0.4]), C) - 0.1) < 1e-15
     assert oracle.componentwise_err(np.array([1.5]), np.array([1.0]), np.array([2.0])) == 0.25
     assert oracle.flops("abc=ai,ibc", dict(a=64, b=64, c=64, i=8)) == 4194304
+
+
+# Index classes the paper does not define, read as the same sum over every index
+# absent from C: batch indices (in A, B and C) and trace indices (one input only).
+GENERAL = ["ab=iab,ib", "abc=aic,ibc", "a=iat,i", "ab=ai,ibt", "abc=aict,ibcs", "b=tb,sb"]
+
+
+@pytest.mark.parametrize("spec", GENERAL)
+@pytest.mark.parametrize("n", [0, 1, 2, 3])
+def test_batch_and_trace_brute_force(spec, n):
+    rng = np.random.default_rng(300 + n)
+    letters = set(spec.replace("=", "").replace(",", ""))
+    ext = {ch: int(rng.integers(max(0, n - 1), n + 2)) for ch in letters}
+    sa, sb, sc = oracle.split_spec(spec)
+    A, B = rand_tensor(rng, sa, ext, True), rand_tensor(rng, sb, ext, True)
+    np.testing.assert_array_equal(oracle.contract(spec, ext, A, B), brute(spec, ext, A, B))
+
+
+def test_batch_index_is_slicewise_contraction():
+    """Each value of a batch index is the paper's contraction of the slices
+    (same summation order, so bit-identical on real data)."""
+    rng = np.random.default_rng(31)
+    ext = dict(a=5, b=4, c=3, i=7)
+    A, B = rand_tensor(rng, "aic", ext), rand_tensor(rng, "ibc", ext)
+    C = oracle.contract("abc=aic,ibc", ext, A, B, alpha=1.5)
+    for c in range(ext["c"]):
+        ref = oracle.contract("ab=ai,ib", dict(a=5, b=4, i=7), np.asfortranarray(A[:, :, c]),
+                              np.asfortranarray(B[:, :, c]), alpha=1.5)
+        np.testing.assert_array_equal(C[:, :, c], ref)
+
+
+def test_trace_index_is_presummed_operand():
+    """A trace index of A equals contracting the summed-out A (integers: exact);
+    the same on B's side."""
+    rng = np.random.default_rng(32)
+    ext = dict(a=6, i=5, t=4, b=3, s=2)
+    A, B = rand_tensor(rng, "iat", ext, True), rand_tensor(rng, "ib", ext, True)
+    got = oracle.contract("ab=iat,ib", ext, A, B)
+    ref = oracle.contract("ab=ia,ib", ext, np.asfortranarray(A.sum(axis=2)), B)
+    np.testing.assert_array_equal(got, ref)
+    A2, B2 = rand_tensor(rng, "ia", ext, True), rand_tensor(rng, "sib", ext, True)
+    got = oracle.contract("ab=ia,sib", ext, A2, B2)
+    ref = oracle.contract("ab=ia,ib", ext, A2, np.asfortranarray(B2.sum(axis=0)))
+    np.testing.assert_array_equal(got, ref)
+
+
+@given(st.data())
+@settings(max_examples=40, deadline=None)
+def test_random_general_specs_vs_brute(data):
+    """Random specs with free, contracted, batch and trace indices."""
+    letters = "abcdeijkst"
+    counts = [data.draw(st.integers(0, 1)) for _ in range(6)]   # fa, fb, k, batch, ta, tb
+    pool = data.draw(st.permutations(list(letters)))
+    groups, at = [], 0
+    for c in counts:
+        groups.append(pool[at:at + c])
+        at += c
+    fa, fb, k, bt, ta, tb = groups
+    sa = "".join(data.draw(st.permutations(fa + k + bt + ta)))
+    sb = "".join(data.draw(st.permutations(fb + k + bt + tb)))
+    sc = "".join(data.draw(st.permutations(fa + fb + bt)))
+    spec = f"{sc}={sa},{sb}"
+    ext = {ch: data.draw(st.integers(0, 3)) for ch in set(sa + sb + sc)}
+    rng = np.random.default_rng(data.draw(st.integers(0, 2**31)))
+    A, B = rand_tensor(rng, sa, ext, True), rand_tensor(rng, sb, ext, True)
+    np.testing.assert_array_equal(oracle.contract(spec, ext, A, B), brute(spec, ext, A, B))
