@@ -205,12 +205,16 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
         for (int d = 0; d < a.m.n; ++d) a.m.d[d] = gv.m[d];
         a.n.n = (int)gv.n.size();
         for (int d = 0; d < a.n.n; ++d) a.n.d[d] = gv.n[d];
-        a.batch.n = 0;
+        a.batch.n = (int)gv.b.size();
+        a.nbatch = 1;
+        for (int d = 0; d < a.batch.n; ++d) {
+            a.batch.d[d] = gv.b[d];
+            a.nbatch *= gv.b[d].ext;
+        }
         a.pass.n = 0;
         a.M = gv.M;
         a.N = gv.N;
         a.Kpad = (int64_t)tab.size() / 2;
-        a.nbatch = 1;
         a.npass = 1;
         a.mode = 0;
         b->items.push_back(a);

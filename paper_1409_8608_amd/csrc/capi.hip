@@ -175,7 +175,7 @@ static tc_status upload(void** p, int64_t* cap, const std::vector<int64_t>& v) {
 namespace tc {
 
 bool use_stream_kernel(const Spec& s, const GemmView& gv) {
-    return gv.K >= 1 && gv.K <= GT_SMALLK_MAX && gv.m.size() == 1 && gv.m[0].sC == 1;
+    return gv.K >= 1 && gv.K <= GT_SMALLK_MAX && gv.m.size() == 1 && gv.m[0].sC == 1 && gv.b.empty();
 }
 
 tc_status prepare_plan(tc_plan_s* p) {
@@ -190,8 +190,9 @@ tc_status prepare_plan(tc_plan_s* p) {
             tc_status st = upload(&p->d_ktab, &p->ktab_cap, tab);
             if (st) return st;
             int64_t ws = 0;
-            p->kslices = s.compute == TC_NATIVE ? mfma_split_plan(f64, p->gv.M, p->gv.N, p->kpad, &p->kslice_tiles, &ws)
-                                                : 1;
+            p->kslices = s.compute == TC_NATIVE && p->gv.b.empty()
+                             ? mfma_split_plan(f64, p->gv.M, p->gv.N, p->kpad, &p->kslice_tiles, &ws)
+                             : 1;
             if (p->kslices > 1) {
                 st = ensure_device_buffer(&p->d_splitk, &p->splitk_cap, ws);
                 if (st) return st;
@@ -273,7 +274,12 @@ static tc_status run_fused(tc_plan_s* p, const void* A, const void* B, void* C, 
     for (int d = 0; d < a.m.n; ++d) a.m.d[d] = gv.m[d];
     a.n.n = (int)gv.n.size();
     for (int d = 0; d < a.n.n; ++d) a.n.d[d] = gv.n[d];
-    a.batch.n = 0;
+    a.batch.n = (int)gv.b.size();
+    a.nbatch = 1;
+    for (int d = 0; d < a.batch.n; ++d) {
+        a.batch.d[d] = gv.b[d];
+        a.nbatch *= gv.b[d].ext;
+    }
     a.pass.n = 0;
     a.ktab = (const int64_t*)p->d_ktab;
     a.kvec = p->kvec;
@@ -283,7 +289,7 @@ static tc_status run_fused(tc_plan_s* p, const void* A, const void* B, void* C, 
         a.kslice_tiles = p->kslice_tiles;
     }
     a.M = gv.M; a.N = gv.N; a.Kpad = p->kpad;
-    a.nbatch = 1; a.npass = 1;
+    a.npass = 1;
     a.alpha = alpha; a.beta = beta;
     a.mode = 0;
     mfma_tiles(f64, a);
@@ -399,7 +405,7 @@ tc_status contract_dispatch(tc_plan_s* p, const void* A, const void* B, void* C,
     const Spec& s = p->spec;
     bool f64 = s.dtype == TC_F64;
     int64_t K = 1;
-    for (char ch : s.contracted) K *= s.e(ch);
+    for (char ch : s.summed()) K *= s.e(ch);
     if (s.nC == 0) return TC_OK;
     if (alpha == 0.0 || K == 0) {
         ScaleArgs sa{};
@@ -443,7 +449,15 @@ tc_status tc_plan(tc_plan_t* out, const char* spec, const char* index_chars, con
         delete p;
         return fail(err.st, err.msg);
     }
+    if (compute != TC_NATIVE && p->spec.general()) {
+        delete p;
+        return fail(TC_E_UNSUPPORTED, "split precision needs contracted and free indices only");
+    }
     p->gv = gemm_view(p->spec);
+    if ((int)p->gv.b.size() > GT_MAXD || (int)p->gv.k.size() > GT_MAXD) {
+        delete p;
+        return fail(TC_E_UNSUPPORTED, "too many batch or contracted dimension groups");
+    }
     *out = p;
     return TC_OK;
 }
@@ -522,7 +536,7 @@ tc_status tc_contract(tc_plan_t p, const void* A, const void* B, void* C, double
     if (!p) return fail(TC_E_NULL, "plan is NULL");
     const Spec& s = p->spec;
     int64_t K = 1;
-    for (char ch : s.contracted) K *= s.e(ch);
+    for (char ch : s.summed()) K *= s.e(ch);
     bool reads_inputs = alpha != 0.0 && K > 0 && s.nC > 0;
     if (s.nC > 0 && !C) return fail(TC_E_NULL, "C is NULL");
     if (reads_inputs && ((s.nA > 0 && !A) || (s.nB > 0 && !B))) return fail(TC_E_NULL, "A or B is NULL");

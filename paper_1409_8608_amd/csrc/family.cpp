@@ -46,6 +46,7 @@ static std::vector<std::string> kept_sets(const Spec& s, int kernel) {
 
 std::vector<Variant> enumerate_family(const Spec& s) {
     std::vector<Variant> fam;
+    if (s.general()) return fam;   // Table 1 covers contracted and free indices only
     int number = 0;
     for (int kernel = 0; kernel < 5; ++kernel) {
         for (const std::string& kept : kept_sets(s, kernel)) {

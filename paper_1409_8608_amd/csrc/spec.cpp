@@ -16,8 +16,10 @@ int64_t Spec::flops() const {
     return n;
 }
 
-// "out=inA,inB": lowercase letters only, no letter twice in one operand, every
-// letter either contracted (both inputs, not C) or free (one input and C).
+// "out=inA,inB": lowercase letters only, no letter twice in one operand; a
+// letter is contracted (both inputs, not C) or free (one input and C), the
+// paper's two classes, or, read as the same sum over every index absent from
+// C, batch (both inputs and C) or trace (one input only).
 tc_status parse_spec(const char* text, Spec& s, Err& err) {
     if (!text) return err.set(TC_E_NULL, "spec is NULL");
     std::string t(text);
@@ -40,22 +42,22 @@ tc_status parse_spec(const char* text, Spec& s, Err& err) {
         }
     }
     s.contracted.clear(); s.free_a.clear(); s.free_b.clear();
+    s.batch.clear(); s.trace_a.clear(); s.trace_b.clear();
     for (char ch : s.a) {
         bool inB = has(s.b, ch), inC = has(s.c, ch);
-        if (inB && inC) return err.set(TC_E_SPEC, std::string("index in A, B and C (batch index) unsupported: ") + ch);
-        if (!inB && !inC) return err.set(TC_E_SPEC, std::string("index only in A (trace) unsupported: ") + ch);
-        if (inB) s.contracted += ch;
+        if (!inB && !inC) s.trace_a += ch;          // summed, B constant along it
+        else if (inB && !inC) s.contracted += ch;
     }
-    for (char ch : s.b) {
-        bool inA = has(s.a, ch), inC = has(s.c, ch);
-        if (!inA && !inC) return err.set(TC_E_SPEC, std::string("index only in B (trace) unsupported: ") + ch);
-    }
+    for (char ch : s.b)
+        if (!has(s.a, ch) && !has(s.c, ch)) s.trace_b += ch;
     for (char ch : s.c) {
         bool inA = has(s.a, ch), inB = has(s.b, ch);
         if (!inA && !inB) return err.set(TC_E_SPEC, std::string("output index in no input: ") + ch);
-        if (inA) s.free_a += ch; else s.free_b += ch;
+        if (inA && inB) s.batch += ch;
+        else if (inA) s.free_a += ch;
+        else s.free_b += ch;
     }
-    s.base = s.c + s.contracted;
+    s.base = s.c + s.summed();
     return TC_OK;
 }
 
@@ -169,13 +171,18 @@ GemmView gemm_view(const Spec& s) {
     auto sb = [&](char ch) { return v.swapped ? s.sA[ch - 'a'] : s.sB[ch - 'a']; };
     for (char ch : fm) v.m.push_back(GtDim{s.e(ch), sa(ch), 0, s.sC[ch - 'a']});
     for (char ch : fn) v.n.push_back(GtDim{s.e(ch), 0, sb(ch), s.sC[ch - 'a']});
-    for (char ch : s.contracted) v.k.push_back(GtDim{s.e(ch), sa(ch), sb(ch), 0});
+    // trace indices are contracted dimensions with stride 0 in the operand
+    // that lacks them (its value is reused along them)
+    for (char ch : s.summed()) v.k.push_back(GtDim{s.e(ch), sa(ch), sb(ch), 0});
+    for (char ch : s.batch) v.b.push_back(GtDim{s.e(ch), sa(ch), sb(ch), s.sC[ch - 'a']});
     auto by_c = [](const GtDim& x, const GtDim& y) { return x.sC < y.sC; };
     std::stable_sort(v.m.begin(), v.m.end(), by_c);
     std::stable_sort(v.n.begin(), v.n.end(), by_c);
     merge_group(v.m);
     merge_group(v.n);
     merge_group(v.k);
+    merge_group(v.b);
+    if (v.b.size() == 1 && v.b[0].ext == 1) v.b.clear();
     std::stable_sort(v.m.begin(), v.m.end(), by_c);
     std::stable_sort(v.n.begin(), v.n.end(), by_c);
     v.M = v.N = v.K = 1;

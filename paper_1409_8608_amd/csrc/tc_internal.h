@@ -24,7 +24,11 @@ struct Spec {
     std::string a, b, c;            // letters of A, B and C in axis order
     std::string contracted;         // in A's axis order
     std::string free_a, free_b;     // in C's axis order
-    std::string base;               // C's letters, then the contracted ones
+    // index classes outside the paper's definition (no family members; the
+    // fused kernel only): batch indices in A, B and C (C's order) and trace
+    // indices in one input only (that input's order)
+    std::string batch, trace_a, trace_b;
+    std::string base;               // C's letters, then the summed ones
     // bound per letter (index by letter - 'a'); stride 0 where the operand lacks it
     int64_t ext[26] = {0};
     int64_t sA[26] = {0}, sB[26] = {0}, sC[26] = {0};
@@ -41,6 +45,9 @@ struct Spec {
     }
     const std::string& letters(int tensor) const { return tensor == 0 ? a : tensor == 1 ? b : c; }
     int64_t flops() const;                 // 2 * product of all extents
+    // indices summed over: contracted, then trace indices of A and of B
+    std::string summed() const { return contracted + trace_a + trace_b; }
+    bool general() const { return !batch.empty() || !trace_a.empty() || !trace_b.empty(); }
     int elem_bytes() const { return dtype == TC_F64 ? 8 : 4; }
 };
 
@@ -94,6 +101,7 @@ std::vector<BenchClass> bench_classes(const Spec& s, const Variant& v, int stage
 // (stride[d+1] == stride[d] * ext[d] in every operand holding them) are merged.
 struct GemmView {
     std::vector<GtDim> m, n, k;       // each group, unit-C-stride dim first where possible
+    std::vector<GtDim> b;             // batch indices (sA, sB, sC)
     bool swapped = false;             // A and B exchanged so that C's unit stride is in M
     int64_t M = 1, N = 1, K = 1;
 };

@@ -26,14 +26,30 @@ def test_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("spec,status", [
-    ("abc=ai", "TC_E_SPEC"), ("abc=ai,ib", "TC_E_SPEC"), ("abc=aic,ibc", "TC_E_SPEC"),
-    ("aa=ai,ia", "TC_E_SPEC"), ("abc=aix,ibc", "TC_E_SPEC"), ("aBc=ai,iBc", "TC_E_SPEC"),
+    ("abc=ai", "TC_E_SPEC"), ("abc=ai,ib", "TC_E_SPEC"), ("abcx=ai,ibc", "TC_E_SPEC"),
+    ("aa=ai,ia", "TC_E_SPEC"), ("aBc=ai,iBc", "TC_E_SPEC"),
 ])
 def test_plan_rejects_bad_specs(spec, status):
     ext = {ch: 2 for ch in set(spec.lower()) if ch.isalpha()}
     with pytest.raises(tc.TcError) as e:
         tc.tc_plan(spec, ext)
     assert e.value.name == status
+
+
+@pytest.mark.parametrize("spec", ["abc=aic,ibc", "abc=aix,ibc", "ab=ai,ibt", "bc=tbc,sbc"])
+def test_batch_and_trace_specs(spec):
+    """Batch (A, B and C) and trace (one input) indices plan for the fused
+    kernel only: no family members, no split-precision forms."""
+    ext = {ch: 3 for ch in set(spec) if ch.isalpha()}
+    p = tc.Plan(spec, ext, "f64")
+    assert p.variants() == []
+    with pytest.raises(tc.TcError) as e:
+        p.set_variant(0)
+    assert e.value.name == "TC_E_VARIANT"
+    for compute in ("bf16x3", "fp8x3"):
+        with pytest.raises(tc.TcError) as e:
+            tc.Plan(spec, ext, "f64", compute=compute)
+        assert e.value.name == "TC_E_UNSUPPORTED"
 
 
 def test_plan_rejects_bad_bindings():

@@ -193,6 +193,63 @@ def test_test2_members_integer_exact():
         check(spec, ext, A, B, got, C0=C, alpha=1.0, beta=2.0, exact=True)
 
 
+# Index classes outside the paper's definition, on the fused kernel: batch
+# indices (in A, B and C) become the matrix-core kernel's batch dimensions,
+# trace indices (one input only) contracted dimensions with stride 0 in the
+# other input.  K <= 32 with a trace index of B and no batch index runs the
+# streaming kernel; the Hadamard form bc=tbc,sbc has one output per tile.
+GENERAL_SHAPES = [
+    ("abc=aic,ibc", dict(a=70, b=40, c=5, i=33)),
+    ("ab=iab,ib", dict(a=100, b=6, i=50)),
+    ("a=iat,i", dict(a=300, i=20, t=7)),
+    ("ab=ai,ibt", dict(a=130, b=70, i=9, t=3)),
+    ("abc=aict,ibcs", dict(a=40, b=30, c=3, i=10, t=2, s=3)),
+    ("bc=tbc,sbc", dict(b=20, c=10, t=5, s=7)),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", GENERAL_SHAPES)
+def test_fused_batch_and_trace_indices(dtype, spec, ext):
+    rng = np.random.default_rng(29)
+    A, B, C0 = wl.tensors(spec, ext, rng, "normal", with_c=True)
+    p = _plan(spec, ext, dtype)
+    assert p.variants() == []
+    got = run(p, A, B, dtype=dtype)
+    check(spec, ext, A, B, got, dtype)
+    got = run(p, A, B, C0, alpha=-0.75, beta=2.0, dtype=dtype)
+    check(spec, ext, A, B, got, dtype, C0=C0, alpha=-0.75, beta=2.0)
+
+
+def test_fused_batch_and_trace_integer_exact():
+    for spec, ext in GENERAL_SHAPES:
+        A, B, C = wl.tensors(spec, ext, np.random.default_rng(33), integer=True, with_c=True)
+        for dtype in ("f64", "f32"):
+            p = _plan(spec, ext, dtype)
+            got = run(p, A, B, C, alpha=1.0, beta=-2.0, dtype=dtype)
+            check(spec, ext, A, B, got, dtype, C0=C, alpha=1.0, beta=-2.0, exact=True)
+
+
+def test_batch_api_with_batch_and_trace_members():
+    """A graph batch mixing ordinary members with batch- and trace-index ones."""
+    import torch
+    specs = [GENERAL_SHAPES[0], GENERAL_SHAPES[2], GENERAL_SHAPES[4], ("abc=ai,ibc", dict(a=50, b=30, c=7, i=40))]
+    plans, host, dev = [], [], []
+    for t, (spec, ext) in enumerate(specs):
+        A, B, _ = wl.tensors(spec, ext, np.random.default_rng(40 + t), "normal")
+        p = _plan(spec, ext)
+        plans.append(p)
+        host.append((spec, ext, A, B))
+        dev.append((tc.to_device_fortran(A, torch.float64), tc.to_device_fortran(B, torch.float64),
+                    tc.empty_fortran(p.shape("C"), torch.float64).fill_(float("nan"))))
+    batch = tc.Batch(plans)
+    As, Bs, Cs = zip(*dev)
+    batch.contract(As, Bs, Cs)
+    torch.cuda.synchronize()
+    for (spec, ext, A, B), C in zip(host, Cs):
+        check(spec, ext, A, B, C.cpu().numpy())
+
+
 def test_fused_mfma_integer_exact():
     spec, ext = "abc=ija,jbic", dict(a=70, b=20, c=9, i=13, j=17)
     A, B, C = wl.tensors(spec, ext, np.random.default_rng(5), integer=True, with_c=True)
