@@ -58,7 +58,7 @@ typedef enum { TC_NATIVE = 0, TC_BF16X3 = 1, TC_FP8X3 = 2 } tc_compute;
 
 typedef enum {
     TC_OK = 0,
-    TC_E_SPEC,         /* malformed spec or an index role outside Section 1 */
+    TC_E_SPEC,         /* malformed spec (repeated letter, C index in no input, ...) */
     TC_E_EXTENT,       /* missing/negative extent, or element count overflow */
     TC_E_STRIDE,       /* negative input stride, non-positive or self-overlapping C stride */
     TC_E_DTYPE,        /* unknown dtype or dtype/compute pair */
@@ -131,10 +131,16 @@ typedef struct {
  * bind extents and strides, enumerate the algorithm family (Section 2,
  * Table 1 x loop orders) and map each member to a GPU schedule.  Host work
  * only; no device memory is touched.
+ *   Index classes: contracted (both inputs, not C) and free (one input and C)
+ *   as in Section 1; also batch (A, B and C) and trace (one input only),
+ *   computed as the same sum over every index absent from C.  Specs with
+ *   batch or trace indices have no family members (fused kernel only) and
+ *   no split-precision forms (TC_E_UNSUPPORTED).
  *   index_chars/extents: n_index letters and their extents (every letter of
  *                        the spec must be given; extra letters are an error).
  *   strides_X: element strides in X's spec order, or NULL for Fortran order.
- * Errors: TC_E_SPEC, TC_E_EXTENT, TC_E_STRIDE, TC_E_DTYPE, TC_E_NULL. */
+ * Errors: TC_E_SPEC, TC_E_EXTENT, TC_E_STRIDE, TC_E_DTYPE, TC_E_NULL,
+ * TC_E_UNSUPPORTED. */
 tc_status tc_plan(tc_plan_t* out, const char* spec,
                   const char* index_chars, const int64_t* extents, int n_index,
                   const int64_t* strides_A, const int64_t* strides_B, const int64_t* strides_C,
