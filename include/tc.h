@@ -31,7 +31,10 @@
  *     storage.  Input strides must be >= 0 (0 broadcasts); C strides must be
  *     > 0 and C must not overlap itself.
  *   - A plan must not be used by two host threads at once; distinct plans are
- *     independent.
+ *     independent.  Calls on one plan reuse its device workspace (copy
+ *     temporaries, split-precision terms, split-K partial tiles): two calls on
+ *     one plan on streams with no ordering between them race; give each
+ *     concurrent stream its own plan.
  */
 #ifndef TC_H
 #define TC_H

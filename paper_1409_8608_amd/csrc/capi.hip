@@ -527,7 +527,7 @@ tc_status tc_plan_prepare(tc_plan_t p) {
 
 tc_status tc_plan_workspace(tc_plan_t p, int64_t* bytes) {
     if (!p || !bytes) return fail(TC_E_NULL, "NULL argument");
-    *bytes = p->ktab_cap + p->var_ktab_cap + p->temp_cap[0] + p->temp_cap[1] + p->split_bytes;
+    *bytes = p->ktab_cap + p->var_ktab_cap + p->temp_cap[0] + p->temp_cap[1] + p->split_bytes + p->splitk_cap;
     return TC_OK;
 }
 

@@ -157,6 +157,17 @@ def test_fused_split_k(dtype, spec, ext):
     check(spec, ext, A, B, got, dtype, C0=C0, alpha=0.5, beta=-1.5)
 
 
+def test_split_k_workspace_is_reported():
+    """The split-K partial tiles are part of the plan's workspace: the Test 2
+    shape a=100, i=120, j=90 (one output tile, 675 K tiles) uses slices of
+    9 K tiles, 75 x 128 x 128 doubles."""
+    spec, ext = "a=iaj,ji", dict(a=100, i=120, j=90)
+    p = _plan(spec, ext)
+    p.prepare()
+    ktab = 2 * 8 * 10800                 # (A, B) offset pairs of the K table
+    assert tc.tc_plan_workspace(p.handle) >= ktab + 75 * 128 * 128 * 8
+
+
 def test_fused_split_k_integer_exact():
     spec, ext = "a=iaj,ji", dict(a=100, i=120, j=90)
     A, B, C = wl.tensors(spec, ext, np.random.default_rng(21), integer=True, with_c=True)
