@@ -181,6 +181,8 @@ GemmView gemm_view(const Spec& s) {
     merge_group(v.m);
     merge_group(v.n);
     merge_group(v.k);
+    // no summed index (an outer product): one K position, offset 0 in both
+    if (v.k.empty()) v.k.push_back(GtDim{1, 0, 0, 0});
     merge_group(v.b);
     if (v.b.size() == 1 && v.b[0].ext == 1) v.b.clear();
     std::stable_sort(v.m.begin(), v.m.end(), by_c);

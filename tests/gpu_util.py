@@ -36,13 +36,14 @@ def rounded(x, dtype):
 
 
 def check(spec, ext, A, B, got, dtype="f64", C0=None, alpha=1.0, beta=0.0, exact=False, tol=None):
-    Ar, Br = rounded(A, dtype), rounded(B, dtype)
+    # np.array(..., order="F") keeps 0-d operands arrays (ufuncs return scalars)
+    Ar, Br = np.array(rounded(A, dtype), order="F"), np.array(rounded(B, dtype), order="F")
     Cr = None if C0 is None else np.array(rounded(C0, dtype), order="F")
     ref = oracle.contract(spec, ext, Ar, Br, C=Cr, alpha=alpha, beta=beta)
     if exact:
         np.testing.assert_array_equal(got, ref)
         return 0.0
-    absAB = oracle.contract(spec, ext, np.abs(Ar), np.abs(Br))
+    absAB = oracle.contract(spec, ext, np.array(np.abs(Ar), order="F"), np.array(np.abs(Br), order="F"))
     err = oracle.normwise_rel_err(got, ref, absAB)
     if tol is None:
         tol = 1e-12 if dtype == "f64" else 1e-5

@@ -261,6 +261,29 @@ def test_batch_api_with_batch_and_trace_members():
         check(spec, ext, A, B, C.cpu().numpy())
 
 
+# Outer products (no summed index): one K position.  C's unit index from A
+# runs the streaming kernel, a permuted C the matrix-core kernel.
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext,strides", [
+    ("abc=ab,c", dict(a=300, b=5, c=7), None),
+    ("bak=ab,k", dict(a=16, b=5, k=9), dict(C=[16 * 9, 9, 1])),
+    ("ab=a,b", dict(a=70, b=130), dict(C=[130, 1])),
+])
+def test_fused_outer_product(dtype, spec, ext, strides):
+    import torch
+    A, B, C0 = wl.tensors(spec, ext, np.random.default_rng(41), "normal", with_c=True)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    p = _plan(spec, ext, dtype, strides=strides)
+    sC = p.strides["C"]
+    shapeC = p.shape("C")
+    span = 1 + sum((e - 1) * st for e, st in zip(shapeC, sC))
+    dC = torch.as_strided(torch.zeros(span, dtype=tdt, device="cuda"), tuple(shapeC), tuple(sC))
+    dC.copy_(torch.from_numpy(np.array(C0)))
+    p.contract(tc.to_device_fortran(A, tdt), tc.to_device_fortran(B, tdt), dC, -0.5, 1.5)
+    torch.cuda.synchronize()
+    check(spec, ext, A, B, dC.double().cpu().numpy(), dtype, C0=C0, alpha=-0.5, beta=1.5)
+
+
 def test_fused_mfma_integer_exact():
     spec, ext = "abc=ija,jbic", dict(a=70, b=20, c=9, i=13, j=17)
     A, B, C = wl.tensors(spec, ext, np.random.default_rng(5), integer=True, with_c=True)

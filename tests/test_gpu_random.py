@@ -1,0 +1,78 @@
+"""Seeded random contractions on the GPU against the oracle: random index
+classes (free, contracted, batch, trace), extents, storage orders (Fortran,
+permuted axes, padded strides), storage types, alpha and beta, through the
+fused path.  Each case prints its seed and spec before it runs."""
+import numpy as np
+import pytest
+
+from gpu_util import check
+
+pytestmark = pytest.mark.gpu
+tc = pytest.importorskip("paper_1409_8608_amd")
+
+
+def _draw_case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    letters = list("abcdefgijklmst")
+    rng.shuffle(letters)
+    n = dict(fa=int(rng.integers(0, 3)), fb=int(rng.integers(0, 3)), k=int(rng.integers(0, 4)),
+             bt=int(rng.random() < 0.3), ta=int(rng.random() < 0.2), tb=int(rng.random() < 0.2))
+    if n["fa"] + n["fb"] + n["bt"] == 0:
+        n["fa"] = 1
+    groups, at = {}, 0
+    for key in ("fa", "fb", "k", "bt", "ta", "tb"):
+        groups[key] = letters[at:at + n[key]]
+        at += n[key]
+    perm = lambda xs: "".join(rng.permutation(xs)) if xs else ""
+    sa = perm(groups["fa"] + groups["k"] + groups["bt"] + groups["ta"])
+    sb = perm(groups["fb"] + groups["k"] + groups["bt"] + groups["tb"])
+    sc = perm(groups["fa"] + groups["fb"] + groups["bt"])
+    spec = f"{sc}={sa},{sb}"
+    ext = {ch: int(np.exp(rng.uniform(0, np.log(48)))) for ch in set(sa + sb + sc)}
+
+    def size(s):
+        return int(np.prod([ext[ch] for ch in s])) if s else 1
+    # operands up to 2^18 elements, contraction length up to 2^13
+    K = "".join(groups["k"] + groups["ta"] + groups["tb"])
+    while max(size(sa), size(sb), size(sc)) > (1 << 18) or size(K) > (1 << 13):
+        big = max(ext, key=ext.get)
+        ext[big] = max(1, ext[big] // 2)
+    dtype = "f64" if rng.random() < 0.6 else "f32"
+    alpha = float(rng.choice([1.0, -0.5, 2.0]))
+    beta = float(rng.choice([0.0, 0.0, 1.0, -1.5]))
+    return rng, spec, ext, dtype, alpha, beta
+
+
+def _layout(shape, rng):
+    """Strides of a permuted, possibly padded storage order (one-to-one)."""
+    nd = len(shape)
+    order = list(rng.permutation(nd)) if rng.random() < 0.5 else list(range(nd))
+    strides, run = [0] * nd, 1
+    for ax in order:
+        strides[ax] = run
+        run *= shape[ax] + (1 if rng.random() < 0.3 else 0)
+    span = 1 + sum((e - 1) * s for e, s in zip(shape, strides)) if nd else 1
+    return strides, span
+
+
+@pytest.mark.parametrize("seed", range(160))
+def test_random_contraction(seed):
+    import torch
+    from paper_1409_8608_amd import workloads as wl
+    rng, spec, ext, dtype, alpha, beta = _draw_case(seed)
+    print(f"case seed={seed} spec={spec} ext={ext} dtype={dtype} alpha={alpha} beta={beta}", flush=True)
+    A, B, C0 = wl.tensors(spec, ext, rng, "normal", with_c=True)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    views, strides = [], {}
+    for name, x in (("A", A), ("B", B), ("C", C0)):
+        st, span = _layout(list(x.shape), rng)
+        buf = torch.full((span + 8,), float("nan"), dtype=tdt, device="cuda")
+        v = torch.as_strided(buf, tuple(x.shape), tuple(st))
+        v.copy_(torch.from_numpy(np.array(x, order="C")))   # keeps 0-d operands 0-d
+        views.append(v)
+        strides[name] = st
+    p = tc.Plan(spec, ext, dtype, strides=strides)
+    p.contract(views[0], views[1], views[2], alpha, beta)
+    torch.cuda.synchronize()
+    got = views[2].double().cpu().numpy()
+    check(spec, ext, A, B, got, dtype, C0=C0, alpha=alpha, beta=beta)
