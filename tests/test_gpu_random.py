@@ -76,3 +76,52 @@ def test_random_contraction(seed):
     torch.cuda.synchronize()
     got = views[2].double().cpu().numpy()
     check(spec, ext, A, B, got, dtype, C0=C0, alpha=alpha, beta=beta)
+
+
+def _draw_family_case(seed):
+    """Paper index classes only (free and contracted), at most 4 indices per
+    operand, small extents so that every member runs quickly."""
+    rng = np.random.default_rng(5000 + seed)
+    letters = list("abcdijkl")
+    rng.shuffle(letters)
+    nfa, nfb, nk = int(rng.integers(0, 3)), int(rng.integers(0, 3)), int(rng.integers(1, 3))
+    if nfa + nfb == 0:
+        nfa = 1
+    fa, fb, k = letters[:nfa], letters[nfa:nfa + nfb], letters[nfa + nfb:nfa + nfb + nk]
+    perm = lambda xs: "".join(rng.permutation(xs)) if xs else ""
+    sa, sb, sc = perm(fa + k), perm(fb + k), perm(fa + fb)
+    ext = {ch: int(rng.integers(1, 20)) for ch in set(sa + sb + sc)}
+    dtype = "f64" if rng.random() < 0.6 else "f32"
+    return rng, f"{sc}={sa},{sb}", ext, dtype
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_family_members(seed):
+    import torch
+    from paper_1409_8608_amd import workloads as wl
+    rng, spec, ext, dtype = _draw_family_case(seed)
+    A, B, C0 = wl.tensors(spec, ext, rng, "normal", with_c=True)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    views, strides = [], {}
+    for name, x in (("A", A), ("B", B), ("C", C0)):
+        st, span = _layout(list(x.shape), rng)
+        buf = torch.full((span + 8,), float("nan"), dtype=tdt, device="cuda")
+        v = torch.as_strided(buf, tuple(x.shape), tuple(st))
+        v.copy_(torch.from_numpy(np.array(x, order="C")))
+        views.append(v)
+        strides[name] = st
+    p = tc.Plan(spec, ext, dtype, strides=strides)
+    infos = p.variants()
+    picks = rng.choice(len(infos), min(8, len(infos)), replace=False)
+    for v in sorted(int(x) for x in picks):
+        print(f"case seed={seed} spec={spec} ext={ext} dtype={dtype} member={infos[v]['name']}", flush=True)
+        p.set_variant(v)
+        views[2].copy_(torch.from_numpy(np.array(C0, order="C")))
+        if any(t == "C" for t, _ in infos[v]["copies"]):
+            with pytest.raises(tc.TcError) as e:
+                p.contract(views[0], views[1], views[2], 1.5, -1.0)
+            assert e.value.name == "TC_E_UNSUPPORTED"
+            continue
+        p.contract(views[0], views[1], views[2], 1.5, -1.0)
+        torch.cuda.synchronize()
+        check(spec, ext, A, B, views[2].double().cpu().numpy(), dtype, C0=C0, alpha=1.5, beta=-1.0)
