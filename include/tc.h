@@ -225,7 +225,9 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n);
 /* Choose each member's tile shape: an estimate composed from device
  * micro-benchmarks (one wave of tiles per shape and contracted-length bucket)
  * ranks the shapes, the best `top_k` are timed on the device one member at a
- * time and the fastest is kept.  Uses -- and overwrites C with
+ * time and the fastest is kept.  The whole batch is then timed with the new
+ * shapes against the previous ones (graph replays), and the previous shapes
+ * stay if they are faster.  Uses -- and overwrites C with
  * alpha * contract(A, B) of -- the operands of the previous tc_batch_contract,
  * which must have been made.  Synchronous.  The share of members whose
  * estimated-best shape measured within 5% of the best is reported by

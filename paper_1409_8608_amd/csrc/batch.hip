@@ -313,6 +313,35 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
     hipStream_t st = b->cap;
     hipEvent_t t0, t1;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return fail(TC_E_HIP, "events");
+    // Whole-batch time of the current configuration: graph replays with the
+    // previous call's operands and beta = 0 (C := alpha * contract(A, B)).
+    auto time_graph = [&](double* out) -> tc_status {
+        for (int c = 0; c < n; ++c) b->h_ptrs[c].beta = 0.0;
+        if (!b->exec) {
+            tc_status cs = capture(b);
+            if (cs) return cs;
+        }
+        hipError_t err = hipGraphLaunch(b->exec, st);   // warm-up
+        if (err == hipSuccess) err = hipEventRecord(t0, st);
+        for (int r = 0; r < 3 && err == hipSuccess; ++r) err = hipGraphLaunch(b->exec, st);
+        if (err == hipSuccess) err = hipEventRecord(t1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(t1);
+        float ms = 0;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, t0, t1);
+        if (err != hipSuccess) return hip_fail(err, "batch timing replays");
+        *out = ms / 3.0;
+        return TC_OK;
+    };
+    double before_ms = 0.0;
+    {
+        tc_status ts = time_graph(&before_ms);
+        if (ts) {
+            (void)hipEventDestroy(t0);
+            (void)hipEventDestroy(t1);
+            return ts;
+        }
+    }
+    const std::vector<int> old_shape = b->shape;
     auto time_one = [&](int c, int sh, double* out) -> hipError_t {
         MfmaArgs a = b->items[c];
         a.A = b->h_ptrs[c].A;
@@ -391,13 +420,28 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
         if (meas[seed_pick] <= 1.05 * truly_best) ++hits;
         b->shape[c] = best;
     }
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    if (e != hipSuccess) return hip_fail(e, "tuning launches");
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+        return hip_fail(e, "tuning launches");
+    }
     b->hit_rate = n ? (double)hits / n : 1.0;
     b->n_tuned = n;
+    // Members timed alone favour small tiles (more parallelism on an idle
+    // device); inside the batch that need not hold, so the whole batch is
+    // timed with the new shapes and the previous ones are kept if faster.
     drop_graph(b);
-    return build_groups(b);
+    tc_status ts = build_groups(b);
+    double after_ms = 0.0;
+    if (!ts) ts = time_graph(&after_ms);
+    if (!ts && after_ms > before_ms) {
+        b->shape = old_shape;
+        drop_graph(b);
+        ts = build_groups(b);
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return ts;
 }
 
 tc_status tc_batch_info(tc_batch_t b, int* n_members, int64_t* n_tiles, int* n_groups, double* tune_hit_rate) {

@@ -128,7 +128,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
 // One BM x BN output tile (all passes) of the contraction described by `a`,
 // with the operand pointers and scalars given separately (a batch keeps them
 // apart from the static descriptors).  Called by a whole block.
-template <typename T, int BM, int BN, int BK, int AMODE, int BMODE>
+template <typename T, int BM, int BN, int BK, int AMODE, int BMODE, bool SPLIT = false, bool DEEP = true>
 __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, const void* Bp, void* Cp,
                                           double alpha_d, double beta_d, int64_t tile, int64_t slice) {
     typedef typename Mfma<T>::acc_t acc_t;
@@ -143,6 +143,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     constexpr int WM = BM >= 64 ? 2 : 1, WN = 4 / WM;
     constexpr int FM = BM / WM / 16, FN = BN / WN / 16;    // 16x16 blocks per wave
     static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
+    static_assert(BM % (256 / BK) == 0 && BN % (256 / BK) == 0, "M/N-major staging needs rows in 16s");
     static_assert(BK == 16, "the LDS layout holds 16 positions per row");
     __shared__ __attribute__((aligned(16))) T As[2][BM * BK];
     __shared__ __attribute__((aligned(16))) T Bs[2][BN * BK];
@@ -190,12 +191,17 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
 
     const T alpha = (T)alpha_d, beta = (T)beta_d;
     // this block's K tiles: all of them, or one slice when K is split
-    int64_t ktiles = a.Kpad / BK, k_first = 0;
-    if (a.kslices > 1) {
-        k_first = slice * a.kslice_tiles;
-        ktiles = std::max<int64_t>(0, std::min<int64_t>(a.kslice_tiles, ktiles - k_first));
+    int64_t kt_count = a.Kpad / BK, k_first = 0;
+    if constexpr (SPLIT) {
+        if (a.kslices > 1) {
+            k_first = slice * a.kslice_tiles;
+            kt_count = std::max<int64_t>(0, std::min<int64_t>(a.kslice_tiles, kt_count - k_first));
+        }
+    } else {
+        (void)slice;
     }
-    const int64_t* __restrict__ ktab0 = a.ktab + 2 * k_first * BK;
+    const int64_t ktiles = kt_count;
+    const int64_t* ktab0 = SPLIT ? a.ktab + 2 * k_first * BK : a.ktab;
 
     int64_t pctr[GT_MAXD];
     for (int d = 0; d < a.pass.n; ++d) pctr[d] = 0;
@@ -212,7 +218,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         // loaded while tile kt is multiplied, so a load has NS - 1 tiles of
         // MFMA time to arrive.  FP32 keeps two tiles in flight (its MFMAs take
         // half as long per tile as FP64's), FP64 one.
-        constexpr int NS = sizeof(T) == 4 ? 3 : 2;
+        constexpr int NS = (sizeof(T) == 4 && DEEP) ? 3 : 2;
         T ra[NS - 1][EA], rb[NS - 1][EB];
         vT va[NS - 1][CA], vb[NS - 1][CB];
         uint32_t okA[NS - 1], okB[NS - 1];
@@ -221,17 +227,21 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         // operand loads: waiting for a table then never waits for operand
         // loads still in flight.  In K-major loading a thread always handles
         // the same k of a tile (one entry); in M/N-major loading EA/EB.
-        constexpr int TA = A_KMAJ ? 1 : EA, TB = B_KMAJ ? 1 : EB;
+        // Every thread handles one K position per tile: tid % BK along K
+        // (K-major) or tid / RT with RT = 256 / BK threads on consecutive
+        // rows (M/N-major, rows tid % RT + RT * e), so one table entry each.
+        constexpr int RT = 256 / BK;
+        constexpr int TA = 1, TB = 1;
         int64_t tA[2][TA], tB[2][TB];
         auto tload = [&](int64_t kt, auto ts_c) {
             constexpr int ts = decltype(ts_c)::value;
             const int64_t* kt0 = ktab0 + 2 * kt * BK;
 #pragma unroll
             for (int e = 0; e < TA; ++e)
-                tA[ts][e] = kt0[2 * (AV ? VEC * (tid % CPR) : A_KMAJ ? tid % BK : (tid + 256 * e) / BM)];
+                tA[ts][e] = kt0[2 * (AV ? VEC * (tid % CPR) : A_KMAJ ? tid % BK : tid / RT)];
 #pragma unroll
             for (int e = 0; e < TB; ++e)
-                tB[ts][e] = kt0[2 * (BV ? VEC * (tid % CPR) : B_KMAJ ? tid % BK : (tid + 256 * e) / BN) + 1];
+                tB[ts][e] = kt0[2 * (BV ? VEC * (tid % CPR) : B_KMAJ ? tid % BK : tid / RT) + 1];
         };
         // Operand loads with clamped addresses (element (batch, pass, 0, 0) is
         // always valid), so no branch sits around a load.  The raw values stay
@@ -253,8 +263,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
 #pragma unroll
                 for (int e = 0; e < EA; ++e) {
                     const int idx = tid + 256 * e;
-                    const int64_t om = sAm[A_KMAJ ? idx / BK : idx % BM];
-                    const int64_t ko = tA[ts][A_KMAJ ? 0 : e];
+                    const int64_t om = sAm[A_KMAJ ? idx / BK : tid % RT + RT * e];
+                    const int64_t ko = tA[ts][0];
                     const bool ok = (om >= 0) & (ko >= 0) & live;
                     ra[sl][e] = Ag[bA + pA + (ok ? om + ko : 0)];
                     ma |= (uint32_t)ok << e;
@@ -272,8 +282,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
 #pragma unroll
                 for (int e = 0; e < EB; ++e) {
                     const int idx = tid + 256 * e;
-                    const int64_t on = sBn[B_KMAJ ? idx / BK : idx % BN];
-                    const int64_t ko = tB[ts][B_KMAJ ? 0 : e];
+                    const int64_t on = sBn[B_KMAJ ? idx / BK : tid % RT + RT * e];
+                    const int64_t ko = tB[ts][0];
                     const bool ok = (on >= 0) & (ko >= 0) & live;
                     rb[sl][e] = Bg[bB + pB + (ok ? on + ko : 0)];
                     mb |= (uint32_t)ok << e;
@@ -294,7 +304,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
 #pragma unroll
                 for (int e = 0; e < EA; ++e) {
                     const int idx = tid + 256 * e;
-                    As[buf][tile_at<T>(A_KMAJ ? idx / BK : idx % BM, A_KMAJ ? idx % BK : idx / BM)] =
+                    As[buf][tile_at<T>(A_KMAJ ? idx / BK : tid % RT + RT * e, A_KMAJ ? idx % BK : tid / RT)] =
                         (okA[sl] >> e) & 1 ? ra[sl][e] : (T)0;
                 }
             }
@@ -308,7 +318,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
 #pragma unroll
                 for (int e = 0; e < EB; ++e) {
                     const int idx = tid + 256 * e;
-                    Bs[buf][tile_at<T>(B_KMAJ ? idx / BK : idx % BN, B_KMAJ ? idx % BK : idx / BN)] =
+                    Bs[buf][tile_at<T>(B_KMAJ ? idx / BK : tid % RT + RT * e, B_KMAJ ? idx % BK : tid / RT)] =
                         (okB[sl] >> e) & 1 ? rb[sl][e] : (T)0;
                 }
             }
@@ -372,6 +382,9 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             auto step = [&](int64_t kt, auto p_c) {
                 constexpr int p = decltype(p_c)::value;
                 tload(std::min<int64_t>(kt + NS, last), std::integral_constant<int, (p + NS) % 2>{});
+                // FP64: the table loads must stay ahead of the operand loads
+                // (the next step's table wait would otherwise wait for them)
+                if constexpr (NS == 2) __builtin_amdgcn_sched_barrier(0);
                 gload(std::integral_constant<int, NS == 3 ? p : 0>{}, std::integral_constant<int, (p + NS - 1) % 2>{},
                       kt + NS - 1 < ktiles);
                 // FP64: keep the loads ahead of the MFMAs (under its register
@@ -380,6 +393,9 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 // MFMAs by itself, which measures faster
                 if constexpr (NS == 2) __builtin_amdgcn_sched_barrier(0);
                 compute(p);
+                // FP64: the store of the next tile (and its wait for the
+                // loads) stays after the MFMAs
+                if constexpr (NS == 2) __builtin_amdgcn_sched_barrier(0);
                 if (kt + 1 < ktiles) sstore(p ^ 1, std::integral_constant<int, NS == 3 ? 1 - p : 0>{});
                 lds_barrier();
             };
@@ -393,7 +409,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         }
 
         // epilogue: lane holds D[n = row(lane, q)][m = lane % 16] of each block
-        if (a.kslices > 1) {
+        if constexpr (SPLIT) if (a.kslices > 1) {
             // split K: raw partial tile to the workspace (rows and columns past
             // the edge hold zeros and are never read)
             T* wsp = (T*)a.ws + (slice * a.ntiles + tile) * (int64_t)(BM * BN);
@@ -438,11 +454,13 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     }
 }
 
-template <typename T, int BM, int BN, int BK, int AMODE, int BMODE>
+// SPLIT: the launch may split K (the split path costs registers, so launches
+// that never split use the kernel without it).
+template <typename T, int BM, int BN, int BK, int AMODE, int BMODE, bool SPLIT>
 __global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
-    const int64_t S = a.kslices > 1 ? a.kslices : 1;
+    const int64_t S = SPLIT && a.kslices > 1 ? a.kslices : 1;
     const int64_t t = xcd_tile(blockIdx.x, a.ntiles * S);
-    mfma_tile<T, BM, BN, BK, AMODE, BMODE>(a, a.A, a.B, a.C, a.alpha, a.beta, t % a.ntiles, t / a.ntiles);
+    mfma_tile<T, BM, BN, BK, AMODE, BMODE, SPLIT>(a, a.A, a.B, a.C, a.alpha, a.beta, t % a.ntiles, t / a.ntiles);
 }
 
 // Split-K reduction: output (m, n) is the sum of its slices' partials, in
@@ -488,7 +506,10 @@ __global__ __launch_bounds__(256) void k_mfma_batch(const MfmaArgs* __restrict__
         for (int w = w0; w < w1; ++w) {
             const int2 wi = work[w];
             const BatchPtrs& pt = ptrs[wi.x];
-            mfma_tile<T, BM, BN, BK, AMODE, BMODE>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha, pt.beta, wi.y, 0);
+            // batch tiles have short K: one step of loads in flight (the
+            // two-deep prefetch costs registers these kernels do not have)
+            mfma_tile<T, BM, BN, BK, AMODE, BMODE, false, false>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha, pt.beta,
+                                                                  wi.y, 0);
             lds_barrier();   // the tile's LDS tables and s_w are reused by the next item
         }
     }
@@ -556,32 +577,35 @@ constexpr int fit_mode(int m) {
     return (m == LD_KVEC && (ROWS * kBK / 256) % (16 / (int)sizeof(T)) != 0) ? LD_KSCAL : m;
 }
 
-template <typename T, int BM, int BN>
+template <typename T, int BM, int BN, bool SPLIT = false>
 static hipError_t tile_dispatch(const MfmaArgs& a, int am, int bm, hipStream_t st) {
-    const int64_t S = a.kslices > 1 ? a.kslices : 1;
+    const int64_t S = SPLIT && a.kslices > 1 ? a.kslices : 1;
     if (a.ntiles <= 0) return hipSuccess;
     if (a.ntiles * S > 0x7fffffff) return hipErrorInvalidConfiguration;
     dim3 g((unsigned)(a.ntiles * S)), b(256);
     constexpr int A0 = fit_mode<T, BM>(0), A1 = fit_mode<T, BM>(1), A2 = fit_mode<T, BM>(2);
     constexpr int B0 = fit_mode<T, BN>(0), B1 = fit_mode<T, BN>(1), B2 = fit_mode<T, BN>(2);
     switch (am * 3 + bm) {
-        case 0: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B0>), g, b, 0, st, a); break;
-        case 1: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B1>), g, b, 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B2>), g, b, 0, st, a); break;
-        case 3: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B0>), g, b, 0, st, a); break;
-        case 4: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B1>), g, b, 0, st, a); break;
-        case 5: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B2>), g, b, 0, st, a); break;
-        case 6: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B0>), g, b, 0, st, a); break;
-        case 7: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B1>), g, b, 0, st, a); break;
-        default: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B2>), g, b, 0, st, a); break;
+        case 0: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B0, SPLIT>), g, b, 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B1, SPLIT>), g, b, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B2, SPLIT>), g, b, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B0, SPLIT>), g, b, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B1, SPLIT>), g, b, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B2, SPLIT>), g, b, 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B0, SPLIT>), g, b, 0, st, a); break;
+        case 7: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B1, SPLIT>), g, b, 0, st, a); break;
+        default: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B2, SPLIT>), g, b, 0, st, a); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st) {
     int am = load_mode(a, f64, 0), bm = load_mode(a, f64, 1);
-    hipError_t e = f64 ? tile_dispatch<double, kBM, kBN>(a, am, bm, st) : tile_dispatch<float, kBM, kBN>(a, am, bm, st);
-    if (e != hipSuccess || a.kslices <= 1 || a.ntiles <= 0) return e;
+    if (a.kslices <= 1)
+        return f64 ? tile_dispatch<double, kBM, kBN>(a, am, bm, st) : tile_dispatch<float, kBM, kBN>(a, am, bm, st);
+    hipError_t e = f64 ? tile_dispatch<double, kBM, kBN, true>(a, am, bm, st)
+                       : tile_dispatch<float, kBM, kBN, true>(a, am, bm, st);
+    if (e != hipSuccess || a.ntiles <= 0) return e;
     if (a.nbatch != 1 || a.npass != 1 || a.mode != 0 || !a.ws) return hipErrorInvalidValue;
     const int64_t total = a.M * a.N;
     dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536))), b(256);
