@@ -138,7 +138,12 @@ typedef struct {
  *   as in Section 1; also batch (A, B and C) and trace (one input only),
  *   computed as the same sum over every index absent from C.  Specs with
  *   batch or trace indices have no family members (fused kernel only) and
- *   no split-precision forms (TC_E_UNSUPPORTED).
+ *   no split-precision forms (TC_E_UNSUPPORTED).  Specs with more than 7
+ *   distinct letters have no family members either (n letters give up to
+ *   (n - 1)! loop orders per kernel).
+ *   Each of M (free indices of one input), N, K, the batch indices and C may
+ *   hold at most 8 dimension groups once indices that continue each other in
+ *   memory are merged; more is TC_E_UNSUPPORTED.
  *   index_chars/extents: n_index letters and their extents (every letter of
  *                        the spec must be given; extra letters are an error).
  *   strides_X: element strides in X's spec order, or NULL for Fortran order.

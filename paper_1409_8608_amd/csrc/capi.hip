@@ -306,15 +306,7 @@ tc_status run_variant(tc_plan_s* p, int v, const void* A, const void* B, void* C
     hipError_t e;
     // C := beta*C, then every invocation adds alpha*(kernel result)
     if (beta != 1.0) {
-        ScaleArgs sa{};
-        sa.C = C;
-        sa.beta = beta;
-        sa.dims.n = 0;
-        sa.total = 1;
-        for (char ch : s.c) {
-            sa.dims.d[sa.dims.n++] = GtDim{s.e(ch), 0, 0, s.stride(2, ch)};
-            sa.total *= s.e(ch);
-        }
+        ScaleArgs sa = scale_args(s, C, beta);
         e = launch_scale(f64, sa, st);
         if (e != hipSuccess) return hip_fail(e, "scale kernel launch");
     }
@@ -408,15 +400,8 @@ tc_status contract_dispatch(tc_plan_s* p, const void* A, const void* B, void* C,
     for (char ch : s.summed()) K *= s.e(ch);
     if (s.nC == 0) return TC_OK;
     if (alpha == 0.0 || K == 0) {
-        ScaleArgs sa{};
-        sa.C = C;
-        sa.beta = beta;
-        sa.total = 1;
-        for (char ch : s.c) {
-            sa.dims.d[sa.dims.n++] = GtDim{s.e(ch), 0, 0, s.stride(2, ch)};
-            sa.total *= s.e(ch);
-        }
         if (beta == 1.0) return TC_OK;
+        ScaleArgs sa = scale_args(s, C, beta);
         hipError_t e = launch_scale(f64, sa, st);
         return e == hipSuccess ? TC_OK : hip_fail(e, "scale kernel launch");
     }
@@ -454,9 +439,12 @@ tc_status tc_plan(tc_plan_t* out, const char* spec, const char* index_chars, con
         return fail(TC_E_UNSUPPORTED, "split precision needs contracted and free indices only");
     }
     p->gv = gemm_view(p->spec);
-    if ((int)p->gv.b.size() > GT_MAXD || (int)p->gv.k.size() > GT_MAXD) {
+    const GemmView& gv = p->gv;
+    if ((int)gv.m.size() > GT_MAXD || (int)gv.n.size() > GT_MAXD || (int)gv.b.size() > GT_MAXD ||
+        (int)gv.k.size() > GT_MAXD || (int)c_dims(p->spec).size() > GT_MAXD) {
         delete p;
-        return fail(TC_E_UNSUPPORTED, "too many batch or contracted dimension groups");
+        return fail(TC_E_UNSUPPORTED, "more than 8 dimension groups (after merging contiguous ones) "
+                                      "in M, N, K, the batch indices or C");
     }
     *out = p;
     return TC_OK;

@@ -265,14 +265,7 @@ static tc_status predict_variant(PredCtx& c, int v, tc_prediction* out) {
         if (it != c.cache.end()) {
             t = it->second;
         } else {
-            ScaleArgs sa{};
-            sa.C = c.C;
-            sa.beta = 0.0;
-            sa.total = 1;
-            for (char ch : s.c) {
-                sa.dims.d[sa.dims.n++] = GtDim{s.e(ch), 0, 0, s.stride(2, ch)};
-                sa.total *= s.e(ch);
-            }
+            ScaleArgs sa = scale_args(s, c.C, 0.0);
             stt = time_median(c, {}, opA, opB, [&]() { return launch_scale(f64, sa, c.st); }, &t);
             if (stt) return stt;
             c.cache[key] = t;

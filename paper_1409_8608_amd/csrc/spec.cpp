@@ -157,6 +157,14 @@ static void merge_group(std::vector<GtDim>& g) {
     g = out;
 }
 
+std::vector<GtDim> c_dims(const Spec& s) {
+    std::vector<GtDim> g;
+    for (char ch : s.c) g.push_back(GtDim{s.e(ch), 0, 0, s.sC[ch - 'a']});
+    merge_group(g);
+    if (g.empty()) g.push_back(GtDim{1, 0, 0, 0});
+    return g;
+}
+
 GemmView gemm_view(const Spec& s) {
     GemmView v;
     // Put C's unit-stride index in M; if it belongs to B, swap the roles of A

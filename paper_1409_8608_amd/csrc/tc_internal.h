@@ -106,6 +106,20 @@ struct GemmView {
     int64_t M = 1, N = 1, K = 1;
 };
 GemmView gemm_view(const Spec& s);
+// C's dimensions (sC), extent-1 ones dropped and contiguous ones merged.
+std::vector<GtDim> c_dims(const Spec& s);
+// Arguments of the C := beta * C kernel over all of C.
+inline ScaleArgs scale_args(const Spec& s, void* C, double beta) {
+    ScaleArgs sa{};
+    sa.C = C;
+    sa.beta = beta;
+    sa.total = 1;
+    for (const GtDim& d : c_dims(s)) {
+        sa.dims.d[sa.dims.n++] = d;
+        sa.total *= d.ext;
+    }
+    return sa;
+}
 
 // Launch sequence of one family member.
 struct CopyStep {

@@ -166,3 +166,35 @@ def test_injected_launch_failure(monkeypatch):
     monkeypatch.delenv("TC_FAULT")
     assert tc.tc_variant_count(h) == len(family.enumerate_family("ab=ai,ib"))
     tc.tc_plan_destroy(h)
+
+
+def test_dimension_group_limits():
+    # the launch descriptors hold 8 dimension groups each: nine free indices of
+    # A whose strides cannot merge are refused at plan time, while the same
+    # indices stored contiguously merge into one group and plan fine
+    letters = "abcdefghj"
+    spec = f"{letters}=i{letters},i"
+    ext = {ch: 2 for ch in letters + "i"}
+    ext["i"] = 3
+    tc.tc_plan_destroy(tc.tc_plan(spec, ext))
+    # strides growing by 3 per index of extent 2: no two indices continue each other
+    strides_A = [1] + [4 * 3 ** q for q in range(len(letters))]
+    strides_C = [2 * 3 ** q for q in range(len(letters))]
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_plan(spec, ext, strides_A=strides_A, strides_C=strides_C)
+    assert e.value.name == "TC_E_UNSUPPORTED"
+
+
+def test_family_letter_limit():
+    # seven letters keep the family; eight leave the plan to the fused kernel
+    h = tc.tc_plan("abcdef=aci,ibdef", {ch: 2 for ch in "abcdefi"})
+    try:
+        assert tc.tc_variant_count(h) == len(family.enumerate_family("abcdef=aci,ibdef"))
+    finally:
+        tc.tc_plan_destroy(h)
+    h = tc.tc_plan("abcdefg=aci,ibdefg", {ch: 2 for ch in "abcdefgi"})
+    try:
+        assert tc.tc_variant_count(h) == 0
+        assert tc.tc_variant_get(h, tc.TC_VARIANT_FUSED)["kernel"] == "fused"
+    finally:
+        tc.tc_plan_destroy(h)
