@@ -7,7 +7,9 @@ imports nothing from the GPU library: the two share no code.
 Contents
   contract.c    plain FP64 loop nest (Section 1, Tensor Notation), own parser;
                 batch indices (in A, B and C) and trace indices (one input
-                only) read as the same sum over every index absent from C
+                only) read as the same sum over every index absent from C;
+                the same loops over complex numbers (real and imaginary
+                parts in FP64, products written out)
   family.py     the algorithm family of Section 2 (Table 1 rules x loop orders)
   interp.py     executes each family member as the paper's loops of BLAS calls
   access.py     the symbolic prediction steps of Section 3 (access distance,
@@ -51,6 +53,10 @@ def _load():
                                         dp, i64p, dp, i64p, dp, i64p,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int]
         lib.oracle_contract.restype = ctypes.c_int
+        lib.oracle_contract_z.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i64p, ctypes.c_int,
+                                          dp, i64p, dp, i64p, dp, i64p,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        lib.oracle_contract_z.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -74,15 +80,18 @@ def contract(spec: str, extents: dict, A: np.ndarray, B: np.ndarray, C: np.ndarr
     """C = alpha * contract(A, B) + beta * C in FP64 (Section 1 definition).
 
     ``A``, ``B`` (and ``C``) are float64 numpy arrays whose axes follow the
-    operand's spec letters; any non-negative strides are honoured, so a
+    operand's spec letters, or all complex128 for the same sum over complex
+    numbers (then alpha and beta may be complex); any non-negative strides are honoured, so a
     Fortran-ordered array is the paper's storage.  If ``C`` is None a new
     Fortran-ordered array is returned (beta must then be 0).  With ``dot2`` the
     sum is accumulated in doubled working precision.
     """
     sa, sb, sc = split_spec(spec)
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(B) or (C is not None and np.iscomplexobj(C))
+    want = np.complex128 if cplx else np.float64
     for name, x, s in (("A", A, sa), ("B", B, sb)):
-        if x.dtype != np.float64:
-            raise TypeError(f"oracle: {name} must be float64 (widen FP32 exactly first)")
+        if x.dtype != want:
+            raise TypeError(f"oracle: {name} must be {np.dtype(want).name} (widen narrower types exactly first)")
         if x.ndim != len(s):
             raise ValueError(f"oracle: {name} has {x.ndim} axes, spec wants {len(s)}")
         for ch, n in zip(s, x.shape):
@@ -91,17 +100,22 @@ def contract(spec: str, extents: dict, A: np.ndarray, B: np.ndarray, C: np.ndarr
     if C is None:
         if beta != 0.0:
             raise ValueError("oracle: beta != 0 needs an input C")
-        C = np.zeros([extents[ch] for ch in sc], dtype=np.float64, order="F")
-    elif C.dtype != np.float64:
-        raise TypeError("oracle: C must be float64")
+        C = np.zeros([extents[ch] for ch in sc], dtype=want, order="F")
+    elif C.dtype != want:
+        raise TypeError(f"oracle: C must be {np.dtype(want).name}")
     chars = "".join(sorted(extents))
     ext = (ctypes.c_int64 * len(chars))(*[int(extents[ch]) for ch in chars])
     dp = ctypes.POINTER(ctypes.c_double)
-    rc = _load().oracle_contract(spec.encode(), chars.encode(), ext, len(chars),
-                                 A.ctypes.data_as(dp), _elem_strides(A),
-                                 B.ctypes.data_as(dp), _elem_strides(B),
-                                 C.ctypes.data_as(dp), _elem_strides(C),
-                                 float(alpha), float(beta), 1 if dot2 else 0)
+    args = (spec.encode(), chars.encode(), ext, len(chars),
+            A.ctypes.data_as(dp), _elem_strides(A), B.ctypes.data_as(dp), _elem_strides(B),
+            C.ctypes.data_as(dp), _elem_strides(C))
+    if cplx:
+        if dot2:
+            raise ValueError("oracle: doubled-precision sums are for real operands")
+        al, be = complex(alpha), complex(beta)
+        rc = _load().oracle_contract_z(*args, al.real, al.imag, be.real, be.imag)
+    else:
+        rc = _load().oracle_contract(*args, float(alpha), float(beta), 1 if dot2 else 0)
     if rc != 0:
         raise ValueError(f"oracle_contract failed with code {rc} for spec {spec!r}")
     return C

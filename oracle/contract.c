@@ -31,6 +31,10 @@
  * Build with -O2 -ffp-contract=off and without fast-math so the products and sums
  * are rounded exactly as written.
  *
+ * oracle_contract_z is the same definition over complex numbers (storage as C99
+ * double complex: real part, then imaginary part), each product written out as
+ * (xr yr - xi yi) + i (xr yi + xi yr) and summed in the same order.
+ *
  * mode 1 ("Dot2") accumulates with an error-free TwoSum/TwoProduct pair
  * (Ogita, Rump, Oishi, "Accurate sum and dot product", SIAM J. Sci. Comput.
  * 26(6), 2005, Algorithm 5.3), giving a result as if computed in twice the
@@ -87,74 +91,109 @@ static int64_t extent_of(char ch, const char* idx_chars, const int64_t* extents,
     return -1;
 }
 
-/* Returns 0 on success.  Strides are in each operand's own spec order; a NULL
- * stride array means Fortran-contiguous for that operand. */
-int oracle_contract(const char* spec, const char* idx_chars, const int64_t* extents, int n_idx,
-                    const double* A, const int64_t* strides_A,
-                    const double* B, const int64_t* strides_B,
-                    double* C, const int64_t* strides_C,
-                    double alpha, double beta, int mode) {
+/* Everything the loops need: parsed spec, per-operand extents and strides,
+ * and the summed indices. */
+typedef struct {
     or_spec p;
-    int rc = or_parse(spec, &p);
-    if (rc) return rc;
-
-    int64_t extA[OR_MAXIDX], extB[OR_MAXIDX], extC[OR_MAXIDX];
+    int64_t extC[OR_MAXIDX];
     int64_t sA[OR_MAXIDX], sB[OR_MAXIDX], sC[OR_MAXIDX];
-    const char* names[3] = {p.a, p.b, p.c};
-    int64_t* exts[3] = {extA, extB, extC};
-    int64_t* strs[3] = {sA, sB, sC};
+    char kidx[2 * OR_MAXIDX + 1];
+    int nk;
+    int64_t kext[2 * OR_MAXIDX];
+    int64_t nC, nK;
+} or_plan;
+
+/* Strides are in each operand's own spec order; a NULL stride array means
+ * Fortran-contiguous for that operand. */
+static int or_setup(const char* spec, const char* idx_chars, const int64_t* extents, int n_idx,
+                    const int64_t* strides_A, const int64_t* strides_B, const int64_t* strides_C,
+                    or_plan* q) {
+    or_spec* p = &q->p;
+    int rc = or_parse(spec, p);
+    if (rc) return rc;
+    const char* names[3] = {p->a, p->b, p->c};
+    int64_t* strs[3] = {q->sA, q->sB, q->sC};
     const int64_t* given[3] = {strides_A, strides_B, strides_C};
-    int lens[3] = {p.na, p.nb, p.nc};
+    int lens[3] = {p->na, p->nb, p->nc};
     for (int t = 0; t < 3; ++t) {
         int64_t run = 1;
         for (int m = 0; m < lens[t]; ++m) {
             int64_t e = extent_of(names[t][m], idx_chars, extents, n_idx);
             if (e < 0) return OR_E_EXTENT;
-            exts[t][m] = e;
+            if (t == 2) q->extC[m] = e;
             strs[t][m] = given[t] ? given[t][m] : run;
             run *= e;
         }
     }
-
     /* summed indices (not in C): A's in A's order, then B's own */
-    char kidx[2 * OR_MAXIDX + 1];
-    int nk = 0;
-    for (int m = 0; m < p.na; ++m)
-        if (pos(p.c, p.a[m]) < 0) kidx[nk++] = p.a[m];
-    for (int m = 0; m < p.nb; ++m)
-        if (pos(p.c, p.b[m]) < 0 && pos(p.a, p.b[m]) < 0) kidx[nk++] = p.b[m];
-    kidx[nk] = 0;
-    int64_t kext[2 * OR_MAXIDX];
-    for (int q = 0; q < nk; ++q) kext[q] = extent_of(kidx[q], idx_chars, extents, n_idx);
+    q->nk = 0;
+    for (int m = 0; m < p->na; ++m)
+        if (pos(p->c, p->a[m]) < 0) q->kidx[q->nk++] = p->a[m];
+    for (int m = 0; m < p->nb; ++m)
+        if (pos(p->c, p->b[m]) < 0 && pos(p->a, p->b[m]) < 0) q->kidx[q->nk++] = p->b[m];
+    q->kidx[q->nk] = 0;
+    for (int k = 0; k < q->nk; ++k) q->kext[k] = extent_of(q->kidx[k], idx_chars, extents, n_idx);
+    q->nC = 1;
+    q->nK = 1;
+    for (int m = 0; m < p->nc; ++m) q->nC *= q->extC[m];
+    for (int k = 0; k < q->nk; ++k) q->nK *= q->kext[k];
+    return OR_OK;
+}
 
-    int64_t nC = 1, nK = 1;
-    for (int m = 0; m < p.nc; ++m) nC *= extC[m];
-    for (int q = 0; q < nk; ++q) nK *= kext[q];
-    if (nC == 0) return OR_OK;
+/* Offsets of C[ci] and of the free parts of A and B. */
+static void or_free_offsets(const or_plan* q, const int64_t* ci, int64_t* offC, int64_t* offA, int64_t* offB) {
+    const or_spec* p = &q->p;
+    *offC = *offA = *offB = 0;
+    for (int m = 0; m < p->nc; ++m) {
+        *offC += ci[m] * q->sC[m];
+        int pa = pos(p->a, p->c[m]), pb = pos(p->b, p->c[m]);
+        if (pa >= 0) *offA += ci[m] * q->sA[pa];
+        if (pb >= 0) *offB += ci[m] * q->sB[pb];
+    }
+}
+
+/* Add the summed part of the offsets at summed position ki. */
+static void or_sum_offsets(const or_plan* q, const int64_t* ki, int64_t* oa, int64_t* ob) {
+    const or_spec* p = &q->p;
+    for (int k = 0; k < q->nk; ++k) {
+        int pa = pos(p->a, q->kidx[k]), pb = pos(p->b, q->kidx[k]);
+        if (pa >= 0) *oa += ki[k] * q->sA[pa];   /* a trace index of B leaves A fixed */
+        if (pb >= 0) *ob += ki[k] * q->sB[pb];
+    }
+}
+
+/* Odometer step, first index fastest. */
+static void or_step(int64_t* idx, const int64_t* ext, int n) {
+    for (int m = 0; m < n; ++m) {
+        if (++idx[m] < ext[m]) return;
+        idx[m] = 0;
+    }
+}
+
+/* Returns 0 on success. */
+int oracle_contract(const char* spec, const char* idx_chars, const int64_t* extents, int n_idx,
+                    const double* A, const int64_t* strides_A,
+                    const double* B, const int64_t* strides_B,
+                    double* C, const int64_t* strides_C,
+                    double alpha, double beta, int mode) {
+    or_plan q;
+    int rc = or_setup(spec, idx_chars, extents, n_idx, strides_A, strides_B, strides_C, &q);
+    if (rc) return rc;
+    if (q.nC == 0) return OR_OK;
     if (!C) return OR_E_NULL;
-    if (alpha != 0.0 && nK > 0 && (!A || !B)) return OR_E_NULL;
+    if (alpha != 0.0 && q.nK > 0 && (!A || !B)) return OR_E_NULL;
 
     int64_t ci[OR_MAXIDX], ki[2 * OR_MAXIDX];
     memset(ci, 0, sizeof ci);
-    for (int64_t f = 0; f < nC; ++f) {
-        /* offset of C[f] and the free parts of A and B */
-        int64_t offC = 0, offA = 0, offB = 0;
-        for (int m = 0; m < p.nc; ++m) {
-            offC += ci[m] * sC[m];
-            int pa = pos(p.a, p.c[m]), pb = pos(p.b, p.c[m]);
-            if (pa >= 0) offA += ci[m] * sA[pa];
-            if (pb >= 0) offB += ci[m] * sB[pb];
-        }
+    for (int64_t f = 0; f < q.nC; ++f) {
+        int64_t offC, offA, offB;
+        or_free_offsets(&q, ci, &offC, &offA, &offB);
         double acc = 0.0, comp = 0.0;
         if (alpha != 0.0) {
             memset(ki, 0, sizeof ki);
-            for (int64_t k = 0; k < nK; ++k) {
+            for (int64_t k = 0; k < q.nK; ++k) {
                 int64_t oa = offA, ob = offB;
-                for (int q = 0; q < nk; ++q) {
-                    int pa = pos(p.a, kidx[q]), pb = pos(p.b, kidx[q]);
-                    if (pa >= 0) oa += ki[q] * sA[pa];   /* a trace index of B leaves A fixed */
-                    if (pb >= 0) ob += ki[q] * sB[pb];
-                }
+                or_sum_offsets(&q, ki, &oa, &ob);
                 double x = A[oa], y = B[ob];
                 if (mode == 1) {
                     /* TwoProduct via fma, TwoSum (Knuth) */
@@ -168,20 +207,63 @@ int oracle_contract(const char* spec, const char* idx_chars, const int64_t* exte
                 } else {
                     acc += x * y;
                 }
-                for (int q = 0; q < nk; ++q) {      /* odometer, first index fastest */
-                    if (++ki[q] < kext[q]) break;
-                    ki[q] = 0;
-                }
+                or_step(ki, q.kext, q.nk);
             }
             if (mode == 1) acc = acc + comp;
         }
         double out = alpha * acc;
         if (beta != 0.0) out += beta * C[offC];
         C[offC] = out;
-        for (int m = 0; m < p.nc; ++m) {
-            if (++ci[m] < extC[m]) break;
-            ci[m] = 0;
+        or_step(ci, q.extC, q.p.nc);
+    }
+    return OR_OK;
+}
+
+/* Complex operands: each element is two doubles (real, imaginary); strides
+ * count complex elements.  alpha and beta are (re, im) pairs.  beta == 0 does
+ * not read C; alpha == 0 does not read A or B. */
+int oracle_contract_z(const char* spec, const char* idx_chars, const int64_t* extents, int n_idx,
+                      const double* A, const int64_t* strides_A,
+                      const double* B, const int64_t* strides_B,
+                      double* C, const int64_t* strides_C,
+                      double alpha_re, double alpha_im, double beta_re, double beta_im) {
+    or_plan q;
+    int rc = or_setup(spec, idx_chars, extents, n_idx, strides_A, strides_B, strides_C, &q);
+    if (rc) return rc;
+    if (q.nC == 0) return OR_OK;
+    if (!C) return OR_E_NULL;
+    int use_ab = alpha_re != 0.0 || alpha_im != 0.0;
+    int use_c = beta_re != 0.0 || beta_im != 0.0;
+    if (use_ab && q.nK > 0 && (!A || !B)) return OR_E_NULL;
+
+    int64_t ci[OR_MAXIDX], ki[2 * OR_MAXIDX];
+    memset(ci, 0, sizeof ci);
+    for (int64_t f = 0; f < q.nC; ++f) {
+        int64_t offC, offA, offB;
+        or_free_offsets(&q, ci, &offC, &offA, &offB);
+        double acc_re = 0.0, acc_im = 0.0;
+        if (use_ab) {
+            memset(ki, 0, sizeof ki);
+            for (int64_t k = 0; k < q.nK; ++k) {
+                int64_t oa = offA, ob = offB;
+                or_sum_offsets(&q, ki, &oa, &ob);
+                double xr = A[2 * oa], xi = A[2 * oa + 1];
+                double yr = B[2 * ob], yi = B[2 * ob + 1];
+                acc_re += xr * yr - xi * yi;
+                acc_im += xr * yi + xi * yr;
+                or_step(ki, q.kext, q.nk);
+            }
         }
+        double out_re = alpha_re * acc_re - alpha_im * acc_im;
+        double out_im = alpha_re * acc_im + alpha_im * acc_re;
+        if (use_c) {
+            double cr = C[2 * offC], cim = C[2 * offC + 1];
+            out_re += beta_re * cr - beta_im * cim;
+            out_im += beta_re * cim + beta_im * cr;
+        }
+        C[2 * offC] = out_re;
+        C[2 * offC + 1] = out_im;
+        or_step(ci, q.extC, q.p.nc);
     }
     return OR_OK;
 }
