@@ -48,7 +48,17 @@ extern "C" {
 typedef struct tc_plan_s* tc_plan_t;     /* opaque, owned by the caller until tc_plan_destroy */
 typedef struct tc_batch_s* tc_batch_t;   /* opaque, owned by the caller until tc_batch_destroy */
 
-typedef enum { TC_F64 = 0, TC_F32 = 1 } tc_dtype;   /* storage type of A, B and C */
+/* Storage type of A, B and C.  TC_C128 / TC_C64 are complex: each element is
+ * its real part followed by its imaginary part (the layout of C99 double
+ * complex / float complex), and strides count complex elements.  A complex
+ * contraction runs as a real one in the matching real precision: one operand
+ * (the one with fewer elements) is written once per call into plan workspace as
+ * real 2x2 blocks [re -im; im re], scaled by alpha, which adds a summed index
+ * over the other operand's (re, im) pair and a free index over C's; that
+ * operand and C are read in place.  Complex plans have no family members, take
+ * TC_NATIVE only, cannot join a batch and need two letters the spec does not
+ * use (TC_E_UNSUPPORTED otherwise). */
+typedef enum { TC_F64 = 0, TC_F32 = 1, TC_C128 = 2, TC_C64 = 3 } tc_dtype;
 
 /* Arithmetic path.  TC_NATIVE computes in the storage type.  TC_BF16X3 splits
  * each power-of-two scaled slice into three BF16 terms and forms the six
@@ -183,6 +193,13 @@ tc_status tc_plan_workspace(tc_plan_t plan, int64_t* bytes);
  * Errors: TC_E_NULL, TC_E_ALIAS, TC_E_UNSUPPORTED, TC_E_HIP, TC_E_NOMEM. */
 tc_status tc_contract(tc_plan_t plan, const void* A, const void* B, void* C,
                       double alpha, double beta, void* stream);
+
+/* tc_contract with complex alpha and beta, (re, im) each; rounded to the plan's
+ * real precision as in tc_contract.  alpha == 0 (both parts): A and B are not
+ * read.  beta == 0: C is not read.  On a real plan both imaginary parts must be
+ * zero (TC_E_UNSUPPORTED otherwise).  Errors as tc_contract. */
+tc_status tc_contract_complex(tc_plan_t plan, const void* A, const void* B, void* C,
+                              double alpha_re, double alpha_im, double beta_re, double beta_im, void* stream);
 
 /* Copy the split terms of the last tc_contract of a TC_BF16X3 or TC_FP8X3
  * plan to host memory, for bit-exact checks of the quantisation.  side 0 = A,

@@ -133,7 +133,8 @@ def flops(spec: str, extents: dict) -> int:
 def normwise_rel_err(C_hat: np.ndarray, C_ref: np.ndarray, scale_ref: np.ndarray | None = None) -> float:
     """Frobenius-norm relative error ||C_hat - C_ref||_F / ||C_ref||_F.  When the
     reference is all zero, ``scale_ref`` (|A|.|B| contracted) is the denominator."""
-    d = np.linalg.norm((np.asarray(C_hat, dtype=np.float64) - C_ref).ravel())
+    C_hat = np.asarray(C_hat)
+    d = np.linalg.norm((C_hat.astype(np.result_type(C_hat, np.float64)) - C_ref).ravel())
     n = np.linalg.norm(np.asarray(C_ref).ravel())
     if n == 0.0:
         if scale_ref is None:

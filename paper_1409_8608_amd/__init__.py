@@ -16,7 +16,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtc.so")
 
-TC_F64, TC_F32 = 0, 1
+TC_F64, TC_F32, TC_C128, TC_C64 = 0, 1, 2, 3
+DTYPES = dict(f64=TC_F64, f32=TC_F32, c128=TC_C128, c64=TC_C64)
 TC_NATIVE, TC_BF16X3, TC_FP8X3 = 0, 1, 2
 TC_VARIANT_FUSED, TC_VARIANT_PREDICTED = -2, -1
 KERNELS = ("dot", "axpy", "gemv", "ger", "gemm", "fused")
@@ -24,7 +25,7 @@ STATUS = ("TC_OK", "TC_E_SPEC", "TC_E_EXTENT", "TC_E_STRIDE", "TC_E_DTYPE", "TC_
           "TC_E_VARIANT", "TC_E_HIP", "TC_E_NOMEM", "TC_E_UNSUPPORTED", "TC_E_CAPACITY")
 TC_MAX_SETUP = 16
 EXPORTS = ("tc_plan", "tc_plan_destroy", "tc_variant_count", "tc_variant_get", "tc_set_variant",
-           "tc_plan_prepare", "tc_plan_workspace", "tc_contract", "tc_access_distance", "tc_bench_classes",
+           "tc_plan_prepare", "tc_plan_workspace", "tc_contract", "tc_contract_complex", "tc_access_distance", "tc_bench_classes",
            "tc_predict", "tc_batch_create", "tc_batch_tune", "tc_batch_contract", "tc_batch_destroy",
            "tc_batch_info", "tc_split_terms", "tc_status_str", "tc_last_error")
 
@@ -80,6 +81,7 @@ def _load():
         "tc_plan_prepare": [P],
         "tc_plan_workspace": [P, I64P],
         "tc_contract": [P, P, P, P, D, D, P],
+        "tc_contract_complex": [P, P, P, P, D, D, D, D, P],
         "tc_access_distance": [P, ctypes.c_int, ctypes.c_int, I64P],
         "tc_bench_classes": [P, ctypes.c_int, ctypes.c_int, D, ctypes.c_int, ctypes.POINTER(tc_bench_class),
                              ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
@@ -166,6 +168,13 @@ def tc_plan_workspace(h) -> int:
 def tc_contract(h, A_ptr: int, B_ptr: int, C_ptr: int, alpha: float = 1.0, beta: float = 0.0, stream: int = 0):
     _check(lib.tc_contract(h, A_ptr or None, B_ptr or None, C_ptr or None, float(alpha), float(beta),
                            stream or None))
+
+
+def tc_contract_complex(h, A_ptr: int, B_ptr: int, C_ptr: int, alpha: complex = 1.0, beta: complex = 0.0,
+                        stream: int = 0):
+    al, be = complex(alpha), complex(beta)
+    _check(lib.tc_contract_complex(h, A_ptr or None, B_ptr or None, C_ptr or None, al.real, al.imag, be.real,
+                                   be.imag, stream or None))
 
 
 def tc_access_distance(h, variant: int, tensor: int) -> int:
@@ -306,7 +315,7 @@ class Plan:
         strides = strides or {}
         self.strides = {t: (list(strides[t]) if t in strides else self._fortran(t)) for t in "ABC"}
         self.handle = tc_plan(spec, self.extents, strides.get("A"), strides.get("B"), strides.get("C"),
-                              TC_F64 if dtype == "f64" else TC_F32,
+                              DTYPES[dtype],
                               dict(native=TC_NATIVE, bf16x3=TC_BF16X3, fp8x3=TC_FP8X3)[compute])
 
     def _fortran(self, t):
@@ -349,8 +358,11 @@ class Plan:
                                  f"{self.shape(t)}/{self.strides[t]}")
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
-        tc_contract(self.handle, A.data_ptr() if A is not None else 0, B.data_ptr() if B is not None else 0,
-                    C.data_ptr() if C is not None else 0, alpha, beta, stream)
+        ptrs = [x.data_ptr() if x is not None else 0 for x in (A, B, C)]
+        if isinstance(alpha, complex) or isinstance(beta, complex):
+            tc_contract_complex(self.handle, *ptrs, alpha, beta, stream)
+        else:
+            tc_contract(self.handle, *ptrs, alpha, beta, stream)
         return C
 
     def predict(self):

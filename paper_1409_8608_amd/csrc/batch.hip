@@ -192,6 +192,10 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
             delete b;
             return fail(TC_E_UNSUPPORTED, "batches run the native compute mode");
         }
+        if (p->spec.is_complex()) {
+            delete b;
+            return fail(TC_E_UNSUPPORTED, "batches take real plans");
+        }
         if (p->spec.nC == 0 || p->gv.K == 0) {
             delete b;
             return fail(TC_E_UNSUPPORTED, "batch members need a non-empty C and contracted extent");

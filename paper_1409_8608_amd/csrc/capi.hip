@@ -147,7 +147,8 @@ int ktab_vec_flags(const std::vector<int64_t>& tab, int v) {
 }  // namespace tc
 
 // ---------------------------------------------------------------------------
-static tc_status ensure_device_buffer(void** p, int64_t* cap, int64_t bytes) {
+namespace tc {
+tc_status ensure_device_buffer(void** p, int64_t* cap, int64_t bytes) {
     if (bytes <= *cap) return TC_OK;
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -160,6 +161,8 @@ static tc_status ensure_device_buffer(void** p, int64_t* cap, int64_t bytes) {
     *cap = std::max<int64_t>(bytes, 256);
     return TC_OK;
 }
+}  // namespace tc
+using tc::ensure_device_buffer;
 
 static tc_status upload(void** p, int64_t* cap, const std::vector<int64_t>& v) {
     int64_t bytes = (int64_t)(v.size() * sizeof(int64_t));
@@ -179,6 +182,7 @@ bool use_stream_kernel(const Spec& s, const GemmView& gv) {
 }
 
 tc_status prepare_plan(tc_plan_s* p) {
+    if (p->real) return prepare_complex(p);
     const Spec& s = p->spec;
     bool f64 = s.dtype == TC_F64;
     int BK = mfma_bk(f64);
@@ -394,6 +398,7 @@ tc_status run_variant(tc_plan_s* p, int v, const void* A, const void* B, void* C
 
 tc_status contract_dispatch(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
                             hipStream_t st) {
+    if (p->real) return run_complex(p, A, B, C, alpha, 0.0, beta, 0.0, st);
     const Spec& s = p->spec;
     bool f64 = s.dtype == TC_F64;
     int64_t K = 1;
@@ -421,9 +426,12 @@ tc_status tc_plan(tc_plan_t* out, const char* spec, const char* index_chars, con
                   const int64_t* strides_C, tc_dtype dtype, tc_compute compute) {
     if (!out) return fail(TC_E_NULL, "out is NULL");
     *out = nullptr;
-    if (dtype != TC_F64 && dtype != TC_F32) return fail(TC_E_DTYPE, "dtype must be TC_F64 or TC_F32");
+    if (dtype != TC_F64 && dtype != TC_F32 && dtype != TC_C128 && dtype != TC_C64)
+        return fail(TC_E_DTYPE, "dtype must be TC_F64, TC_F32, TC_C128 or TC_C64");
     if (compute != TC_NATIVE && compute != TC_BF16X3 && compute != TC_FP8X3)
         return fail(TC_E_DTYPE, "unknown compute mode");
+    if (compute != TC_NATIVE && (dtype == TC_C128 || dtype == TC_C64))
+        return fail(TC_E_UNSUPPORTED, "complex plans compute in their storage precision (TC_NATIVE)");
     tc_plan_s* p = new (std::nothrow) tc_plan_s();
     if (!p) return fail(TC_E_NOMEM, "host allocation");
     Err err;
@@ -437,6 +445,15 @@ tc_status tc_plan(tc_plan_t* out, const char* spec, const char* index_chars, con
     if (compute != TC_NATIVE && p->spec.general()) {
         delete p;
         return fail(TC_E_UNSUPPORTED, "split precision needs contracted and free indices only");
+    }
+    if (p->spec.is_complex()) {
+        tc_status st = build_complex(p);
+        if (st) {
+            tc_plan_destroy(p);
+            return st;
+        }
+        *out = p;
+        return TC_OK;
     }
     p->gv = gemm_view(p->spec);
     const GemmView& gv = p->gv;
@@ -452,6 +469,7 @@ tc_status tc_plan(tc_plan_t* out, const char* spec, const char* index_chars, con
 
 tc_status tc_plan_destroy(tc_plan_t p) {
     if (!p) return TC_OK;
+    if (p->real) tc_plan_destroy(p->real);
     release_plan_device(p);
     delete p;
     return TC_OK;
@@ -515,17 +533,25 @@ tc_status tc_plan_prepare(tc_plan_t p) {
 
 tc_status tc_plan_workspace(tc_plan_t p, int64_t* bytes) {
     if (!p || !bytes) return fail(TC_E_NULL, "NULL argument");
-    *bytes = p->ktab_cap + p->var_ktab_cap + p->temp_cap[0] + p->temp_cap[1] + p->split_bytes + p->splitk_cap;
+    *bytes = p->ktab_cap + p->var_ktab_cap + p->temp_cap[0] + p->temp_cap[1] + p->split_bytes + p->splitk_cap +
+             p->zexp_cap;
+    if (p->real) {
+        int64_t inner = 0;
+        tc_plan_workspace(p->real, &inner);
+        *bytes += inner;
+    }
     return TC_OK;
 }
 
-tc_status tc_contract(tc_plan_t p, const void* A, const void* B, void* C, double alpha, double beta,
-                      void* stream) {
+static tc_status contract_entry(tc_plan_t p, const void* A, const void* B, void* C, double alpha_re,
+                                double alpha_im, double beta_re, double beta_im, void* stream) {
     if (!p) return fail(TC_E_NULL, "plan is NULL");
     const Spec& s = p->spec;
+    if (!s.is_complex() && (alpha_im != 0.0 || beta_im != 0.0))
+        return fail(TC_E_UNSUPPORTED, "complex alpha or beta on a real plan");
     int64_t K = 1;
     for (char ch : s.summed()) K *= s.e(ch);
-    bool reads_inputs = alpha != 0.0 && K > 0 && s.nC > 0;
+    bool reads_inputs = (alpha_re != 0.0 || alpha_im != 0.0) && K > 0 && s.nC > 0;
     if (s.nC > 0 && !C) return fail(TC_E_NULL, "C is NULL");
     if (reads_inputs && ((s.nA > 0 && !A) || (s.nB > 0 && !B))) return fail(TC_E_NULL, "A or B is NULL");
     int es = s.elem_bytes();
@@ -542,7 +568,18 @@ tc_status tc_contract(tc_plan_t p, const void* A, const void* B, void* C, double
         return fail(TC_E_HIP, "injected launch failure (TC_FAULT=launch)");
     tc_status st = prepare_plan(p);
     if (st) return st;
-    return contract_dispatch(p, A, B, C, alpha, beta, (hipStream_t)stream);
+    if (p->real) return run_complex(p, A, B, C, alpha_re, alpha_im, beta_re, beta_im, (hipStream_t)stream);
+    return contract_dispatch(p, A, B, C, alpha_re, beta_re, (hipStream_t)stream);
+}
+
+tc_status tc_contract(tc_plan_t p, const void* A, const void* B, void* C, double alpha, double beta,
+                      void* stream) {
+    return contract_entry(p, A, B, C, alpha, 0.0, beta, 0.0, stream);
+}
+
+tc_status tc_contract_complex(tc_plan_t p, const void* A, const void* B, void* C, double alpha_re,
+                              double alpha_im, double beta_re, double beta_im, void* stream) {
+    return contract_entry(p, A, B, C, alpha_re, alpha_im, beta_re, beta_im, stream);
 }
 
 tc_status tc_access_distance(tc_plan_t p, int variant, int tensor, int64_t* out) {

@@ -47,6 +47,7 @@ static std::vector<std::string> kept_sets(const Spec& s, int kernel) {
 std::vector<Variant> enumerate_family(const Spec& s) {
     std::vector<Variant> fam;
     if (s.general()) return fam;   // Table 1 covers contracted and free indices only
+    if (s.is_complex()) return fam;  // complex plans run the fused kernel only
     // n letters give up to (n - 1)! loop orders per kernel; beyond 7 letters the
     // family is left to the fused kernel (a member's launch describes at most
     // GT_MAXD loops)

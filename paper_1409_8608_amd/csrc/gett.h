@@ -105,3 +105,24 @@ struct ScaleArgs {
     int64_t total;
     double beta;
 };
+
+// Complex operand -> real 2x2 blocks (times alpha).  For each complex element y
+// of the source, with t = alpha * y, the destination holds t_re at its offset,
+// -t_im one re/im step of the other operand further (s_in), t_im one re/im step
+// of C further (s_out) and t_re at both steps.
+struct ZExpandArgs {
+    const void* src;
+    void* dst;
+    GtDims dims;        // sA = source stride (complex elements), sC = destination stride (reals)
+    int64_t total;
+    int64_t s_in, s_out;
+    double alpha_re, alpha_im;
+};
+
+// C := beta * C for complex C (beta == 0 writes zeros without reading C).
+struct ZScaleArgs {
+    void* C;
+    GtDims dims;        // sC, complex elements
+    int64_t total;
+    double beta_re, beta_im;
+};

@@ -45,6 +45,16 @@ struct tc_plan_s {
     int var_ktab_for = -1;
     void* d_temp[2] = {nullptr, nullptr};   // copy temporaries of A and B
     int64_t temp_cap[2] = {0, 0};
+    // complex storage: the contraction runs as the real plan `real` over an
+    // embedded form in which operand `zside` is expanded into 2x2 real blocks
+    tc_plan_s* real = nullptr;
+    int zside = -1;
+    GtDims zdims{};                  // expanded operand: sA source stride (complex elements),
+                                     // sC destination stride (reals)
+    int64_t zelems = 0;              // its complex elements
+    int64_t zs_in = 0, zs_out = 0;   // destination strides of the two re/im indices
+    void* d_zexp = nullptr;          // the expanded operand
+    int64_t zexp_cap = 0;
     // split-precision buffers (one allocation)
     void* d_split = nullptr;
     int64_t split_bytes = 0;
@@ -59,6 +69,7 @@ private:
 namespace tc {
 extern thread_local std::string g_last_error;
 tc_status fail(tc_status s, const std::string& msg);
+tc_status ensure_device_buffer(void** p, int64_t* cap, int64_t bytes);
 tc_status hip_fail(hipError_t e, const char* what);
 
 std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA = 4, bool a_first = false, int G = 0);
@@ -75,4 +86,10 @@ tc_status prepare_split(tc_plan_s* p);
 tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
                     hipStream_t st);
 void release_plan_device(tc_plan_s* p);
+
+// complex storage (complex.hip)
+tc_status build_complex(tc_plan_s* p);
+tc_status prepare_complex(tc_plan_s* p);
+tc_status run_complex(tc_plan_s* p, const void* A, const void* B, void* C, double alpha_re, double alpha_im,
+                      double beta_re, double beta_im, hipStream_t st);
 }  // namespace tc

@@ -131,7 +131,7 @@ tc_status bind_spec(Spec& s, const char* index_chars, const int64_t* extents, in
 
 // ---------------------------------------------------------------------------
 // GEMM view.
-static void merge_group(std::vector<GtDim>& g) {
+void merge_group(std::vector<GtDim>& g) {
     // drop extent-1 dims (they add nothing), then merge d+1 into d when it
     // continues d in every tensor
     std::vector<GtDim> out;

@@ -48,7 +48,9 @@ struct Spec {
     // indices summed over: contracted, then trace indices of A and of B
     std::string summed() const { return contracted + trace_a + trace_b; }
     bool general() const { return !batch.empty() || !trace_a.empty() || !trace_b.empty(); }
-    int elem_bytes() const { return dtype == TC_F64 ? 8 : 4; }
+    // bytes per element (a complex element holds its real and imaginary part)
+    int elem_bytes() const { return dtype == TC_C128 ? 16 : dtype == TC_F64 || dtype == TC_C64 ? 8 : 4; }
+    bool is_complex() const { return dtype == TC_C128 || dtype == TC_C64; }
 };
 
 tc_status parse_spec(const char* text, Spec& s, Err& err);
@@ -106,6 +108,8 @@ struct GemmView {
     int64_t M = 1, N = 1, K = 1;
 };
 GemmView gemm_view(const Spec& s);
+// Drop extent-1 dims and merge dims that continue each other in A, B and C.
+void merge_group(std::vector<GtDim>& g);
 // C's dimensions (sC), extent-1 ones dropped and contiguous ones merged.
 std::vector<GtDim> c_dims(const Spec& s);
 // Arguments of the C := beta * C kernel over all of C.

@@ -198,3 +198,43 @@ def test_family_letter_limit():
         assert tc.tc_variant_get(h, tc.TC_VARIANT_FUSED)["kernel"] == "fused"
     finally:
         tc.tc_plan_destroy(h)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_complex_plans(dtype):
+    """Complex plans: fused kernel only, native compute only, no batches."""
+    p = tc.Plan("abc=ai,ibc", dict(a=4, b=3, c=2, i=5), dtype)
+    assert p.variants() == []
+    assert tc.tc_variant_get(p.handle, tc.TC_VARIANT_FUSED)["kernel"] == "fused"
+    assert tc.tc_plan_workspace(p.handle) == 0          # nothing allocated before prepare
+    with pytest.raises(tc.TcError) as e:
+        p.set_variant(0)
+    assert e.value.name == "TC_E_VARIANT"
+    for compute in ("bf16x3", "fp8x3"):
+        with pytest.raises(tc.TcError) as e:
+            tc.Plan("abc=ai,ibc", dict(a=4, b=3, c=2, i=5), dtype, compute=compute)
+        assert e.value.name == "TC_E_UNSUPPORTED"
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_batch_create([p.handle])
+    assert e.value.name == "TC_E_UNSUPPORTED"
+
+
+def test_complex_plan_needs_two_spare_letters():
+    # 25 letters: a and n free, the rest trace indices; one spare letter only
+    A, B = "abcdefghijklm", "nopqrstuvwxy"
+    ext = {ch: 1 for ch in A + B}
+    tc.tc_plan_destroy(tc.tc_plan(f"an={A},{B}", ext))                  # real: fine
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_plan(f"an={A},{B}", ext, dtype=tc.TC_C128)
+    assert e.value.name == "TC_E_UNSUPPORTED"
+
+
+def test_complex_scalars_on_real_plan_are_refused():
+    p = tc.Plan("ab=ai,ib", dict(a=2, b=2, i=2), "f64")
+    # refused before any device work: the pointers are never touched
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_contract_complex(p.handle, 16, 32, 4096, 1j, 0.0)
+    assert e.value.name == "TC_E_UNSUPPORTED"
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_contract_complex(p.handle, 16, 32, 4096, 1.0, 2 + 1j)
+    assert e.value.name == "TC_E_UNSUPPORTED"

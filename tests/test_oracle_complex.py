@@ -137,3 +137,10 @@ def test_strided_views_and_zero_extents():
     out = oracle.contract(spec, ext0, np.zeros((3, 0), np.complex128, order="F"),
                           np.zeros((0, 2, 2), np.complex128, order="F"))
     assert out.shape == (3, 2, 2) and np.all(out == 0)
+
+
+def test_error_metric_counts_imaginary_parts():
+    ref = np.array([3 + 4j, 0j])
+    assert oracle.normwise_rel_err(ref, ref) == 0.0
+    assert oracle.normwise_rel_err(np.array([3 + 3j, 0j]), ref) == pytest.approx(1 / 5)
+    assert oracle.normwise_rel_err(np.array([3 + 4j, 1j]), ref) == pytest.approx(1 / 5)
