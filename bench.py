@@ -137,7 +137,7 @@ def cpu_baseline(w, seconds):
                        "one host core, plain FP64 loop nest)")
 
 
-FORMS = ("permuted", "precision", "batched")
+FORMS = ("permuted", "precision", "batched", "complex")
 
 
 def forms(args, torch, tc, wl):
@@ -170,6 +170,9 @@ def forms(args, torch, tc, wl):
     for dt in (("f64", "f32") if "batched" in chosen else ()):
         out[f"batched_{dt}"] = batched(args, torch, tc, wl, dt)
         print(f"# batched {dt} done", file=sys.stderr, flush=True)
+    if "complex" in chosen:
+        out.update(complex_forms(args, torch, tc, wl))
+        print("# complex done", file=sys.stderr, flush=True)
     if "batched_f32" in out and "batched_f64" in out:
         out["batched_f32"]["factor_vs_sequential_fp64"] = round(
             out["batched_f64"]["sequential_ms"] / out["batched_f32"]["batched_tuned_ms"], 3)
@@ -237,6 +240,61 @@ def batched(args, torch, tc, wl, dtype):
     return rec
 
 
+
+
+def complex_forms(args, torch, tc, wl):
+    """Complex storage: the headline shape (streamed C, few summed positions)
+    and a square product (matrix cores through the real embedding), each with
+    sampled outputs against the oracle."""
+    import numpy as np
+    import oracle
+    res = {}
+    rng = np.random.default_rng(5)
+    for name, w in (("smallk", wl.complex_smallk(1024, 8)), ("square", wl.complex_square(4096))):
+        ext = w["ext"]
+        sa, sb, sc = oracle.split_spec(w["spec"])
+        picks = {ch: np.sort(rng.choice(ext[ch], min(ext[ch], 8), replace=False)) for ch in sc}
+        sub = dict(ext, **{ch: len(v) for ch, v in picks.items()})
+        Asub = w["A"][np.ix_(*[picks.get(ch, np.arange(ext[ch])) for ch in sa])]
+        Bsub = w["B"][np.ix_(*[picks.get(ch, np.arange(ext[ch])) for ch in sb])]
+        ref = oracle.contract(w["spec"], sub, np.asfortranarray(Asub), np.asfortranarray(Bsub))
+        for dt, tdt, cb, peak in (("c128", torch.complex128, 16, FP64_PEAK_TFS),
+                                  ("c64", torch.complex64, 8, FP32_PEAK_TFS)):
+            plan = tc.Plan(w["spec"], ext, dt)
+            plan.prepare()
+            dA = tc.to_device_fortran(w["A"], tdt)
+            dB = tc.to_device_fortran(w["B"], tdt)
+            dC = tc.empty_fortran(plan.shape("C"), tdt)
+            ms, _ = _events_time(lambda: plan.contract(dA, dB, dC, 1 + 0j, 0j), max(3, args.steps // 4),
+                                 max(2, args.warmup // 2), torch)
+            idx = [torch.as_tensor(picks[ch], device="cuda") for ch in sc]
+            got = dC
+            for ax, ix in enumerate(idx):
+                got = got.index_select(ax, ix)
+            got = got.cpu().numpy().astype(np.complex128)
+            refd = ref if dt == "c128" else oracle.contract(
+                w["spec"], sub, np.asfortranarray(Asub.astype(np.complex64).astype(np.complex128)),
+                np.asfortranarray(Bsub.astype(np.complex64).astype(np.complex128)))
+            err = oracle.normwise_rel_err(got, refd)
+            n_all = {t: int(np.prod([ext[ch] for ch in lets])) for t, lets in (("A", sa), ("B", sb), ("C", sc))}
+            flops = 8 * int(np.prod([ext[ch] for ch in set(sa + sb + sc)]))
+            rec = dict(workload=f"{w['spec']} " + ", ".join(f"{k}={v}" for k, v in ext.items()) +
+                       f", complex uniform[-1,1] parts, {dt}",
+                       ms=round(ms, 4), gflops_real=round(flops / (ms * 1e-3) / 1e9, 1),
+                       normwise_err_sampled=err)
+            if name == "smallk":
+                gbs = cb * sum(n_all.values()) / (ms * 1e-3) / 1e9
+                rec["roofline"] = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                                       frac=round(gbs / HBM_PEAK_GBS, 4),
+                                       counts="A, B read once and C written once, complex elements")
+            else:
+                tfs = flops / (ms * 1e-3) / 1e12
+                rec["roofline"] = dict(bound="mfma", achieved=round(tfs, 2), peak=peak, unit="TFLOP/s",
+                                       frac=round(tfs / peak, 4), counts="8 real flops per complex term")
+            res[f"complex_{name}_{dt}"] = rec
+            del dA, dB, dC
+            torch.cuda.empty_cache()
+    return res
 
 
 def precision(args, torch, tc, wl):

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <string>
 
+#include "devutil.h"
 #include "plan.h"
 
 namespace tc {
@@ -75,6 +76,217 @@ __global__ __launch_bounds__(256) void k_zscale(ZScaleArgs a) {
         C[2 * oc] = re;
         C[2 * oc + 1] = im;
     }
+}
+
+// Streaming kernel for few summed positions on complex data (the complex form
+// of the real streaming kernel).  The embedding above doubles the summed length
+// and stores each element of the expanded operand twice, which for a streamed
+// C multiplies the on-chip reads per byte of C; here the operands stay complex.
+// A block is four waves, one C column each (R columns per wave).  Along C's
+// unit-stride M dimension a lane owns W chunks of 16 bytes (CPC complex
+// elements each), 64 chunks apart, so every load and store instruction of a
+// wave covers 1 KB of contiguous memory; it keeps A's K values for them in
+// registers and reuses them for all R columns.  kA/kB (complex-element offsets)
+// are padded by the host to KT entries repeating the last one; padded terms are
+// zeroed by selects.
+template <typename T, int KT, int W, int R, bool BETA>
+__global__ __launch_bounds__(256) void k_zstream_wave(const T* __restrict__ A, const T* __restrict__ B,
+                                                      T* __restrict__ C, StreamArgs a, double alpha_im,
+                                                      double beta_im) {
+    constexpr int CPC = 8 / (int)sizeof(T);          // complex elements per 16-byte chunk
+    constexpr int VEC = W * CPC;                      // complex elements per lane
+    typedef T vec_t __attribute__((ext_vector_type(2 * CPC)));
+    constexpr int SPAN = 64 * VEC;
+    const int tid = threadIdx.x;
+    const uint32_t mblocks = (uint32_t)(a.M / SPAN);
+    const uint32_t mb = blockIdx.x % mblocks;
+    const uint32_t nb = blockIdx.x / mblocks;
+    const int row = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int64_t m0 = (int64_t)mb * SPAN + (tid % 64) * CPC;   // chunk w starts at m0 + 64 CPC w
+
+    int64_t offB[R], offC[R];
+    bool ok[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int64_t n = ((int64_t)nb * R + q) * 4 + row;
+        ok[q] = n < a.N;
+        const int64_t nn = ok[q] ? n : a.N - 1;
+        if (a.n.n == 1) {
+            offB[q] = nn * a.n.d[0].sB;
+            offC[q] = nn * a.n.d[0].sC;
+        } else {
+            int64_t rem = nn, ob = 0, oc = 0;
+            for (int d = 0; d < a.n.n; ++d) {
+                const int64_t r = divmod(rem, a.n.d[d].ext);
+                ob += r * a.n.d[d].sB;
+                oc += r * a.n.d[d].sC;
+            }
+            offB[q] = ob;
+            offC[q] = oc;
+        }
+    }
+    T br[R][KT], bi[R][KT];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            const T* bp = B + 2 * (offB[q] + a.kB[k]);
+            const T xr = bp[0], xi = bp[1];
+            br[q][k] = (k < a.K) ? xr : (T)0;
+            bi[q][k] = (k < a.K) ? xi : (T)0;
+        }
+    T ar[VEC][KT], ai[VEC][KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k)
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const vec_t t = *(const vec_t*)(A + 2 * (a.kA[k] + m0 + 64 * CPC * w));
+#pragma unroll
+            for (int c = 0; c < CPC; ++c) {
+                ar[w * CPC + c][k] = (k < a.K) ? t[2 * c] : (T)0;
+                ai[w * CPC + c][k] = (k < a.K) ? t[2 * c + 1] : (T)0;
+            }
+        }
+    const T alr = (T)a.alpha, ali = (T)alpha_im;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        if (!ok[q]) break;   // columns grow with q: the rest are past N too
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            vec_t val;
+#pragma unroll
+            for (int c = 0; c < CPC; ++c) {
+                const int v = w * CPC + c;
+                T sr = 0, si = 0;
+#pragma unroll
+                for (int k = 0; k < KT; ++k) {   // four fused multiply-adds per complex term
+                    sr += ar[v][k] * br[q][k];
+                    sr -= ai[v][k] * bi[q][k];
+                    si += ar[v][k] * bi[q][k];
+                    si += ai[v][k] * br[q][k];
+                }
+                val[2 * c] = alr * sr - ali * si;
+                val[2 * c + 1] = alr * si + ali * sr;
+            }
+            vec_t* cp = (vec_t*)(C + 2 * (offC[q] + m0 + 64 * CPC * w));
+            if (BETA) {
+                const vec_t old = *cp;
+                const T bre = (T)a.beta, bim = (T)beta_im;
+#pragma unroll
+                for (int c = 0; c < CPC; ++c) {
+                    val[2 * c] += bre * old[2 * c] - bim * old[2 * c + 1];
+                    val[2 * c + 1] += bre * old[2 * c + 1] + bim * old[2 * c];
+                }
+            }
+            __builtin_nontemporal_store(val, cp);
+        }
+    }
+}
+
+// Columns per wave: registers hold 2 R KT values of B and 2 VEC KT of A.
+static int zstream_r(int K) { return K <= 8 ? 4 : 2; }
+
+template <typename T, int W, bool BETA>
+static void launch_zstream(const StreamArgs& w, double alpha_im, double beta_im, unsigned grid, hipStream_t st) {
+    const T* A = (const T*)w.A;
+    const T* B = (const T*)w.B;
+    T* C = (T*)w.C;
+    dim3 g(grid), b(256);
+    if (w.K <= 4)
+        hipLaunchKernelGGL((k_zstream_wave<T, 4, W, 4, BETA>), g, b, 0, st, A, B, C, w, alpha_im, beta_im);
+    else if (w.K <= 8)
+        hipLaunchKernelGGL((k_zstream_wave<T, 8, W, 4, BETA>), g, b, 0, st, A, B, C, w, alpha_im, beta_im);
+    else if constexpr (W == 1)   // 16 positions: one chunk per lane only (registers)
+        hipLaunchKernelGGL((k_zstream_wave<T, 16, 1, 2, BETA>), g, b, 0, st, A, B, C, w, alpha_im, beta_im);
+}
+
+// Complex elements per lane: a wide form (two 16-byte chunks, twice the
+// outputs per B value read) and a narrow one (one chunk).
+static int zvec_narrow(bool f64) { return f64 ? 1 : 2; }
+
+// The complex streaming kernel takes a plan whose complex GEMM view has at most
+// 16 summed positions, one M dimension with unit stride in C and in A (after
+// the swap that puts C's unit stride in M), no batch indices, M a whole number
+// of wave spans (64 VEC), and every N stride of C and K stride of A a multiple
+// of a chunk's complex elements.  Returns the widest VEC that fits, 0 if none;
+// the call then also needs A and C to start on 16 bytes.
+static int zstream_vec(const tc_plan_s* p) {
+    const GemmView& gv = p->gv;
+    const bool f64 = p->spec.dtype == TC_C128;
+    const int cpc = zvec_narrow(f64);
+    if (gv.K < 1 || gv.K > 16 || gv.m.size() != 1 || !gv.b.empty()) return 0;
+    if (gv.m[0].sC != 1 || gv.m[0].sA != 1) return 0;
+    for (const GtDim& d : gv.n)
+        if (d.sC % cpc != 0) return 0;
+    for (const GtDim& d : gv.k)
+        if (d.sA % cpc != 0) return 0;
+    if (gv.M % (128 * cpc) == 0) return 2 * cpc;
+    return gv.M % (64 * cpc) == 0 ? cpc : 0;
+}
+
+// Runs the streaming kernel if the pointers allow; *ran is false otherwise.
+static tc_status run_zstream(tc_plan_s* p, const void* A, const void* B, void* C, double alpha_re,
+                             double alpha_im, double beta_re, double beta_im, hipStream_t st, bool* ran) {
+    const GemmView& gv = p->gv;
+    const bool f64 = p->spec.dtype == TC_C128;
+    const int cbytes = f64 ? 16 : 8;
+    *ran = false;
+    if (gv.swapped) std::swap(A, B);
+    int vec = p->zvec;
+    if (gv.K > 8) vec = zvec_narrow(f64);
+    // every access is one 16-byte chunk: A and C must start on 16 bytes
+    (void)cbytes;
+    if (((uintptr_t)A) % 16 != 0 || ((uintptr_t)C) % 16 != 0) return TC_OK;
+    StreamArgs w{};
+    w.A = A; w.B = B; w.C = C;
+    w.M = gv.M;
+    w.sAm = 1;
+    w.N = gv.N;
+    w.n.n = (int)gv.n.size();
+    for (int d = 0; d < w.n.n; ++d) w.n.d[d] = gv.n[d];
+    w.K = (int)gv.K;
+    std::vector<int64_t> idx(gv.k.size(), 0);
+    for (int k = 0; k < w.K; ++k) {
+        int64_t oa = 0, ob = 0;
+        for (size_t d = 0; d < gv.k.size(); ++d) {
+            oa += idx[d] * gv.k[d].sA;
+            ob += idx[d] * gv.k[d].sB;
+        }
+        w.kA[k] = oa;
+        w.kB[k] = ob;
+        for (size_t d = 0; d < gv.k.size(); ++d) {
+            if (++idx[d] < gv.k[d].ext) break;
+            idx[d] = 0;
+        }
+    }
+    for (int k = w.K; k < GT_SMALLK_MAX; ++k) {
+        w.kA[k] = w.kA[w.K - 1];
+        w.kB[k] = w.kB[w.K - 1];
+    }
+    w.alpha = alpha_re;
+    w.beta = beta_re;
+    const int64_t cols = 4 * (int64_t)zstream_r(w.K);
+    const int64_t grid = (gv.M / (64 * vec)) * ((gv.N + cols - 1) / cols);
+    if (grid > 0x7fffffff) return TC_OK;
+    const bool beta = beta_re != 0.0 || beta_im != 0.0;
+    const unsigned g = (unsigned)grid;
+    const bool wide = vec > zvec_narrow(f64);
+    if (f64 && wide) {
+        if (beta) launch_zstream<double, 2, true>(w, alpha_im, beta_im, g, st);
+        else launch_zstream<double, 2, false>(w, alpha_im, beta_im, g, st);
+    } else if (f64) {
+        if (beta) launch_zstream<double, 1, true>(w, alpha_im, beta_im, g, st);
+        else launch_zstream<double, 1, false>(w, alpha_im, beta_im, g, st);
+    } else if (wide) {
+        if (beta) launch_zstream<float, 2, true>(w, alpha_im, beta_im, g, st);
+        else launch_zstream<float, 2, false>(w, alpha_im, beta_im, g, st);
+    } else {
+        if (beta) launch_zstream<float, 1, true>(w, alpha_im, beta_im, g, st);
+        else launch_zstream<float, 1, false>(w, alpha_im, beta_im, g, st);
+    }
+    *ran = true;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TC_OK : hip_fail(e, "complex streaming kernel launch");
 }
 
 // ---------------------------------------------------------------------------
@@ -147,6 +359,9 @@ tc_status build_complex(tc_plan_s* p) {
     p->zelems = y == 0 ? s.nA : s.nB;
     p->zs_in = st_exp[zi - 'a'];
     p->zs_out = st_exp[zo - 'a'];
+    // the complex GEMM view (strides in complex elements) for the streaming kernel
+    p->gv = gemm_view(s);
+    p->zvec = zstream_vec(p);
     return TC_OK;
 }
 
@@ -165,6 +380,11 @@ tc_status run_complex(tc_plan_s* p, const void* A, const void* B, void* C, doubl
     int64_t K = 1;
     for (char ch : s.summed()) K *= s.e(ch);
     const bool no_product = (alpha_re == 0.0 && alpha_im == 0.0) || K == 0;
+    if (!no_product && p->zvec) {
+        bool ran = false;
+        tc_status r = run_zstream(p, A, B, C, alpha_re, alpha_im, beta_re, beta_im, st, &ran);
+        if (r || ran) return r;
+    }
     double inner_beta = beta_re;
     if (no_product || beta_im != 0.0) {
         // C := beta * C here; the real contraction (if any) then adds to it
@@ -187,6 +407,7 @@ tc_status run_complex(tc_plan_s* p, const void* A, const void* B, void* C, doubl
         if (no_product) return TC_OK;
         inner_beta = 1.0;
     }
+
     tc_status stt = prepare_complex(p);
     if (stt) return stt;
     ZExpandArgs a{};

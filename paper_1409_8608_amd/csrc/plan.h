@@ -55,6 +55,7 @@ struct tc_plan_s {
     int64_t zs_in = 0, zs_out = 0;   // destination strides of the two re/im indices
     void* d_zexp = nullptr;          // the expanded operand
     int64_t zexp_cap = 0;
+    int zvec = 0;                    // complex streaming kernel's widest lane form (0: not used); gv complex
     // split-precision buffers (one allocation)
     void* d_split = nullptr;
     int64_t split_bytes = 0;

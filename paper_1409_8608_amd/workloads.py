@@ -14,6 +14,10 @@ Workloads (the paper uses dense synthetic tensors defined by shape only):
                       and B[:, b, :] scaled by its own log-uniform[1e-3, 1e3]
                       factor; normal(0, 1), seed 41
   batch(...)          4096 contractions drawn from four patterns; seed 51
+  complex_smallk(n, i), complex_square(m)
+                      complex128 forms of smallk_cube (seed 61) and of a square
+                      product C_ab = A_ai B_ib, a = b = i = m (seed 71); real and
+                      imaginary parts uniform[-1, 1], drawn parts-first per operand
 Draw order within one generator: A's entries, A's scales, B's entries, B's
 scales, then C (only when an input C is requested).
 """
@@ -122,3 +126,33 @@ def batch_values(item: dict, integer: bool = False):
     rng = np.random.default_rng(item["seed_seq"])
     A, B, _ = tensors(item["spec"], item["ext"], rng, "uniform", False, integer)
     return A, B
+
+
+def complex_tensors(spec: str, ext: dict, rng: np.random.Generator):
+    """Complex A and B for `spec`: real part then imaginary part of A, then of B,
+    each uniform[-1, 1]; Fortran order, complex128."""
+    sa, sb, _ = _split(spec)
+
+    def draw(letters):
+        shape = _shape(letters, ext)
+        re = rng.uniform(-1.0, 1.0, size=shape)
+        im = rng.uniform(-1.0, 1.0, size=shape)
+        return np.array(re + 1j * im, dtype=np.complex128, order="F")
+
+    A = draw(sa)
+    B = draw(sb)
+    return A, B
+
+
+def complex_smallk(n: int = 1024, i: int = 8):
+    spec = "abc=ai,ibc"
+    ext = dict(a=n, b=n, c=n, i=i)
+    A, B = complex_tensors(spec, ext, np.random.default_rng(61))
+    return dict(spec=spec, ext=ext, A=A, B=B)
+
+
+def complex_square(m: int = 4096):
+    spec = "ab=ai,ib"
+    ext = dict(a=m, b=m, i=m)
+    A, B = complex_tensors(spec, ext, np.random.default_rng(71))
+    return dict(spec=spec, ext=ext, A=A, B=B)

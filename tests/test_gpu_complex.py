@@ -200,3 +200,59 @@ def test_complex_predict_and_workspace():
     got = run(p, A2, B2, None, "c128")
     check(spec, ext, A2, B2, got, "c128")
     torch.cuda.synchronize()
+
+
+# Complex streaming kernel: M a whole number of wave spans along C's unit
+# stride (narrow lanes: 64 complex doubles, 128 complex floats; wide lanes:
+# twice that), at most 16 summed positions (template sizes 4, 8 and 16), N not
+# a multiple of the block's columns, two summed dims, C's unit stride in B
+# (operands swapped), a trace index, an outer product, and padded operands
+# (M = 128 takes the narrow form of complex floats, M = 256 the wide one).
+ZSTREAM_CASES = [
+    ("abc=ai,ibc", dict(a=128, b=20, c=3, i=8), None),
+    ("abc=ai,ibc", dict(a=256, b=9, c=5, i=3), None),
+    ("abc=ai,ibc", dict(a=128, b=7, c=3, i=16), None),
+    ("ab=aij,jib", dict(a=256, b=30, i=3, j=4), None),
+    ("ba=ai,ib", dict(a=20, b=128, i=6), None),
+    ("ab=ai,ibt", dict(a=128, b=10, i=4, t=2), None),
+    ("ab=a,b", dict(a=128, b=33), None),
+    ("ab=ai,ib", dict(a=128, b=21, i=5), dict(A=[1, 128], B=[1, 5], C=[1, 130])),
+    ("abc=ai,ibc", dict(a=512, b=11, c=2, i=7), None),
+    ("ab=ai,ib", dict(a=256, b=9, i=6), dict(A=[1, 258], B=[1, 6], C=[1, 258])),
+]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("spec,ext,strides", ZSTREAM_CASES)
+def test_complex_streaming_parity(spec, ext, strides, dtype):
+    rng = np.random.default_rng(zlib.crc32(repr((spec, sorted(ext.items()))).encode()))
+    A, B, C0 = operands(spec, ext, rng, with_c=True)
+    p = tc.Plan(spec, ext, dtype, strides=strides)
+    got = run(p, A, B, None, dtype, strides=strides)
+    check(spec, ext, A, B, got, dtype)
+    got = run(p, A, B, C0, dtype, 0.5 + 2j, -0.75 + 0.5j, strides=strides)
+    check(spec, ext, A, B, got, dtype, C0, 0.5 + 2j, -0.75 + 0.5j)
+    Ai, Bi, Ci = operands(spec, ext, rng, integer=True, with_c=True)
+    for alpha, beta in ((1.0, 0.0), (1j, 1 - 1j), (-2.0, 1.0)):
+        got = run(p, Ai, Bi, Ci, dtype, alpha, beta, strides=strides)
+        check(spec, ext, Ai, Bi, got, dtype, Ci, alpha, beta, exact=True)
+
+
+@pytest.mark.parametrize("dtype,offset", [("c64", 1), ("c64", 2), ("c128", 1), ("c128", 0)])
+def test_complex_streaming_alignment_forms(dtype, offset):
+    # A starting `offset` complex elements into an allocation: a 16-byte-aligned
+    # start keeps the streaming kernel (wide lane form at M = 256), an
+    # 8-byte-aligned one takes the embedded real form
+    torch = _torch()
+    spec, ext = "abc=ai,ibc", dict(a=256, b=6, c=4, i=8)
+    rng = np.random.default_rng(21)
+    A, B, _ = operands(spec, ext, rng, integer=True)
+    p = tc.Plan(spec, ext, dtype)
+    store = torch.zeros(offset + 256 * 8, dtype=tdtype(dtype), device="cuda")
+    dA = torch.as_strided(store, (256, 8), (1, 256), offset)
+    dA.copy_(torch.from_numpy(A))
+    dB = device(B, dtype)
+    dC = tc.empty_fortran([256, 6, 4], tdtype(dtype))
+    p.contract(dA, dB, dC, 1 + 0j, 0j)
+    torch.cuda.synchronize()
+    check(spec, ext, A, B, dC.cpu().numpy().astype(np.complex128), dtype, exact=True)
