@@ -45,6 +45,18 @@ own class are counted in the nearest inner class that has one.
 Readings where the paper leaves a choice: the prefetch distance is 0 (its worked
 example); line failures split only the steady class; a loop nest without loops
 gives every operand distance 0.
+
+Root precondition (case 3 made explicit).  At the root the paper assumes the
+contraction runs again and again with nothing in between, because it cannot
+know the surrounding program.  A caller who does know it states, per operand,
+how many elements of other data the program touches between the operand's
+previous use and this run (its gap); the distance at the root is then |M| plus
+that gap.  Gaps of 0 are the paper's assumption.  For a chain of contractions
+run in order, again and again, with tensors named by ids, the gap of an operand
+is the total size of the distinct tensors that the contractions run since the
+operand was last used access, leaving out the tensors of the contraction being
+predicted (its own operands are in M already); if no other contraction uses
+the tensor, "since it was last used" is the previous run of this contraction.
 """
 from __future__ import annotations
 
@@ -72,23 +84,52 @@ def varies(r: Region, loop: str, joined: set) -> bool:
 
 
 def access_distance(op: Region, ops, loops, extents: dict, start: int | None = None,
-                    preset: set | None = None) -> int:
+                    preset: set | None = None, root_gap: int = 0) -> int:
     """Distance of ``op`` for a kernel nested in ``loops`` (outermost first).
 
     ``start``/``preset`` implement the first-iteration variant: the walk starts
-    at loop index ``start`` (it and the loops inside it already joined)."""
+    at loop index ``start`` (it and the loops inside it already joined).
+    ``root_gap`` is added when the walk reaches the root (case 3)."""
     joined = set(preset or ())
     pos = len(loops) - 1 if start is None else start - 1
+    at_root = True
     while pos >= 0:
         loop = loops[pos]
         if not varies(op, loop, joined):
+            at_root = False
             break                                   # case 1
         joined.add(loop)                            # case 2
         pos -= 1
-    # case 1 or case 3 (root)
+    gap = int(root_gap) if at_root else 0           # case 3: the caller's precondition
     if not joined:
-        return 0
-    return sum(region_size(r, joined, extents) for r in ops)
+        return gap
+    return sum(region_size(r, joined, extents) for r in ops) + gap
+
+
+def chain_root_gaps(chain):
+    """Root gaps, in bytes, for a chain of contractions run in order, again and
+    again.  ``chain``: one entry per contraction, a list of three (tensor_id,
+    bytes) pairs for A, B and C.  Returns one [gap_A, gap_B, gap_C] per
+    contraction."""
+    n = len(chain)
+    size = {}
+    for ops in chain:
+        for tid, nbytes in ops:
+            size[tid] = max(size.get(tid, 0), int(nbytes))
+    out = []
+    for j, ops in enumerate(chain):
+        own = {tid for tid, _ in ops}
+        gaps = []
+        for tid, _ in ops:
+            seen = set()
+            for back in range(1, n + 1):            # contractions run since tid was last used
+                k = (j - back) % n
+                if k == j or tid in {t for t, _ in chain[k]}:
+                    break
+                seen |= {t for t, _ in chain[k]}
+            gaps.append(sum(size[t] for t in seen - own))
+        out.append(gaps)
+    return out
 
 
 def build_setup(items, cache_elems: float):
@@ -163,14 +204,16 @@ class BenchClass:
 
 
 def predict_classes(ops, loops, extents: dict, cache_elems: float, line_elems: int,
-                    stage: int = 5):
+                    stage: int = 5, root_gaps: dict | None = None):
     """Benchmark classes with their shares of the invocations, for prediction
-    stage 1 (repeated execution) .. 5 (first iterations separate)."""
+    stage 1 (repeated execution) .. 5 (first iterations separate).
+    ``root_gaps`` maps an operand's tensor name to its root gap (elements)."""
     names = [r.tensor for r in ops]
     sizes = [region_size(r, set(), extents) for r in ops]
+    gaps = {n: int((root_gaps or {}).get(n, 0)) for n in names}
     if stage == 1:
         return [BenchClass("steady", 1.0, [])]
-    dist = [access_distance(r, ops, loops, extents) for r in ops]
+    dist = [access_distance(r, ops, loops, extents, root_gap=gaps[r.tensor]) for r in ops]
     kinds = [prefetch_kind(r, loops, extents, line_elems) if stage >= 3 else None for r in ops]
 
     def setup_with(prefetched):
@@ -211,7 +254,7 @@ def predict_classes(ops, loops, extents: dict, cache_elems: float, line_elems: i
             preset = set(loops[k:])
             items = []
             for nme, s, r in zip(names, sizes, ops):
-                d = access_distance(r, ops, loops, extents, start=k, preset=preset)
+                d = access_distance(r, ops, loops, extents, start=k, preset=preset, root_gap=gaps[r.tensor])
                 items.append((nme, s, d))
             st = build_setup(items, cache_elems)
             classes.append(BenchClass(f"first@{loops[k]}", share, [] if only_operands(st) else st))

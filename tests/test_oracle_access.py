@@ -84,3 +84,49 @@ def test_case_rules_on_other_printed_algorithms():
     first = [c for c in cls if c.label == "first@i"][0]
     assert abs(first.weight - (1 / 8) * (1 - 1 / 400)) < 1e-15 or abs(first.weight - 1 / 8) < 1e-15
     assert any(c.label.startswith("first") for c in cls)
+
+
+def test_root_gap_only_where_the_walk_reaches_the_root(golden):
+    """Section 3.2's third case: in the worked example only C's walk reaches the
+    root (its set M holds every operand whole), so a caller's gap moves C's
+    distance by exactly the gap and leaves A's and B's (case 1) alone."""
+    g = golden("access_example.json")
+    v = {x.name: x for x in family.enumerate_family(g["spec"])}[g["variant"]]
+    ops = regions(v)
+    ext = g["extents"]
+    at_root = {t for t, m in g["M_sets"].items() if m and all(":" in x and "c" not in x.split("[")[1] for x in m)}
+    assert at_root == {"C"}
+    for gap in (0, 1, 1000, 10 ** 9):
+        for r in ops:
+            want = g["distances"][r.tensor] + (gap if r.tensor in at_root else 0)
+            assert ac.access_distance(r, ops, v.loops, ext, root_gap=gap) == want
+
+
+def test_large_root_gap_makes_an_operand_cold():
+    """A gap beyond 5/4 of the cache pushes an operand whose walk reaches the
+    root out of the cut setup list; a gap of 0 keeps the paper's list."""
+    spec, ext = "abc=ai,ibc", dict(a=40, b=30, c=20, i=8)
+    cache = 20000.0
+    for v in family.enumerate_family(spec):
+        ops = regions(v)
+        for r in ops:
+            d0 = ac.access_distance(r, ops, v.loops, ext)
+            d1 = ac.access_distance(r, ops, v.loops, ext, root_gap=10 ** 6)
+            if d1 == d0 or d0 + ac.region_size(r, set(), ext) > 1.25 * cache:
+                continue
+            base = ac.predict_classes(ops, v.loops, ext, cache, 8, stage=2)[0].setup
+            cold = ac.predict_classes(ops, v.loops, ext, cache, 8, stage=2, root_gaps={r.tensor: 10 ** 6})[0].setup
+            assert ["op", r.tensor, ac.region_size(r, set(), ext)] in [list(e) for e in base], v.name
+            assert r.tensor not in [e[1] for e in cold], v.name
+
+
+def test_chain_root_gaps_hand_worked():
+    # two contractions, T = A B then D = T E (ids 1..5, bytes)
+    two = [[(1, 100), (2, 1000), (3, 5000)], [(3, 5000), (4, 300), (5, 700)]]
+    assert ac.chain_root_gaps(two) == [[1000, 1000, 0], [0, 1100, 1100]]
+    # three contractions over six tensors of 10..60 bytes
+    s = {i: 10 * i for i in range(1, 7)}
+    three = [[(1, s[1]), (2, s[2]), (3, s[3])], [(3, s[3]), (4, s[4]), (5, s[5])], [(5, s[5]), (1, s[1]), (6, s[6])]]
+    assert ac.chain_root_gaps(three) == [[0, 150, 110], [0, 90, 30], [0, 70, 90]]
+    # one contraction alone is the paper's assumption: nothing in between
+    assert ac.chain_root_gaps([[(1, 8), (2, 8), (3, 8)]]) == [[0, 0, 0]]
