@@ -225,6 +225,30 @@ tc_status tc_access_distance(tc_plan_t plan, int variant, int tensor, int64_t* o
 tc_status tc_bench_classes(tc_plan_t plan, int variant, int stage, double cache_elems,
                            int line_elems, tc_bench_class* out, int capacity, int* n_out);
 
+/* Cache precondition of the prediction (Section 3.2, the walk's third case).
+ * When the back-traversal of an operand reaches the algorithm's root, the paper
+ * assumes the contraction runs again and again with nothing in between, since
+ * it cannot know the surrounding program.  gap[t] (t = 0 A, 1 B, 2 C) states
+ * what the caller's program does: the number of elements (of the plan's storage
+ * type) of other data it accesses between the previous use of operand t and
+ * this contraction.  It is added to the access distance at the root, in
+ * tc_access_distance, tc_bench_classes and tc_predict.  NULL or all zero is the
+ * paper's assumption (the default); a gap of 5/4 of the cache or more makes
+ * the operand cold.  Clears an earlier prediction.  Host only.
+ * Errors: TC_E_NULL, TC_E_EXTENT (negative gap). */
+tc_status tc_set_root_gap(tc_plan_t plan, const int64_t* gap);
+
+/* Root gaps for a chain of n contractions that a program runs in this order,
+ * again and again (for instance T = A B, then D = T E).  ids holds 3 * n tensor
+ * ids, A, B and C of each plan; equal ids name the same tensor.  For operand t
+ * of plan j the gap is the total size of the distinct tensors accessed by the
+ * plans run since that tensor was last used (by an earlier plan of the chain,
+ * or else by plan j's own previous run), leaving out plan j's own tensors,
+ * which the walk counts already; sizes are element counts times element bytes,
+ * converted to plan j's elements.  Calls tc_set_root_gap on every plan.
+ * Host only.  Errors: TC_E_NULL. */
+tc_status tc_chain_root_gaps(const tc_plan_t* plans, const int* ids, int n);
+
 /* Predict the run time of every member (and the fused kernel, last) on the
  * current device: for each member's benchmark classes, run the GPU
  * micro-benchmark (setup accesses, then the member's kernel on a sample of its

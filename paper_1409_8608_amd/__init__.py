@@ -27,7 +27,8 @@ TC_MAX_SETUP = 16
 EXPORTS = ("tc_plan", "tc_plan_destroy", "tc_variant_count", "tc_variant_get", "tc_set_variant",
            "tc_plan_prepare", "tc_plan_workspace", "tc_contract", "tc_contract_complex", "tc_access_distance", "tc_bench_classes",
            "tc_predict", "tc_batch_create", "tc_batch_tune", "tc_batch_contract", "tc_batch_destroy",
-           "tc_batch_info", "tc_split_terms", "tc_status_str", "tc_last_error")
+           "tc_batch_info", "tc_split_terms", "tc_status_str", "tc_last_error", "tc_set_root_gap",
+           "tc_chain_root_gaps")
 
 
 class TcError(RuntimeError):
@@ -94,6 +95,8 @@ def _load():
         "tc_batch_info": [P, ctypes.POINTER(ctypes.c_int), I64P, ctypes.POINTER(ctypes.c_int),
                           ctypes.POINTER(ctypes.c_double)],
         "tc_split_terms": [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_int32), I64P, I64P],
+        "tc_set_root_gap": [P, I64P],
+        "tc_chain_root_gaps": [ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int), ctypes.c_int],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -196,6 +199,20 @@ def tc_bench_classes(h, variant: int, stage: int, cache_elems: float, line_elems
             items.append(("op", "ABC"[it.tensor], it.size) if it.kind == 0 else ("remote", None, it.size))
         out.append(dict(label=c.label.decode(), weight=c.weight, setup=items))
     return out
+
+
+def tc_set_root_gap(h, gaps=None):
+    """gaps: three element counts (A, B, C), or None for the paper's assumption."""
+    _check(lib.tc_set_root_gap(h, _i64(gaps) if gaps is not None else None))
+
+
+def tc_chain_root_gaps(handles, ids):
+    """handles: plans of the chain in run order; ids: 3 tensor ids per plan."""
+    n = len(handles)
+    ids = [int(x) for x in ids]
+    if len(ids) != 3 * n:
+        raise ValueError("tc_chain_root_gaps: three tensor ids per plan")
+    _check(lib.tc_chain_root_gaps((ctypes.c_void_p * max(1, n))(*handles), (ctypes.c_int * max(1, 3 * n))(*ids), n))
 
 
 def tc_predict(h) -> list:
@@ -367,6 +384,9 @@ class Plan:
 
     def predict(self):
         return tc_predict(self.handle)
+
+    def set_root_gap(self, gaps=None):
+        tc_set_root_gap(self.handle, gaps)
 
     def bench_classes(self, variant, stage, cache_elems, line_elems):
         return tc_bench_classes(self.handle, variant, stage, cache_elems, line_elems)

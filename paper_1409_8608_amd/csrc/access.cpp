@@ -28,8 +28,11 @@ static bool depends(const Operand& op, char loop, const std::string& joined) {
 // position `start` with that loop and every loop inside it already joined).
 // Case 1: the operand does not change across the loop -> stop.  Case 2: it does
 // -> join all kernel operands along the loop and go up.  Case 3: root -> stop.
-// The distance is the size of the joined operands (empty set -> 0).
-int64_t access_distance(const Spec& s, const Variant& v, int tensor, int start) {
+// The distance is the size of the joined operands (empty set -> 0), plus the
+// caller's root gap in case 3: the paper assumes the contraction runs again
+// and again with nothing in between, a caller who knows the surrounding
+// program states what is accessed in between.
+int64_t access_distance(const Spec& s, const Variant& v, int tensor, int start, int64_t root_gap) {
     std::string joined;
     int pos = (int)v.loops.size() - 1;
     if (start >= 0) {
@@ -41,10 +44,11 @@ int64_t access_distance(const Spec& s, const Variant& v, int tensor, int start) 
         if (!depends(v.ops[tensor], loop, joined)) break;
         joined += loop;
     }
-    if (joined.empty()) return 0;
+    const int64_t gap = pos < 0 ? root_gap : 0;
+    if (joined.empty()) return gap;
     int64_t d = 0;
     for (int t = 0; t < 3; ++t) d += region_size(s, v.ops[t], joined);
-    return d;
+    return d + gap;
 }
 
 // 1: the innermost loop indexes the operand's first axis (cache-line sharing);
@@ -113,7 +117,9 @@ static std::vector<SetupItem> setup_list(std::vector<Item> items, double cache_e
 }
 
 std::vector<BenchClass> bench_classes(const Spec& s, const Variant& v, int stage,
-                                      double cache_elems, int line_elems) {
+                                      double cache_elems, int line_elems, const int64_t* root_gaps) {
+    const int64_t gap0[3] = {0, 0, 0};
+    const int64_t* gap = root_gaps ? root_gaps : gap0;
     std::vector<BenchClass> out;
     if (stage <= 1) {
         BenchClass c;
@@ -127,7 +133,7 @@ std::vector<BenchClass> bench_classes(const Spec& s, const Variant& v, int stage
     int kind[3];
     for (int t = 0; t < 3; ++t) {
         size[t] = region_size(s, v.ops[t], "");
-        dist[t] = access_distance(s, v, t, -1);
+        dist[t] = access_distance(s, v, t, -1, gap[t]);
         kind[t] = stage >= 3 ? prefetch_kind(s, v, t, line_elems) : 0;
     }
     auto steady_with = [&](const bool pf[3]) {
@@ -174,7 +180,7 @@ std::vector<BenchClass> bench_classes(const Spec& s, const Variant& v, int stage
             int k = own[q];
             double share = first[k] - (q + 1 < own.size() ? first[own[q + 1]] : 0.0);
             std::vector<Item> items;
-            for (int t = 0; t < 3; ++t) items.push_back(Item{t, size[t], access_distance(s, v, t, k)});
+            for (int t = 0; t < 3; ++t) items.push_back(Item{t, size[t], access_distance(s, v, t, k, gap[t])});
             BenchClass c{std::string("first@") + v.loops[k], share, setup_list(items, cache_elems), k,
                          std::vector<bool>(3, false)};
             out.push_back(c);

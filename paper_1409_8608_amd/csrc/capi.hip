@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -586,7 +588,7 @@ tc_status tc_access_distance(tc_plan_t p, int variant, int tensor, int64_t* out)
     if (!p || !out) return fail(TC_E_NULL, "NULL argument");
     if (variant < 0 || variant >= (int)p->fam().size()) return fail(TC_E_VARIANT, "variant out of range");
     if (tensor < 0 || tensor > 2) return fail(TC_E_VARIANT, "tensor must be 0, 1 or 2");
-    *out = access_distance(p->spec, p->fam()[variant], tensor, -1);
+    *out = access_distance(p->spec, p->fam()[variant], tensor, -1, p->root_gap[tensor]);
     return TC_OK;
 }
 
@@ -596,7 +598,8 @@ tc_status tc_bench_classes(tc_plan_t p, int variant, int stage, double cache_ele
     if (variant < 0 || variant >= (int)p->fam().size()) return fail(TC_E_VARIANT, "variant out of range");
     if (stage < 1 || stage > 5 || line_elems < 1 || !(cache_elems > 0))
         return fail(TC_E_UNSUPPORTED, "stage must be 1..5, line and cache positive");
-    std::vector<BenchClass> cls = bench_classes(p->spec, p->fam()[variant], stage, cache_elems, line_elems);
+    std::vector<BenchClass> cls =
+        bench_classes(p->spec, p->fam()[variant], stage, cache_elems, line_elems, p->root_gap);
     *n_out = (int)cls.size();
     if ((int)cls.size() > capacity || (capacity > 0 && !out)) return fail(TC_E_CAPACITY, "capacity too small");
     for (size_t c = 0; c < cls.size(); ++c) {
@@ -610,6 +613,52 @@ tc_status tc_bench_classes(tc_plan_t p, int variant, int stage, double cache_ele
             o.items[k].tensor = cls[c].setup[k].tensor;
             o.items[k].size = cls[c].setup[k].size;
         }
+    }
+    return TC_OK;
+}
+
+tc_status tc_set_root_gap(tc_plan_t p, const int64_t* gap) {
+    if (!p) return fail(TC_E_NULL, "plan is NULL");
+    for (int t = 0; t < 3; ++t)
+        if (gap && gap[t] < 0) return fail(TC_E_EXTENT, "root gaps must be >= 0");
+    for (int t = 0; t < 3; ++t) p->root_gap[t] = gap ? gap[t] : 0;
+    p->have_prediction = false;     // an earlier prediction assumed other gaps
+    return TC_OK;
+}
+
+tc_status tc_chain_root_gaps(const tc_plan_t* plans, const int* ids, int n) {
+    if (n < 0 || (n > 0 && (!plans || !ids))) return fail(TC_E_NULL, "plans or ids is NULL");
+    for (int j = 0; j < n; ++j)
+        if (!plans[j]) return fail(TC_E_NULL, "a plan is NULL");
+    // bytes of every tensor id (the largest operand that names it)
+    std::map<int, int64_t> bytes;
+    for (int j = 0; j < n; ++j) {
+        const Spec& s = plans[j]->spec;
+        const int64_t cnt[3] = {s.nA, s.nB, s.nC};
+        for (int t = 0; t < 3; ++t) {
+            int64_t b = cnt[t] * s.elem_bytes();
+            int64_t& have = bytes[ids[3 * j + t]];
+            have = std::max(have, b);
+        }
+    }
+    auto uses = [&](int k, int id) { return ids[3 * k] == id || ids[3 * k + 1] == id || ids[3 * k + 2] == id; };
+    for (int j = 0; j < n; ++j) {
+        int64_t gap[3];
+        for (int t = 0; t < 3; ++t) {
+            const int id = ids[3 * j + t];
+            std::set<int> seen;   // tensors the contractions run since `id` was last used access
+            for (int back = 1; back <= n; ++back) {
+                const int k = ((j - back) % n + n) % n;
+                if (k == j || uses(k, id)) break;
+                for (int q = 0; q < 3; ++q) seen.insert(ids[3 * k + q]);
+            }
+            int64_t b = 0;
+            for (int x : seen)
+                if (!uses(j, x)) b += bytes[x];
+            gap[t] = b / plans[j]->spec.elem_bytes();
+        }
+        tc_status st = tc_set_root_gap(plans[j], gap);
+        if (st) return st;
     }
     return TC_OK;
 }

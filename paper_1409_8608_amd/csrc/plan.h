@@ -29,6 +29,9 @@ struct tc_plan_s {
         for (auto& v : fam_) vplans_.push_back(tc::plan_variant(spec, v));
         family_built_ = true;
     }
+    // caller's cache precondition: elements of other data accessed between an
+    // operand's previous use and this run (A, B, C), added at the walk's root
+    int64_t root_gap[3] = {0, 0, 0};
     int selected = TC_VARIANT_FUSED;
     int predicted_best = TC_VARIANT_FUSED;
     bool have_prediction = false;

@@ -276,7 +276,7 @@ static tc_status predict_variant(PredCtx& c, int v, tc_prediction* out) {
     const double cache_elems = kCacheBytes / s.elem_bytes();
     const int line_elems = kLineBytes / s.elem_bytes();
     for (int stage = 1; stage <= 5; ++stage) {
-        std::vector<BenchClass> cls = bench_classes(s, var, stage, cache_elems, line_elems);
+        std::vector<BenchClass> cls = bench_classes(s, var, stage, cache_elems, line_elems, p->root_gap);
         double total = fixed;
         for (const BenchClass& bc : cls) {
             if (bc.weight <= 0) continue;

@@ -90,10 +90,12 @@ struct BenchClass {
 };
 
 int64_t region_size(const Spec& s, const Operand& op, const std::string& joined);
-int64_t access_distance(const Spec& s, const Variant& v, int tensor, int start = -1);
+// root_gap: elements of other data accessed between the operand's previous use
+// and this run, added when the walk reaches the root (0: the paper's assumption)
+int64_t access_distance(const Spec& s, const Variant& v, int tensor, int start = -1, int64_t root_gap = 0);
 int prefetch_kind(const Spec& s, const Variant& v, int tensor, int line_elems);  // 0 none, 1 line, 2 stream
 std::vector<BenchClass> bench_classes(const Spec& s, const Variant& v, int stage,
-                                      double cache_elems, int line_elems);
+                                      double cache_elems, int line_elems, const int64_t* root_gaps = nullptr);
 
 // ---------------------------------------------------------------------------
 // GPU schedules.

@@ -4,6 +4,7 @@ symbolic prediction steps) against the independent oracle."""
 import os
 import re
 
+import numpy as np
 import pytest
 
 import oracle
@@ -238,3 +239,75 @@ def test_complex_scalars_on_real_plan_are_refused():
     with pytest.raises(tc.TcError) as e:
         tc.tc_contract_complex(p.handle, 16, 32, 4096, 1.0, 2 + 1j)
     assert e.value.name == "TC_E_UNSUPPORTED"
+
+
+@pytest.mark.parametrize("spec", SPECS)
+@pytest.mark.parametrize("stage", [2, 5])
+def test_root_gap_matches_oracle(spec, stage):
+    """The caller's root precondition through the ABI against the oracle."""
+    ext = {ch: n for ch, n in zip("abcdij", (400, 30, 20, 12, 8, 6))}
+    ext = {ch: ext[ch] for ch in set(spec) if ch.isalpha()}
+    gaps = dict(A=1234, B=0, C=987654)
+    h = tc.tc_plan(spec, ext)
+    tc.tc_set_root_gap(h, [gaps["A"], gaps["B"], gaps["C"]])
+    for v in family.enumerate_family(spec):
+        idx = v.number - 1
+        ops = _regions(v)
+        for t, r in enumerate(ops):
+            want = ac.access_distance(r, ops, v.loops, ext, root_gap=gaps[r.tensor])
+            assert tc.tc_access_distance(h, idx, t) == want, (v.name, t)
+        for cache, line in ((786432.0, 8), (5000.0, 16)):
+            want = ac.predict_classes(ops, v.loops, ext, cache, line, stage=stage, root_gaps=gaps)
+            got = tc.tc_bench_classes(h, idx, stage, cache, line)
+            assert [g["label"] for g in got] == [w.label for w in want], v.name
+            for g, w in zip(got, want):
+                assert abs(g["weight"] - w.weight) < 1e-12, (v.name, g["label"])
+                assert [tuple(e) for e in g["setup"]] == [tuple(e) for e in w.setup], (v.name, g["label"])
+    tc.tc_set_root_gap(h, None)       # back to the paper's assumption
+    v = family.enumerate_family(spec)[-1]
+    ops = _regions(v)
+    for t, r in enumerate(ops):
+        assert tc.tc_access_distance(h, v.number - 1, t) == ac.access_distance(r, ops, v.loops, ext)
+    with pytest.raises(tc.TcError) as e:
+        tc.tc_set_root_gap(h, [0, -1, 0])
+    assert e.value.name == "TC_E_EXTENT"
+    tc.tc_plan_destroy(h)
+
+
+def test_chain_root_gaps_match_oracle():
+    """T = A B, D = T E, then F = A D: the gaps the ABI derives for the chain
+    equal the oracle's chain rule, converted to each plan's elements; checked on
+    a member whose walk reaches the root for every operand."""
+    specs = [("abc=ai,ibc", dict(a=40, b=30, c=20, i=8), tc.TC_F64, 8),      # T(abc) = A(ai) B(ibc)
+             ("ja=abc,jbc", dict(a=40, b=30, c=20, j=6), tc.TC_F32, 4),      # D(ja) = T E(jbc)
+             ("ij=ai,ja", dict(a=40, i=8, j=6), tc.TC_F64, 8)]               # F(ij) = A D
+    ids = [1, 2, 3, 3, 4, 5, 1, 5, 6]
+    plans = [tc.tc_plan(sp, ex, dtype=dt) for sp, ex, dt, _ in specs]
+    chain = []
+    for j, (sp, ex, _, eb) in enumerate(specs):
+        letters = oracle.split_spec(sp)
+        n = [int(np.prod([ex[ch] for ch in letters[t]])) for t in range(3)]
+        chain.append([(ids[3 * j + t], n[t] * eb) for t in range(3)])
+    want = ac.chain_root_gaps(chain)
+    assert any(g for row in want for g in row)
+    tc.tc_chain_root_gaps(plans, ids)
+    checked = reachable = 0
+    for j, (sp, ex, _, eb) in enumerate(specs):
+        fam = family.enumerate_family(sp)
+        for t in range(3):
+            gap = want[j][t] // eb
+            # an operand reused across every loop of every member (A of the
+            # first contraction) never reaches the root: its gap has no effect
+            reachable += any(ac.access_distance(_regions(v)[t], _regions(v), v.loops, ex, root_gap=1) !=
+                             ac.access_distance(_regions(v)[t], _regions(v), v.loops, ex) for v in fam)
+            for v in fam:
+                ops = _regions(v)
+                if ac.access_distance(ops[t], ops, v.loops, ex, root_gap=1) == ac.access_distance(ops[t], ops, v.loops, ex):
+                    continue                  # this member's walk stops before the root
+                assert tc.tc_access_distance(plans[j], v.number - 1, t) == \
+                    ac.access_distance(ops[t], ops, v.loops, ex, root_gap=gap), (sp, v.name, t)
+                checked += 1
+                break
+    assert checked == reachable >= 7
+    for h in plans:
+        tc.tc_plan_destroy(h)
