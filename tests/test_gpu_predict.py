@@ -67,3 +67,27 @@ def test_predict_and_select(spec, ext):
           f"{meas[best]*1e6:.1f} us; stage rho " +
           " ".join(f"{spearman([q['stage_s'][s] for q in preds], meas):.2f}" for s in range(5)))
     assert rho > 0.0
+
+
+def test_predict_with_chain_root_gaps():
+    """A chain T = A B, D = T E: the root gaps it derives enter every member's
+    benchmark classes; predictions stay finite, the old prediction is cleared
+    by a change of gaps, and the member picked under the chain's gaps computes
+    the right contraction."""
+    spec, ext = "abc=ai,ibc", dict(a=48, b=40, c=24, i=8)
+    p = tc.Plan(spec, ext)
+    q = tc.Plan("ja=abc,jbc", dict(a=48, b=40, c=24, j=4))
+    tc.tc_chain_root_gaps([p.handle, q.handle], [1, 2, 3, 3, 4, 5])
+    preds = p.predict()
+    assert len(preds) == len(p.variants()) + 1
+    assert all(np.isfinite(x["predicted_s"]) and x["predicted_s"] > 0 for x in preds)
+    p.set_variant(tc.TC_VARIANT_PREDICTED)
+    p.set_root_gap([0, 0, 10 ** 9])          # new gaps: the prediction no longer holds
+    with pytest.raises(tc.TcError) as e:
+        p.set_variant(tc.TC_VARIANT_PREDICTED)
+    assert e.value.name == "TC_E_VARIANT"
+    p.predict()
+    p.set_variant(tc.TC_VARIANT_PREDICTED)
+    A, B, _ = wl.tensors(spec, ext, np.random.default_rng(3))
+    got = run(p, A, B)
+    check(spec, ext, A, B, got)
