@@ -55,9 +55,10 @@ typedef struct tc_batch_s* tc_batch_t;   /* opaque, owned by the caller until tc
  * (the one with fewer elements) is written once per call into plan workspace as
  * real 2x2 blocks [re -im; im re], scaled by alpha, which adds a summed index
  * over the other operand's (re, im) pair and a free index over C's; that
- * operand and C are read in place.  Complex plans have no family members, take
- * TC_NATIVE only, cannot join a batch and need two letters the spec does not
- * use (TC_E_UNSUPPORTED otherwise). */
+ * operand and C are read in place.  Complex plans have no family members,
+ * cannot join a batch and need two letters the spec does not use
+ * (TC_E_UNSUPPORTED otherwise).  With TC_BF16X3 / TC_FP8X3 the split forms
+ * run on the embedded real operands, and tc_split_terms reports those. */
 typedef enum { TC_F64 = 0, TC_F32 = 1, TC_C128 = 2, TC_C64 = 3 } tc_dtype;
 
 /* Arithmetic path.  TC_NATIVE computes in the storage type.  TC_BF16X3 splits

@@ -432,8 +432,6 @@ tc_status tc_plan(tc_plan_t* out, const char* spec, const char* index_chars, con
         return fail(TC_E_DTYPE, "dtype must be TC_F64, TC_F32, TC_C128 or TC_C64");
     if (compute != TC_NATIVE && compute != TC_BF16X3 && compute != TC_FP8X3)
         return fail(TC_E_DTYPE, "unknown compute mode");
-    if (compute != TC_NATIVE && (dtype == TC_C128 || dtype == TC_C64))
-        return fail(TC_E_UNSUPPORTED, "complex plans compute in their storage precision (TC_NATIVE)");
     tc_plan_s* p = new (std::nothrow) tc_plan_s();
     if (!p) return fail(TC_E_NOMEM, "host allocation");
     Err err;

@@ -13,7 +13,8 @@
 // doubled (in reals); Y -- the operand with fewer elements -- is expanded once
 // per call into plan workspace with alpha folded in.  Every real kernel
 // (streaming, matrix core, split K) then applies unchanged, and the flop count
-// is that of the complex sum: four real products per complex one.
+// is that of the complex sum: four real products per complex one.  The
+// split-precision forms apply the same way, to the embedded real operands.
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -346,7 +347,7 @@ tc_status build_complex(tc_plan_s* p) {
     const tc_dtype rdt = s.dtype == TC_C128 ? TC_F64 : TC_F32;
     tc_status st = tc_plan(&p->real, spec.c_str(), chars.c_str(), exts.data(), (int)chars.size(),
                            y == 0 ? stY.data() : stX.data(), y == 0 ? stX.data() : stY.data(), stC.data(), rdt,
-                           TC_NATIVE);
+                           s.compute);
     if (st) return st;
 
     std::vector<GtDim> g;
@@ -361,7 +362,8 @@ tc_status build_complex(tc_plan_s* p) {
     p->zs_out = st_exp[zo - 'a'];
     // the complex GEMM view (strides in complex elements) for the streaming kernel
     p->gv = gemm_view(s);
-    p->zvec = zstream_vec(p);
+    // the split-precision forms run on the embedded real plan only
+    p->zvec = s.compute == TC_NATIVE ? zstream_vec(p) : 0;
     return TC_OK;
 }
 

@@ -888,6 +888,7 @@ extern "C" tc_status tc_split_terms(tc_plan_t p, int side, void* terms, int32_t*
                                     int64_t* kp) {
     using namespace tc;
     if (!p || !rows || !kp) return fail(TC_E_NULL, "NULL argument");
+    if (p->real) return tc_split_terms(p->real, side, terms, exps, rows, kp);   // complex: the embedded operands
     if (p->spec.compute == TC_NATIVE) return fail(TC_E_UNSUPPORTED, "plan has no split precision");
     if (!p->d_split) return fail(TC_E_UNSUPPORTED, "no split computed yet: run tc_contract first");
     if (side != 0 && side != 1) return fail(TC_E_VARIANT, "side must be 0 (A) or 1 (B)");

@@ -203,7 +203,8 @@ def test_family_letter_limit():
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_complex_plans(dtype):
-    """Complex plans: fused kernel only, native compute only, no batches."""
+    """Complex plans: fused path only, split forms only without batch or trace
+    indices, no batches."""
     p = tc.Plan("abc=ai,ibc", dict(a=4, b=3, c=2, i=5), dtype)
     assert p.variants() == []
     assert tc.tc_variant_get(p.handle, tc.TC_VARIANT_FUSED)["kernel"] == "fused"
@@ -212,8 +213,9 @@ def test_complex_plans(dtype):
         p.set_variant(0)
     assert e.value.name == "TC_E_VARIANT"
     for compute in ("bf16x3", "fp8x3"):
+        tc.Plan("abc=ai,ibc", dict(a=4, b=3, c=2, i=5), dtype, compute=compute)   # on the embedded operands
         with pytest.raises(tc.TcError) as e:
-            tc.Plan("abc=ai,ibc", dict(a=4, b=3, c=2, i=5), dtype, compute=compute)
+            tc.Plan("abc=aic,ibc", dict(a=4, b=3, c=2, i=5), dtype, compute=compute)   # batch index
         assert e.value.name == "TC_E_UNSUPPORTED"
     with pytest.raises(tc.TcError) as e:
         tc.tc_batch_create([p.handle])

@@ -256,3 +256,23 @@ def test_complex_streaming_alignment_forms(dtype, offset):
     p.contract(dA, dB, dC, 1 + 0j, 0j)
     torch.cuda.synchronize()
     check(spec, ext, A, B, dC.cpu().numpy().astype(np.complex128), dtype, exact=True)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("compute,tol", [("bf16x3", 1e-5), ("fp8x3", 2e-3)])
+@pytest.mark.parametrize("spec,ext", [("abc=ai,ibc", dict(a=96, b=40, c=3, i=40)),
+                                      ("abc=ija,jbic", dict(a=72, b=40, c=6, i=6, j=5)),
+                                      ("ab=ia,ib", dict(a=300, b=20, i=64))])
+def test_complex_split_precision(spec, ext, dtype, compute, tol):
+    """The split forms on the embedded real operands, against the complex oracle
+    (normwise, as for real operands)."""
+    rng = np.random.default_rng(31)
+    A, B, C0 = operands(spec, ext, rng, with_c=True)
+    p = tc.Plan(spec, ext, dtype, compute=compute)
+    got = run(p, A, B, C0, dtype, 1 - 0.5j, 0.5j)
+    ref = oracle.contract(spec, ext, rounded(A, dtype), rounded(B, dtype), C=rounded(C0, dtype), alpha=1 - 0.5j,
+                          beta=0.5j)
+    err = oracle.normwise_rel_err(got, ref)
+    assert err <= tol, f"normwise error {err:.3e} > {tol:.1e}"
+    rows, kp = tc.tc_split_terms(p.handle, 0, fp8=compute == "fp8x3")[0].shape[1:]
+    assert rows > 0 and kp > 0
