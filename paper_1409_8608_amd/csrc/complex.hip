@@ -230,13 +230,11 @@ static tc_status run_zstream(tc_plan_s* p, const void* A, const void* B, void* C
                              double alpha_im, double beta_re, double beta_im, hipStream_t st, bool* ran) {
     const GemmView& gv = p->gv;
     const bool f64 = p->spec.dtype == TC_C128;
-    const int cbytes = f64 ? 16 : 8;
     *ran = false;
     if (gv.swapped) std::swap(A, B);
     int vec = p->zvec;
     if (gv.K > 8) vec = zvec_narrow(f64);
     // every access is one 16-byte chunk: A and C must start on 16 bytes
-    (void)cbytes;
     if (((uintptr_t)A) % 16 != 0 || ((uintptr_t)C) % 16 != 0) return TC_OK;
     StreamArgs w{};
     w.A = A; w.B = B; w.C = C;
