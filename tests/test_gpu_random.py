@@ -125,3 +125,42 @@ def test_random_family_members(seed):
         p.contract(views[0], views[1], views[2], 1.5, -1.0)
         torch.cuda.synchronize()
         check(spec, ext, A, B, views[2].double().cpu().numpy(), dtype, C0=C0, alpha=1.5, beta=-1.0)
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_random_complex_contraction(seed):
+    """The same random cases in complex storage (both types), complex alpha and
+    beta, against the complex oracle."""
+    import torch
+    import oracle
+    from paper_1409_8608_amd import workloads as wl
+    rng, spec, ext, dtype, alpha, beta = _draw_case(seed)
+    dtype = "c128" if dtype == "f64" else "c64"
+    alpha = complex(alpha, float(rng.choice([0.0, 0.5, -1.0])))
+    beta = complex(beta, float(rng.choice([0.0, 0.0, 0.25])))
+    print(f"case seed={seed} spec={spec} ext={ext} dtype={dtype} alpha={alpha} beta={beta}", flush=True)
+    A, B = wl.complex_tensors(spec, ext, rng)
+    sc = spec.split("=")[0]
+    shape_c = [ext[ch] for ch in sc]
+    C0 = np.array(rng.uniform(-1, 1, size=shape_c) + 1j * rng.uniform(-1, 1, size=shape_c), dtype=np.complex128,
+                  order="F")
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    views, strides = [], {}
+    for name, x in (("A", A), ("B", B), ("C", C0)):
+        st, span = _layout(list(x.shape), rng)
+        buf = torch.full((span + 8,), complex(np.nan, np.nan), dtype=tdt, device="cuda")
+        v = torch.as_strided(buf, tuple(x.shape), tuple(st))
+        v.copy_(torch.from_numpy(np.array(x, order="C")))
+        views.append(v)
+        strides[name] = st
+    p = tc.Plan(spec, ext, dtype, strides=strides)
+    p.contract(views[0], views[1], views[2], alpha, beta)
+    torch.cuda.synchronize()
+    got = np.array(views[2].cpu().numpy(), dtype=np.complex128)
+
+    def rnd(x):
+        return np.array(x if dtype == "c128" else x.astype(np.complex64), dtype=np.complex128, order="F")
+    ref = oracle.contract(spec, ext, rnd(A), rnd(B), C=rnd(C0), alpha=alpha, beta=beta)
+    err = oracle.normwise_rel_err(got, ref)
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    assert err <= tol, f"normwise error {err:.3e} > {tol:.1e}"
