@@ -179,6 +179,33 @@ static tc_status upload(void** p, int64_t* cap, const std::vector<int64_t>& v) {
 
 namespace tc {
 
+StreamArgs stream_args(const GemmView& gv, bool f64) {
+    StreamArgs a{};
+    a.M = gv.m[0].ext;
+    a.sAm = gv.m[0].sA;
+    a.N = gv.N;
+    a.n.n = (int)gv.n.size();
+    for (int d = 0; d < a.n.n; ++d) a.n.d[d] = gv.n[d];
+    // contracted positions in odometer order (first index fastest)
+    a.K = (int)gv.K;
+    std::vector<int64_t> idx(gv.k.size(), 0);
+    for (int k = 0; k < a.K; ++k) {
+        int64_t oa = 0, ob = 0;
+        for (size_t d = 0; d < gv.k.size(); ++d) {
+            oa += idx[d] * gv.k[d].sA;
+            ob += idx[d] * gv.k[d].sB;
+        }
+        a.kA[k] = oa;
+        a.kB[k] = ob;
+        for (size_t d = 0; d < gv.k.size(); ++d) {
+            if (++idx[d] < gv.k[d].ext) break;
+            idx[d] = 0;
+        }
+    }
+    stream_shape(f64, a);
+    return a;
+}
+
 bool use_stream_kernel(const Spec& s, const GemmView& gv) {
     return gv.K >= 1 && gv.K <= GT_SMALLK_MAX && gv.m.size() == 1 && gv.m[0].sC == 1 && gv.b.empty();
 }
@@ -245,32 +272,10 @@ static tc_status run_fused(tc_plan_s* p, const void* A, const void* B, void* C, 
     if (gv.swapped) std::swap(A, B);
     if (s.compute != TC_NATIVE) return run_split(p, A, B, C, alpha, beta, st);
     if (use_stream_kernel(s, gv)) {
-        StreamArgs a{};
+        StreamArgs a = stream_args(gv, f64);
         a.A = A; a.B = B; a.C = C;
-        a.M = gv.m[0].ext;
-        a.sAm = gv.m[0].sA;
-        a.N = gv.N;
-        a.n.n = (int)gv.n.size();
-        for (int d = 0; d < a.n.n; ++d) a.n.d[d] = gv.n[d];
-        // contracted positions in odometer order (first index fastest)
-        a.K = (int)gv.K;
-        std::vector<int64_t> idx(gv.k.size(), 0);
-        for (int k = 0; k < a.K; ++k) {
-            int64_t oa = 0, ob = 0;
-            for (size_t d = 0; d < gv.k.size(); ++d) {
-                oa += idx[d] * gv.k[d].sA;
-                ob += idx[d] * gv.k[d].sB;
-            }
-            a.kA[k] = oa;
-            a.kB[k] = ob;
-            for (size_t d = 0; d < gv.k.size(); ++d) {
-                if (++idx[d] < gv.k[d].ext) break;
-                idx[d] = 0;
-            }
-        }
         a.alpha = alpha;
         a.beta = beta;
-        stream_shape(f64, a);
         hipError_t e = launch_stream(f64, a, st);
         return e == hipSuccess ? TC_OK : hip_fail(e, "stream kernel launch");
     }

@@ -79,6 +79,9 @@ tc_status hip_fail(hipError_t e, const char* what);
 std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA = 4, bool a_first = false, int G = 0);
 int ktab_vec_flags(const std::vector<int64_t>& tab, int v);
 bool use_stream_kernel(const Spec& s, const GemmView& gv);
+// Shape part of the streaming kernel's arguments (M, N, K tables, threads per
+// row) for a plan that use_stream_kernel accepts; pointers and scalars unset.
+StreamArgs stream_args(const GemmView& gv, bool f64);
 tc_status prepare_plan(tc_plan_s* p);
 tc_status contract_dispatch(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
                             hipStream_t st);

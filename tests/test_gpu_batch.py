@@ -106,3 +106,51 @@ def test_batch_errors():
     with pytest.raises(tc.TcError) as e:
         tc.Batch([ps])
     assert e.value.name == "TC_E_UNSUPPORTED"
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_mixed_members(dtype):
+    """Few and many summed positions, odd M, padded or permuted C, C's unit
+    stride in B, a trace index, with alpha and beta, over two replays with new
+    operands; integer data, exact."""
+    import torch
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    cases = [("abc=ai,ibc", dict(a=37, b=9, c=5, i=3), dict(C=[1, 40, 400])),
+             ("abcd=ai,ibcd", dict(a=130, b=3, c=4, d=5, i=8), None),
+             ("ba=ai,ib", dict(a=17, b=96, i=6), None),
+             ("ab=ai,ibt", dict(a=64, b=33, i=5, t=2), None),
+             ("abc=ai,ibc", dict(a=21, b=30, c=2, i=29), dict(A=[1, 24], C=[2 * 30, 2, 1])),
+             ("abc=ija,jbic", dict(a=40, b=24, c=3, i=6, j=9), None),          # matrix core (K = 54)
+             ("ab=iaj,jbi", dict(a=50, b=45, i=8, j=8), None)]                # matrix core (K = 64)
+    rng = np.random.default_rng(17)
+    plans = [tc.Plan(sp, ex, dtype, strides=st) for sp, ex, st in cases]
+    batch = tc.Batch(plans)
+
+    def views(sp, ex, st, arrays):
+        out = []
+        for name, x in zip("ABC", arrays):
+            strides = (st or {}).get(name)
+            if strides is None:
+                out.append(tc.to_device_fortran(x, tdt))
+                continue
+            span = 1 + sum((n - 1) * s for n, s in zip(x.shape, strides))
+            buf = torch.full((span,), float("nan"), dtype=tdt, device="cuda")
+            v = torch.as_strided(buf, tuple(x.shape), tuple(strides))
+            v.copy_(torch.from_numpy(np.ascontiguousarray(x)))
+            out.append(v)
+        return out
+    for rep in range(2):
+        host, dev = [], []
+        for sp, ex, st in cases:
+            A, B, C0 = wl.tensors(sp, ex, rng, integer=True, with_c=True)
+            host.append((A, B, C0))
+            dev.append(views(sp, ex, st, (A, B, C0)))
+        alphas = [float(rng.choice([1.0, -2.0, 0.5])) for _ in cases]
+        betas = [float(rng.choice([0.0, 1.0, -1.0])) for _ in cases]
+        batch.contract([d[0] for d in dev], [d[1] for d in dev], [d[2] for d in dev], alphas, betas)
+        torch.cuda.synchronize()
+        for (sp, ex, st), (A, B, C0), d, al, be in zip(cases, host, dev, alphas, betas):
+            ref = oracle.contract(sp, ex, A, B, C=np.array(C0, order="F"), alpha=al, beta=be)
+            np.testing.assert_array_equal(d[2].double().cpu().numpy(), ref, err_msg=f"{sp} {ex} replay {rep}")
+    info = batch.info()
+    assert info["members"] == len(cases) and info["tiles"] >= len(cases)
