@@ -206,8 +206,18 @@ StreamArgs stream_args(const GemmView& gv, bool f64) {
     return a;
 }
 
+// The streaming kernel runs contractions with at most 32 summed positions whose
+// C is unit-stride along one free index of an input.  Beyond 8 positions it
+// keeps the job only when M is a whole number of wave spans with A unit-stride
+// along it (the straight-line wave kernel covers all of M): measured on MI355X
+// over 504 small-K contractions with M log-uniform in 8..256, the general
+// streaming kernel took 16.6 ms where matrix-core tiles took 8.6 ms for 9..32
+// positions, and 2.3 ms against 4.1 ms for up to 8.
 bool use_stream_kernel(const Spec& s, const GemmView& gv) {
-    return gv.K >= 1 && gv.K <= GT_SMALLK_MAX && gv.m.size() == 1 && gv.m[0].sC == 1 && gv.b.empty();
+    if (gv.K < 1 || gv.K > GT_SMALLK_MAX || gv.m.size() != 1 || gv.m[0].sC != 1 || !gv.b.empty()) return false;
+    if (gv.K <= 8) return true;
+    const int64_t span = 64 * (s.dtype == TC_F64 ? 2 : 4);
+    return gv.m[0].sA == 1 && gv.M % span == 0;
 }
 
 tc_status prepare_plan(tc_plan_s* p) {

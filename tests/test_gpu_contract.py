@@ -35,7 +35,8 @@ def test_fused_smallk_integer_exact_and_beta():
 # Streaming shapes: M a whole number of wave spans (128 doubles, 256 floats),
 # M with a tail for the general kernel, N of two dimensions that do not merge,
 # K padded up to the kernel's template size (1, 5, 12), K = 32, odd M (no
-# vector path at all), N not a whole number of block column sets.
+# vector path at all), N not a whole number of block column sets.  Beyond 8
+# summed positions only M in whole wave spans streams (else matrix cores).
 STREAM_SHAPES = [
     ("abc=ai,ibc", dict(a=384, b=7, c=5, i=8)),
     ("abc=ai,ibc", dict(a=300, b=9, c=4, i=5)),
@@ -43,8 +44,30 @@ STREAM_SHAPES = [
     ("abc=ai,ibc", dict(a=256, b=3, c=11, i=32)),
     ("ab=ai,ib", dict(a=1024, b=33, i=1)),
     ("abc=ai,ibc", dict(a=129, b=5, c=3, i=7)),
-    ("abc=aij,jibc", dict(a=520, b=3, c=5, i=3, j=4)),
+    ("abc=aij,jibc", dict(a=512, b=3, c=5, i=3, j=4)),
+    ("abc=aij,jibc", dict(a=520, b=3, c=5, i=3, j=4)),           # 12 positions, ragged M: matrix cores
 ]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("K", [12, 32])
+def test_fused_stream_general_kernel_misaligned(dtype, K):
+    """M in whole wave spans but A starting one element into its allocation:
+    the wave kernel needs 16-byte rows, so the general streaming kernel (9..32
+    positions) covers all of M."""
+    import torch
+    spec, ext = "abc=ai,ibc", dict(a=256, b=5, c=7, i=K)
+    A, B, C0 = wl.tensors(spec, ext, np.random.default_rng(9), integer=True, with_c=True)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    p = _plan(spec, ext, dtype)
+    store = torch.zeros(1 + 256 * K, dtype=tdt, device="cuda")
+    dA = torch.as_strided(store, (256, K), (1, 256), 1)
+    dA.copy_(torch.from_numpy(A))
+    dB = tc.to_device_fortran(B, tdt)
+    dC = tc.to_device_fortran(C0, tdt)
+    p.contract(dA, dB, dC, 2.0, -1.0)
+    torch.cuda.synchronize()
+    check(spec, ext, A, B, dC.double().cpu().numpy(), dtype, C0=C0, alpha=2.0, beta=-1.0, exact=True)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
