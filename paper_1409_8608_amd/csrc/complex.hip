@@ -216,6 +216,7 @@ static int zstream_vec(const tc_plan_s* p) {
     const bool f64 = p->spec.dtype == TC_C128;
     const int cpc = zvec_narrow(f64);
     if (gv.K < 1 || gv.K > 16 || gv.m.size() != 1 || !gv.b.empty()) return 0;
+    if ((int)gv.n.size() > GT_MAXD || (int)gv.k.size() > GT_MAXD) return 0;   // launch descriptor sizes
     if (gv.m[0].sC != 1 || gv.m[0].sA != 1) return 0;
     for (const GtDim& d : gv.n)
         if (d.sC % cpc != 0) return 0;
