@@ -273,10 +273,10 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n);
  * micro-benchmarks (one wave of tiles per shape and contracted-length bucket)
  * ranks the shapes, the best `top_k` are timed on the device one member at a
  * time and the fastest is kept.  The whole batch is then timed with the new
- * shapes against the previous ones (graph replays), and the previous shapes
- * stay if they are faster.  Uses -- and overwrites C with
- * alpha * contract(A, B) of -- the operands of the previous tc_batch_contract,
- * which must have been made.  Synchronous.  The share of members whose
+ * shapes against the previous ones (graph replays), and the new shapes are
+ * kept only if they beat two timings of the previous ones.  Uses -- and
+ * overwrites C with alpha * contract(A, B) of -- the operands of the previous
+ * tc_batch_contract, which must have been made.  Synchronous.  The share of members whose
  * estimated-best shape measured within 5% of the best is reported by
  * tc_batch_info. */
 tc_status tc_batch_tune(tc_batch_t batch, int top_k);

@@ -327,13 +327,13 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
         }
         hipError_t err = hipGraphLaunch(b->exec, st);   // warm-up
         if (err == hipSuccess) err = hipEventRecord(t0, st);
-        for (int r = 0; r < 3 && err == hipSuccess; ++r) err = hipGraphLaunch(b->exec, st);
+        for (int r = 0; r < 5 && err == hipSuccess; ++r) err = hipGraphLaunch(b->exec, st);
         if (err == hipSuccess) err = hipEventRecord(t1, st);
         if (err == hipSuccess) err = hipEventSynchronize(t1);
         float ms = 0;
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, t0, t1);
         if (err != hipSuccess) return hip_fail(err, "batch timing replays");
-        *out = ms / 3.0;
+        *out = ms / 5.0;
         return TC_OK;
     };
     double before_ms = 0.0;
@@ -433,15 +433,25 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
     b->n_tuned = n;
     // Members timed alone favour small tiles (more parallelism on an idle
     // device); inside the batch that need not hold, so the whole batch is
-    // timed with the new shapes and the previous ones are kept if faster.
-    drop_graph(b);
-    tc_status ts = build_groups(b);
+    // timed with the new shapes and the previous ones are kept unless the new
+    // ones are faster than both timings of the previous ones (replay times
+    // drift by a few percent, as much as a change of shapes gains or loses).
+    const std::vector<int> new_shape = b->shape;
+    auto use = [&](const std::vector<int>& shp) {
+        b->shape = shp;
+        drop_graph(b);
+        return build_groups(b);
+    };
+    tc_status ts = use(new_shape);
     double after_ms = 0.0;
     if (!ts) ts = time_graph(&after_ms);
-    if (!ts && after_ms > before_ms) {
-        b->shape = old_shape;
-        drop_graph(b);
-        ts = build_groups(b);
+    if (!ts && after_ms < before_ms) {
+        double again_ms = 0.0;
+        ts = use(old_shape);
+        if (!ts) ts = time_graph(&again_ms);
+        if (!ts && after_ms < again_ms) ts = use(new_shape);
+    } else if (!ts) {
+        ts = use(old_shape);
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
