@@ -12,8 +12,10 @@ Printed: ONE JSON line with the headline value plus
   cpu_baseline  the FP64 oracle (plain C loop nest, one core) on a bounded
                 slab of the same workload
   forms         the other forms of the metric on the same GPU, each with its
-                own roofline: FP64/FP32 fused permuted contraction, split-BF16
-                matrix product, batched launch (when built)
+                own roofline: FP64/FP32 fused permuted contraction, FP64/FP32
+                and split-BF16/FP8 matrix products, batched launch, complex
+                storage; their sampled error columns compare against an FP64
+                numpy.einsum of the sampled slices
 """
 from __future__ import annotations
 
@@ -32,6 +34,36 @@ FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 FP8_PEAK_TFS = 5000.0        # MI355X dense FP8 matrix peak (TFLOP/s)
 BF16_PEAK_TFS = 2500.0
+
+
+def _split(spec):
+    out, ins = spec.split("=")
+    a, b = ins.split(",")
+    return a, b, out
+
+
+def _flops(spec, ext):
+    """2 x the product of all extents: one multiply and one add per term."""
+    n = 2
+    for ch in set(spec.replace("=", "").replace(",", "")):
+        n *= int(ext[ch])
+    return n
+
+
+def _einsum_ref(spec, A, B):
+    """Reference for the sampled error columns of the forms: numpy.einsum in
+    FP64 (complex128 for complex data) on the sampled slices."""
+    import numpy as np
+    a, b, out = _split(spec)
+    return np.einsum(f"{a},{b}->{out}", A, B, optimize=True)
+
+
+def _normwise(got, ref):
+    import numpy as np
+    got = np.asarray(got)
+    d = np.linalg.norm((got.astype(np.result_type(got, np.float64)) - ref).ravel())
+    n = np.linalg.norm(np.asarray(ref).ravel())
+    return float(d / n) if n else float(d)
 
 
 def _events_time(fn, steps, warmup, torch):
@@ -184,7 +216,6 @@ def batched(args, torch, tc, wl, dtype):
     tc_contract per member on one stream versus one graph replay (before and
     after tuning).  Device data from a seeded torch generator (uniform[-1,1])."""
     import numpy as np
-    import oracle
     shapes, redraws = wl.batch_shapes(4096)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     es = 8 if dtype == "f64" else 4
@@ -199,7 +230,7 @@ def batched(args, torch, tc, wl, dtype):
         B = tc.empty_fortran(p.shape("B"), tdt).uniform_(-1, 1, generator=gen)
         C = tc.empty_fortran(p.shape("C"), tdt)
         As.append(A); Bs.append(B); Cs.append(C)
-        flops += oracle.flops(it["spec"], it["ext"])
+        flops += _flops(it["spec"], it["ext"])
         bytes_ += es * (A.numel() + B.numel() + C.numel())
     for p in plans:
         p.prepare()
@@ -221,8 +252,8 @@ def batched(args, torch, tc, wl, dtype):
     worst = 0.0
     for t in rng.choice(len(plans), 6, replace=False):
         it = shapes[t]
-        ref = oracle.contract(it["spec"], it["ext"], As[t].double().cpu().numpy(), Bs[t].double().cpu().numpy())
-        worst = max(worst, oracle.normwise_rel_err(Cs[t].double().cpu().numpy(), ref))
+        ref = _einsum_ref(it["spec"], As[t].double().cpu().numpy(), Bs[t].double().cpu().numpy())
+        worst = max(worst, _normwise(Cs[t].double().cpu().numpy(), ref))
     peak = FP64_PEAK_TFS if dtype == "f64" else FP32_PEAK_TFS
     bound_ms = max(flops / (peak * 1e12), bytes_ / (HBM_PEAK_GBS * 1e9)) * 1e3
     rec = dict(workload="4096 contractions from {abc=ai,ibc; abc=ija,jbic; ab=iaj,jbi; abcd=ai,ibcd}, free extents "
@@ -245,19 +276,18 @@ def batched(args, torch, tc, wl, dtype):
 def complex_forms(args, torch, tc, wl):
     """Complex storage: the headline shape (streamed C, few summed positions)
     and a square product (matrix cores through the real embedding), each with
-    sampled outputs against the oracle."""
+    sampled outputs against an FP64 einsum of the sampled slices."""
     import numpy as np
-    import oracle
     res = {}
     rng = np.random.default_rng(5)
     for name, w in (("smallk", wl.complex_smallk(1024, 8)), ("square", wl.complex_square(4096))):
         ext = w["ext"]
-        sa, sb, sc = oracle.split_spec(w["spec"])
+        sa, sb, sc = _split(w["spec"])
         picks = {ch: np.sort(rng.choice(ext[ch], min(ext[ch], 8), replace=False)) for ch in sc}
         sub = dict(ext, **{ch: len(v) for ch, v in picks.items()})
         Asub = w["A"][np.ix_(*[picks.get(ch, np.arange(ext[ch])) for ch in sa])]
         Bsub = w["B"][np.ix_(*[picks.get(ch, np.arange(ext[ch])) for ch in sb])]
-        ref = oracle.contract(w["spec"], sub, np.asfortranarray(Asub), np.asfortranarray(Bsub))
+        ref = _einsum_ref(w["spec"], Asub, Bsub)
         for dt, tdt, cb, peak in (("c128", torch.complex128, 16, FP64_PEAK_TFS),
                                   ("c64", torch.complex64, 8, FP32_PEAK_TFS)):
             plan = tc.Plan(w["spec"], ext, dt)
@@ -272,10 +302,9 @@ def complex_forms(args, torch, tc, wl):
             for ax, ix in enumerate(idx):
                 got = got.index_select(ax, ix)
             got = got.cpu().numpy().astype(np.complex128)
-            refd = ref if dt == "c128" else oracle.contract(
-                w["spec"], sub, np.asfortranarray(Asub.astype(np.complex64).astype(np.complex128)),
-                np.asfortranarray(Bsub.astype(np.complex64).astype(np.complex128)))
-            err = oracle.normwise_rel_err(got, refd)
+            refd = ref if dt == "c128" else _einsum_ref(w["spec"], Asub.astype(np.complex64).astype(np.complex128),
+                                                        Bsub.astype(np.complex64).astype(np.complex128))
+            err = _normwise(got, refd)
             n_all = {t: int(np.prod([ext[ch] for ch in lets])) for t, lets in (("A", sa), ("B", sb), ("C", sc))}
             flops = 8 * int(np.prod([ext[ch] for ch in set(sa + sb + sc)]))
             rec = dict(workload=f"{w['spec']} " + ", ".join(f"{k}={v}" for k, v in ext.items()) +
@@ -299,22 +328,19 @@ def complex_forms(args, torch, tc, wl):
 
 def precision(args, torch, tc, wl):
     import numpy as np
-    import oracle
     res = {}
     w = wl.scaled_matrix(4096, 64)
     fl = 2 * 4096 * 4096 * 64 * 64
     rng = np.random.default_rng(7)
     rows = np.sort(rng.choice(4096, 24, replace=False))
     cols = np.sort(rng.choice(4096, 24, replace=False))
-    ext_s = dict(a=len(rows), b=len(cols), i=64, j=64)
-    ref = oracle.contract(w["spec"], ext_s, np.asfortranarray(w["A"][:, rows, :]),
-                          np.asfortranarray(w["B"][:, cols, :]))
+    ref = _einsum_ref(w["spec"], w["A"][:, rows, :], w["B"][:, cols, :])
     dA = tc.to_device_fortran(w["A"], torch.float64)
     dB = tc.to_device_fortran(w["B"], torch.float64)
     base_ms = None
     # FP64 plain, FP32 plain (FP32-rounded inputs, FP32 matrix cores), and the
-    # split-BF16 and split-FP8 forms on the FP64 inputs; errors against the
-    # FP64 oracle
+    # split-BF16 and split-FP8 forms on the FP64 inputs; errors against an
+    # FP64 einsum of the sampled slices
     for name, dtype, compute, peak in (("fp64", "f64", "native", FP64_PEAK_TFS),
                                        ("fp32", "f32", "native", FP32_PEAK_TFS),
                                        ("bf16x3", "f64", "bf16x3", BF16_PEAK_TFS),
@@ -326,7 +352,7 @@ def precision(args, torch, tc, wl):
         dC = tc.empty_fortran(plan.shape("C"), tdt)
         ms, _ = _events_time(lambda: plan.contract(xA, xB, dC), 10, max(1, args.warmup // 5), torch)
         got = dC[torch.as_tensor(rows, device="cuda")][:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
-        err = oracle.normwise_rel_err(got, ref)
+        err = _normwise(got, ref)
         tfs = fl / (ms * 1e-3) / 1e12
         executed = fl * (6 if compute != "native" else 1)
         rec = dict(workload="C_ab = A_iaj B_jbi, a=b=4096, i=j=64, normal(0,1) x logU[1e-3,1e3] per slice",
