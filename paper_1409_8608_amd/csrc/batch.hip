@@ -8,8 +8,8 @@
 // area).  The first tc_batch_contract captures a graph: a staging kernel that
 // copies the call's pointers and scalars from pinned host memory, a kernel
 // that zeroes the work counters (no memset nodes), and one persistent kernel
-// per group whose blocks take tiles off the group's counter.  Later calls
-// replay the graph.
+// per group whose blocks take tiles off the group's counter, the groups spread
+// over up to four graph branches.  Later calls replay the graph.
 //
 // tc_batch_tune chooses each contraction's tile shape.  Seed: micro-benchmarks
 // time one full wave of tiles for each shape and contracted-length bucket, and
@@ -52,6 +52,8 @@ struct tc_batch_s {
     int* d_counters = nullptr;
     int64_t* d_ktab = nullptr;       // all K tables, concatenated
     hipStream_t cap = nullptr;
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};   // capture branches (default priority)
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -148,11 +150,22 @@ static tc_status capture(tc_batch_s* b) {
     if (e != hipSuccess) return hip_fail(e, "begin capture");
     hipLaunchKernelGGL(k_stage, dim3((n + 255) / 256), dim3(256), 0, b->cap, b->h_ptrs, b->d_ptrs, n);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, b->cap, b->d_counters, (int)b->groups.size());
-    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    // the groups are independent: up to four branches of the graph, so that one
+    // group's tail overlaps the next group's blocks
+    const int nb = (int)std::min<size_t>(4, b->groups.size());
+    if (nb > 1 && e == hipSuccess) e = hipEventRecord(b->fork, b->cap);
+    for (int q = 1; q < nb && e == hipSuccess; ++q) e = hipStreamWaitEvent(b->side[q - 1], b->fork, 0);
+    for (size_t gi = 0; gi < b->groups.size() && e == hipSuccess; ++gi) {
         BatchGroup& g = b->groups[gi];
+        const int q = (int)(gi % nb);
+        hipStream_t st = q == 0 ? b->cap : b->side[q - 1];
         hipError_t le = launch_mfma_batch(g.f64, g.shape, g.ak, g.bk, b->d_items, b->d_ptrs, g.d_work,
-                                          (int)g.work.size(), b->d_counters + gi, g.grid, b->cap);
+                                          (int)g.work.size(), b->d_counters + gi, g.grid, st);
         if (le != hipSuccess) e = le;
+    }
+    for (int q = 1; q < nb && e == hipSuccess; ++q) {
+        e = hipEventRecord(b->join[q - 1], b->side[q - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[q - 1], 0);
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
@@ -233,6 +246,9 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
     if (e == hipSuccess) e = hipMalloc(&b->d_ptrs, sizeof(BatchPtrs) * std::max(1, n));
     if (e == hipSuccess) e = hipHostMalloc(&b->h_ptrs, sizeof(BatchPtrs) * std::max(1, n), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipStreamCreateWithFlags(&b->side[q], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreateWithFlags(&b->join[q], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
     if (e != hipSuccess) {
         tc_batch_destroy(b);
@@ -258,6 +274,11 @@ tc_status tc_batch_destroy(tc_batch_t b) {
     if (b->h_ptrs) (void)hipHostFree(b->h_ptrs);
     if (b->d_ktab) (void)hipFree(b->d_ktab);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int q = 0; q < 3; ++q) {
+        if (b->side[q]) (void)hipStreamDestroy(b->side[q]);
+        if (b->join[q]) (void)hipEventDestroy(b->join[q]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->done) (void)hipEventDestroy(b->done);
     delete b;
     return TC_OK;
