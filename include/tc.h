@@ -286,7 +286,7 @@ tc_status tc_batch_tune(tc_batch_t batch, int top_k);
  * tensors, borrowed as in tc_contract; alpha_t must be non-zero).  The first
  * call (and the first after tc_batch_tune) captures a HIP graph -- pointer
  * staging from pinned host memory, counter reset, one persistent kernel per
- * group -- later calls replay it on `stream`.  The call waits for the
+ * group on up to four graph branches -- later calls replay it on `stream`.  The call waits for the
  * previous replay of this batch before restaging pointers.
  * Errors: TC_E_NULL, TC_E_ALIAS, TC_E_UNSUPPORTED, TC_E_HIP. */
 tc_status tc_batch_contract(tc_batch_t batch, const void* const* A, const void* const* B,
