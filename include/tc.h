@@ -246,7 +246,8 @@ tc_status tc_set_root_gap(tc_plan_t plan, const int64_t* gap);
  * plans run since that tensor was last used (by an earlier plan of the chain,
  * or else by plan j's own previous run), leaving out plan j's own tensors,
  * which the walk counts already; sizes are element counts times element bytes,
- * converted to plan j's elements.  Calls tc_set_root_gap on every plan.
+ * converted to plan j's elements.  Calls tc_set_root_gap on every plan; a plan
+ * listed more than once keeps the gaps of its last position.
  * Host only.  Errors: TC_E_NULL. */
 tc_status tc_chain_root_gaps(const tc_plan_t* plans, const int* ids, int n);
 
