@@ -114,7 +114,7 @@ def headline(args, torch, tc, wl):
                     flops=flops, algorithmic_bytes=bytes_alg),
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
-                      kernel="k_stream_wave<double,8,2,4,64,false>"),
+                      kernel="k_stream_wave<double,8,2,8,64,false>"),
         finite=ok,
     )
     del dC
