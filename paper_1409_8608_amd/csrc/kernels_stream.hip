@@ -218,10 +218,12 @@ constexpr int kWaveTpr = 64;
 // columns per thread row: four for K <= 8, fewer for larger K (registers)
 static int stream_r(int K) { return K <= 8 ? 4 : K <= 16 ? 2 : 1; }
 
-// columns per wave of k_stream_wave: eight for 5..8 positions (measured at
-// n = 1024, i = 8: 1.339 ms against 1.378 ms with four, each wave reading its A
-// rows once for twice the stores), else as the general kernel
-static int wave_r(int K) { return K > 4 && K <= 8 ? 8 : stream_r(K); }
+// columns per wave of k_stream_wave, measured at a = b = c = 1024 (FP64):
+// four for up to 4 positions (eight: 2-3% slower), eight for 5..8 (1.339 ms
+// against 1.378 ms with four), four for 9..16 (2.61 ms against 3.06 ms with
+// two), one beyond; more columns per wave read each wave's A rows once for
+// more stores
+static int wave_r(int K) { return K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 4 : 1; }
 
 void stream_shape(bool f64, StreamArgs& a) {
     const int VEC = f64 ? 2 : 4;
@@ -243,7 +245,7 @@ static void launch_wave(const T* A, const T* B, T* C, const StreamArgs& w, unsig
     dim3 g(grid), b(256);
     if (w.K <= 4) hipLaunchKernelGGL((k_stream_wave<T, 4, VEC, 4, kWaveTpr, BETA>), g, b, 0, st, A, B, C, w);
     else if (w.K <= 8) hipLaunchKernelGGL((k_stream_wave<T, 8, VEC, 8, kWaveTpr, BETA>), g, b, 0, st, A, B, C, w);
-    else if (w.K <= 16) hipLaunchKernelGGL((k_stream_wave<T, 16, VEC, 2, kWaveTpr, BETA>), g, b, 0, st, A, B, C, w);
+    else if (w.K <= 16) hipLaunchKernelGGL((k_stream_wave<T, 16, VEC, 4, kWaveTpr, BETA>), g, b, 0, st, A, B, C, w);
     else hipLaunchKernelGGL((k_stream_wave<T, 32, VEC, 1, kWaveTpr, BETA>), g, b, 0, st, A, B, C, w);
 }
 
