@@ -206,15 +206,17 @@ StreamArgs stream_args(const GemmView& gv, bool f64) {
     return a;
 }
 
-// The streaming kernel runs contractions with at most 32 summed positions whose
-// C is unit-stride along one free index of an input.  Beyond 8 positions it
-// keeps the job only when M is a whole number of wave spans with A unit-stride
-// along it (the straight-line wave kernel covers all of M): measured on MI355X
-// over 504 small-K contractions with M log-uniform in 8..256, the general
-// streaming kernel took 16.6 ms where matrix-core tiles took 8.6 ms for 9..32
-// positions, and 2.3 ms against 4.1 ms for up to 8.
+// The streaming kernel runs contractions whose C is unit-stride along one free
+// index of an input, with at most 8 summed positions, or 9..16 where M is a
+// whole number of wave spans with A unit-stride along it (the straight-line
+// wave kernel then covers all of M).  Matrix-core tiles take the rest.
+// Measured on MI355X: over 504 small-K contractions with M log-uniform in
+// 8..256, the general streaming kernel took 2.3 ms against 4.1 ms for up to 8
+// positions and 16.6 ms against 8.6 ms for 9..32; at a = b = c = 1024 the wave
+// kernel took 2.49-2.61 ms against 3.33 ms for 12..16 positions (FP64) and
+// 7.8-8.2 ms against 4.0 ms for 24..32 (FP32: 6.6-7.1 against 1.9).
 bool use_stream_kernel(const Spec& s, const GemmView& gv) {
-    if (gv.K < 1 || gv.K > GT_SMALLK_MAX || gv.m.size() != 1 || gv.m[0].sC != 1 || !gv.b.empty()) return false;
+    if (gv.K < 1 || gv.K > 16 || gv.m.size() != 1 || gv.m[0].sC != 1 || !gv.b.empty()) return false;
     if (gv.K <= 8) return true;
     const int64_t span = 64 * (s.dtype == TC_F64 ? 2 : 4);
     return gv.m[0].sA == 1 && gv.M % span == 0;
