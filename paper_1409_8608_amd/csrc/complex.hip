@@ -184,9 +184,6 @@ __global__ __launch_bounds__(256) void k_zstream_wave(const T* __restrict__ A, c
     }
 }
 
-// Columns per wave: registers hold 2 R KT values of B and 2 VEC KT of A.
-static int zstream_r(int K) { return K <= 8 ? 4 : 2; }
-
 template <typename T, int W, bool BETA>
 static void launch_zstream(const StreamArgs& w, double alpha_im, double beta_im, unsigned grid, hipStream_t st) {
     const T* A = (const T*)w.A;
@@ -195,10 +192,8 @@ static void launch_zstream(const StreamArgs& w, double alpha_im, double beta_im,
     dim3 g(grid), b(256);
     if (w.K <= 4)
         hipLaunchKernelGGL((k_zstream_wave<T, 4, W, 4, BETA>), g, b, 0, st, A, B, C, w, alpha_im, beta_im);
-    else if (w.K <= 8)
+    else
         hipLaunchKernelGGL((k_zstream_wave<T, 8, W, 4, BETA>), g, b, 0, st, A, B, C, w, alpha_im, beta_im);
-    else if constexpr (W == 1)   // 16 positions: one chunk per lane only (registers)
-        hipLaunchKernelGGL((k_zstream_wave<T, 16, 1, 2, BETA>), g, b, 0, st, A, B, C, w, alpha_im, beta_im);
 }
 
 // Complex elements per lane: a wide form (two 16-byte chunks, twice the
@@ -206,7 +201,9 @@ static void launch_zstream(const StreamArgs& w, double alpha_im, double beta_im,
 static int zvec_narrow(bool f64) { return f64 ? 1 : 2; }
 
 // The complex streaming kernel takes a plan whose complex GEMM view has at most
-// 16 summed positions, one M dimension with unit stride in C and in A (after
+// 8 summed positions (beyond that the embedding on matrix-core tiles is faster:
+// at a = b = c = 1024 with 12 or 16 positions 8.05 ms against 8.9-9.4 ms for
+// c128, 3.75 against 4.1-4.5 ms for c64), one M dimension with unit stride in C and in A (after
 // the swap that puts C's unit stride in M), no batch indices, M a whole number
 // of wave spans (64 VEC), and every N stride of C and K stride of A a multiple
 // of a chunk's complex elements.  Returns the widest VEC that fits, 0 if none;
@@ -215,7 +212,7 @@ static int zstream_vec(const tc_plan_s* p) {
     const GemmView& gv = p->gv;
     const bool f64 = p->spec.dtype == TC_C128;
     const int cpc = zvec_narrow(f64);
-    if (gv.K < 1 || gv.K > 16 || gv.m.size() != 1 || !gv.b.empty()) return 0;
+    if (gv.K < 1 || gv.K > 8 || gv.m.size() != 1 || !gv.b.empty()) return 0;
     if ((int)gv.n.size() > GT_MAXD || (int)gv.k.size() > GT_MAXD) return 0;   // launch descriptor sizes
     if (gv.m[0].sC != 1 || gv.m[0].sA != 1) return 0;
     for (const GtDim& d : gv.n)
@@ -233,8 +230,7 @@ static tc_status run_zstream(tc_plan_s* p, const void* A, const void* B, void* C
     const bool f64 = p->spec.dtype == TC_C128;
     *ran = false;
     if (gv.swapped) std::swap(A, B);
-    int vec = p->zvec;
-    if (gv.K > 8) vec = zvec_narrow(f64);
+    const int vec = p->zvec;
     // every access is one 16-byte chunk: A and C must start on 16 bytes
     if (((uintptr_t)A) % 16 != 0 || ((uintptr_t)C) % 16 != 0) return TC_OK;
     StreamArgs w{};
@@ -265,7 +261,7 @@ static tc_status run_zstream(tc_plan_s* p, const void* A, const void* B, void* C
     }
     w.alpha = alpha_re;
     w.beta = beta_re;
-    const int64_t cols = 4 * (int64_t)zstream_r(w.K);
+    const int64_t cols = 4 * 4;   // four waves of four columns (R = 4 in every launch above)
     const int64_t grid = (gv.M / (64 * vec)) * ((gv.N + cols - 1) / cols);
     if (grid > 0x7fffffff) return TC_OK;
     const bool beta = beta_re != 0.0 || beta_im != 0.0;

@@ -204,10 +204,11 @@ def test_complex_predict_and_workspace():
 
 # Complex streaming kernel: M a whole number of wave spans along C's unit
 # stride (narrow lanes: 64 complex doubles, 128 complex floats; wide lanes:
-# twice that), at most 16 summed positions (template sizes 4, 8 and 16), N not
-# a multiple of the block's columns, two summed dims, C's unit stride in B
-# (operands swapped), a trace index, an outer product, and padded operands
-# (M = 128 takes the narrow form of complex floats, M = 256 the wide one).
+# twice that), at most 8 summed positions (template sizes 4 and 8; the 12- and
+# 16-position cases take the embedding), N not a multiple of the block's
+# columns, two summed dims, C's unit stride in B (operands swapped), a trace
+# index, an outer product, and padded operands (M = 128 takes the narrow form of
+# complex floats, M = 256 the wide one).
 ZSTREAM_CASES = [
     ("abc=ai,ibc", dict(a=128, b=20, c=3, i=8), None),
     ("abc=ai,ibc", dict(a=256, b=9, c=5, i=3), None),
