@@ -213,6 +213,28 @@ tc_status tc_contract_complex(tc_plan_t plan, const void* A, const void* B, void
  * device.  Errors: TC_E_UNSUPPORTED (no split yet), TC_E_VARIANT (bad side). */
 tc_status tc_split_terms(tc_plan_t plan, int side, void* terms, int32_t* exps, int64_t* rows, int64_t* kp);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tc_contract
+ * with the fused kernel, whose device buffers beyond A, B and C (the
+ * matrix-core kernel's table of contracted positions, 16 bytes per position,
+ * and its split-K partial tiles) live in a static device array of
+ * TC_NOALLOC_SCRATCH_BYTES that each GPU holds from the library's load to the
+ * end of the process.  The call makes no device allocation of any kind (and
+ * does not touch the plan's own workspace); the table is copied host to device
+ * on `stream` (hipMemcpyAsync) before the launch.  Every call on one GPU shares
+ * that GPU's array and overwrites it: calls that overlap on one GPU (streams
+ * with no ordering between them) race, so order them on one stream.  Same
+ * semantics and checks as tc_contract.  Needs a real plan, the native compute
+ * mode and the fused kernel selected (the default); the streaming kernel (few
+ * summed positions) needs no scratch.  A split-K choice is limited to what fits
+ * in the array beside the table (fewer slices, down to none).
+ * Errors: as tc_contract; TC_E_UNSUPPORTED for a complex or split-precision
+ * plan, a member variant selected, or a table of contracted positions larger
+ * than the array (more than TC_NOALLOC_SCRATCH_BYTES / 16 positions). */
+#define TC_NOALLOC_SCRATCH_BYTES (64LL << 20)
+tc_status tc_contract_noalloc(tc_plan_t plan, const void* A, const void* B, void* C,
+                              double alpha, double beta, void* stream);
+
 /* --- performance prediction (Section 3) ----------------------------------- */
 
 /* Access distance, in elements, of kernel operand `tensor` (0 = A, 1 = B,

@@ -28,7 +28,7 @@ EXPORTS = ("tc_plan", "tc_plan_destroy", "tc_variant_count", "tc_variant_get", "
            "tc_plan_prepare", "tc_plan_workspace", "tc_contract", "tc_contract_complex", "tc_access_distance", "tc_bench_classes",
            "tc_predict", "tc_batch_create", "tc_batch_tune", "tc_batch_contract", "tc_batch_destroy",
            "tc_batch_info", "tc_split_terms", "tc_status_str", "tc_last_error", "tc_set_root_gap",
-           "tc_chain_root_gaps")
+           "tc_chain_root_gaps", "tc_contract_noalloc")
 
 
 class TcError(RuntimeError):
@@ -83,6 +83,7 @@ def _load():
         "tc_plan_workspace": [P, I64P],
         "tc_contract": [P, P, P, P, D, D, P],
         "tc_contract_complex": [P, P, P, P, D, D, D, D, P],
+        "tc_contract_noalloc": [P, P, P, P, D, D, P],
         "tc_access_distance": [P, ctypes.c_int, ctypes.c_int, I64P],
         "tc_bench_classes": [P, ctypes.c_int, ctypes.c_int, D, ctypes.c_int, ctypes.POINTER(tc_bench_class),
                              ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
@@ -171,6 +172,12 @@ def tc_plan_workspace(h) -> int:
 def tc_contract(h, A_ptr: int, B_ptr: int, C_ptr: int, alpha: float = 1.0, beta: float = 0.0, stream: int = 0):
     _check(lib.tc_contract(h, A_ptr or None, B_ptr or None, C_ptr or None, float(alpha), float(beta),
                            stream or None))
+
+
+def tc_contract_noalloc(h, A_ptr: int, B_ptr: int, C_ptr: int, alpha: float = 1.0, beta: float = 0.0,
+                        stream: int = 0):
+    _check(lib.tc_contract_noalloc(h, A_ptr or None, B_ptr or None, C_ptr or None, float(alpha), float(beta),
+                                   stream or None))
 
 
 def tc_contract_complex(h, A_ptr: int, B_ptr: int, C_ptr: int, alpha: complex = 1.0, beta: complex = 0.0,

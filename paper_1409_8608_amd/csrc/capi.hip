@@ -275,22 +275,26 @@ static const char* ptr_add(const void* p, int64_t elems, int esize) {
     return (const char*)p + elems * esize;
 }
 
-// The fused direct contraction: one launch.
-static tc_status run_fused(tc_plan_s* p, const void* A, const void* B, void* C, double alpha,
-                           double beta, hipStream_t st) {
-    const Spec& s = p->spec;
+// The fused direct contraction on the streaming kernel (few summed positions;
+// the K offsets travel in the launch arguments).  A and B in GEMM-view order.
+tc_status launch_fused_stream(const tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
+                              hipStream_t st) {
+    StreamArgs a = stream_args(p->gv, p->spec.dtype == TC_F64);
+    a.A = A; a.B = B; a.C = C;
+    a.alpha = alpha;
+    a.beta = beta;
+    hipError_t e = launch_stream(p->spec.dtype == TC_F64, a, st);
+    return e == hipSuccess ? TC_OK : hip_fail(e, "stream kernel launch");
+}
+
+// The fused direct contraction on matrix-core tiles, with the K table and the
+// split-K partial tiles given by the caller (the plan's workspace, or the
+// no-allocation entry point's scratch).  A and B are in GEMM-view order.
+tc_status launch_fused_mfma(const tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
+                            const int64_t* ktab, int64_t kpad, int kvec, void* ws, int64_t kslices,
+                            int64_t kslice_tiles, hipStream_t st) {
     const GemmView& gv = p->gv;
-    bool f64 = s.dtype == TC_F64;
-    if (gv.swapped) std::swap(A, B);
-    if (s.compute != TC_NATIVE) return run_split(p, A, B, C, alpha, beta, st);
-    if (use_stream_kernel(s, gv)) {
-        StreamArgs a = stream_args(gv, f64);
-        a.A = A; a.B = B; a.C = C;
-        a.alpha = alpha;
-        a.beta = beta;
-        hipError_t e = launch_stream(f64, a, st);
-        return e == hipSuccess ? TC_OK : hip_fail(e, "stream kernel launch");
-    }
+    const bool f64 = p->spec.dtype == TC_F64;
     MfmaArgs a{};
     a.A = A; a.B = B; a.C = C;
     a.m.n = (int)gv.m.size();
@@ -304,20 +308,32 @@ static tc_status run_fused(tc_plan_s* p, const void* A, const void* B, void* C, 
         a.nbatch *= gv.b[d].ext;
     }
     a.pass.n = 0;
-    a.ktab = (const int64_t*)p->d_ktab;
-    a.kvec = p->kvec;
-    if (p->kslices > 1) {
-        a.ws = p->d_splitk;
-        a.kslices = p->kslices;
-        a.kslice_tiles = p->kslice_tiles;
+    a.ktab = ktab;
+    a.kvec = kvec;
+    if (kslices > 1) {
+        a.ws = ws;
+        a.kslices = kslices;
+        a.kslice_tiles = kslice_tiles;
     }
-    a.M = gv.M; a.N = gv.N; a.Kpad = p->kpad;
+    a.M = gv.M; a.N = gv.N; a.Kpad = kpad;
     a.npass = 1;
     a.alpha = alpha; a.beta = beta;
     a.mode = 0;
     mfma_tiles(f64, a);
     hipError_t e = launch_mfma(f64, a, st);
     return e == hipSuccess ? TC_OK : hip_fail(e, "mfma kernel launch");
+}
+
+// The fused direct contraction: one launch (two with split K).
+static tc_status run_fused(tc_plan_s* p, const void* A, const void* B, void* C, double alpha,
+                           double beta, hipStream_t st) {
+    const Spec& s = p->spec;
+    const GemmView& gv = p->gv;
+    if (gv.swapped) std::swap(A, B);
+    if (s.compute != TC_NATIVE) return run_split(p, A, B, C, alpha, beta, st);
+    if (use_stream_kernel(s, gv)) return launch_fused_stream(p, A, B, C, alpha, beta, st);
+    return launch_fused_mfma(p, A, B, C, alpha, beta, (const int64_t*)p->d_ktab, p->kpad, p->kvec, p->d_splitk,
+                             p->kslices, p->kslice_tiles, st);
 }
 
 tc_status run_variant(tc_plan_s* p, int v, const void* A, const void* B, void* C, double alpha,
@@ -435,6 +451,35 @@ tc_status contract_dispatch(tc_plan_s* p, const void* A, const void* B, void* C,
     return run_variant(p, v, A, B, C, alpha, beta, st);
 }
 
+}  // namespace tc
+
+namespace tc {
+// Checks of a contraction call made before any device work: NULL pointers and
+// aliasing of C with an input that is read.  Sets *runs to false when the call
+// has nothing to compute (an empty C).
+tc_status validate_call(const tc_plan_s* p, const void* A, const void* B, const void* C, double alpha_re,
+                        double alpha_im, double beta_im, bool* runs) {
+    if (!p) return fail(TC_E_NULL, "plan is NULL");
+    const Spec& s = p->spec;
+    if (!s.is_complex() && (alpha_im != 0.0 || beta_im != 0.0))
+        return fail(TC_E_UNSUPPORTED, "complex alpha or beta on a real plan");
+    int64_t K = 1;
+    for (char ch : s.summed()) K *= s.e(ch);
+    bool reads_inputs = (alpha_re != 0.0 || alpha_im != 0.0) && K > 0 && s.nC > 0;
+    if (s.nC > 0 && !C) return fail(TC_E_NULL, "C is NULL");
+    if (reads_inputs && ((s.nA > 0 && !A) || (s.nB > 0 && !B))) return fail(TC_E_NULL, "A or B is NULL");
+    int es = s.elem_bytes();
+    auto overlap = [&](const void* x, int64_t span_x, const void* y, int64_t span_y) {
+        if (!x || !y || span_x == 0 || span_y == 0) return false;
+        uintptr_t x0 = (uintptr_t)x, x1 = x0 + (uintptr_t)(span_x * es);
+        uintptr_t y0 = (uintptr_t)y, y1 = y0 + (uintptr_t)(span_y * es);
+        return x0 < y1 && y0 < x1;
+    };
+    if (reads_inputs && (overlap(C, s.spanC, A, s.spanA) || overlap(C, s.spanC, B, s.spanB)))
+        return fail(TC_E_ALIAS, "C overlaps A or B");
+    *runs = s.nC > 0;
+    return TC_OK;
+}
 }  // namespace tc
 
 // ===========================================================================
@@ -560,30 +605,15 @@ tc_status tc_plan_workspace(tc_plan_t p, int64_t* bytes) {
     return TC_OK;
 }
 
+
 static tc_status contract_entry(tc_plan_t p, const void* A, const void* B, void* C, double alpha_re,
                                 double alpha_im, double beta_re, double beta_im, void* stream) {
-    if (!p) return fail(TC_E_NULL, "plan is NULL");
-    const Spec& s = p->spec;
-    if (!s.is_complex() && (alpha_im != 0.0 || beta_im != 0.0))
-        return fail(TC_E_UNSUPPORTED, "complex alpha or beta on a real plan");
-    int64_t K = 1;
-    for (char ch : s.summed()) K *= s.e(ch);
-    bool reads_inputs = (alpha_re != 0.0 || alpha_im != 0.0) && K > 0 && s.nC > 0;
-    if (s.nC > 0 && !C) return fail(TC_E_NULL, "C is NULL");
-    if (reads_inputs && ((s.nA > 0 && !A) || (s.nB > 0 && !B))) return fail(TC_E_NULL, "A or B is NULL");
-    int es = s.elem_bytes();
-    auto overlap = [&](const void* x, int64_t span_x, const void* y, int64_t span_y) {
-        if (!x || !y || span_x == 0 || span_y == 0) return false;
-        uintptr_t x0 = (uintptr_t)x, x1 = x0 + (uintptr_t)(span_x * es);
-        uintptr_t y0 = (uintptr_t)y, y1 = y0 + (uintptr_t)(span_y * es);
-        return x0 < y1 && y0 < x1;
-    };
-    if (reads_inputs && (overlap(C, s.spanC, A, s.spanA) || overlap(C, s.spanC, B, s.spanB)))
-        return fail(TC_E_ALIAS, "C overlaps A or B");
-    if (s.nC == 0) return TC_OK;
+    bool runs = false;
+    tc_status st = validate_call(p, A, B, C, alpha_re, alpha_im, beta_im, &runs);
+    if (st || !runs) return st;
     if (std::getenv("TC_FAULT") && std::strcmp(std::getenv("TC_FAULT"), "launch") == 0)
         return fail(TC_E_HIP, "injected launch failure (TC_FAULT=launch)");
-    tc_status st = prepare_plan(p);
+    st = prepare_plan(p);
     if (st) return st;
     if (p->real) return run_complex(p, A, B, C, alpha_re, alpha_im, beta_re, beta_im, (hipStream_t)stream);
     return contract_dispatch(p, A, B, C, alpha_re, beta_re, (hipStream_t)stream);

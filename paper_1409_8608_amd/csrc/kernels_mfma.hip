@@ -617,9 +617,10 @@ hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st) {
 // Split-K choice for a fused M x N x Kpad launch (one batch, one pass): none
 // while the output tiles fill about two waves of resident blocks, or when K is
 // short; else enough slices of at least 8 K tiles to fill them, with the
-// workspace (slices x tiles x 128 x 128 elements) at most 64 MiB.  Returns the
-// slice count and sets the tiles per slice and the workspace bytes.
-int64_t mfma_split_plan(bool f64, int64_t M, int64_t N, int64_t Kpad, int64_t* slice_tiles, int64_t* ws_bytes) {
+// workspace (slices x tiles x 128 x 128 elements) at most ws_cap bytes.
+// Returns the slice count and sets the tiles per slice and the workspace bytes.
+int64_t mfma_split_plan(bool f64, int64_t M, int64_t N, int64_t Kpad, int64_t* slice_tiles, int64_t* ws_bytes,
+                        int64_t ws_cap) {
     const int64_t ntiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
     const int64_t ktiles = Kpad / kBK;
     const int64_t fill = f64 ? 256 : 512;   // resident blocks of the two tile kernels on 256 CUs
@@ -628,7 +629,7 @@ int64_t mfma_split_plan(bool f64, int64_t M, int64_t N, int64_t Kpad, int64_t* s
     *ws_bytes = 0;
     if (ntiles <= 0 || ntiles >= fill || ktiles < 16) return 1;
     int64_t S = std::min<int64_t>((2 * fill + ntiles - 1) / ntiles, ktiles / 8);
-    S = std::min<int64_t>(S, (64LL << 20) / (ntiles * kBM * kBN * esize));
+    S = std::min<int64_t>(S, ws_cap / (ntiles * kBM * kBN * esize));
     if (S < 2) return 1;
     const int64_t per = (ktiles + S - 1) / S;
     S = (ktiles + per - 1) / per;

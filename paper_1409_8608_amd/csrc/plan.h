@@ -59,6 +59,9 @@ struct tc_plan_s {
     void* d_zexp = nullptr;          // the expanded operand
     int64_t zexp_cap = 0;
     int zvec = 0;                    // complex streaming kernel's widest lane form (0: not used); gv complex
+    // host copy of the fused K table, for the no-allocation entry point
+    std::vector<int64_t> h_ktab;
+    int h_kvec = 0;
     // split-precision buffers (one allocation)
     void* d_split = nullptr;
     int64_t split_bytes = 0;
@@ -85,6 +88,14 @@ StreamArgs stream_args(const GemmView& gv, bool f64);
 tc_status prepare_plan(tc_plan_s* p);
 tc_status contract_dispatch(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
                             hipStream_t st);
+tc_status validate_call(const tc_plan_s* p, const void* A, const void* B, const void* C, double alpha_re,
+                        double alpha_im, double beta_im, bool* runs);
+// Fused launches with A and B in GEMM-view order (swapped already).
+tc_status launch_fused_stream(const tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
+                              hipStream_t st);
+tc_status launch_fused_mfma(const tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
+                            const int64_t* ktab, int64_t kpad, int kvec, void* ws, int64_t kslices,
+                            int64_t kslice_tiles, hipStream_t st);
 tc_status run_variant(tc_plan_s* p, int v, const void* A, const void* B, void* C, double alpha, double beta,
                       hipStream_t st);
 
