@@ -44,7 +44,11 @@ own class are counted in the nearest inner class that has one.
 
 Readings where the paper leaves a choice: the prefetch distance is 0 (its worked
 example); line failures split only the steady class; a loop nest without loops
-gives every operand distance 0.
+gives every operand distance 0.  Operands at equal distance keep the order of
+the access-distance list (Section 3.3 folds the prefetch distances into that
+list, and its example lists C[a,:,c], A[a,:], B[:,:,c] in the order of their
+access distances); operands at equal access distance are taken in the order
+A, B, C.
 
 Root precondition (case 3 made explicit).  At the root the paper assumes the
 contraction runs again and again with nothing in between, because it cannot
@@ -203,11 +207,28 @@ class BenchClass:
     setup: list         # setup list
 
 
+def first_iteration_class(ops, loops, extents: dict, k: int, share: float, cache_elems: float,
+                          gaps: dict, keep_operand_only: bool = False) -> BenchClass:
+    """Class of the first iteration of loop ``k`` (Section 3.5): the walk starts
+    at that loop with M holding every kernel operand joined across it and the
+    loops inside it; every operand is accessed whole (no prefetch emulation)."""
+    preset = set(loops[k:])
+    items = []
+    for r in ops:
+        d = access_distance(r, ops, loops, extents, start=k, preset=preset, root_gap=gaps[r.tensor])
+        items.append((r.tensor, region_size(r, set(), extents), d))
+    st = build_setup(items, cache_elems)
+    return BenchClass(f"first@{loops[k]}", share, st if keep_operand_only or not only_operands(st) else [])
+
+
 def predict_classes(ops, loops, extents: dict, cache_elems: float, line_elems: int,
-                    stage: int = 5, root_gaps: dict | None = None):
+                    stage: int = 5, root_gaps: dict | None = None, keep_operand_only: bool = False):
     """Benchmark classes with their shares of the invocations, for prediction
     stage 1 (repeated execution) .. 5 (first iterations separate).
-    ``root_gaps`` maps an operand's tensor name to its root gap (elements)."""
+    ``root_gaps`` maps an operand's tensor name to its root gap (elements).
+    ``keep_operand_only`` keeps setup lists made only of operand accesses
+    (normally dropped: the repetitions already touch every operand), so that
+    they can be inspected."""
     names = [r.tensor for r in ops]
     sizes = [region_size(r, set(), extents) for r in ops]
     gaps = {n: int((root_gaps or {}).get(n, 0)) for n in names}
@@ -215,16 +236,18 @@ def predict_classes(ops, loops, extents: dict, cache_elems: float, line_elems: i
         return [BenchClass("steady", 1.0, [])]
     dist = [access_distance(r, ops, loops, extents, root_gap=gaps[r.tensor]) for r in ops]
     kinds = [prefetch_kind(r, loops, extents, line_elems) if stage >= 3 else None for r in ops]
+    # the access-distance list's order (ties: A, B, C); later stages keep it for ties
+    order = sorted(range(len(ops)), key=lambda t: -dist[t])
 
     def setup_with(prefetched):
         items = []
-        for n, s, d, r, pf in zip(names, sizes, dist, ops, prefetched):
-            if pf:
-                items.append((n, prefetch_access_size(r, extents, line_elems), 0))
+        for t in order:
+            if prefetched[t]:
+                items.append((names[t], prefetch_access_size(ops[t], extents, line_elems), 0))
             else:
-                items.append((n, s, d))
+                items.append((names[t], sizes[t], dist[t]))
         st = build_setup(items, cache_elems)
-        return [] if only_operands(st) else st
+        return st if keep_operand_only or not only_operands(st) else []
 
     steady_setup = setup_with([k is not None for k in kinds])
     classes = []
@@ -247,15 +270,10 @@ def predict_classes(ops, loops, extents: dict, cache_elems: float, line_elems: i
                 s /= int(extents[loops[m]])
             first_share[k] = s
         own = [k for k in range(n) if k == n - 1 or first_share[k] > 0.01]
-        for idx, k in enumerate(sorted(own, reverse=True)):
+        for k in sorted(own, reverse=True):
             outer = [o for o in own if o < k]
             nxt = max(outer) if outer else None
             share = first_share[k] - (first_share[nxt] if nxt is not None else 0.0)
-            preset = set(loops[k:])
-            items = []
-            for nme, s, r in zip(names, sizes, ops):
-                d = access_distance(r, ops, loops, extents, start=k, preset=preset, root_gap=gaps[r.tensor])
-                items.append((nme, s, d))
-            st = build_setup(items, cache_elems)
-            classes.append(BenchClass(f"first@{loops[k]}", share, [] if only_operands(st) else st))
+            classes.append(first_iteration_class(ops, loops, extents, k, share, cache_elems, gaps,
+                                                 keep_operand_only))
     return classes

@@ -136,11 +136,18 @@ std::vector<BenchClass> bench_classes(const Spec& s, const Variant& v, int stage
         dist[t] = access_distance(s, v, t, -1, gap[t]);
         kind[t] = stage >= 3 ? prefetch_kind(s, v, t, line_elems) : 0;
     }
+    // Operands in the order of the access-distance list (ties: A, B, C); the
+    // prefetch distances of Section 3.3 are folded into that list, so equal
+    // distances keep it (its example lists C[a,:,c], A[a,:], B[:,:,c]).
+    int order[3] = {0, 1, 2};
+    std::stable_sort(order, order + 3, [&](int x, int y) { return dist[x] > dist[y]; });
     auto steady_with = [&](const bool pf[3]) {
         std::vector<Item> items;
-        for (int t = 0; t < 3; ++t)
+        for (int q = 0; q < 3; ++q) {
+            const int t = order[q];
             items.push_back(pf[t] ? Item{t, one_line_size(s, v.ops[t], line_elems), 0}
                                   : Item{t, size[t], dist[t]});
+        }
         return setup_list(items, cache_elems);
     };
     const int L = (int)v.loops.size();

@@ -79,11 +79,147 @@ def test_case_rules_on_other_printed_algorithms():
     d = {r.tensor: ac.access_distance(r, ops, v.loops, ext) for r in ops}
     assert d["C"] == 0                                  # C[:,b,:] does not vary with i
     assert d["A"] == 400 * 8 + 8 * 400 + 400 * 400       # A[:,:], B[:,b,:], C[:,b,:]
-    v = vs["ci-ger"]                       # first iteration of i: C[:,:,c] changes (Section 3.5)
-    cls = ac.predict_classes(regions(v), v.loops, ext, 786432, 8, stage=5)
-    first = [c for c in cls if c.label == "first@i"][0]
-    assert abs(first.weight - (1 / 8) * (1 - 1 / 400)) < 1e-15 or abs(first.weight - 1 / 8) < 1e-15
-    assert any(c.label.startswith("first") for c in cls)
+
+
+# The worked numbers below are derived by hand from the rules of Sections
+# 3.2-3.5 at a = b = c = 400, i = 8, a 64-byte line (8 doubles) and the 6 MB
+# cache (786,432 doubles, 5/4 of it 983,040), the paper's example setting.
+EXT_400 = dict(a=400, b=400, c=400, i=8)
+CACHE_6MB, LINE_8 = 786432, 8
+
+
+def _ci_ger_first_iteration_problems(acc):
+    """Mismatches between module ``acc``'s first-iteration class of ci-ger and
+    Section 3.5's example.  ci-ger is: for c, for i: C[:,:,c] += A[:,i] B[i,:,c]^T.
+    The class of the first i iteration (the next c iteration) starts the walk at
+    loop i with M = {A[:,:], B[:,:,c], C[:,:,c]} (every operand joined across i):
+      A[:,:] does not change across c (case 1): distance |M| = 3,200 + 3,200 +
+        160,000 = 166,400 -- not 0, so A's prefetch "fails", as the paper says;
+      B[:,:,c] and C[:,:,c] change across c (case 2): joined along c, M =
+        A[:,:] + B[:,:,:] + C[:,:,:] = 3,200 + 1,280,000 + 64,000,000 =
+        65,283,200 at the root (case 3) -- C "refers to a different memory
+        location", so its distance is not 0.
+    No prefetch emulation: A is accessed whole (400 doubles, not one line).
+    Setup list: B 400, C 160,000 (the remote region between two operands at
+    the same distance would be negative: dropped), remote 65,283,200 - 166,400
+    - 400 = 65,116,400, A 400, remote 166,400; cut from the front to 983,040:
+    remote 983,040 - 166,800 = 816,240, A 400, remote 166,400.
+    Shares: loop i's first iteration is 1/8 of the invocations; loop c's
+    (1/3200, under 1%) has no class of its own and counts in first@i, so
+    first@i weighs exactly 1/8 and the steady and failure classes share 7/8
+    (7/8 * 7/8 and 7/8 * 1/8: B[i,:,c] shares cache lines along i)."""
+    vs = {x.name: x for x in family.enumerate_family("abc=ai,ibc")}
+    v = vs["ci-ger"]
+    problems = []
+    if "".join(v.loops) != "ci":
+        return [f"loops {v.loops}"]
+    ops = regions(v)
+    want = {"A": 166400, "B": 65283200, "C": 65283200}
+    for r in ops:
+        got = acc.access_distance(r, ops, v.loops, EXT_400, start=1, preset={"i"})
+        if got != want[r.tensor]:
+            problems.append(f"distance {r.tensor} {got} != {want[r.tensor]}")
+    cls = acc.predict_classes(ops, v.loops, EXT_400, 1e30, LINE_8, stage=5)
+    first = [c for c in cls if c.label.startswith("first")]
+    if [c.label for c in first] != ["first@i"]:
+        return problems + [f"first-iteration classes {[c.label for c in first]}"]
+    f = first[0]
+    if f.weight != 1 / 8:
+        problems.append(f"weight {f.weight!r} != 1/8")
+    full = [["op", "B", 400], ["op", "C", 160000], ["remote", None, 65116400], ["op", "A", 400],
+            ["remote", None, 166400]]
+    if [list(e) for e in f.setup] != full:
+        problems.append(f"uncut setup {f.setup}")
+    cut = acc.predict_classes(ops, v.loops, EXT_400, CACHE_6MB, LINE_8, stage=5)
+    fc = [c for c in cut if c.label == "first@i"]
+    if not fc or [list(e) for e in fc[0].setup] != [["remote", None, 816240], ["op", "A", 400],
+                                                    ["remote", None, 166400]]:
+        problems.append(f"cut setup {fc[0].setup if fc else None}")
+    w = {c.label: c.weight for c in cut}
+    if w.get("steady") != (7 / 8) * (7 / 8) or w.get("fail") != (7 / 8) / 8:
+        problems.append(f"steady/fail weights {w}")
+    return problems
+
+
+def test_first_iteration_class_ci_ger():
+    assert _ci_ger_first_iteration_problems(ac) == []
+
+
+def test_first_iteration_pin_catches_planted_mistakes(monkeypatch):
+    """Each plausible mistake in the first-iteration walk, planted in the
+    oracle (on the CPU), makes the pin above fail."""
+    real_distance = ac.access_distance
+
+    def one_loop_out(r, ops, loops, extents, start=None, preset=None, root_gap=0):
+        if start is not None and start > 0:          # start at the loop outside, joined across it too
+            start -= 1
+            preset = set(loops[start:])
+        return real_distance(r, ops, loops, extents, start, preset, root_gap)
+
+    def m_not_preloaded(r, ops, loops, extents, start=None, preset=None, root_gap=0):
+        return real_distance(r, ops, loops, extents, start, None, root_gap)
+
+    real_first = ac.first_iteration_class
+
+    def prefetch_kept(ops, loops, extents, k, share, cache_elems, gaps, keep_operand_only=False):
+        c = real_first(ops, loops, extents, k, share, cache_elems, gaps, keep_operand_only)
+        pre = {r.tensor: ac.prefetch_access_size(r, extents, LINE_8) for r in ops
+               if ac.prefetch_kind(r, loops, extents, LINE_8)}
+        c.setup = [(e[0], e[1], pre.get(e[1], e[2]) if e[0] == "op" else e[2]) for e in c.setup]
+        return c
+
+    for name, fn in (("access_distance", one_loop_out), ("access_distance", m_not_preloaded),
+                     ("first_iteration_class", prefetch_kept)):
+        with monkeypatch.context() as m:
+            m.setattr(ac, name, fn)
+            assert _ci_ger_first_iteration_problems(ac), fn.__name__
+
+
+def test_prefetch_access_sizes():
+    """Section 3.3: a prefetched operand's setup access is limited to one cache
+    line along its first axis.  ca-gemv (its second example): C[a,:,c] and
+    A[a,:] have extent 1 along their first axis, so they are accessed whole
+    (400 and 8), and the reduced list, before it is dropped for holding only
+    operand accesses, is C[a,:,c], A[a,:], B[:,:,c] (400, 8, 3,200), in the
+    order of their access distances.  bi-ger (its first example): A[:,i] is
+    streamed along its 400-long first axis, so its access is one line of 8
+    doubles; B[i,b,:] (first-axis extent 1) is whole, 400; C[:,b,:] is not
+    prefetched and keeps its 160,000.  Its access distances order the list
+    B (65,283,200), A (166,400), C (0)."""
+    vs = {x.name: x for x in family.enumerate_family("abc=ai,ibc")}
+    v = vs["ca-gemv"]
+    ops = regions(v)
+    assert {r.tensor: ac.prefetch_access_size(r, EXT_400, LINE_8) for r in ops} == {"A": 8, "B": 3200, "C": 400}
+    st = ac.predict_classes(ops, v.loops, EXT_400, CACHE_6MB, LINE_8, stage=3, keep_operand_only=True)
+    assert [list(e) for e in st[0].setup] == [["op", "C", 400], ["op", "A", 8], ["op", "B", 3200]]
+    v = vs["bi-ger"]
+    ops = regions(v)
+    sizes = {r.tensor: ac.prefetch_access_size(r, EXT_400, LINE_8) for r in ops}
+    assert sizes["A"] == 8 and sizes["B"] == 400
+    st = ac.predict_classes(ops, v.loops, EXT_400, CACHE_6MB, LINE_8, stage=3, keep_operand_only=True)
+    assert [list(e) for e in st[0].setup] == [["op", "B", 400], ["op", "A", 8], ["op", "C", 160000]]
+    # Section 3.4: the failure benchmark drops the line-sharing emulation of
+    # B[i,b,:] (back at its access distance), A stays one streamed line:
+    # B 400, remote 65,283,200 - 0 - 8, A 8, C 160,000; cut to 983,040:
+    # remote 983,040 - 160,008 = 823,032, A 8, C 160,000
+    st = ac.predict_classes(ops, v.loops, EXT_400, CACHE_6MB, LINE_8, stage=4)
+    fail = [c for c in st if c.label == "fail"][0]
+    assert [list(e) for e in fail.setup] == [["remote", None, 823032], ["op", "A", 8], ["op", "C", 160000]]
+    assert fail.weight == 1 / 8
+
+
+def test_prefetch_list_order_pin_catches_operand_order(golden):
+    """The printed reduced list of Section 3.3 fixes the order of operands at
+    equal distance: ordering ties by operand (A, B, C) instead of by access
+    distance gives A, B, C and fails."""
+    g = golden("access_example.json")
+    v = {x.name: x for x in family.enumerate_family(g["spec"])}[g["variant"]]
+    ops = regions(v)
+    st = ac.predict_classes(ops, v.loops, g["extents"], g["cache_elems"], g["line_elems"], stage=3,
+                            keep_operand_only=True)
+    assert [list(e) for e in st[0].setup] == g["setup_prefetch_operands"]
+    items = [(r.tensor, ac.prefetch_access_size(r, g["extents"], g["line_elems"]), 0) for r in ops]
+    assert [list(e) for e in ac.build_setup(items, g["cache_elems"])] != g["setup_prefetch_operands"]
 
 
 def test_root_gap_only_where_the_walk_reaches_the_root(golden):
