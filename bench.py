@@ -3,19 +3,29 @@
 Headline workload (the metric's sweep, largest point): C_abc = A_ai B_ibc,
 a = b = c = 1024, i = 8, FP64, column-major, entries uniform[-1, 1] (seed 28),
 computed by the fused kernel.  One step = one tc_contract (plan and workspace
-are set up before the timed region; inputs are resident in HBM).
+are set up before the timed region; inputs are resident in HBM).  Before the
+--warmup steps the contraction runs for a fixed settling period (about 100
+launches): on a fresh MI355X the launch time of this kernel falls from 3.7 ms
+to 1.34 ms over its first 30 or so launches whatever ran before, so a short
+warm-up alone would time the device's ramp rather than the kernel.
 
 Printed: ONE JSON line with the headline value plus
   roofline      the dominant kernel's achieved algorithmic bandwidth (bytes of
                 A + B + C once each / average launch time from HIP events on
                 the launch stream) against the 8 TB/s HBM peak
-  cpu_baseline  the FP64 oracle (plain C loop nest, one core) on a bounded
-                slab of the same workload
+  cpu_baseline  the FP64 oracle (plain C loop nest) on a bounded slab of the
+                same workload, on all host cores (the primary value) and on
+                one; the error of the timed GPU result against the oracle on
+                the slab both computed; host CPU model and thread count; the
+                paper's own flops/cycle figures and the GPU's flops/cycle at
+                its measured engine clock
   forms         the other forms of the metric on the same GPU, each with its
-                own roofline: FP64/FP32 fused permuted contraction, FP64/FP32
-                and split-BF16/FP8 matrix products, batched launch, complex
-                storage; their sampled error columns compare against an FP64
-                numpy.einsum of the sampled slices
+                own roofline and its own fixed warm-up: FP64/FP32 fused
+                permuted contraction, FP64/FP32 and split-BF16/FP8 matrix
+                products, batched launch, complex storage; their sampled error
+                columns compare against an FP64 numpy.einsum of the sampled
+                slices (the oracle runs in the CPU-baseline leg only; the GPU
+                parity tests check these configurations against it)
 """
 from __future__ import annotations
 
@@ -83,26 +93,69 @@ def _events_time(fn, steps, warmup, torch):
     return start.elapsed_time(stop) / steps, wall
 
 
+SETTLE_MS = 150.0      # settling period before the warm-up steps
+
+
+def settle(fn, torch, ms=SETTLE_MS):
+    """Run ``fn`` until ``ms`` of device time have passed; returns the launches."""
+    t0 = time.perf_counter()
+    n = 0
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        for _ in range(10):
+            fn()
+        n += 10
+        torch.cuda.synchronize()
+    return n
+
+
+def gpu_sclk_mhz(fn, torch):
+    """Engine clock (MHz) reported by rocm-smi while ``fn`` runs back to back
+    (outside the timed region); None if rocm-smi gives no reading."""
+    import re
+    import subprocess
+    import threading
+    stop = threading.Event()
+
+    def busy():
+        while not stop.is_set():
+            for _ in range(20):
+                fn()
+            torch.cuda.synchronize()
+    th = threading.Thread(target=busy)
+    th.start()
+    try:
+        time.sleep(0.2)
+        out = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20).stdout
+    except (OSError, subprocess.SubprocessError):
+        out = ""
+    finally:
+        stop.set()
+        th.join()
+    vals = [int(v) for line in out.splitlines() if "sclk" in line.lower()
+            for v in re.findall(r"(\d+)\s*Mhz", line, flags=re.I)]
+    return max(vals) if vals else None
+
+
 def headline(args, torch, tc, wl):
     n, i = args.n, 8
     w = wl.smallk_cube(n, i)
     spec, ext = w["spec"], w["ext"]
     plan = tc.Plan(spec, ext, "f64")
     plan.set_variant(tc.TC_VARIANT_FUSED)
-    plan.prepare()
     dA = tc.to_device_fortran(w["A"], torch.float64)
     dB = tc.to_device_fortran(w["B"], torch.float64)
     dC = tc.empty_fortran(plan.shape("C"), torch.float64)
     fn = lambda: plan.contract(dA, dB, dC, 1.0, 0.0)
+    settled = settle(fn, torch)
     ms, wall = _events_time(fn, args.steps, args.warmup, torch)
     flops = 2 * n * n * n * i
     bytes_alg = 8 * (n * i + i * n * n + n * n * n)
-    # sampled parity of the timed result (a few output columns)
+    # the timed result's first slabs C[:, :, 0:8], for the CPU-baseline leg's
+    # comparison with the oracle
     import numpy as np
-    rng = np.random.default_rng(0)
-    cs = rng.integers(0, n, 2)
-    Cs = dC[:, :, torch.as_tensor(cs, device="cuda")].cpu().numpy()
-    ok = bool(np.isfinite(Cs).all())
+    gpu_slab = dC[:, :, :HEADLINE_CHECK_SLABS].cpu().numpy()
+    ok = bool(np.isfinite(gpu_slab).all())
+    sclk = gpu_sclk_mhz(fn, torch)
     gflops = flops / (ms * 1e-3) / 1e9
     achieved = bytes_alg / (ms * 1e-3) / 1e9
     rec = dict(
@@ -115,11 +168,15 @@ def headline(args, torch, tc, wl):
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
                       kernel="k_stream_wave<double,8,2,8,64,false>"),
+        settle=dict(launches=settled, ms=SETTLE_MS, note="untimed launches before the warm-up steps"),
         finite=ok,
+        gpu_clock=dict(sclk_mhz_measured=sclk, peak_mhz=2400,
+                       flops_per_cycle_at_measured=round(flops / (ms * 1e-3) / (sclk * 1e6), 1) if sclk else None,
+                       flops_per_cycle_at_peak_clock=round(flops / (ms * 1e-3) / 2.4e9, 1)),
     )
     del dC
     torch.cuda.empty_cache()
-    return rec, w
+    return rec, w, gpu_slab
 
 
 def measured_traffic():
@@ -147,29 +204,88 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(w, seconds):
-    """The oracle as it stands on a slab C[:, :, 0:s] of the workload: one
-    slab times the rate, then one run sized to about `seconds`."""
+HEADLINE_CHECK_SLABS = 8
+
+# The paper's own figures (FP64, x86, BLAS), context for the oracle's rate:
+# flops per cycle as its text states them.
+PAPER_FLOPS_PER_CYCLE = [
+    dict(value=60, peak=80, what="best Test 3 gemm members (i'c-gemm, i'b-gemm), C_abc = A_ija B_jbic",
+         hardware="10-core Ivy Bridge-EP E5-2680 v2, 10 threads, OpenBLAS", source="Section 4.3"),
+    dict(value=20, peak=80, what="slowest Test 3 gemm member (jb'-gemm), same setting", source="Section 4.3"),
+    dict(value=None, peak=8, what="per-core peak, Test 1 (C_abc = A_ai B_ibc, a=b=c=128, i swept)",
+         hardware="Ivy Bridge-EP E5-2680 v2, one core, MKL", source="Section 4.1"),
+    dict(value=None, peak=4, what="per-core peak, Section 3 case study (C_abc = A_ai B_ibc, i=8)",
+         hardware="Harpertown E5450, one core, OpenBLAS", source="Section 3"),
+]
+
+
+def host_threads():
+    """Host threads the CPU leg may use: this process's CPU affinity, capped by
+    OMP_NUM_THREADS when set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, seconds, gpu_slab, gpu_rec):
+    """The oracle as it stands on slabs C[:, :, 0:s] of the workload, on all
+    host threads (C's outermost index spread over them) and on one: a short run
+    gives the rate, then one run is sized to about `seconds`.  The all-thread
+    run always covers C[:, :, 0:8], which the GPU's timed result is compared
+    with."""
     import numpy as np
     import oracle
     n, i = w["ext"]["a"], w["ext"]["i"]
 
-    def run(s):
+    def run(s, threads):
         B = np.asfortranarray(w["B"][:, :, :s])
         t0 = time.perf_counter()
-        oracle.contract("abc=ai,ibc", dict(a=n, b=n, c=s, i=i), w["A"], B)
-        return time.perf_counter() - t0
+        C = oracle.contract("abc=ai,ibc", dict(a=n, b=n, c=s, i=i), w["A"], B, threads=threads)
+        return time.perf_counter() - t0, C
 
-    dt4 = run(4)
-    s = int(max(1, min(n, round(4 * seconds / max(dt4, 1e-6)))))
-    dt = run(s)
-    flops = 2 * n * n * s * i
-    return dict(value=round(flops / dt / 1e9, 4), unit="GFLOP/s", cores=1, kind="oracle",
-                sample=f"C[:, :, 0:{s}] of the a=b=c={n}, i={i} workload ({flops / 1e9:.2f} GFLOP in {dt:.1f} s, "
-                       "one host core, plain FP64 loop nest)")
+    def leg(threads, s_min, s_max):
+        probe = min(n, max(2, threads))              # one slab per thread gives the rate
+        dt0, _ = run(probe, threads)
+        s = int(max(s_min, min(s_max, round(probe * seconds / max(dt0, 1e-6)))))
+        dt, C = run(s, threads)
+        fl = 2 * n * n * s * i
+        return dict(value=round(fl / dt / 1e9, 4), seconds=round(dt, 2), slabs=s, gflop=round(fl / 1e9, 2)), C
+
+    threads = host_threads()
+    allc, C = leg(threads, HEADLINE_CHECK_SLABS, min(n, 256))
+    err = _normwise(gpu_slab, C[:, :, :HEADLINE_CHECK_SLABS])
+    del C
+    one, _ = leg(1, 1, n)
+    ghz = 2.4
+    return dict(value=allc["value"], unit="GFLOP/s", cores=threads, kind="oracle",
+                sample=f"C[:, :, 0:{allc['slabs']}] of the a=b=c={n}, i={i} workload ({allc['gflop']} GFLOP in "
+                       f"{allc['seconds']} s, plain FP64 loop nest, C's outermost index over {threads} threads)",
+                one_core=dict(value=one["value"], unit="GFLOP/s", cores=1,
+                              sample=f"C[:, :, 0:{one['slabs']}] ({one['gflop']} GFLOP in {one['seconds']} s)"),
+                host=dict(cpu_model=cpu_model(), cpu_count=os.cpu_count(), threads_used=threads),
+                gpu_result_error=dict(normwise_vs_oracle=err, tolerance=1e-12,
+                                      slab=f"C[:, :, 0:{HEADLINE_CHECK_SLABS}] of the timed result"),
+                speedup_gpu_over_oracle=round(gpu_rec["value"] / allc["value"], 1),
+                paper_flops_per_cycle=PAPER_FLOPS_PER_CYCLE,
+                gpu_flops_per_cycle=gpu_rec["gpu_clock"])
 
 
 FORMS = ("permuted", "precision", "batched", "complex")
+# Each form settles for 100 ms, then takes its own warm-up and timed launches,
+# independent of the headline's --steps / --warmup.
+FORM_WARMUP, FORM_STEPS = 10, 20
 
 
 def forms(args, torch, tc, wl):
@@ -186,7 +302,9 @@ def forms(args, torch, tc, wl):
         dA = tc.to_device_fortran(w["A"], tdt)
         dB = tc.to_device_fortran(w["B"], tdt)
         dC = tc.empty_fortran(plan.shape("C"), tdt)
-        ms, _ = _events_time(lambda: plan.contract(dA, dB, dC), max(3, args.steps // 4), max(2, args.warmup // 2), torch)
+        fn = lambda: plan.contract(dA, dB, dC)
+        settle(fn, torch, 100.0)
+        ms, _ = _events_time(fn, FORM_STEPS, FORM_WARMUP, torch)
         fl = 2 * 256 ** 3 * 32 * 32
         tfs = fl / (ms * 1e-3) / 1e12
         out[f"permuted_{dt}"] = dict(workload="C_abc = A_ija B_jbic, a=b=c=256, i=j=32, normal(0,1)",
@@ -240,7 +358,8 @@ def batched(args, torch, tc, wl, dtype):
             p.contract(A, B, C)
     seq_ms, seq_wall = _events_time(seq, 2, 1, torch)
     batch = tc.Batch(plans)
-    run = lambda: batch.contract(As, Bs, Cs)
+    bound = batch.bind(As, Bs, Cs)        # operands checked once; each replay is one library call
+    run = lambda: batch.run(bound)
     bat_ms, _ = _events_time(run, 5, 3, torch)
     t0 = time.perf_counter()
     batch.tune(2)
@@ -295,8 +414,9 @@ def complex_forms(args, torch, tc, wl):
             dA = tc.to_device_fortran(w["A"], tdt)
             dB = tc.to_device_fortran(w["B"], tdt)
             dC = tc.empty_fortran(plan.shape("C"), tdt)
-            ms, _ = _events_time(lambda: plan.contract(dA, dB, dC, 1 + 0j, 0j), max(3, args.steps // 4),
-                                 max(2, args.warmup // 2), torch)
+            fn = lambda: plan.contract(dA, dB, dC, 1 + 0j, 0j)
+            settle(fn, torch, 100.0)
+            ms, _ = _events_time(fn, FORM_STEPS, FORM_WARMUP, torch)
             idx = [torch.as_tensor(picks[ch], device="cuda") for ch in sc]
             got = dC
             for ax, ix in enumerate(idx):
@@ -350,7 +470,9 @@ def precision(args, torch, tc, wl):
         plan = tc.Plan(w["spec"], w["ext"], dtype, compute=compute)
         plan.prepare()
         dC = tc.empty_fortran(plan.shape("C"), tdt)
-        ms, _ = _events_time(lambda: plan.contract(xA, xB, dC), 10, max(1, args.warmup // 5), torch)
+        fn = lambda: plan.contract(xA, xB, dC)
+        settle(fn, torch, 100.0)
+        ms, _ = _events_time(fn, FORM_STEPS, FORM_WARMUP, torch)
         got = dC[torch.as_tensor(rows, device="cuda")][:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
         err = _normwise(got, ref)
         tfs = fl / (ms * 1e-3) / 1e12
@@ -408,13 +530,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    rec, w = headline(args, torch, tc, wl)
+    rec, w, gpu_slab = headline(args, torch, tc, wl)
     print(f"# headline done: {rec['value']} GFLOP/s", file=sys.stderr, flush=True)
     if not args.no_forms:
         rec["forms"] = forms(args, torch, tc, wl)
         print("# forms done", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, gpu_slab, rec)
     print(json.dumps(rec), flush=True)
 
 

@@ -143,8 +143,12 @@ typedef struct {
 
 /* Build a plan: parse `spec` ("abc=ai,ibc"), classify indices (Section 1),
  * bind extents and strides, enumerate the algorithm family (Section 2,
- * Table 1 x loop orders) and map each member to a GPU schedule.  Host work
- * only; no device memory is touched.
+ * Table 1 x loop orders) and map each member to a GPU schedule.  When a GPU is
+ * visible, the plan then allocates on the current device every buffer the
+ * fused kernel needs (K table, split-K partial tiles, split-precision terms,
+ * complex expansion), so that tc_contract never allocates; a plan built where
+ * no GPU is visible is host-only (queries and the symbolic model) until
+ * tc_plan_prepare.
  *   Index classes: contracted (both inputs, not C) and free (one input and C)
  *   as in Section 1; also batch (A, B and C) and trace (one input only),
  *   computed as the same sum over every index absent from C.  Specs with
@@ -165,33 +169,49 @@ tc_status tc_plan(tc_plan_t* out, const char* spec,
                   const int64_t* strides_A, const int64_t* strides_B, const int64_t* strides_C,
                   tc_dtype dtype, tc_compute compute);
 
-/* Free a plan and its device workspace.  NULL is accepted. */
+/* Free a plan and its device workspace.  NULL is accepted.  (Lifetime of the
+ * plan object; no passage.) */
 tc_status tc_plan_destroy(tc_plan_t plan);
 
-/* Number of family members of the plan (36 for "abc=ai,ibc"). */
+/* Number of members of the plan's algorithm family (Section 2: Table 1's
+ * kernels x every loop order of the other indices; 36 for "abc=ai,ibc",
+ * Section 3's case study). */
 tc_status tc_variant_count(tc_plan_t plan, int* n);
 
-/* Describe member `variant` (0-based) or TC_VARIANT_FUSED. */
+/* Describe member `variant` (0-based) or TC_VARIANT_FUSED: the paper's name
+ * and number (Section 2, footnote on names; Figure 2/4/5 legends), kernel,
+ * loops and copies, and its GPU schedule. */
 tc_status tc_variant_get(tc_plan_t plan, int variant, tc_variant_info* out);
 
-/* Select what tc_contract runs: a 0-based member, TC_VARIANT_FUSED (default),
- * or TC_VARIANT_PREDICTED (requires a prior tc_predict). */
+/* Select which algorithm tc_contract runs: a 0-based member of the family
+ * (Section 2), TC_VARIANT_FUSED (default), or TC_VARIANT_PREDICTED, the one
+ * Section 3's prediction ranks fastest (requires a prior tc_predict; changing
+ * the root gaps clears the prediction, and tc_contract then returns
+ * TC_E_VARIANT until tc_predict runs again).  When a GPU is visible the
+ * selected member's buffers (copy temporaries, K table) are allocated here.
+ * Errors: TC_E_VARIANT, TC_E_UNSUPPORTED, TC_E_NOMEM, TC_E_HIP. */
 tc_status tc_set_variant(tc_plan_t plan, int variant);
 
-/* Allocate every device buffer the selected variant needs (copy temporaries,
- * split buffers, index tables) so that the following tc_contract calls do not
- * allocate and can be captured in a HIP graph.  tc_contract calls it itself on
- * first use.  Errors: TC_E_NOMEM, TC_E_HIP. */
+/* Allocate every device buffer the selected variant needs on the current
+ * device: temporaries of the copies of Section 2 (the operands marked ' in a
+ * member's name), K tables, split-K partial tiles, split-precision terms.
+ * tc_plan and tc_set_variant do this themselves when a GPU is visible; call it
+ * for a plan built without one.  Idempotent.  Errors: TC_E_NOMEM, TC_E_HIP. */
 tc_status tc_plan_prepare(tc_plan_t plan);
 
-/* Bytes of device workspace the plan holds now. */
+/* Bytes of device workspace the plan holds now (the buffers tc_plan_prepare
+ * lists; no passage). */
 tc_status tc_plan_workspace(tc_plan_t plan, int64_t* bytes);
 
-/* Run the contraction with the selected variant on `stream`:
+/* Run the contraction (Section 1's definition; the kernels of Section 2
+ * accumulate, read here as alpha and beta) with the selected variant on
+ * `stream`:
  *     C = alpha * contract(A, B) + beta * C
  * alpha/beta are rounded to the storage type.  beta == 0: C is not read.
  * alpha == 0: A and B are not read.  Asynchronous; returns after the launches.
- * Errors: TC_E_NULL, TC_E_ALIAS, TC_E_UNSUPPORTED, TC_E_HIP, TC_E_NOMEM. */
+ * Never allocates: a plan without its device workspace (built with no GPU
+ * visible) gives TC_E_UNSUPPORTED, so calls can be captured in a HIP graph.
+ * Errors: TC_E_NULL, TC_E_ALIAS, TC_E_VARIANT, TC_E_UNSUPPORTED, TC_E_HIP. */
 tc_status tc_contract(tc_plan_t plan, const void* A, const void* B, void* C,
                       double alpha, double beta, void* stream);
 
@@ -203,7 +223,8 @@ tc_status tc_contract_complex(tc_plan_t plan, const void* A, const void* B, void
                               double alpha_re, double alpha_im, double beta_re, double beta_im, void* stream);
 
 /* Copy the split terms of the last tc_contract of a TC_BF16X3 or TC_FP8X3
- * plan to host memory, for bit-exact checks of the quantisation.  side 0 = A,
+ * plan to host memory, for bit-exact checks of the quantisation (the
+ * library's split-precision form; not in the paper).  side 0 = A,
  * 1 = B.  The GEMM view of the plan orders rows by the free indices of that
  * side (first fastest) and columns by the plan's K order.  terms: 3 * rows * kp
  * elements, term-major, row-major: BF16 bit patterns (uint16) for TC_BF16X3,
@@ -284,12 +305,16 @@ tc_status tc_predict(tc_plan_t plan, tc_prediction* out, int capacity, int* n_ou
 
 /* --- batches ----------------------------------------------------------------- */
 
-/* Build a batch of n independent contractions (plans stay owned by the caller
- * and must outlive the batch; each needs the native compute mode, a non-empty
- * C and a contracted extent > 0).  Every contraction becomes matrix-core tiles
- * (128x128 outputs, or 64x64 when M or N is at most 64); work lists of
- * (contraction, tile) pairs, longest tiles first, go to device memory once.
- * Errors: TC_E_NULL, TC_E_UNSUPPORTED, TC_E_NOMEM. */
+/* Build a batch of n independent contractions (not in the paper: many
+ * contractions in one launch; its tuner is seeded as Section 3 predicts).
+ * Plans stay owned by the caller and must outlive the batch; each needs the
+ * native compute mode, a non-empty C and a contracted extent > 0.  Every
+ * contraction becomes matrix-core tiles (128x128 outputs, 64x64 when M or N is
+ * at most 64, 32x128 when M is at most 32); work lists of (contraction, tile)
+ * pairs, longest tiles first, go to device memory once, and the HIP graph that
+ * tc_batch_contract replays is captured here: pointer staging from pinned host
+ * memory, counter reset, one persistent kernel per group on up to four graph
+ * branches.  Errors: TC_E_NULL, TC_E_UNSUPPORTED, TC_E_NOMEM, TC_E_HIP. */
 tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n);
 
 /* Choose each member's tile shape: an estimate composed from device
@@ -304,25 +329,29 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n);
  * tc_batch_info. */
 tc_status tc_batch_tune(tc_batch_t batch, int top_k);
 
-/* Run all contractions: C_t = alpha_t * contract(A_t, B_t) + beta_t * C_t.
- * A, B, C, alpha, beta are host arrays of n entries (device pointers for the
- * tensors, borrowed as in tc_contract; alpha_t must be non-zero).  The first
- * call (and the first after tc_batch_tune) captures a HIP graph -- pointer
- * staging from pinned host memory, counter reset, one persistent kernel per
- * group on up to four graph branches -- later calls replay it on `stream`.  The call waits for the
- * previous replay of this batch before restaging pointers.
+/* Run all contractions (each Section 1's definition, as in tc_contract):
+ * C_t = alpha_t * contract(A_t, B_t) + beta_t * C_t.  A, B, C, alpha, beta are
+ * host arrays of n entries (device pointers for the tensors, borrowed as in
+ * tc_contract).  alpha_t == 0: A_t and B_t are not read (and may be NULL);
+ * beta_t == 0: C_t is not read.  Writes the pointers and scalars to the
+ * batch's pinned staging buffer and replays the graph captured by
+ * tc_batch_create (or tc_batch_tune) on `stream`; allocates nothing.  The call
+ * waits for the previous replay of this batch before restaging pointers.
  * Errors: TC_E_NULL, TC_E_ALIAS, TC_E_UNSUPPORTED, TC_E_HIP. */
 tc_status tc_batch_contract(tc_batch_t batch, const void* const* A, const void* const* B,
                             void* const* C, const double* alpha, const double* beta, void* stream);
 
 /* Members, work items (tiles), persistent-kernel groups and the tuner's hit
- * rate (-1 before tc_batch_tune).  Any pointer may be NULL. */
+ * rate (-1 before tc_batch_tune; the share of members where the estimate's
+ * pick measured within 5% of the best, the paper's goal of picking the
+ * fastest algorithm, Section 1).  Any pointer may be NULL. */
 tc_status tc_batch_info(tc_batch_t batch, int* n_members, int64_t* n_tiles, int* n_groups, double* tune_hit_rate);
 
-/* Free a batch (its graph, work lists and staging buffers).  NULL is accepted. */
+/* Free a batch (its graph, work lists and staging buffers).  NULL is
+ * accepted.  (Lifetime of the batch object; no passage.) */
 tc_status tc_batch_destroy(tc_batch_t batch);
 
-/* --- errors ------------------------------------------------------------------ */
+/* --- errors (library conventions; no passage) ------------------------------- */
 const char* tc_status_str(tc_status s);
 const char* tc_last_error(void);
 

@@ -37,7 +37,7 @@ def build(force: bool = False) -> str:
     """Compile contract.c with gcc (-O2, no FMA contraction, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-fopenmp",
                                "-shared", "-std=c99", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -57,6 +57,8 @@ def _load():
                                           dp, i64p, dp, i64p, dp, i64p,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         lib.oracle_contract_z.restype = ctypes.c_int
+        lib.oracle_contract_par.argtypes = lib.oracle_contract.argtypes
+        lib.oracle_contract_par.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -76,7 +78,7 @@ def _elem_strides(x: np.ndarray):
 
 
 def contract(spec: str, extents: dict, A: np.ndarray, B: np.ndarray, C: np.ndarray | None = None,
-             alpha: float = 1.0, beta: float = 0.0, dot2: bool = False) -> np.ndarray:
+             alpha: float = 1.0, beta: float = 0.0, dot2: bool = False, threads: int = 1) -> np.ndarray:
     """C = alpha * contract(A, B) + beta * C in FP64 (Section 1 definition).
 
     ``A``, ``B`` (and ``C``) are float64 numpy arrays whose axes follow the
@@ -84,7 +86,9 @@ def contract(spec: str, extents: dict, A: np.ndarray, B: np.ndarray, C: np.ndarr
     numbers (then alpha and beta may be complex); any non-negative strides are honoured, so a
     Fortran-ordered array is the paper's storage.  If ``C`` is None a new
     Fortran-ordered array is returned (beta must then be 0).  With ``dot2`` the
-    sum is accumulated in doubled working precision.
+    sum is accumulated in doubled working precision.  ``threads`` > 1 spreads
+    C's outermost index over host threads (real operands; same result bit for
+    bit: each element is summed by one thread in the same order).
     """
     sa, sb, sc = split_spec(spec)
     cplx = np.iscomplexobj(A) or np.iscomplexobj(B) or (C is not None and np.iscomplexobj(C))
@@ -114,6 +118,10 @@ def contract(spec: str, extents: dict, A: np.ndarray, B: np.ndarray, C: np.ndarr
             raise ValueError("oracle: doubled-precision sums are for real operands")
         al, be = complex(alpha), complex(beta)
         rc = _load().oracle_contract_z(*args, al.real, al.imag, be.real, be.imag)
+    elif threads > 1:
+        if dot2:
+            raise ValueError("oracle: doubled-precision sums run on one thread")
+        rc = _load().oracle_contract_par(*args, float(alpha), float(beta), int(threads))
     else:
         rc = _load().oracle_contract(*args, float(alpha), float(beta), 1 if dot2 else 0)
     if rc != 0:

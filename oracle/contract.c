@@ -35,6 +35,11 @@
  * double complex: real part, then imaginary part), each product written out as
  * (xr yr - xi yi) + i (xr yi + xi yr) and summed in the same order.
  *
+ * oracle_contract_par is oracle_contract with C's outermost index spread over
+ * host threads (OpenMP): every output element is summed by one thread in the
+ * same order, so its results equal the serial ones bit for bit.  Only the
+ * CPU-baseline timing uses it.
+ *
  * mode 1 ("Dot2") accumulates with an error-free TwoSum/TwoProduct pair
  * (Ogita, Rump, Oishi, "Accurate sum and dot product", SIAM J. Sci. Comput.
  * 26(6), 2005, Algorithm 5.3), giving a result as if computed in twice the
@@ -170,22 +175,13 @@ static void or_step(int64_t* idx, const int64_t* ext, int n) {
     }
 }
 
-/* Returns 0 on success. */
-int oracle_contract(const char* spec, const char* idx_chars, const int64_t* extents, int n_idx,
-                    const double* A, const int64_t* strides_A,
-                    const double* B, const int64_t* strides_B,
-                    double* C, const int64_t* strides_C,
-                    double alpha, double beta, int mode) {
-    or_plan q;
-    int rc = or_setup(spec, idx_chars, extents, n_idx, strides_A, strides_B, strides_C, &q);
-    if (rc) return rc;
-    if (q.nC == 0) return OR_OK;
-    if (!C) return OR_E_NULL;
-    if (alpha != 0.0 && q.nK > 0 && (!A || !B)) return OR_E_NULL;
-
-    int64_t ci[OR_MAXIDX], ki[2 * OR_MAXIDX];
-    memset(ci, 0, sizeof ci);
-    for (int64_t f = 0; f < q.nC; ++f) {
+/* Elements f0 .. f0 + count - 1 of C in the fixed order, ci holding the
+ * multi-index of f0. */
+static void or_run(const or_plan* pq, int64_t* ci, int64_t count,
+                   const double* A, const double* B, double* C, double alpha, double beta, int mode) {
+    const or_plan q = *pq;
+    int64_t ki[2 * OR_MAXIDX];
+    for (int64_t f = 0; f < count; ++f) {
         int64_t offC, offA, offB;
         or_free_offsets(&q, ci, &offC, &offA, &offB);
         double acc = 0.0, comp = 0.0;
@@ -215,6 +211,54 @@ int oracle_contract(const char* spec, const char* idx_chars, const int64_t* exte
         if (beta != 0.0) out += beta * C[offC];
         C[offC] = out;
         or_step(ci, q.extC, q.p.nc);
+    }
+}
+
+static int or_check(const char* spec, const char* idx_chars, const int64_t* extents, int n_idx,
+                    const int64_t* strides_A, const int64_t* strides_B, const int64_t* strides_C,
+                    const double* A, const double* B, const double* C, double alpha, or_plan* q) {
+    int rc = or_setup(spec, idx_chars, extents, n_idx, strides_A, strides_B, strides_C, q);
+    if (rc) return rc;
+    if (q->nC == 0) return OR_OK;
+    if (!C) return OR_E_NULL;
+    if (alpha != 0.0 && q->nK > 0 && (!A || !B)) return OR_E_NULL;
+    return OR_OK;
+}
+
+/* Returns 0 on success. */
+int oracle_contract(const char* spec, const char* idx_chars, const int64_t* extents, int n_idx,
+                    const double* A, const int64_t* strides_A,
+                    const double* B, const int64_t* strides_B,
+                    double* C, const int64_t* strides_C,
+                    double alpha, double beta, int mode) {
+    or_plan q;
+    int rc = or_check(spec, idx_chars, extents, n_idx, strides_A, strides_B, strides_C, A, B, C, alpha, &q);
+    if (rc || q.nC == 0) return rc;
+    int64_t ci[OR_MAXIDX];
+    memset(ci, 0, sizeof ci);
+    or_run(&q, ci, q.nC, A, B, C, alpha, beta, mode);
+    return OR_OK;
+}
+
+/* The same, C's outermost (last) index spread over `threads` host threads. */
+int oracle_contract_par(const char* spec, const char* idx_chars, const int64_t* extents, int n_idx,
+                        const double* A, const int64_t* strides_A,
+                        const double* B, const int64_t* strides_B,
+                        double* C, const int64_t* strides_C,
+                        double alpha, double beta, int threads) {
+    or_plan q;
+    int rc = or_check(spec, idx_chars, extents, n_idx, strides_A, strides_B, strides_C, A, B, C, alpha, &q);
+    if (rc || q.nC == 0) return rc;
+    const int last = q.p.nc - 1;
+    const int64_t outer = last >= 0 ? q.extC[last] : 1;
+    const int64_t per = q.nC / outer;          /* elements per value of the outermost index */
+    int64_t o;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads)
+    for (o = 0; o < outer; ++o) {
+        int64_t ci[OR_MAXIDX];
+        memset(ci, 0, sizeof ci);
+        if (last >= 0) ci[last] = o;
+        or_run(&q, ci, per, A, B, C, alpha, beta, 0);
     }
     return OR_OK;
 }

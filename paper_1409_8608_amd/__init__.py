@@ -246,9 +246,17 @@ def tc_batch_tune(h, top_k: int = 3):
 
 def tc_batch_contract(h, A_ptrs, B_ptrs, C_ptrs, alphas, betas, stream: int = 0):
     n = len(A_ptrs)
-    P = ctypes.c_void_p * n
-    D = ctypes.c_double * n
-    _check(lib.tc_batch_contract(h, P(*A_ptrs), P(*B_ptrs), P(*C_ptrs), D(*alphas), D(*betas), stream or None))
+    if not (len(B_ptrs) == len(C_ptrs) == len(alphas) == len(betas) == n):
+        raise ValueError("tc_batch_contract: A, B, C, alpha and beta need one entry per batch member")
+    members = ctypes.c_int()
+    _check(lib.tc_batch_info(h, ctypes.byref(members), None, None, None))
+    if n != members.value:
+        raise ValueError(f"tc_batch_contract: {n} entries for a batch of {members.value} members")
+    P = ctypes.c_void_p * max(1, n)
+    D = ctypes.c_double * max(1, n)
+    nul = lambda v: [x or None for x in v]
+    _check(lib.tc_batch_contract(h, P(*nul(A_ptrs)), P(*nul(B_ptrs)), P(*nul(C_ptrs)), D(*alphas), D(*betas),
+                                 stream or None))
 
 
 def tc_batch_destroy(h):
@@ -279,15 +287,41 @@ class Batch:
                 pass
             self.handle = None
 
-    def contract(self, As, Bs, Cs, alphas=None, betas=None, stream=None):
+    class Bound:
+        """Operands of every member, checked once against the plans, with the
+        pointer and scalar arrays of the C call built ahead: replaying a bound
+        set costs one library call and no Python work per member."""
+
+        def __init__(self, batch, As, Bs, Cs, alphas, betas):
+            n = len(batch.plans)
+            alphas = [1.0] * n if alphas is None else [float(x) for x in alphas]
+            betas = [0.0] * n if betas is None else [float(x) for x in betas]
+            if not (len(As) == len(Bs) == len(Cs) == len(alphas) == len(betas) == n):
+                raise ValueError(f"Batch.contract: {n} members need {n} entries of A, B, C, alpha and beta")
+            for p, A, B, C in zip(batch.plans, As, Bs, Cs):
+                p.check_tensors(A, B, C, device=False)
+            for p, A, B, C in zip(batch.plans, As, Bs, Cs):
+                p.check_tensors(A, B, C)
+            self.tensors = (list(As), list(Bs), list(Cs))          # kept alive while bound
+            ptr = lambda x: (x.data_ptr() or None) if x is not None else None   # None: not read (alpha = 0)
+            P, D = ctypes.c_void_p * max(1, n), ctypes.c_double * max(1, n)
+            self.args = (P(*[ptr(x) for x in As]), P(*[ptr(x) for x in Bs]), P(*[ptr(x) for x in Cs]),
+                         D(*alphas), D(*betas))
+
+    def bind(self, As, Bs, Cs, alphas=None, betas=None):
+        """Check the operands once; ``run`` then replays them."""
+        return Batch.Bound(self, As, Bs, Cs, alphas, betas)
+
+    def run(self, bound, stream=None):
         import torch
-        n = len(self.plans)
-        alphas = [1.0] * n if alphas is None else alphas
-        betas = [0.0] * n if betas is None else betas
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
-        tc_batch_contract(self.handle, [x.data_ptr() for x in As], [x.data_ptr() for x in Bs],
-                          [x.data_ptr() for x in Cs], alphas, betas, stream)
+        _check(lib.tc_batch_contract(self.handle, *bound.args, stream or None))
+
+    def contract(self, As, Bs, Cs, alphas=None, betas=None, stream=None):
+        """Check every member's tensors (dtype, shape, strides, device) and run
+        the batch; use ``bind`` and ``run`` to replay the same operands."""
+        self.run(self.bind(As, Bs, Cs, alphas, betas), stream)
 
     def tune(self, top_k: int = 2):
         tc_batch_tune(self.handle, top_k)
@@ -371,15 +405,30 @@ class Plan:
     def prepare(self):
         tc_plan_prepare(self.handle)
 
-    def contract(self, A, B, C, alpha=1.0, beta=0.0, stream=None):
-        """A, B, C: torch tensors on the GPU whose strides match the plan."""
+    TORCH_DTYPES = dict(f64="float64", f32="float32", c128="complex128", c64="complex64")
+
+    def check_tensors(self, A, B, C, device=True):
+        """Raise ValueError unless A, B and C (torch tensors, None where not
+        read) are GPU tensors of the plan's dtype, shape and strides (the
+        device only with ``device``)."""
         import torch
+        want = getattr(torch, self.TORCH_DTYPES[self.dtype])
         for t, x in zip("ABC", (A, B, C)):
             if x is None:
                 continue
+            if x.dtype != want:
+                raise ValueError(f"{t}: dtype {x.dtype} does not match the plan's {self.dtype}")
             if list(x.shape) != self.shape(t) or list(x.stride()) != self.strides[t] and x.numel() > 1:
                 raise ValueError(f"{t}: shape/strides {tuple(x.shape)}/{x.stride()} do not match the plan "
                                  f"{self.shape(t)}/{self.strides[t]}")
+        for t, x in zip("ABC", (A, B, C) if device else ()):
+            if x is not None and not x.is_cuda:
+                raise ValueError(f"{t}: tensor on {x.device}, the library takes GPU tensors")
+
+    def contract(self, A, B, C, alpha=1.0, beta=0.0, stream=None):
+        """A, B, C: torch tensors on the GPU whose dtype and strides match the plan."""
+        import torch
+        self.check_tensors(A, B, C)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         ptrs = [x.data_ptr() if x is not None else 0 for x in (A, B, C)]

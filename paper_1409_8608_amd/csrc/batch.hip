@@ -5,11 +5,12 @@
 // contraction to device memory and builds work lists of (contraction, tile)
 // pairs, one per (storage type, tile shape, operand layout) group, ordered
 // longest-first by the estimated cost of a tile (contracted length x tile
-// area).  The first tc_batch_contract captures a graph: a staging kernel that
-// copies the call's pointers and scalars from pinned host memory, a kernel
-// that zeroes the work counters (no memset nodes), and one persistent kernel
-// per group whose blocks take tiles off the group's counter, the groups spread
-// over up to four graph branches.  Later calls replay the graph.
+// area).  tc_batch_create (and tc_batch_tune after a change of shapes)
+// captures a graph: a staging kernel that copies the call's pointers and
+// scalars from pinned host memory, a kernel that zeroes the work counters (no
+// memset nodes), and one persistent kernel per group whose blocks take tiles
+// off the group's counter, the groups spread over up to four graph branches.
+// tc_batch_contract only writes the staging buffer and replays the graph.
 //
 // tc_batch_tune chooses each contraction's tile shape.  Seed: micro-benchmarks
 // time one full wave of tiles for each shape and contracted-length bucket, and
@@ -256,6 +257,7 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
     }
     std::memset(b->h_ptrs, 0, sizeof(BatchPtrs) * std::max(1, n));
     tc_status st = build_groups(b);
+    if (!st) st = capture(b);          // the graph reads the call's pointers from pinned staging
     if (st) {
         tc_batch_destroy(b);
         return st;
@@ -292,8 +294,9 @@ tc_status tc_batch_contract(tc_batch_t b, const void* const* A, const void* cons
     if (!A || !B || !C || !alpha || !beta) return fail(TC_E_NULL, "NULL argument array");
     for (int c = 0; c < n; ++c) {
         const Spec& s = b->plans[c]->spec;
-        if (!A[c] || !B[c] || !C[c]) return fail(TC_E_NULL, "NULL tensor in batch member " + std::to_string(c));
-        if (alpha[c] == 0.0) return fail(TC_E_UNSUPPORTED, "alpha = 0 in a batch (use tc_contract)");
+        if (!C[c]) return fail(TC_E_NULL, "NULL C in batch member " + std::to_string(c));
+        if (alpha[c] == 0.0) continue;            // A and B are not read
+        if (!A[c] || !B[c]) return fail(TC_E_NULL, "NULL A or B in batch member " + std::to_string(c));
         const int es = s.elem_bytes();
         auto ov = [&](const void* x, int64_t sx, const void* y, int64_t sy) {
             uintptr_t x0 = (uintptr_t)x, x1 = x0 + (uintptr_t)(sx * es), y0 = (uintptr_t)y, y1 = y0 + (uintptr_t)(sy * es);
@@ -314,10 +317,7 @@ tc_status tc_batch_contract(tc_batch_t b, const void* const* A, const void* cons
         b->h_ptrs[c].alpha = alpha[c];
         b->h_ptrs[c].beta = beta[c];
     }
-    if (!b->exec) {
-        tc_status st = capture(b);
-        if (st) return st;
-    }
+    if (!b->exec) return fail(TC_E_UNSUPPORTED, "batch graph missing (an earlier tc_batch_tune failed)");
     hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launch batch graph");
     e = hipEventRecord(b->done, (hipStream_t)stream);
@@ -461,7 +461,8 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
     auto use = [&](const std::vector<int>& shp) {
         b->shape = shp;
         drop_graph(b);
-        return build_groups(b);
+        tc_status r = build_groups(b);
+        return r ? r : capture(b);
     };
     tc_status ts = use(new_shape);
     double after_ms = 0.0;

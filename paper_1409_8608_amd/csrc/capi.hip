@@ -150,8 +150,27 @@ int ktab_vec_flags(const std::vector<int64_t>& tab, int v) {
 
 // ---------------------------------------------------------------------------
 namespace tc {
+static thread_local bool g_no_alloc = false;
+bool allocation_forbidden() { return g_no_alloc; }
+NoAllocScope::NoAllocScope() : saved(g_no_alloc) { g_no_alloc = true; }
+NoAllocScope::~NoAllocScope() { g_no_alloc = saved; }
+tc_status fail_unprepared() {
+    return fail(TC_E_UNSUPPORTED, "the plan's device workspace for the selected variant is not allocated "
+                                  "(no GPU was visible when the plan was built or the variant selected): "
+                                  "call tc_plan_prepare");
+}
+
+bool device_visible() {
+    static const bool visible = [] {
+        int n = 0;
+        return hipGetDeviceCount(&n) == hipSuccess && n > 0;
+    }();
+    return visible;
+}
+
 tc_status ensure_device_buffer(void** p, int64_t* cap, int64_t bytes) {
     if (bytes <= *cap) return TC_OK;
+    if (g_no_alloc) return fail_unprepared();
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     *cap = 0;
@@ -167,6 +186,7 @@ tc_status ensure_device_buffer(void** p, int64_t* cap, int64_t bytes) {
 using tc::ensure_device_buffer;
 
 static tc_status upload(void** p, int64_t* cap, const std::vector<int64_t>& v) {
+    if (allocation_forbidden()) return fail_unprepared();
     int64_t bytes = (int64_t)(v.size() * sizeof(int64_t));
     tc_status s = ensure_device_buffer(p, cap, bytes);
     if (s) return s;
@@ -228,7 +248,7 @@ tc_status prepare_plan(tc_plan_s* p) {
     bool f64 = s.dtype == TC_F64;
     int BK = mfma_bk(f64);
     if (p->selected == TC_VARIANT_FUSED || p->selected == TC_VARIANT_PREDICTED) {
-        if (!use_stream_kernel(s, p->gv) && p->d_ktab == nullptr) {
+        if (!use_stream_kernel(s, p->gv) && !p->ktab_ready) {
             std::vector<int64_t> tab = build_ktab(p->gv.k, BK, 4, mfma_a_first(p->gv.M, p->gv.N), 4);
             p->kpad = (int64_t)tab.size() / 2;
             p->kvec = ktab_vec_flags(tab, f64 ? 2 : 4);
@@ -242,12 +262,16 @@ tc_status prepare_plan(tc_plan_s* p) {
                 st = ensure_device_buffer(&p->d_splitk, &p->splitk_cap, ws);
                 if (st) return st;
             }
+            p->ktab_ready = true;
         }
         if (s.compute != TC_NATIVE) {
             tc_status st = prepare_split(p);
             if (st) return st;
         }
     }
+    if (p->selected == TC_VARIANT_PREDICTED && !p->have_prediction)
+        return fail(TC_E_VARIANT, "the prediction behind TC_VARIANT_PREDICTED was cleared (root gaps changed): "
+                                  "call tc_predict again or select a variant");
     int v = p->selected == TC_VARIANT_PREDICTED ? p->predicted_best : p->selected;
     if (v >= 0) {
         VariantPlan& vp = p->vplans()[v];
@@ -510,6 +534,7 @@ tc_status tc_plan(tc_plan_t* out, const char* spec, const char* index_chars, con
     }
     if (p->spec.is_complex()) {
         tc_status st = build_complex(p);
+        if (!st && device_visible()) st = prepare_plan(p);
         if (st) {
             tc_plan_destroy(p);
             return st;
@@ -524,6 +549,13 @@ tc_status tc_plan(tc_plan_t* out, const char* spec, const char* index_chars, con
         delete p;
         return fail(TC_E_UNSUPPORTED, "more than 8 dimension groups (after merging contiguous ones) "
                                       "in M, N, K, the batch indices or C");
+    }
+    if (device_visible()) {
+        tc_status st = prepare_plan(p);
+        if (st) {
+            tc_plan_destroy(p);
+            return st;
+        }
     }
     *out = p;
     return TC_OK;
@@ -584,7 +616,17 @@ tc_status tc_set_variant(tc_plan_t p, int variant) {
     }
     if (variant >= 0 && p->spec.compute != TC_NATIVE)
         return fail(TC_E_UNSUPPORTED, "split precision runs in the fused kernel only");
+    const int previous = p->selected;
     p->selected = variant;
+    // a member that would copy C has no GPU schedule: tc_contract refuses it
+    const bool runnable = variant < 0 || !p->vplans()[variant].needs_c_copy;
+    if (runnable && device_visible()) {
+        tc_status st = prepare_plan(p);
+        if (st) {
+            p->selected = previous;
+            return st;
+        }
+    }
     return TC_OK;
 }
 
@@ -613,7 +655,10 @@ static tc_status contract_entry(tc_plan_t p, const void* A, const void* B, void*
     if (st || !runs) return st;
     if (std::getenv("TC_FAULT") && std::strcmp(std::getenv("TC_FAULT"), "launch") == 0)
         return fail(TC_E_HIP, "injected launch failure (TC_FAULT=launch)");
-    st = prepare_plan(p);
+    {
+        NoAllocScope no_alloc;          // every buffer was allocated by tc_plan / tc_set_variant
+        st = prepare_plan(p);
+    }
     if (st) return st;
     if (p->real) return run_complex(p, A, B, C, alpha_re, alpha_im, beta_re, beta_im, (hipStream_t)stream);
     return contract_dispatch(p, A, B, C, alpha_re, beta_re, (hipStream_t)stream);

@@ -405,8 +405,7 @@ tc_status run_complex(tc_plan_s* p, const void* A, const void* B, void* C, doubl
         inner_beta = 1.0;
     }
 
-    tc_status stt = prepare_complex(p);
-    if (stt) return stt;
+    if (!p->d_zexp) return fail_unprepared();
     ZExpandArgs a{};
     a.src = p->zside == 0 ? A : B;
     a.dst = p->d_zexp;

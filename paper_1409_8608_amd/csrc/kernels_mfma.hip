@@ -200,7 +200,9 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     } else {
         (void)slice;
     }
-    const int64_t ktiles = kt_count;
+    // alpha = 0 reads neither A nor B: no K tiles, so the epilogue writes
+    // beta * C (zeros without reading C when beta = 0)
+    const int64_t ktiles = alpha_d == 0.0 ? 0 : kt_count;
     const int64_t* ktab0 = SPLIT ? a.ktab + 2 * k_first * BK : a.ktab;
 
     int64_t pctr[GT_MAXD];

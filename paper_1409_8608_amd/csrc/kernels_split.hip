@@ -720,6 +720,7 @@ static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 tc_status prepare_split(tc_plan_s* p) {
     if (p->d_split) return TC_OK;
+    if (allocation_forbidden()) return fail_unprepared();
     const bool fp8 = p->spec.compute == TC_FP8X3;
     const int SB = fp8 ? F8_BK : SPLIT_BK;   // K positions per product-kernel stage
     const int64_t tb = fp8 ? 1 : 2;          // bytes per term element

@@ -38,6 +38,7 @@ struct tc_plan_s {
 
     // device workspace (allocated by prepare, freed by destroy)
     void* d_ktab = nullptr;          // fused matrix-core K table
+    bool ktab_ready = false;         // d_ktab (and the split-K workspace) set up
     int64_t ktab_cap = 0, kpad = 0;
     int kvec = 0;                    // chunk flags of d_ktab (MfmaArgs::kvec)
     void* d_splitk = nullptr;        // split-K partial tiles of the fused kernel
@@ -77,6 +78,18 @@ namespace tc {
 extern thread_local std::string g_last_error;
 tc_status fail(tc_status s, const std::string& msg);
 tc_status ensure_device_buffer(void** p, int64_t* cap, int64_t bytes);
+// tc_contract never allocates: while it checks a plan's workspace, every step
+// of prepare_plan that would allocate or upload fails instead (fail_unprepared)
+bool allocation_forbidden();
+tc_status fail_unprepared();
+struct NoAllocScope {
+    bool saved;
+    NoAllocScope();
+    ~NoAllocScope();
+};
+// Is a HIP device visible to this process?  (Looked up once.)  Plans built
+// with one allocate their workspace at once; without one they stay host-only.
+bool device_visible();
 tc_status hip_fail(hipError_t e, const char* what);
 
 std::vector<int64_t> build_ktab(const std::vector<GtDim>& kd, int BK, int bA = 4, bool a_first = false, int G = 0);

@@ -361,6 +361,8 @@ extern "C" tc_status tc_predict(tc_plan_t p, tc_prediction* out, int capacity, i
         if (out[count - 1].predicted_s < best_t) best = TC_VARIANT_FUSED;
         p->predicted_best = best;
         p->have_prediction = true;
+        // a plan that selects the predicted member gets that member's workspace now
+        if (p->selected == TC_VARIANT_PREDICTED) st = prepare_plan(p);
     }
     if (c.st) (void)hipStreamDestroy(c.st);
     for (void* b : {c.A, c.B, c.C, c.scratch, (void*)c.sink})

@@ -313,3 +313,33 @@ def test_chain_root_gaps_match_oracle():
     assert checked == reachable >= 7
     for h in plans:
         tc.tc_plan_destroy(h)
+
+
+def test_binding_checks_tensors_before_the_library():
+    """Plan.contract and Batch.contract refuse tensors whose dtype, device,
+    shape or count do not match the plans, before any call reaches the C ABI
+    (a float32 tensor on an f64 plan would make every kernel read and write
+    twice its allocation)."""
+    import torch
+    p = tc.Plan("ab=ai,ib", dict(a=4, b=3, i=2), "f64")
+    ok = lambda shape, dt=torch.float64: torch.zeros(shape[::-1], dtype=dt).t()   # Fortran strides, CPU
+    A, B, C = ok((4, 2)), ok((2, 3)), ok((4, 3))
+    with pytest.raises(ValueError, match="dtype"):
+        p.contract(ok((4, 2), torch.float32), B, C)
+    with pytest.raises(ValueError, match="GPU"):
+        p.contract(A, B, C)                          # right dtype and strides, but host memory
+    with pytest.raises(ValueError, match="shape"):
+        p.contract(A, ok((3, 3)), C)
+    q = tc.Plan("ab=ai,ib", dict(a=4, b=3, i=2), "f32")
+    with pytest.raises(ValueError, match="dtype"):
+        q.contract(ok((4, 2), torch.float32), ok((2, 3), torch.float32), C)
+    b = tc.Batch.__new__(tc.Batch)               # member checks run before the batch handle is used
+    b.plans, b.handle = [p, p], None
+    with pytest.raises(ValueError, match="entries"):
+        b.contract([A, A], [B], [C, C])
+    with pytest.raises(ValueError, match="entries"):
+        b.contract([A, A], [B, B], [C, C], alphas=[1.0])
+    with pytest.raises(ValueError, match="dtype"):
+        b.contract([A, ok((4, 2), torch.float32)], [B, B], [C, C])
+    with pytest.raises(ValueError, match="one entry per batch member"):
+        tc.tc_batch_contract(None, [1, 2], [3], [4, 5], [1.0, 1.0], [0.0, 0.0])

@@ -86,8 +86,11 @@ def test_predict_with_chain_root_gaps():
     with pytest.raises(tc.TcError) as e:
         p.set_variant(tc.TC_VARIANT_PREDICTED)
     assert e.value.name == "TC_E_VARIANT"
+    A, B, _ = wl.tensors(spec, ext, np.random.default_rng(3))
+    with pytest.raises(tc.TcError) as e:     # nor does tc_contract run the member picked under the old gaps
+        run(p, A, B)
+    assert e.value.name == "TC_E_VARIANT"
     p.predict()
     p.set_variant(tc.TC_VARIANT_PREDICTED)
-    A, B, _ = wl.tensors(spec, ext, np.random.default_rng(3))
     got = run(p, A, B)
     check(spec, ext, A, B, got)

@@ -282,3 +282,24 @@ def test_random_general_specs_vs_brute(data):
     rng = np.random.default_rng(data.draw(st.integers(0, 2**31)))
     A, B = rand_tensor(rng, sa, ext, True), rand_tensor(rng, sb, ext, True)
     np.testing.assert_array_equal(oracle.contract(spec, ext, A, B), brute(spec, ext, A, B))
+
+
+@pytest.mark.parametrize("spec,ext", [
+    ("abc=ai,ibc", dict(a=13, b=7, c=9, i=5)),
+    ("abc=ija,jbic", dict(a=6, b=5, c=11, i=3, j=4)),
+    ("ab=iaj,jbi", dict(a=9, b=8, i=3, j=5)),
+    ("=i,i", dict(i=17)),
+    ("abcd=ai,ibcd", dict(a=3, b=4, c=2, d=6, i=3)),
+])
+def test_threaded_oracle_equals_serial(spec, ext):
+    """The CPU-baseline timing's threaded run (C's outermost index over host
+    threads) gives the serial oracle's values bit for bit, with alpha and beta,
+    for every pattern and a 0-d C."""
+    from paper_1409_8608_amd import workloads as wl
+    A, B, C0 = wl.tensors(spec, ext, np.random.default_rng(7), with_c=True)
+    for alpha, beta in ((1.0, 0.0), (-0.75, 1.5), (0.0, 2.0)):
+        r1 = oracle.contract(spec, ext, A, B, C=np.array(C0, order="F"), alpha=alpha, beta=beta)
+        for threads in (2, 5):
+            rt = oracle.contract(spec, ext, A, B, C=np.array(C0, order="F"), alpha=alpha, beta=beta,
+                                 threads=threads)
+            np.testing.assert_array_equal(rt, r1)
