@@ -365,6 +365,11 @@ def batched(args, torch, tc, wl, dtype):
     batch.tune(2)
     tune_s = time.perf_counter() - t0
     tuned_ms, _ = _events_time(run, 5, 3, torch)
+    t0 = time.perf_counter()
+    score = batch.score(256, 51)          # every candidate of 256 seeded members timed alone
+    score_s = time.perf_counter() - t0
+    on_members = sum(1 for t in range(len(plans)) if batch.choice(t)["variant"] >= 0)
+    batch.run(bound)                      # C again from the tuned graph (tuning and scoring overwrite it)
     info = batch.info()
     # sampled parity of the last replay
     rng = np.random.default_rng(3)
@@ -380,7 +385,10 @@ def batched(args, torch, tc, wl, dtype):
                redraws=redraws, gflop=round(flops / 1e9, 2), gbytes=round(bytes_ / 1e9, 2),
                sequential_ms=round(seq_ms, 3), sequential_wall_ms=round(seq_wall, 3),
                batched_ms=round(bat_ms, 3), batched_tuned_ms=round(tuned_ms, 3), tune_s=round(tune_s, 2),
-               speedup_vs_sequential=round(seq_ms / tuned_ms, 3), tune_hit_rate=info["tune_hit_rate"],
+               speedup_vs_sequential=round(seq_ms / tuned_ms, 3),
+               tuner=dict(top_k=2, candidates="(fused view | gemm members with all loops free) x 3 tile shapes",
+                          members_on_family_variants=on_members, score_s=round(score_s, 2),
+                          score={k: (round(v, 4) if isinstance(v, float) else v) for k, v in score.items()}),
                tiles=info["tiles"], groups=info["groups"], normwise_err_sampled_max=worst,
                gflops=round(flops / (tuned_ms * 1e-3) / 1e9, 1),
                roofline=dict(bound="max(mfma, hbm)", lower_bound_ms=round(bound_ms, 3),

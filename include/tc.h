@@ -317,16 +317,22 @@ tc_status tc_predict(tc_plan_t plan, tc_prediction* out, int capacity, int* n_ou
  * branches.  Errors: TC_E_NULL, TC_E_UNSUPPORTED, TC_E_NOMEM, TC_E_HIP. */
 tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n);
 
-/* Choose each member's tile shape: an estimate composed from device
- * micro-benchmarks (one wave of tiles per shape and contracted-length bucket)
- * ranks the shapes, the best `top_k` are timed on the device one member at a
- * time and the fastest is kept.  The whole batch is then timed with the new
- * shapes against the previous ones (graph replays), and the new shapes are
- * kept only if they beat two timings of the previous ones.  Uses -- and
- * overwrites C with alpha * contract(A, B) of -- the operands of the previous
- * tc_batch_contract, which must have been made.  Synchronous.  The share of members whose
- * estimated-best shape measured within 5% of the best is reported by
- * tc_batch_info. */
+/* Choose each member's candidate -- a loop/kernel variant (the fused GEMM
+ * view, or a gemm member of the paper's family whose loops are all free
+ * indices, Section 2) with a tile shape (128x128, 64x64, 32x128) -- the way
+ * Section 3 predicts a member: micro-benchmarks of the tile kernel run after
+ * the cache set-up a batch member meets (its operands cold: a remote region
+ * of 5/4 of the device cache), median of ten, composed by tile counts into an
+ * estimate per candidate.  The best `top_k` candidates by estimate are timed
+ * on the device one member at a time (after the same set-up) and the fastest
+ * picked.  The whole batch is then timed (graph replays) with those picks,
+ * with the estimate's first choices and with the previous choices; a new set
+ * replaces the kept one only if it beats two timings of it.  The kept choices
+ * go to a process-wide tuning cache that later batches start from, and the
+ * graph is captured again.  Uses --
+ * and overwrites C with alpha * contract(A, B) of -- the operands of the
+ * previous tc_batch_contract, which must have been made (members whose A or B
+ * was NULL keep their choice).  Synchronous; allocates tuning scratch. */
 tc_status tc_batch_tune(tc_batch_t batch, int top_k);
 
 /* Run all contractions (each Section 1's definition, as in tc_contract):
@@ -341,10 +347,46 @@ tc_status tc_batch_tune(tc_batch_t batch, int top_k);
 tc_status tc_batch_contract(tc_batch_t batch, const void* const* A, const void* const* B,
                             void* const* C, const double* alpha, const double* beta, void* stream);
 
-/* Members, work items (tiles), persistent-kernel groups and the tuner's hit
- * rate (-1 before tc_batch_tune; the share of members where the estimate's
- * pick measured within 5% of the best, the paper's goal of picking the
- * fastest algorithm, Section 1).  Any pointer may be NULL. */
+/* Scores of the tuner against exhaustive measurement (the paper's goal of
+ * picking the fastest algorithm, Section 1 and the conclusions): for a seeded
+ * sample of members, every candidate is timed alone after the batch's cache
+ * set-up (median of five), and four choices are compared with the measured
+ * best: the estimate's first choice, tc_batch_tune's pick among its top_k
+ * timed alone, the choice it kept after timing whole batches, and the untuned
+ * default (fused view, default shape).  A choice "hits" when it
+ * measures within 5% of the best (several candidates can be about equally
+ * fast); "argmin" counts exact picks of the fastest; the regret is the
+ * geometric mean of time(choice) / time(best). */
+typedef struct {
+    int    n_sampled;
+    double candidates_mean;        /* candidates (variant x shape) per sampled member */
+    double within5_seed, argmin_seed, regret_seed;
+    double within5_tuned, argmin_tuned, regret_tuned;
+    double within5_default, argmin_default, regret_default;
+    double member_best_share;      /* sampled members whose fastest candidate is a family member */
+    double within5_topk, argmin_topk, regret_topk;   /* tc_batch_tune's pick among its top_k timed alone */
+} tc_tune_score;
+
+/* Score the current choices on `sample` members drawn with `seed` (see
+ * tc_tune_score).  Uses -- and overwrites C of -- the previous
+ * tc_batch_contract's operands, as tc_batch_tune does.  Synchronous.
+ * Errors: TC_E_NULL, TC_E_UNSUPPORTED, TC_E_NOMEM, TC_E_HIP. */
+tc_status tc_batch_score(tc_batch_t batch, int sample, uint64_t seed, tc_tune_score* out);
+
+/* The candidate member `member` runs with: its variant (TC_VARIANT_FUSED or a
+ * 0-based family member of its plan), tile shape (0: 128x128, 1: 64x64,
+ * 2: 32x128) and how many candidates it has.  Any output pointer may be NULL. */
+tc_status tc_batch_choice(tc_batch_t batch, int member, int* variant, int* shape, int* n_candidates);
+
+/* Make member `member` run candidate (variant, shape) -- variant
+ * TC_VARIANT_FUSED or a family member of its plan that is a candidate (see
+ * tc_batch_tune), shape 0..2 -- and capture the graph again.  Allocates
+ * (work lists).  Errors: TC_E_NULL, TC_E_VARIANT, TC_E_NOMEM, TC_E_HIP. */
+tc_status tc_batch_set_choice(tc_batch_t batch, int member, int variant, int shape);
+
+/* Members, work items (tiles), persistent-kernel groups and the within-5%
+ * rate of the tuned choices in the last tc_batch_score (-1 before one).
+ * Any pointer may be NULL. */
 tc_status tc_batch_info(tc_batch_t batch, int* n_members, int64_t* n_tiles, int* n_groups, double* tune_hit_rate);
 
 /* Free a batch (its graph, work lists and staging buffers).  NULL is

@@ -28,7 +28,8 @@ EXPORTS = ("tc_plan", "tc_plan_destroy", "tc_variant_count", "tc_variant_get", "
            "tc_plan_prepare", "tc_plan_workspace", "tc_contract", "tc_contract_complex", "tc_access_distance", "tc_bench_classes",
            "tc_predict", "tc_batch_create", "tc_batch_tune", "tc_batch_contract", "tc_batch_destroy",
            "tc_batch_info", "tc_split_terms", "tc_status_str", "tc_last_error", "tc_set_root_gap",
-           "tc_chain_root_gaps", "tc_contract_noalloc")
+           "tc_chain_root_gaps", "tc_contract_noalloc", "tc_batch_score", "tc_batch_choice",
+           "tc_batch_set_choice")
 
 
 class TcError(RuntimeError):
@@ -52,6 +53,16 @@ class tc_setup_item(ctypes.Structure):
 class tc_bench_class(ctypes.Structure):
     _fields_ = [("label", ctypes.c_char * 16), ("weight", ctypes.c_double), ("n_items", ctypes.c_int),
                 ("items", tc_setup_item * TC_MAX_SETUP)]
+
+
+class tc_tune_score(ctypes.Structure):
+    _fields_ = [("n_sampled", ctypes.c_int), ("candidates_mean", ctypes.c_double),
+                ("within5_seed", ctypes.c_double), ("argmin_seed", ctypes.c_double), ("regret_seed", ctypes.c_double),
+                ("within5_tuned", ctypes.c_double), ("argmin_tuned", ctypes.c_double),
+                ("regret_tuned", ctypes.c_double), ("within5_default", ctypes.c_double),
+                ("argmin_default", ctypes.c_double), ("regret_default", ctypes.c_double),
+                ("member_best_share", ctypes.c_double), ("within5_topk", ctypes.c_double),
+                ("argmin_topk", ctypes.c_double), ("regret_topk", ctypes.c_double)]
 
 
 class tc_prediction(ctypes.Structure):
@@ -93,6 +104,10 @@ def _load():
         "tc_batch_contract": [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                               ctypes.POINTER(D), ctypes.POINTER(D), P],
         "tc_batch_destroy": [P],
+        "tc_batch_score": [P, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(tc_tune_score)],
+        "tc_batch_choice": [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                            ctypes.POINTER(ctypes.c_int)],
+        "tc_batch_set_choice": [P, ctypes.c_int, ctypes.c_int, ctypes.c_int],
         "tc_batch_info": [P, ctypes.POINTER(ctypes.c_int), I64P, ctypes.POINTER(ctypes.c_int),
                           ctypes.POINTER(ctypes.c_double)],
         "tc_split_terms": [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_int32), I64P, I64P],
@@ -259,6 +274,22 @@ def tc_batch_contract(h, A_ptrs, B_ptrs, C_ptrs, alphas, betas, stream: int = 0)
                                  stream or None))
 
 
+def tc_batch_score(h, sample: int = 256, seed: int = 51) -> dict:
+    sc = tc_tune_score()
+    _check(lib.tc_batch_score(h, int(sample), int(seed), ctypes.byref(sc)))
+    return {name: getattr(sc, name) for name, _ in tc_tune_score._fields_}
+
+
+def tc_batch_choice(h, member: int) -> dict:
+    v, sh, nc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib.tc_batch_choice(h, int(member), ctypes.byref(v), ctypes.byref(sh), ctypes.byref(nc)))
+    return dict(variant=v.value, shape=sh.value, candidates=nc.value)
+
+
+def tc_batch_set_choice(h, member: int, variant: int, shape: int):
+    _check(lib.tc_batch_set_choice(h, int(member), int(variant), int(shape)))
+
+
 def tc_batch_destroy(h):
     _check(lib.tc_batch_destroy(h))
 
@@ -325,6 +356,15 @@ class Batch:
 
     def tune(self, top_k: int = 2):
         tc_batch_tune(self.handle, top_k)
+
+    def score(self, sample: int = 256, seed: int = 51):
+        return tc_batch_score(self.handle, sample, seed)
+
+    def choice(self, member: int):
+        return tc_batch_choice(self.handle, member)
+
+    def set_choice(self, member: int, variant: int, shape: int):
+        tc_batch_set_choice(self.handle, member, variant, shape)
 
     def info(self):
         return tc_batch_info(self.handle)

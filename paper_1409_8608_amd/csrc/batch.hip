@@ -1,30 +1,48 @@
 // Batches: many independent contractions in one HIP graph.
 //
-// tc_batch_create turns every contraction into matrix-core tiles of a chosen
-// shape (128x128, 64x64 or 32x128 outputs), writes one static descriptor per
-// contraction to device memory and builds work lists of (contraction, tile)
-// pairs, one per (storage type, tile shape, operand layout) group, ordered
-// longest-first by the estimated cost of a tile (contracted length x tile
-// area).  tc_batch_create (and tc_batch_tune after a change of shapes)
-// captures a graph: a staging kernel that copies the call's pointers and
-// scalars from pinned host memory, a kernel that zeroes the work counters (no
-// memset nodes), and one persistent kernel per group whose blocks take tiles
-// off the group's counter, the groups spread over up to four graph branches.
-// tc_batch_contract only writes the staging buffer and replays the graph.
+// Every contraction of a batch runs as matrix-core tiles in a persistent
+// kernel.  Its candidates are (loop/kernel variant x tile shape): the fused
+// GEMM view, or a gemm member of the paper's family (Section 2) whose loops
+// are all free indices, so that they become batch dimensions of the tile
+// kernel -- for C_abc = A_ai B_ibc, c-gemm and b-gemm -- each with the tile
+// shapes 128x128, 64x64 and 32x128 (m x n).  tc_batch_create picks the fused
+// view with a default shape (or the tuning cache's choice for a contraction
+// seen before), writes one static descriptor per contraction to device memory,
+// builds work lists of (contraction, tile) pairs, one per (storage type, tile
+// shape, operand layout) group, ordered longest-first by the estimated cost of
+// a tile (contracted length x tile area), and captures a graph: a staging
+// kernel that copies the call's pointers and scalars from pinned host memory,
+// a kernel that zeroes the work counters (no memset nodes), and one persistent
+// kernel per group whose blocks take tiles off the group's counter, the
+// groups spread over up to four graph branches.  tc_batch_contract only writes
+// the staging buffer and replays the graph.
 //
-// tc_batch_tune chooses each contraction's tile shape.  Seed: micro-benchmarks
-// time one full wave of tiles for each shape and contracted-length bucket, and
-// a contraction's estimate is its tile count times the per-tile share of that
-// wave (cost composed from kernel micro-benchmarks, as in Section 3).  The
-// top_k candidates by estimate are then timed on the device, one contraction
-// at a time, and the fastest is kept; the share of contractions where the
-// estimate's first choice was within 5% of the measured best is recorded.
+// tc_batch_tune chooses each contraction's candidate the way Section 3
+// predicts a family member: micro-benchmarks of the kernel, run after the
+// cache set-up the member meets, composed by invocation counts.  In a batch a
+// member's operands were last touched a whole replay ago, so every walk
+// reaches the root with a gap of the batch's other data, beyond 5/4 of the
+// device cache: the set-up is one remote region of 5/4 of the cache (every
+// operand cold).  One micro-benchmark per (storage, shape, contracted-length
+// bucket, operand layouts, C layout) times a representative launch after that
+// set-up (median of ten); a candidate's estimate is its tile count times the
+// per-tile share of the device.  The top_k candidates by estimate are then
+// timed alone, each after the same set-up, and the fastest is picked.  Whole
+// batches are timed with those picks, with the estimate's first choices and
+// with the previous choices, and the fastest set is kept (and put in the
+// tuning cache).  tc_batch_score times every candidate of a seeded sample of
+// members alone, the same way, and reports how often the estimate's first
+// choice, the top_k pick, the kept choice and the untuned default fall within
+// 5% of the measured best (and are the best), with their geometric-mean
+// regret.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -32,6 +50,18 @@
 #include "plan.h"
 
 using namespace tc;
+
+namespace {
+
+// One way to run a batch member: a loop/kernel variant (the fused view or a
+// gemm member) with a tile shape.
+struct Cand {
+    int variant;        // TC_VARIANT_FUSED or a family member index
+    int shape;          // 0: 128x128, 1: 64x64, 2: 32x128
+    int64_t tab_off;    // its K table in the batch's table array
+    int64_t kpad;
+    bool swap;          // A and B exchange places in the tile kernel
+};
 
 struct BatchGroup {
     bool f64;
@@ -42,10 +72,36 @@ struct BatchGroup {
     int grid = 1;
 };
 
+constexpr int kShapes = 3;
+constexpr int BATCH_BK = 16;
+constexpr double kCacheBytes = 256.0 * 1024 * 1024;   // the device's last-level cache
+
+// Tuning cache: a contraction's kept candidate (variant, shape) by its plan
+// signature, for the batches a process builds later.
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune_cache;
+
+std::string signature(const tc_plan_s* p) {
+    const Spec& s = p->spec;
+    std::string k = std::to_string((int)s.dtype) + "|" + s.a + "," + s.b + "=" + s.c + "|";
+    for (char ch : s.base) k += std::to_string(s.e(ch)) + ",";
+    for (int t = 0; t < 3; ++t) {
+        k += "|";
+        for (char ch : s.letters(t)) k += std::to_string(s.stride(t, ch)) + ",";
+    }
+    return k;
+}
+
+}  // namespace
+
 struct tc_batch_s {
     std::vector<tc_plan_s*> plans;
-    std::vector<MfmaArgs> items;     // static descriptors (pointers filled per call)
-    std::vector<int> shape;          // tile shape per contraction
+    std::vector<std::vector<Cand>> cands;   // per member
+    std::vector<int> choice;                // index into cands[c]
+    std::vector<int> deflt;                 // the untuned default's index
+    std::vector<std::vector<double>> est;   // seed estimates (seconds), filled by tuning
+    std::vector<int> topk;                  // the tuner's pick among the top_k timed alone (-1: none)
+    std::vector<MfmaArgs> items;            // static descriptors of the chosen candidates
     std::vector<BatchGroup> groups;
     MfmaArgs* d_items = nullptr;
     BatchPtrs* d_ptrs = nullptr;
@@ -59,13 +115,10 @@ struct tc_batch_s {
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
     bool launched = false;
-    double hit_rate = -1.0;
-    int n_tuned = 0;
+    double hit_rate = -1.0;          // within-5% rate of the tuned choice in the last score
 };
 
 namespace tc {
-
-constexpr int BATCH_BK = 16;
 
 __global__ void k_stage(const BatchPtrs* __restrict__ src, BatchPtrs* __restrict__ dst, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -92,9 +145,64 @@ static void drop_graph(tc_batch_s* b) {
     b->graph = nullptr;
 }
 
+static int default_shape(const MfmaArgs& a) { return a.M <= 32 ? 2 : (a.M <= 64 || a.N <= 64) ? 1 : 0; }
+
+// A family member the tile kernel runs as one item: a gemm whose loops are all
+// free indices (they become batch dimensions), with no copies.
+static bool batchable_member(const VariantPlan& vp) {
+    return vp.mfma && vp.copies.empty() && vp.hoisted.empty() && vp.body.pass.n == 0 && !vp.needs_c_copy;
+}
+
+// The static descriptor of candidate `cd` of member `c` (pointers unset).
+static MfmaArgs make_item(const tc_batch_s* b, int c, const Cand& cd) {
+    tc_plan_s* p = b->plans[c];
+    MfmaArgs a{};
+    if (cd.variant == TC_VARIANT_FUSED) {
+        const GemmView& gv = p->gv;
+        a.m.n = (int)gv.m.size();
+        for (int d = 0; d < a.m.n; ++d) a.m.d[d] = gv.m[d];
+        a.n.n = (int)gv.n.size();
+        for (int d = 0; d < a.n.n; ++d) a.n.d[d] = gv.n[d];
+        a.batch.n = (int)gv.b.size();
+        a.nbatch = 1;
+        for (int d = 0; d < a.batch.n; ++d) {
+            a.batch.d[d] = gv.b[d];
+            a.nbatch *= gv.b[d].ext;
+        }
+        a.M = gv.M;
+        a.N = gv.N;
+    } else {
+        // the member's body (Section 2 loop nest on the device): M and N the
+        // kernel's kept free indices, its loops the batch dimensions
+        const GtDesc& d = p->vplans()[cd.variant].body;
+        a.m.n = d.nm;
+        if (d.nm) a.m.d[0] = d.out.d[0];
+        a.n.n = d.nn;
+        if (d.nn) a.n.d[0] = d.out.d[d.nm];
+        a.batch.n = 0;
+        a.nbatch = 1;
+        for (int q = d.nm + d.nn; q < d.out.n; ++q) {
+            a.batch.d[a.batch.n++] = d.out.d[q];
+            a.nbatch *= d.out.d[q].ext;
+        }
+        a.M = d.nm ? d.out.d[0].ext : 1;
+        a.N = d.nn ? d.out.d[d.nm].ext : 1;
+    }
+    a.pass.n = 0;
+    a.npass = 1;
+    a.ktab = b->d_ktab + cd.tab_off;
+    a.Kpad = cd.kpad;
+    a.mode = 0;
+    mfma_tiles_shape(cd.shape, a);
+    return a;
+}
+
 // work lists per group, longest tiles first
 static tc_status build_groups(tc_batch_s* b) {
     free_groups(b);
+    const int n = (int)b->plans.size();
+    b->items.resize(n);
+    for (int c = 0; c < n; ++c) b->items[c] = make_item(b, c, b->cands[c][b->choice[c]]);
     std::map<int, int> gid;   // key -> group index
     std::vector<std::vector<std::pair<int64_t, int2>>> lists;
     int ncu = 256;
@@ -103,12 +211,11 @@ static tc_status build_groups(tc_batch_s* b) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
     }
-    for (int c = 0; c < (int)b->items.size(); ++c) {
+    for (int c = 0; c < n; ++c) {
         MfmaArgs& a = b->items[c];
         const bool f64 = b->plans[c]->spec.dtype == TC_F64;
         const bool ak = mfma_kmajor_a(a), bk = mfma_kmajor_b(a);
-        const int sh = b->shape[c];
-        mfma_tiles_shape(sh, a);
+        const int sh = b->cands[c][b->choice[c]].shape;
         const int key = (f64 ? 16 : 0) | (sh << 2) | (ak ? 2 : 0) | (bk ? 1 : 0);   // sh in 0..3
         if (!gid.count(key)) {
             gid[key] = (int)b->groups.size();
@@ -180,9 +287,126 @@ static tc_status capture(tc_batch_s* b) {
     return TC_OK;
 }
 
-constexpr int kShapes = 3;   // tile shapes 128x128, 64x64, 32x128
+static tc_status rebuild(tc_batch_s* b) {
+    drop_graph(b);
+    tc_status st = build_groups(b);
+    return st ? st : capture(b);
+}
 
-static int default_shape(const MfmaArgs& a) { return a.M <= 32 ? 2 : (a.M <= 64 || a.N <= 64) ? 1 : 0; }
+// Timing of single members' candidates after the batch's cache set-up (every
+// operand cold: a remote region of 5/4 of the device cache is touched first).
+struct Timer {
+    tc_batch_s* b;
+    hipStream_t st;
+    void* scratch = nullptr;
+    float* sink = nullptr;
+    int64_t scratch_bytes = 0;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    int ncu = 256;
+
+    tc_status open() {
+        st = b->cap;
+        scratch_bytes = (int64_t)(1.25 * kCacheBytes) + (1 << 20);
+        if (hipMalloc(&scratch, (size_t)scratch_bytes) != hipSuccess) return fail(TC_E_NOMEM, "tuning scratch");
+        if (hipMalloc(&sink, 256) != hipSuccess) return fail(TC_E_NOMEM, "tuning scratch");
+        if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return fail(TC_E_HIP, "events");
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            ncu = prop.multiProcessorCount;
+        return TC_OK;
+    }
+    ~Timer() {
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+        if (scratch) (void)hipFree(scratch);
+        if (sink) (void)hipFree(sink);
+    }
+    // the previous call gave this member all three operands (an alpha = 0
+    // member may have left A and B out: it is not timed)
+    bool usable(int c) const { return b->h_ptrs[c].A && b->h_ptrs[c].B && b->h_ptrs[c].C; }
+    MfmaArgs item(int c, const Cand& cd) {
+        MfmaArgs a = make_item(b, c, cd);
+        const BatchPtrs& pt = b->h_ptrs[c];
+        a.A = cd.swap ? pt.B : pt.A;
+        a.B = cd.swap ? pt.A : pt.B;
+        a.C = pt.C;
+        a.alpha = pt.alpha == 0.0 ? 1.0 : pt.alpha;
+        a.beta = 0.0;
+        return a;
+    }
+    // median of `reps` timings (seconds) of candidate cd of member c, one warm-up first
+    hipError_t time(int c, const Cand& cd, int reps, double* out) {
+        MfmaArgs a = item(c, cd);
+        const bool f64 = b->plans[c]->spec.dtype == TC_F64;
+        std::vector<float> ts;
+        for (int r = 0; r <= reps; ++r) {
+            hipError_t e = launch_touch(scratch, scratch_bytes, sink, st);
+            if (e == hipSuccess) e = hipEventRecord(t0, st);
+            if (e == hipSuccess) e = launch_mfma_shape(f64, cd.shape, a, st);
+            if (e == hipSuccess) e = hipEventRecord(t1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (e != hipSuccess) return e;
+            if (r > 0) ts.push_back(ms);
+        }
+        std::sort(ts.begin(), ts.end());
+        *out = ts[ts.size() / 2] * 1e-3;
+        return hipSuccess;
+    }
+};
+
+static int kbucket(int64_t kpad) {
+    int bkt = 0;
+    while ((16LL << bkt) < kpad && bkt < 12) ++bkt;
+    return bkt;
+}
+
+// micro-benchmark key of a candidate: storage, shape, contracted-length
+// bucket, operand layouts, C unit-stride along m
+static std::string bench_key(const tc_batch_s* b, int c, const Cand& cd, const MfmaArgs& a) {
+    const bool cm1 = a.m.n > 0 && a.m.d[0].sC == 1;
+    return std::to_string((int)b->plans[c]->spec.dtype) + "/" + std::to_string(cd.shape) + "/" +
+           std::to_string(kbucket(cd.kpad)) + "/" + std::to_string((int)mfma_kmajor_a(a)) +
+           std::to_string((int)mfma_kmajor_b(a)) + std::to_string((int)cm1);
+}
+
+// Seed estimates of every candidate (see the file comment).
+static tc_status seed_estimates(tc_batch_s* b, Timer& tm) {
+    const int n = (int)b->plans.size();
+    std::map<std::string, std::pair<int64_t, std::pair<int, int>>> rep;   // key -> (tiles, (member, cand))
+    for (int c = 0; c < n; ++c)
+        for (int j = 0; j < (int)b->cands[c].size() && tm.usable(c); ++j) {
+            const MfmaArgs a = make_item(b, c, b->cands[c][j]);
+            const std::string key = bench_key(b, c, b->cands[c][j], a);
+            auto it = rep.find(key);
+            if (it == rep.end() || it->second.first < a.ntiles) rep[key] = {a.ntiles, {c, j}};
+        }
+    std::map<std::string, double> per_tile;
+    for (auto& kv : rep) {
+        const int c = kv.second.second.first, j = kv.second.second.second;
+        const Cand& cd = b->cands[c][j];
+        const MfmaArgs a = make_item(b, c, cd);
+        const bool f64 = b->plans[c]->spec.dtype == TC_F64;
+        double t;
+        hipError_t e = tm.time(c, cd, 10, &t);            // Section 3: median of ten
+        if (e != hipSuccess) return hip_fail(e, "tuning micro-benchmark");
+        const int64_t wave = (int64_t)mfma_batch_occupancy(f64, cd.shape, mfma_kmajor_a(a), mfma_kmajor_b(a)) * tm.ncu;
+        per_tile[kv.first] = t / (double)std::max<int64_t>(a.ntiles, wave);
+    }
+    b->est.assign(n, {});
+    for (int c = 0; c < n; ++c)
+        for (const Cand& cd : b->cands[c]) {
+            const MfmaArgs a = make_item(b, c, cd);
+            b->est[c].push_back(per_tile[bench_key(b, c, cd, a)] * (double)a.ntiles);
+        }
+    return TC_OK;
+}
+
+static int argmin(const std::vector<double>& v) {
+    return (int)(std::min_element(v.begin(), v.end()) - v.begin());
+}
 
 }  // namespace tc
 
@@ -195,7 +419,6 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
     tc_batch_s* b = new (std::nothrow) tc_batch_s();
     if (!b) return fail(TC_E_NOMEM, "host allocation");
     std::vector<int64_t> tab_all;
-    std::vector<int64_t> tab_off;
     for (int c = 0; c < n; ++c) {
         tc_plan_s* p = plans[c];
         if (!p) {
@@ -214,35 +437,44 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
             delete b;
             return fail(TC_E_UNSUPPORTED, "batch members need a non-empty C and contracted extent");
         }
-        const GemmView& gv = p->gv;
-        std::vector<int64_t> tab = build_ktab(gv.k, BATCH_BK);
-        tab_off.push_back((int64_t)tab_all.size());
-        tab_all.insert(tab_all.end(), tab.begin(), tab.end());
-        MfmaArgs a{};
-        a.m.n = (int)gv.m.size();
-        for (int d = 0; d < a.m.n; ++d) a.m.d[d] = gv.m[d];
-        a.n.n = (int)gv.n.size();
-        for (int d = 0; d < a.n.n; ++d) a.n.d[d] = gv.n[d];
-        a.batch.n = (int)gv.b.size();
-        a.nbatch = 1;
-        for (int d = 0; d < a.batch.n; ++d) {
-            a.batch.d[d] = gv.b[d];
-            a.nbatch *= gv.b[d].ext;
-        }
-        a.pass.n = 0;
-        a.M = gv.M;
-        a.N = gv.N;
-        a.Kpad = (int64_t)tab.size() / 2;
-        a.npass = 1;
-        a.mode = 0;
-        b->items.push_back(a);
         b->plans.push_back(p);
-        b->shape.push_back(default_shape(a));
+        std::vector<Cand> cs;
+        auto add_variant = [&](int v, const std::vector<GtDim>& kd, bool swap) {
+            std::vector<int64_t> tab = build_ktab(kd, BATCH_BK);
+            const int64_t off = (int64_t)tab_all.size();
+            tab_all.insert(tab_all.end(), tab.begin(), tab.end());
+            for (int sh = 0; sh < kShapes; ++sh) cs.push_back(Cand{v, sh, off, (int64_t)tab.size() / 2, swap});
+        };
+        add_variant(TC_VARIANT_FUSED, p->gv.k, p->gv.swapped);
+        // gemm members keep the one contracted index: only specs with a single
+        // contracted index (and no batch or trace index) have members whose
+        // loops are all free
+        if (p->spec.contracted.size() == 1 && !p->spec.general()) {
+            for (int v = 0; v < (int)p->fam().size(); ++v) {
+                const VariantPlan& vp = p->vplans()[v];
+                if (batchable_member(vp)) add_variant(v, {vp.body.kb}, false);
+            }
+        }
+        b->cands.push_back(cs);
     }
     hipError_t e = hipMalloc(&b->d_ktab, sizeof(int64_t) * std::max<size_t>(1, tab_all.size()));
     if (e == hipSuccess && !tab_all.empty())
         e = hipMemcpy(b->d_ktab, tab_all.data(), sizeof(int64_t) * tab_all.size(), hipMemcpyHostToDevice);
-    for (int c = 0; c < n; ++c) b->items[c].ktab = b->d_ktab + tab_off[c];
+    // default: the fused view with the default shape, or the tuning cache's choice
+    for (int c = 0; c < n && e == hipSuccess; ++c) {
+        int d = 0;
+        const MfmaArgs a0 = make_item(b, c, b->cands[c][0]);
+        for (int j = 0; j < (int)b->cands[c].size(); ++j)
+            if (b->cands[c][j].variant == TC_VARIANT_FUSED && b->cands[c][j].shape == default_shape(a0)) d = j;
+        b->deflt.push_back(d);
+        int ch = d;
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(signature(b->plans[c]));
+        if (it != g_tune_cache.end())
+            for (int j = 0; j < (int)b->cands[c].size(); ++j)
+                if (b->cands[c][j].variant == it->second.first && b->cands[c][j].shape == it->second.second) ch = j;
+        b->choice.push_back(ch);
+    }
     if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(MfmaArgs) * std::max(1, n));
     if (e == hipSuccess) e = hipMalloc(&b->d_ptrs, sizeof(BatchPtrs) * std::max(1, n));
     if (e == hipSuccess) e = hipHostMalloc(&b->h_ptrs, sizeof(BatchPtrs) * std::max(1, n), hipHostMallocDefault);
@@ -256,8 +488,7 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
         return fail(TC_E_NOMEM, std::string("batch set-up: ") + hipGetErrorString(e));
     }
     std::memset(b->h_ptrs, 0, sizeof(BatchPtrs) * std::max(1, n));
-    tc_status st = build_groups(b);
-    if (!st) st = capture(b);          // the graph reads the call's pointers from pinned staging
+    tc_status st = rebuild(b);          // the graph reads the call's pointers from pinned staging
     if (st) {
         tc_batch_destroy(b);
         return st;
@@ -310,7 +541,7 @@ tc_status tc_batch_contract(tc_batch_t b, const void* const* A, const void* cons
         if (e != hipSuccess) return hip_fail(e, "wait for previous batch");
     }
     for (int c = 0; c < n; ++c) {
-        const bool sw = b->plans[c]->gv.swapped;
+        const bool sw = b->cands[c][b->choice[c]].swap;
         b->h_ptrs[c].A = sw ? B[c] : A[c];
         b->h_ptrs[c].B = sw ? A[c] : B[c];
         b->h_ptrs[c].C = C[c];
@@ -326,7 +557,7 @@ tc_status tc_batch_contract(tc_batch_t b, const void* const* A, const void* cons
     return TC_OK;
 }
 
-// Tile-shape tuning (see the file comment).  Uses the operands of the previous
+// Candidate choice (see the file comment).  Uses the operands of the previous
 // tc_batch_contract call, which must have been made.
 tc_status tc_batch_tune(tc_batch_t b, int top_k) {
     if (!b) return fail(TC_E_NULL, "batch is NULL");
@@ -334,160 +565,210 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
     if (top_k < 1) top_k = 1;
     hipError_t e = hipEventSynchronize(b->done);
     if (e != hipSuccess) return hip_fail(e, "synchronize");
-    const int n = (int)b->items.size();
-    hipStream_t st = b->cap;
-    hipEvent_t t0, t1;
-    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return fail(TC_E_HIP, "events");
-    // Whole-batch time of the current configuration: graph replays with the
-    // previous call's operands and beta = 0 (C := alpha * contract(A, B)).
+    const int n = (int)b->plans.size();
+    // the tuned members' staging entries: the previous call's pointers (in
+    // candidate-independent order) and alpha; C := alpha * contract(A, B)
+    for (int c = 0; c < n; ++c)
+        if (b->cands[c][b->choice[c]].swap) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
+    Timer tm{b, nullptr};
+    tc_status st = tm.open();
+    if (!st) st = seed_estimates(b, tm);
+    // whole-batch time of a configuration: graph replays with beta = 0
     auto time_graph = [&](double* out) -> tc_status {
-        for (int c = 0; c < n; ++c) b->h_ptrs[c].beta = 0.0;
-        if (!b->exec) {
-            tc_status cs = capture(b);
-            if (cs) return cs;
+        for (int c = 0; c < n; ++c) {
+            b->h_ptrs[c].beta = 0.0;
+            if (b->h_ptrs[c].alpha == 0.0) b->h_ptrs[c].alpha = 1.0;
         }
-        hipError_t err = hipGraphLaunch(b->exec, st);   // warm-up
-        if (err == hipSuccess) err = hipEventRecord(t0, st);
-        for (int r = 0; r < 5 && err == hipSuccess; ++r) err = hipGraphLaunch(b->exec, st);
-        if (err == hipSuccess) err = hipEventRecord(t1, st);
-        if (err == hipSuccess) err = hipEventSynchronize(t1);
+        // staging holds the pointers in A, B order; the graph wants each
+        // member's kernel order
+        std::vector<BatchPtrs> keep(b->h_ptrs, b->h_ptrs + n);
+        for (int c = 0; c < n; ++c)
+            if (b->cands[c][b->choice[c]].swap) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
+        hipError_t err = hipGraphLaunch(b->exec, tm.st);   // warm-up
+        if (err == hipSuccess) err = hipEventRecord(tm.t0, tm.st);
+        for (int r = 0; r < 5 && err == hipSuccess; ++r) err = hipGraphLaunch(b->exec, tm.st);
+        if (err == hipSuccess) err = hipEventRecord(tm.t1, tm.st);
+        if (err == hipSuccess) err = hipEventSynchronize(tm.t1);
         float ms = 0;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, t0, t1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, tm.t0, tm.t1);
+        std::copy(keep.begin(), keep.end(), b->h_ptrs);
         if (err != hipSuccess) return hip_fail(err, "batch timing replays");
         *out = ms / 5.0;
         return TC_OK;
     };
     double before_ms = 0.0;
-    {
-        tc_status ts = time_graph(&before_ms);
-        if (ts) {
-            (void)hipEventDestroy(t0);
-            (void)hipEventDestroy(t1);
-            return ts;
-        }
-    }
-    const std::vector<int> old_shape = b->shape;
-    auto time_one = [&](int c, int sh, double* out) -> hipError_t {
-        MfmaArgs a = b->items[c];
-        a.A = b->h_ptrs[c].A;
-        a.B = b->h_ptrs[c].B;
-        a.C = b->h_ptrs[c].C;
-        a.alpha = b->h_ptrs[c].alpha;
-        a.beta = 0.0;
-        mfma_tiles_shape(sh, a);
-        const bool f64 = b->plans[c]->spec.dtype == TC_F64;
-        std::vector<float> ts;
-        for (int r = 0; r < 4; ++r) {
-            hipError_t err = hipEventRecord(t0, st);
-            if (err == hipSuccess) err = launch_mfma_shape(f64, sh, a, st);
-            if (err == hipSuccess) err = hipEventRecord(t1, st);
-            if (err == hipSuccess) err = hipEventSynchronize(t1);
-            float ms = 0;
-            if (err == hipSuccess) err = hipEventElapsedTime(&ms, t0, t1);
-            if (err != hipSuccess) return err;
-            if (r > 0) ts.push_back(ms);
-        }
-        std::sort(ts.begin(), ts.end());
-        *out = ts[ts.size() / 2] * 1e-3;
-        return hipSuccess;
-    };
-    // seed: per (storage, shape, K bucket) the time of one tile, measured on the
-    // batch's own member with the most tiles in that bucket, divided by its tile
-    // count (a wave's worth of tiles shares the device)
-    std::map<std::string, double> tile_cost;
-    auto bucket = [](int64_t kpad) {
-        int bkt = 0;
-        while ((16LL << bkt) < kpad && bkt < 12) ++bkt;
-        return bkt;
-    };
-    std::map<std::string, std::pair<int64_t, int>> rep;   // key -> (tiles, member)
-    for (int c = 0; c < n; ++c)
-        for (int sh = 0; sh < kShapes; ++sh) {
-            MfmaArgs a = b->items[c];
-            mfma_tiles_shape(sh, a);
-            std::string key = std::to_string(b->plans[c]->spec.dtype) + "/" + std::to_string(sh) + "/" +
-                              std::to_string(bucket(a.Kpad));
-            if (!rep.count(key) || rep[key].first < a.ntiles) rep[key] = {a.ntiles, c};
-        }
-    for (auto& kv : rep) {
-        int sh = kv.first[2] - '0';
-        double t;
-        e = time_one(kv.second.second, sh, &t);
-        if (e != hipSuccess) break;
-        tile_cost[kv.first] = t / (double)std::max<int64_t>(1, kv.second.first);
-    }
-    int hits = 0;
-    for (int c = 0; c < n && e == hipSuccess; ++c) {
-        std::vector<std::pair<double, int>> cand;
-        for (int sh = 0; sh < kShapes; ++sh) {
-            MfmaArgs a = b->items[c];
-            mfma_tiles_shape(sh, a);
-            std::string key = std::to_string(b->plans[c]->spec.dtype) + "/" + std::to_string(sh) + "/" +
-                              std::to_string(bucket(a.Kpad));
-            cand.push_back({tile_cost[key] * (double)a.ntiles, sh});
-        }
-        std::sort(cand.begin(), cand.end());
-        int seed_pick = cand[0].second;
+    if (!st) st = time_graph(&before_ms);
+    const std::vector<int> old_choice = b->choice;
+    std::vector<int> seed_choice = b->choice, iso_choice = b->choice;
+    b->topk.assign(n, -1);
+    for (int c = 0; c < n && !st; ++c) {
+        if (!tm.usable(c)) continue;
+        std::vector<int> order(b->cands[c].size());
+        for (int j = 0; j < (int)order.size(); ++j) order[j] = j;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->est[c][x] < b->est[c][y]; });
+        seed_choice[c] = order[0];
         double best_t = INFINITY;
-        int best = seed_pick;
-        std::vector<double> meas(kShapes, INFINITY);
-        for (int q = 0; q < (int)cand.size() && q < std::max(top_k, 2); ++q) {
+        int best = order[0];
+        for (int q = 0; q < (int)order.size() && q < top_k; ++q) {
             double t;
-            e = time_one(c, cand[q].second, &t);
-            if (e != hipSuccess) break;
-            meas[cand[q].second] = t;
-            if (q < top_k && t < best_t) {
+            e = tm.time(c, b->cands[c][order[q]], 3, &t);
+            if (e != hipSuccess) {
+                st = hip_fail(e, "tuning launches");
+                break;
+            }
+            if (t < best_t) {
                 best_t = t;
-                best = cand[q].second;
+                best = order[q];
             }
         }
-        double truly_best = *std::min_element(meas.begin(), meas.end());
-        if (meas[seed_pick] <= 1.05 * truly_best) ++hits;
-        b->shape[c] = best;
+        iso_choice[c] = best;
+        b->topk[c] = best;
     }
-    if (e != hipSuccess) {
-        (void)hipEventDestroy(t0);
-        (void)hipEventDestroy(t1);
-        return hip_fail(e, "tuning launches");
-    }
-    b->hit_rate = n ? (double)hits / n : 1.0;
-    b->n_tuned = n;
-    // Members timed alone favour small tiles (more parallelism on an idle
-    // device); inside the batch that need not hold, so the whole batch is
-    // timed with the new shapes and the previous ones are kept unless the new
-    // ones are faster than both timings of the previous ones (replay times
-    // drift by a few percent, as much as a change of shapes gains or loses).
-    const std::vector<int> new_shape = b->shape;
-    auto use = [&](const std::vector<int>& shp) {
-        b->shape = shp;
-        drop_graph(b);
-        tc_status r = build_groups(b);
-        return r ? r : capture(b);
+    // A member timed alone runs on an idle device, where small tiles win by
+    // parallelism; inside the batch the device is full and a tile's share of
+    // it counts, which the estimate models (tile count x per-tile share).  So
+    // the whole batch is timed with the picks among the top_k, with the
+    // estimate's first choices, and with the previous choices, and a new
+    // configuration replaces the kept one only if it beats two timings of it
+    // (replay times drift by a few percent, as much as a change gains or
+    // loses).
+    auto use = [&](const std::vector<int>& ch) {
+        b->choice = ch;
+        return rebuild(b);
     };
-    tc_status ts = use(new_shape);
-    double after_ms = 0.0;
-    if (!ts) ts = time_graph(&after_ms);
-    if (!ts && after_ms < before_ms) {
-        double again_ms = 0.0;
-        ts = use(old_shape);
-        if (!ts) ts = time_graph(&again_ms);
-        if (!ts && after_ms < again_ms) ts = use(new_shape);
-    } else if (!ts) {
-        ts = use(old_shape);
+    std::vector<int> kept = old_choice;
+    double kept_ms = before_ms;
+    for (const std::vector<int>* cfg : {&iso_choice, &seed_choice}) {
+        if (st || *cfg == kept) continue;
+        double new_ms = 0.0, again_ms = 0.0;
+        st = use(*cfg);
+        if (!st) st = time_graph(&new_ms);
+        if (st || new_ms >= kept_ms) continue;
+        st = use(kept);
+        if (!st) st = time_graph(&again_ms);
+        if (!st && new_ms < again_ms) {
+            kept = *cfg;
+            kept_ms = new_ms;
+        }
     }
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    return ts;
+    if (!st) st = use(kept);
+    // staging back in each kept choice's kernel order
+    for (int c = 0; c < n; ++c)
+        if (b->cands[c][b->choice[c]].swap) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
+    if (!st) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (int c = 0; c < n; ++c)
+            g_tune_cache[signature(b->plans[c])] = {b->cands[c][b->choice[c]].variant, b->cands[c][b->choice[c]].shape};
+    }
+    return st;
+}
+
+tc_status tc_batch_score(tc_batch_t b, int sample, uint64_t seed, tc_tune_score* out) {
+    if (!b || !out) return fail(TC_E_NULL, "NULL argument");
+    if (!b->launched) return fail(TC_E_UNSUPPORTED, "call tc_batch_contract once before scoring");
+    std::memset(out, 0, sizeof(*out));
+    hipError_t e = hipEventSynchronize(b->done);
+    if (e != hipSuccess) return hip_fail(e, "synchronize");
+    const int n = (int)b->plans.size();
+    if (n == 0 || sample <= 0) return TC_OK;
+    Timer tm{b, nullptr};
+    tc_status st = tm.open();
+    // the staging entries in A, B order for the timer
+    for (int c = 0; c < n; ++c)
+        if (b->cands[c][b->choice[c]].swap) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
+    if (!st && b->est.empty()) st = seed_estimates(b, tm);
+    std::vector<int> members;
+    for (int c = 0; c < n; ++c)
+        if (tm.usable(c)) members.push_back(c);
+    std::mt19937_64 rng(seed);
+    std::shuffle(members.begin(), members.end(), rng);
+    members.resize(std::min((int)members.size(), sample));
+    if (members.empty()) st = fail(TC_E_UNSUPPORTED, "no member with all three operands to time");
+    double lr[4] = {0, 0, 0, 0};
+    int hit[4] = {0, 0, 0, 0}, top[4] = {0, 0, 0, 0}, best_member = 0, n_cand = 0;
+    for (int c : members) {
+        if (st) break;
+        std::vector<double> t(b->cands[c].size());
+        for (size_t j = 0; j < t.size(); ++j) {
+            e = tm.time(c, b->cands[c][j], 5, &t[j]);
+            if (e != hipSuccess) {
+                st = hip_fail(e, "scoring launches");
+                break;
+            }
+        }
+        if (st) break;
+        n_cand += (int)t.size();
+        const int best = argmin(t);
+        if (b->cands[c][best].variant != TC_VARIANT_FUSED) ++best_member;
+        const int pick[4] = {argmin(b->est[c]), b->choice[c], b->deflt[c],
+                             b->topk.empty() || b->topk[c] < 0 ? argmin(b->est[c]) : b->topk[c]};
+        for (int q = 0; q < 4; ++q) {
+            const double r = t[pick[q]] / t[best];
+            lr[q] += std::log(r);
+            if (r <= 1.05) ++hit[q];
+            if (pick[q] == best) ++top[q];
+        }
+    }
+    for (int c = 0; c < n; ++c)
+        if (b->cands[c][b->choice[c]].swap) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
+    if (st) return st;
+    const double m = (double)members.size();
+    out->n_sampled = (int)members.size();
+    out->candidates_mean = n_cand / m;
+    out->within5_seed = hit[0] / m;
+    out->argmin_seed = top[0] / m;
+    out->regret_seed = std::exp(lr[0] / m);
+    out->within5_tuned = hit[1] / m;
+    out->argmin_tuned = top[1] / m;
+    out->regret_tuned = std::exp(lr[1] / m);
+    out->within5_default = hit[2] / m;
+    out->argmin_default = top[2] / m;
+    out->regret_default = std::exp(lr[2] / m);
+    out->within5_topk = hit[3] / m;
+    out->argmin_topk = top[3] / m;
+    out->regret_topk = std::exp(lr[3] / m);
+    out->member_best_share = best_member / m;
+    b->hit_rate = out->within5_tuned;
+    return TC_OK;
 }
 
 tc_status tc_batch_info(tc_batch_t b, int* n_members, int64_t* n_tiles, int* n_groups, double* tune_hit_rate) {
     if (!b) return fail(TC_E_NULL, "batch is NULL");
     int64_t tiles = 0;
     for (auto& g : b->groups) tiles += (int64_t)g.work.size();
-    if (n_members) *n_members = (int)b->items.size();
+    if (n_members) *n_members = (int)b->plans.size();
     if (n_tiles) *n_tiles = tiles;
     if (n_groups) *n_groups = (int)b->groups.size();
     if (tune_hit_rate) *tune_hit_rate = b->hit_rate;
+    return TC_OK;
+}
+
+tc_status tc_batch_set_choice(tc_batch_t b, int member, int variant, int shape) {
+    if (!b) return fail(TC_E_NULL, "batch is NULL");
+    if (member < 0 || member >= (int)b->plans.size()) return fail(TC_E_VARIANT, "member out of range");
+    int j = -1;
+    for (int q = 0; q < (int)b->cands[member].size(); ++q)
+        if (b->cands[member][q].variant == variant && b->cands[member][q].shape == shape) j = q;
+    if (j < 0) return fail(TC_E_VARIANT, "not a candidate of this member (a gemm member whose loops are all free "
+                                          "indices, or the fused view, with shape 0..2)");
+    if (b->launched) {
+        hipError_t e = hipEventSynchronize(b->done);
+        if (e != hipSuccess) return hip_fail(e, "synchronize");
+    }
+    // the staged pointers follow the member's kernel order
+    if (b->cands[member][b->choice[member]].swap != b->cands[member][j].swap)
+        std::swap(b->h_ptrs[member].A, b->h_ptrs[member].B);
+    b->choice[member] = j;
+    return rebuild(b);
+}
+
+tc_status tc_batch_choice(tc_batch_t b, int member, int* variant, int* shape, int* n_candidates) {
+    if (!b) return fail(TC_E_NULL, "batch is NULL");
+    if (member < 0 || member >= (int)b->plans.size()) return fail(TC_E_VARIANT, "member out of range");
+    const Cand& cd = b->cands[member][b->choice[member]];
+    if (variant) *variant = cd.variant;
+    if (shape) *shape = cd.shape;
+    if (n_candidates) *n_candidates = (int)b->cands[member].size();
     return TC_OK;
 }
 

@@ -78,8 +78,16 @@ def test_batch_real_data_and_tune(dtype):
     batch.contract(As, Bs, Cs)
     _check_all(shapes, host, Cs, dtype, exact=False)
     batch.tune(2)
-    info = batch.info()
-    assert 0.0 <= info["tune_hit_rate"] <= 1.0
+    assert batch.info()["tune_hit_rate"] == -1.0             # no score yet
+    sc = batch.score(sample=16, seed=3)
+    assert sc["n_sampled"] == 16 and sc["candidates_mean"] >= 3
+    for q in ("seed", "topk", "tuned", "default"):
+        assert 0.0 <= sc["argmin_" + q] <= sc["within5_" + q] <= 1.0
+        assert sc["regret_" + q] >= 1.0
+    assert batch.info()["tune_hit_rate"] == sc["within5_tuned"]
+    # the tuning cache: a new batch of the same contractions starts from the kept choices
+    again = tc.Batch(plans)
+    assert [again.choice(t) for t in range(len(plans))] == [batch.choice(t) for t in range(len(plans))]
     for C in Cs:
         C.fill_(float("nan"))
     batch.contract(As, Bs, Cs)
@@ -184,3 +192,54 @@ def test_batch_alpha_zero_reads_neither_input(dtype):
     for (sp, ex), (A, B, C0), C, al, be in zip(cases, host, Cs, alphas, betas):
         ref = oracle.contract(sp, ex, A, B, C=np.array(C0, order="F"), alpha=al, beta=be)
         np.testing.assert_array_equal(C.double().cpu().numpy(), ref, err_msg=f"{sp} alpha={al} beta={be}")
+
+
+def _batch_candidates(plan):
+    """The loop/kernel variants a batch member can run: the fused view and
+    the gemm members whose loops are all free indices (no copies)."""
+    sa, sb, sc = plan.letters
+    contracted = [ch for ch in sa if ch in sb and ch not in sc]
+    out = [tc.TC_VARIANT_FUSED]
+    if len(contracted) == 1 and all(ch in sc for ch in set(sa + sb) - set(contracted)):
+        out += [v["index"] for v in plan.variants()
+                if v["kernel"] == "gemm" and not v["copies"] and not any(ch in contracted for ch in v["loops"])]
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_every_candidate_exact(dtype):
+    """Every candidate of every member -- the fused view or a gemm member of
+    the paper's family whose loops become batch dimensions, with each of the
+    three tile shapes -- computes the contraction exactly on integer data
+    inside the persistent kernel, alongside members running other candidates."""
+    import torch
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    cases = [("abc=ai,ibc", dict(a=37, b=9, c=5, i=3)), ("abcd=ai,ibcd", dict(a=20, b=3, c=4, d=5, i=7)),
+             ("abc=ija,jbic", dict(a=40, b=24, c=3, i=6, j=9)), ("ab=iaj,jbi", dict(a=50, b=45, i=8, j=8)),
+             ("abc=ai,ibc", dict(a=130, b=70, c=3, i=20))]
+    plans = [tc.Plan(sp, ex, dtype) for sp, ex in cases]
+    batch = tc.Batch(plans)
+    rng = np.random.default_rng(29)
+    host = [wl.tensors(sp, ex, rng, integer=True) for sp, ex in cases]
+    As = [tc.to_device_fortran(A, tdt) for A, _, _ in host]
+    Bs = [tc.to_device_fortran(B, tdt) for _, B, _ in host]
+    Cs = [tc.empty_fortran(p.shape("C"), tdt) for p in plans]
+    refs = [oracle.contract(sp, ex, A, B) for (sp, ex), (A, B, _) in zip(cases, host)]
+    batch.contract(As, Bs, Cs)
+    cands = [[(v, sh) for v in _batch_candidates(p) for sh in range(3)] for p in plans]
+    assert [len(c) for c in cands] == [batch.choice(t)["candidates"] for t in range(len(plans))]
+    assert [len(c) for c in cands] == [9, 21, 3, 3, 9]
+    bound = batch.bind(As, Bs, Cs)
+    for r in range(max(len(c) for c in cands)):
+        for t, c in enumerate(cands):
+            batch.set_choice(t, *c[(r + t) % len(c)])
+        for C in Cs:
+            C.fill_(float("nan"))
+        batch.run(bound)
+        torch.cuda.synchronize()
+        for t, (C, ref) in enumerate(zip(Cs, refs)):
+            np.testing.assert_array_equal(C.double().cpu().numpy(), ref,
+                                          err_msg=f"{cases[t]} candidate {cands[t][(r + t) % len(cands[t])]}")
+    with pytest.raises(tc.TcError) as e:
+        batch.set_choice(2, 0, 0)                 # abc=ija,jbic has no member candidates
+    assert e.value.name == "TC_E_VARIANT"
