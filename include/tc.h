@@ -109,6 +109,8 @@ typedef struct {
     int     n_hoisted;             /* leading contracted loops run as separate launch passes */
     int64_t launches;              /* kernel launches per contraction, copies and prologue included */
     int64_t invocations;           /* kernel calls of the paper's loop nest (product of loop extents) */
+    int     runs_on_gpu;           /* 0: tc_contract refuses the member (a copy of C with a contracted
+                                      loop at or outside it among the free loops) */
 } tc_variant_info;
 
 /* One entry of a micro-benchmark setup list (Section 3.2): an access to a kernel

@@ -43,7 +43,8 @@ class tc_variant_info(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("number", ctypes.c_int), ("kernel", ctypes.c_int),
                 ("kept", ctypes.c_char * 8), ("loops", ctypes.c_char * 16), ("n_copies", ctypes.c_int),
                 ("copy_tensor", ctypes.c_char * 4), ("copy_level", ctypes.c_int * 4),
-                ("n_hoisted", ctypes.c_int), ("launches", ctypes.c_int64), ("invocations", ctypes.c_int64)]
+                ("n_hoisted", ctypes.c_int), ("launches", ctypes.c_int64), ("invocations", ctypes.c_int64),
+                ("runs_on_gpu", ctypes.c_int)]
 
 
 class tc_setup_item(ctypes.Structure):
@@ -167,7 +168,8 @@ def tc_variant_get(h, variant: int) -> dict:
                 kept=info.kept.decode(), loops=info.loops.decode(),
                 copies=[(info.copy_tensor[c].decode() if isinstance(info.copy_tensor[c], bytes)
                          else chr(info.copy_tensor[c]), info.copy_level[c]) for c in range(info.n_copies)],
-                n_hoisted=info.n_hoisted, launches=info.launches, invocations=info.invocations)
+                n_hoisted=info.n_hoisted, launches=info.launches, invocations=info.invocations,
+                runs_on_gpu=bool(info.runs_on_gpu))
 
 
 def tc_set_variant(h, variant: int):

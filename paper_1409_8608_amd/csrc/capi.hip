@@ -275,8 +275,10 @@ tc_status prepare_plan(tc_plan_s* p) {
     int v = p->selected == TC_VARIANT_PREDICTED ? p->predicted_best : p->selected;
     if (v >= 0) {
         VariantPlan& vp = p->vplans()[v];
-        if (vp.needs_c_copy) return fail(TC_E_UNSUPPORTED, "member needs a copy of C, not run on the GPU");
-        for (int t = 0; t < 2; ++t) {
+        if (vp.needs_c_copy)
+            return fail(TC_E_UNSUPPORTED, "member copies C with a contracted loop at or outside the copy inside "
+                                          "its free loops: not run on the GPU");
+        for (int t = 0; t < 3; ++t) {
             tc_status st = ensure_device_buffer(&p->d_temp[t], &p->temp_cap[t], vp.temp_elems[t] * s.elem_bytes());
             if (st) return st;
         }
@@ -405,7 +407,18 @@ tc_status run_variant(tc_plan_s* p, int v, const void* A, const void* B, void* C
         }
         const void* a_ptr = copied[0] ? p->d_temp[0] : ptr_add(A, hA, es);
         const void* b_ptr = copied[1] ? p->d_temp[1] : ptr_add(B, hB, es);
-        void* c_ptr = (void*)ptr_add(C, hC, es);
+        void* c_dst = (void*)ptr_add(C, hC, es);
+        // C's slices into their temporary before the body, back after it
+        for (auto& cs : vp.c_copies) {
+            CopyArgs ca{};
+            ca.src = c_dst;
+            ca.dst = p->d_temp[2];
+            ca.dims = cs.dims;
+            ca.total = cs.slice_elems * cs.slots;
+            e = launch_copy(f64, ca, st);
+            if (e != hipSuccess) return hip_fail(e, "copy kernel launch (C in)");
+        }
+        void* c_ptr = vp.c_copies.empty() ? c_dst : p->d_temp[2];
         const GtDesc& d = vp.body;
         if (vp.mfma) {
             MfmaArgs a{};
@@ -446,6 +459,16 @@ tc_status run_variant(tc_plan_s* p, int v, const void* A, const void* B, void* C
             a.alpha = alpha;
             e = launch_simt(f64, a, st);
             if (e != hipSuccess) return hip_fail(e, "simt body launch");
+        }
+        for (auto& cs : vp.c_copies) {
+            CopyArgs ca{};
+            ca.src = p->d_temp[2];
+            ca.dst = c_dst;
+            ca.dims = cs.dims;
+            for (int q = 0; q < ca.dims.n; ++q) std::swap(ca.dims.d[q].sA, ca.dims.d[q].sC);
+            ca.total = cs.slice_elems * cs.slots;
+            e = launch_copy(f64, ca, st);
+            if (e != hipSuccess) return hip_fail(e, "copy kernel launch (C out)");
         }
         for (int q = H - 1; q >= 0; --q) {
             if (++h[q] < vp.hoisted[q].ext) break;
@@ -584,6 +607,7 @@ tc_status tc_variant_get(tc_plan_t p, int variant, tc_variant_info* out) {
         out->kernel = TC_KERNEL_FUSED;
         out->launches = 1;
         out->invocations = 1;
+        out->runs_on_gpu = 1;
         return TC_OK;
     }
     if (variant < 0 || variant >= (int)p->fam().size()) return fail(TC_E_VARIANT, "variant out of range");
@@ -600,6 +624,7 @@ tc_status tc_variant_get(tc_plan_t p, int variant, tc_variant_info* out) {
     }
     out->n_hoisted = v.n_hoisted;
     out->launches = p->vplans()[variant].launches;
+    out->runs_on_gpu = p->vplans()[variant].needs_c_copy ? 0 : 1;
     int64_t inv = 1;
     for (char ch : v.loops) inv *= p->spec.e(ch);
     out->invocations = inv;
@@ -637,7 +662,8 @@ tc_status tc_plan_prepare(tc_plan_t p) {
 
 tc_status tc_plan_workspace(tc_plan_t p, int64_t* bytes) {
     if (!p || !bytes) return fail(TC_E_NULL, "NULL argument");
-    *bytes = p->ktab_cap + p->var_ktab_cap + p->temp_cap[0] + p->temp_cap[1] + p->split_bytes + p->splitk_cap +
+    *bytes = p->ktab_cap + p->var_ktab_cap + p->temp_cap[0] + p->temp_cap[1] + p->temp_cap[2] + p->split_bytes +
+             p->splitk_cap +
              p->zexp_cap;
     if (p->real) {
         int64_t inner = 0;

@@ -131,12 +131,16 @@ VariantPlan plan_variant(const Spec& s, const Variant& v) {
     int H = v.n_hoisted;
     for (int p = 0; p < H; ++p) vp.hoisted.push_back(dim(v.loops[p]));
 
-    // temp layout of each copied input: kept axes compact in operand order,
+    // temp layout of each copied operand: kept axes compact in operand order,
     // then one slot axis per non-hoisted loop at or outside the copy level
-    int64_t tstride[2][26];
-    bool copied[2] = {false, false};
+    int64_t tstride[3][26];
+    bool copied[3] = {false, false, false};
     for (auto& c : v.copies) {
-        if (c.first == 2) { vp.needs_c_copy = true; continue; }
+        if (c.first == 2) {
+            for (int p = H; p <= c.second; ++p)
+                if (has(s.contracted, v.loops[p])) vp.needs_c_copy = true;
+            if (vp.needs_c_copy) continue;
+        }
         int t = c.first;
         copied[t] = true;
         for (int k = 0; k < 26; ++k) tstride[t][k] = 0;
@@ -166,11 +170,12 @@ VariantPlan plan_variant(const Spec& s, const Variant& v) {
         if (cs.slice_elems == 0) cs.slots = 0;
         cs.hoist_depth = std::min(H, c.second + 1);
         vp.temp_elems[t] = run;
-        vp.copies.push_back(cs);
+        (t == 2 ? vp.c_copies : vp.copies).push_back(cs);
     }
     auto sa = [&](char ch) { return copied[0] ? tstride[0][ch - 'a'] : s.sA[ch - 'a']; };
     auto sb = [&](char ch) { return copied[1] ? tstride[1][ch - 'a'] : s.sB[ch - 'a']; };
-    auto gd = [&](char ch) { return GtDim{s.e(ch), sa(ch), sb(ch), s.sC[ch - 'a']}; };
+    auto sc = [&](char ch) { return copied[2] ? tstride[2][ch - 'a'] : s.sC[ch - 'a']; };
+    auto gd = [&](char ch) { return GtDim{s.e(ch), sa(ch), sb(ch), sc(ch)}; };
 
     vp.mfma = (v.kernel == TC_KERNEL_GEMM);
     d.out.n = 0;
@@ -204,6 +209,7 @@ VariantPlan plan_variant(const Spec& s, const Variant& v) {
         for (int p = 0; p < cs.hoist_depth; ++p) n *= vp.hoisted[p].ext;
         copy_launches += n;
     }
+    copy_launches += 2 * passes * (int64_t)vp.c_copies.size();   // C in and out around every body launch
     vp.launches = 1 + passes + copy_launches;   // C prologue, bodies, copies
     return vp;
 }

@@ -47,8 +47,8 @@ struct tc_plan_s {
     int64_t var_ktab_cap = 0, var_kpad = 0;
     int var_kvec = 0;
     int var_ktab_for = -1;
-    void* d_temp[2] = {nullptr, nullptr};   // copy temporaries of A and B
-    int64_t temp_cap[2] = {0, 0};
+    void* d_temp[3] = {nullptr, nullptr, nullptr};   // copy temporaries of A, B and C
+    int64_t temp_cap[3] = {0, 0, 0};
     // complex storage: the contraction runs as the real plan `real` over an
     // embedded form in which operand `zside` is expanded into 2x2 real blocks
     tc_plan_s* real = nullptr;

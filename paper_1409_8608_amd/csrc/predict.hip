@@ -89,9 +89,11 @@ static double sample_desc(const VariantPlan& vp, GtDesc& d, int64_t target) {
 static hipError_t launch_body(PredCtx& c, const VariantPlan& vp, const GtDesc& d, const void* A, const void* B) {
     tc_plan_s* p = c.p;
     bool f64 = p->spec.dtype == TC_F64;
+    // a member that copies C runs its body on C's temporary
+    void* Cb = vp.c_copies.empty() ? c.C : p->d_temp[2];
     if (vp.mfma) {
         MfmaArgs a{};
-        a.A = A; a.B = B; a.C = c.C;
+        a.A = A; a.B = B; a.C = Cb;
         a.m.n = d.nm;
         if (d.nm) a.m.d[0] = d.out.d[0];
         a.n.n = d.nn;
@@ -115,7 +117,7 @@ static hipError_t launch_body(PredCtx& c, const VariantPlan& vp, const GtDesc& d
         return launch_mfma(f64, a, c.st);
     }
     SimtArgs a{};
-    a.A = A; a.B = B; a.C = c.C;
+    a.A = A; a.B = B; a.C = Cb;
     a.out = d.out;
     a.kb = d.kb;
     a.pass = d.pass;
@@ -257,6 +259,29 @@ static tc_status predict_variant(PredCtx& c, int v, tc_prediction* out) {
             c.cache[key] = t;
         }
         fixed += t * (double)n;
+    }
+    // C's copies in and out around every body launch (one of each per pass)
+    for (auto& cs : vp.c_copies) {
+        std::string key = "ccopy|" + std::to_string(cs.slice_elems) + "|" + std::to_string(cs.slots);
+        for (int q = 0; q < cs.dims.n; ++q)
+            key += "," + std::to_string(cs.dims.d[q].ext) + ":" + std::to_string(cs.dims.d[q].sA);
+        double t;
+        auto it = c.cache.find(key);
+        if (it != c.cache.end()) {
+            t = it->second;
+        } else {
+            CopyArgs ca{};
+            ca.src = c.C;
+            ca.dst = p->d_temp[2];
+            ca.dims = cs.dims;
+            ca.total = cs.slice_elems * cs.slots;
+            stt = time_median(c, {}, opA, opB, [&]() { return launch_copy(f64, ca, c.st); }, &t);
+            if (stt) return stt;
+            c.cache[key] = t;
+        }
+        int64_t passes = 1;
+        for (auto& h : vp.hoisted) passes *= h.ext;
+        fixed += 2.0 * t * (double)passes;
     }
     {
         std::string key = "scale";

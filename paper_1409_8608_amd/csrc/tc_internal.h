@@ -138,11 +138,18 @@ struct CopyStep {
 struct VariantPlan {
     GtDesc body;                       // body launch (hoisted-loop offsets added per pass)
     std::vector<GtDim> hoisted;        // hoisted loops (outermost first): strides into A, B, C
-    std::vector<CopyStep> copies;
-    int64_t temp_elems[2] = {0, 0};    // temp buffer sizes for A and B copies
+    std::vector<CopyStep> copies;      // copies of A and B slices
+    // copy of C's slices (Section 2: a copy "prior and/or after" the call):
+    // per pass, C -> temp before the body and temp -> C after it; dims as
+    // for the copy in (sA = C's stride, sC = the temp's)
+    std::vector<CopyStep> c_copies;
+    int64_t temp_elems[3] = {0, 0, 0}; // temp buffer sizes for A, B and C copies
     bool mfma = false;                 // gemm body on matrix cores
     int n_body_dims = 0;               // leading out dims that are the kernel's own free indices
-    bool needs_c_copy = false;         // unsupported on the GPU
+    // a C copy with a contracted loop at or outside its level inside the free
+    // loops: its in/out copies would interleave with the sequential passes of
+    // the body launch, which this schedule does not do
+    bool needs_c_copy = false;
     int64_t launches = 0;
 };
 VariantPlan plan_variant(const Spec& s, const Variant& v);

@@ -338,9 +338,9 @@ def test_explicit_strides():
     for v in [tc.TC_VARIANT_FUSED] + list(range(0, 176, 7)):
         p.set_variant(v)
         dCv.fill_(float("nan"))
-        if v >= 0 and any(t == "C" for t, _ in infos[v]["copies"]):
-            # C's unit-stride index is sliced: the member would copy C in and
-            # out around each call, which the GPU schedule does not run
+        if v >= 0 and not infos[v]["runs_on_gpu"]:
+            # a copy of C with a contracted loop at or outside it among the
+            # free loops: the GPU schedule refuses it
             with pytest.raises(tc.TcError) as e:
                 p.contract(dA, dB, dCv, 1.0, 0.0)
             assert e.value.name == "TC_E_UNSUPPORTED"
@@ -428,3 +428,34 @@ def test_alias_and_null_errors():
     with pytest.raises(tc.TcError) as e:
         tc.tc_contract(p.handle, 0, buf.data_ptr(), buf.data_ptr() + 128 * 8)
     assert e.value.name == "TC_E_NULL"
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", [
+    ("bac=ai,ibc", dict(a=33, b=20, c=7, i=5)),
+    ("bca=ija,jbic", dict(a=18, b=12, c=5, i=3, j=4)),
+    ("bacd=ai,ibcd", dict(a=9, b=6, c=5, d=4, i=3)),
+])
+def test_members_copying_c(spec, ext, dtype):
+    """Members that copy C's slice in before the call and out after it (Section
+    2): per pass, a copy launch into a temporary, the body on the temporary, a
+    copy launch back.  Every member of specs with such members, with alpha and
+    beta, integer data, bit-exact against the oracle; the members whose C copy
+    has a contracted loop at or outside it among the free loops are refused."""
+    A, B, C0 = wl.tensors(spec, ext, np.random.default_rng(41), integer=True, with_c=True)
+    p = _plan(spec, ext, dtype)
+    infos = p.variants()
+    copying = [v for v in range(len(infos)) if any(t == "C" for t, _ in infos[v]["copies"])]
+    assert copying
+    ran = 0
+    for v in range(len(infos)):
+        p.set_variant(v)
+        if not infos[v]["runs_on_gpu"]:
+            with pytest.raises(tc.TcError) as e:
+                run(p, A, B, C0, alpha=2.0, beta=-1.0, dtype=dtype)
+            assert e.value.name == "TC_E_UNSUPPORTED"
+            continue
+        got = run(p, A, B, C0, alpha=2.0, beta=-1.0, dtype=dtype)
+        check(spec, ext, A, B, got, dtype, C0=C0, alpha=2.0, beta=-1.0, exact=True)
+        ran += v in copying
+    assert ran >= 3

@@ -99,3 +99,25 @@ def test_misplaced_copy_is_caught():
     bad = dataclasses.replace(v, copies=(("B", 0),))      # copy at c, but it depends on j
     with pytest.raises(AssertionError):
         interp.run_variant(bad, spec, ext, A, B, np.zeros((2, 2, 3), order="F"))
+
+
+@pytest.mark.parametrize("spec", ["bac=ai,ibc", "bca=ija,jbic", "bacd=ai,ibcd"])
+def test_members_copying_c_equal_contraction(spec):
+    """Specs whose C does not start with a kept index of every ger/gemm member:
+    those members copy C's slice before the call and back after it (Section 2,
+    copies "prior and/or after" the call); every member, copies of C included,
+    equals the plain contraction on integer data."""
+    rng = np.random.default_rng(23)
+    letters = sorted(set(spec.replace("=", "").replace(",", "")))
+    ext = {ch: int(v) for ch, v in zip(letters, rng.integers(2, 4, len(letters)))}
+    sa, sb, sc = oracle.split_spec(spec)
+    A = np.asfortranarray(rng.integers(-2, 3, [ext[c] for c in sa]).astype(float))
+    B = np.asfortranarray(rng.integers(-2, 3, [ext[c] for c in sb]).astype(float))
+    ref = oracle.contract(spec, ext, A, B)
+    fam = family.enumerate_family(spec)
+    with_c = [v for v in fam if any(t == "C" for t, _ in v.copies)]
+    assert len(with_c) >= 3
+    for v in fam:
+        C = np.zeros([ext[c] for c in sc], order="F")
+        interp.run_variant(v, spec, ext, A, B, C)
+        np.testing.assert_array_equal(C, ref, err_msg=f"{spec} {v.name}")
