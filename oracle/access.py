@@ -207,34 +207,50 @@ class BenchClass:
     setup: list         # setup list
 
 
+def _name(r: Region) -> str:
+    """The kernel operand slot ('A', 'B', 'C') of a region (a copy's buffer X~ is X's slot)."""
+    return r.tensor.rstrip("~")
+
+
 def first_iteration_class(ops, loops, extents: dict, k: int, share: float, cache_elems: float,
-                          gaps: dict, keep_operand_only: bool = False) -> BenchClass:
+                          gaps: dict, keep_operand_only: bool = False, distance=None) -> BenchClass:
     """Class of the first iteration of loop ``k`` (Section 3.5): the walk starts
     at that loop with M holding every kernel operand joined across it and the
-    loops inside it; every operand is accessed whole (no prefetch emulation)."""
-    preset = set(loops[k:])
+    loops inside it; every operand is accessed whole (no prefetch emulation).
+    ``distance(region, start, gap)`` is the walk (default: the single-kernel one)."""
+    if distance is None:
+        distance = lambda r, start, gap: access_distance(r, ops, loops, extents, start=start,
+                                                         preset=set(loops[start:]) if start is not None else None,
+                                                         root_gap=gap)
     items = []
     for r in ops:
-        d = access_distance(r, ops, loops, extents, start=k, preset=preset, root_gap=gaps[r.tensor])
-        items.append((r.tensor, region_size(r, set(), extents), d))
+        d = distance(r, k, gaps[_name(r)])
+        items.append((_name(r), region_size(r, set(), extents), d))
     st = build_setup(items, cache_elems)
     return BenchClass(f"first@{loops[k]}", share, st if keep_operand_only or not only_operands(st) else [])
 
 
 def predict_classes(ops, loops, extents: dict, cache_elems: float, line_elems: int,
-                    stage: int = 5, root_gaps: dict | None = None, keep_operand_only: bool = False):
+                    stage: int = 5, root_gaps: dict | None = None, keep_operand_only: bool = False,
+                    distance=None):
     """Benchmark classes with their shares of the invocations, for prediction
     stage 1 (repeated execution) .. 5 (first iterations separate).
     ``root_gaps`` maps an operand's tensor name to its root gap (elements).
     ``keep_operand_only`` keeps setup lists made only of operand accesses
     (normally dropped: the repetitions already touch every operand), so that
-    they can be inspected."""
-    names = [r.tensor for r in ops]
+    they can be inspected.  ``distance(region, start, gap)`` is the walk
+    (default: the single-kernel walk over ``ops``; ``predict_member`` passes
+    the walk of the member's whole program)."""
+    names = [_name(r) for r in ops]
     sizes = [region_size(r, set(), extents) for r in ops]
     gaps = {n: int((root_gaps or {}).get(n, 0)) for n in names}
     if stage == 1:
         return [BenchClass("steady", 1.0, [])]
-    dist = [access_distance(r, ops, loops, extents, root_gap=gaps[r.tensor]) for r in ops]
+    if distance is None:
+        distance = lambda r, start, gap: access_distance(r, ops, loops, extents, start=start,
+                                                         preset=set(loops[start:]) if start is not None else None,
+                                                         root_gap=gap)
+    dist = [distance(r, None, gaps[n]) for r, n in zip(ops, names)]
     kinds = [prefetch_kind(r, loops, extents, line_elems) if stage >= 3 else None for r in ops]
     # the access-distance list's order (ties: A, B, C); later stages keep it for ties
     order = sorted(range(len(ops)), key=lambda t: -dist[t])
@@ -275,5 +291,176 @@ def predict_classes(ops, loops, extents: dict, cache_elems: float, line_elems: i
             nxt = max(outer) if outer else None
             share = first_share[k] - (first_share[nxt] if nxt is not None else 0.0)
             classes.append(first_iteration_class(ops, loops, extents, k, share, cache_elems, gaps,
-                                                 keep_operand_only))
+                                                 keep_operand_only, distance))
     return classes
+
+
+# ---------------------------------------------------------------------------
+# Algorithms with several statements (Section 3.2: the back-traversal "allows
+# for any combinations of loops and multiple kernels within the AST").
+#
+# A family member with copies is such an AST: a copy statement X~ := X[slice]
+# sits at the head of the body of the loop that the slice depends on most
+# deeply (before all loops for a slice fixed by none), the kernel works on the
+# copy X~ (one buffer, reused in every iteration), and a copy of C is written
+# back after the loops inside its level.  The walk of an operand Op of a
+# statement S goes backwards through the program from S:
+#   - earlier statements of the same loop body (this iteration): if one
+#     accesses Op's tensor, Op's previous access is found and the walk stops;
+#     otherwise all its regions, joined along the loops inside it, go into M;
+#   - then the enclosing loop L:
+#       case 1, Op does not vary across L: Op's previous access was in the
+#         previous iteration of L; the statements after S's position in L's
+#         body ran after it: they are walked backwards from the end of the
+#         body, with the same stop rule, and the walk ends;
+#       case 2, Op varies across L: every region of L's body, joined along L
+#         and the loops inside it, goes into M, Op is joined along L, and the
+#         walk continues one level up with L in the place of S;
+#   - at the root (case 3), the distance is |M| plus the caller's gap.
+# For a single statement this is exactly the walk above.  M holds one region
+# per tensor: two regions of a tensor are merged into the smallest region
+# holding both (an axis joined in either is joined), which is their union for
+# the nested regions a walk produces.  The walk of a first-iteration class
+# (Section 3.5) starts at loop k with M holding every region of its body joined
+# along it and the loops inside it.
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class Stmt:
+    kind: str            # 'kernel', 'copy-in' (X~ := X[slice]) or 'copy-out' (X[slice] := X~)
+    regions: tuple       # Region records; a copy's are (source, target)
+
+
+@dataclass
+class Loop:
+    index: str
+    body: list           # Stmt and Loop nodes, in program order
+
+
+def _temp(r: Region) -> Region:
+    """The buffer X~ of a copied slice: the slice's kept axes, fixed by no loop."""
+    kept = "".join(ch for ch, f in zip(r.letters, r.fixed) if not f)
+    return Region(r.tensor + "~", kept, tuple(False for _ in kept))
+
+
+def build_ast(variant):
+    """The member's program: its loops, its copies at their levels, the kernel
+    innermost.  Returns (root body, path to the kernel) where a path is a list
+    of (body, position) from the root down."""
+    ops = [Region(o.tensor, o.letters, o.fixed) for o in variant.operands]
+    kernel_regions = tuple(_temp(r) if any(t == r.tensor for t, _ in variant.copies) else r for r in ops)
+    kernel = Stmt("kernel", kernel_regions)
+    by_level = {}
+    for t, lv in variant.copies:
+        by_level.setdefault(lv, []).append(t)
+    reg = {r.tensor: r for r in ops}
+
+    def body_at(level):
+        """Statements of the body at loop position `level` (-1: the root)."""
+        if level + 1 < len(variant.loops):
+            inner = [Loop(variant.loops[level + 1], body_at(level + 1))]
+        else:
+            inner = [kernel]
+        ins = [Stmt("copy-in", (reg[t], _temp(reg[t]))) for t in by_level.get(level, [])]
+        outs = [Stmt("copy-out", (_temp(reg[t]), reg[t])) for t in by_level.get(level, []) if t == "C"]
+        return ins + inner + outs
+
+    root = body_at(-1)
+    path, body = [], root
+    while True:
+        pos = next(i for i, n in enumerate(body) if isinstance(n, Loop) or n is kernel)
+        path.append((body, pos))
+        if body[pos] is kernel:
+            return root, path
+        body = body[pos].body
+
+
+def _join(r: Region, loops) -> Region:
+    return Region(r.tensor, r.letters, tuple(f and ch not in loops for ch, f in zip(r.letters, r.fixed)))
+
+
+def _regions_of(node, joined):
+    """Every region a node accesses, joined along `joined` and the loops inside it."""
+    if isinstance(node, Stmt):
+        return [_join(r, joined) for r in node.regions]
+    out = []
+    for n in node.body:
+        out += _regions_of(n, set(joined) | {node.index})
+    return out
+
+
+def _tensors_of(node):
+    return {r.tensor for r in _regions_of(node, set())}
+
+
+def _merge(M: dict, regions):
+    for r in regions:
+        if r.tensor in M:
+            q = M[r.tensor]
+            M[r.tensor] = Region(r.tensor, r.letters, tuple(a and b for a, b in zip(q.fixed, r.fixed)))
+        else:
+            M[r.tensor] = r
+
+
+def ast_distance(path, region: Region, extents: dict, start: int | None = None, root_gap: int = 0) -> int:
+    """Access distance of ``region`` (accessed by the statement at the end of
+    ``path``) by the walk above; ``start`` = loop depth of a first-iteration
+    class (the walk then starts at that loop, M preloaded)."""
+    M = {}
+    op = region
+    depth = len(path) - 1                 # path[depth] = (body, position) of the current node
+    if start is not None:
+        # path[start] holds the loop at depth `start` (the loop at loop position start)
+        body, pos = path[start]
+        loop = body[pos]
+        inner = {loop.index} | {n.index for b, p in path[start + 1:] for n in [b[p]] if isinstance(n, Loop)}
+        _merge(M, _regions_of(loop, set()))
+        op = _join(op, inner)
+        depth = start
+    while True:
+        body, pos = path[depth]
+        for node in reversed(body[:pos]):                     # earlier statements, this iteration
+            if op.tensor in _tensors_of(node):
+                return sum(region_size(r, set(), extents) for r in M.values())
+            _merge(M, _regions_of(node, set()))
+        if depth == 0:                                        # case 3: the root
+            return sum(region_size(r, set(), extents) for r in M.values()) + int(root_gap)
+        pbody, ppos = path[depth - 1]
+        loop = pbody[ppos]
+        if not varies(op, loop.index, set()):                 # case 1: previous iteration of the loop
+            for node in reversed(body[pos + 1:]):
+                if op.tensor in _tensors_of(node):
+                    break
+                _merge(M, _regions_of(node, set()))
+            return sum(region_size(r, set(), extents) for r in M.values())
+        _merge(M, _regions_of(loop, set()))                   # case 2: the whole loop, joined along it
+        op = _join(op, {loop.index})
+        depth -= 1
+
+
+def kernel_distances(variant, extents: dict, start: int | None = None, root_gaps: dict | None = None):
+    """Access distances of the kernel's operands (copies' buffers for copied
+    operands), keyed by the operand's tensor name ('A', 'B', 'C')."""
+    root, path = build_ast(variant)
+    body, pos = path[-1]
+    out = {}
+    for r in body[pos].regions:
+        name = r.tensor.rstrip("~")
+        gap = int((root_gaps or {}).get(name, 0))
+        out[name] = ast_distance(path, r, extents, start=start, root_gap=gap)
+    return out
+
+
+def predict_member(variant, extents: dict, cache_elems: float, line_elems: int, stage: int = 5,
+                   root_gaps: dict | None = None, keep_operand_only: bool = False):
+    """predict_classes for the kernel of a family member, its operands and
+    distances taken from the member's whole program (copies included): a
+    copied operand is the copy's buffer, which no loop changes, so it is never
+    prefetched and its setup access is the whole buffer."""
+    root, path = build_ast(variant)
+    body, pos = path[-1]
+    ops = list(body[pos].regions)
+    distance = lambda r, start, gap: ast_distance(path, r, extents, start=start, root_gap=gap)
+    return predict_classes(ops, variant.loops, extents, cache_elems, line_elems, stage, root_gaps,
+                           keep_operand_only, distance)

@@ -161,8 +161,8 @@ def test_first_iteration_pin_catches_planted_mistakes(monkeypatch):
 
     real_first = ac.first_iteration_class
 
-    def prefetch_kept(ops, loops, extents, k, share, cache_elems, gaps, keep_operand_only=False):
-        c = real_first(ops, loops, extents, k, share, cache_elems, gaps, keep_operand_only)
+    def prefetch_kept(ops, loops, extents, k, share, cache_elems, gaps, keep_operand_only=False, distance=None):
+        c = real_first(ops, loops, extents, k, share, cache_elems, gaps, keep_operand_only, distance)
         pre = {r.tensor: ac.prefetch_access_size(r, extents, LINE_8) for r in ops
                if ac.prefetch_kind(r, loops, extents, LINE_8)}
         c.setup = [(e[0], e[1], pre.get(e[1], e[2]) if e[0] == "op" else e[2]) for e in c.setup]
@@ -269,3 +269,75 @@ def test_chain_root_gaps_hand_worked():
     assert ac.chain_root_gaps(three) == [[0, 150, 110], [0, 90, 30], [0, 70, 90]]
     # one contraction alone is the paper's assumption: nothing in between
     assert ac.chain_root_gaps([[(1, 8), (2, 8), (3, 8)]]) == [[0, 0, 0]]
+
+
+# Algorithms with several statements: the copy members of Section 2 (the walk
+# of Section 3.2 over an AST with a copy statement and the kernel).
+
+def test_program_walk_equals_single_kernel_walk_without_copies():
+    """With no copy the member's program is one kernel in its loops, and the
+    walk over the program gives exactly the single-kernel classes (every stage,
+    with and without root gaps) for every copy-free member of six patterns."""
+    ext = {ch: n for ch, n in zip("abcdij", (40, 30, 20, 10, 8, 6))}
+    n = 0
+    for spec in ("abc=ai,ibc", "abc=ija,jbic", "a=iaj,ji", "ab=iaj,jbi", "bac=ai,ibc", "abcd=ai,ibcd"):
+        for v in family.enumerate_family(spec):
+            if v.copies:
+                continue
+            for stage in range(1, 6):
+                for gaps in (None, {"A": 1000, "B": 0, "C": 50000}):
+                    a = ac.predict_classes(regions(v), v.loops, ext, 1000.0, 16, stage=stage, root_gaps=gaps)
+                    b = ac.predict_member(v, ext, 1000.0, 16, stage=stage, root_gaps=gaps)
+                    assert [(c.label, c.weight, c.setup) for c in a] == [(c.label, c.weight, c.setup) for c in b]
+                    n += 1
+    assert n > 3000
+
+
+def test_copy_members_hand_worked():
+    """Test 3 (a=b=c=256, i=j=32): A is 262,144 elements, B 67,108,864, C
+    16,777,216, the copy buffer A~ = A[i,:,:] 8,192.
+    i'c-gemm: for i { A~ := A[i,:,:]; for c { C[:,:,c] += A~^T B[:,:,i,c] } }
+      A~: the same buffer in every c iteration (case 1 at loop c): 0.
+      B[:,:,i,c]: varies with c, M = {A~, B[:,:,i,:], C}; then the copy, one
+        statement earlier in loop i's body, adds A[i,:,:]; varies with i: all of
+        it joined along i, the root: |A| + |A~| + |B| + |C| = 84,156,416.
+      C[:,:,c]: varies with c, M = {A~, B[:,:,i,:], C}; the copy adds A[i,:,:];
+        C[:,:,:] does not vary with i (case 1): 8,192 + 2,097,152 + 16,777,216
+        + 8,192 = 18,890,752.
+    ci'-gemm: for c { for i { A~ := A[i,:,:]; C[:,:,c] += A~^T B[:,:,i,c] } }
+      A~: the copy just before it wrote it: 0.
+      B: as above, 84,156,416.
+      C[:,:,c]: the copy adds A[i,:,:] and A~; C does not vary with i (case
+        1): 16,384 -- where the single-kernel walk, blind to the copy, gives 0.
+    Test 2's i'-gemv (a=i=j=n): for i { A~ := A[i,:,:]; C[:] += A~ B[:,i] }:
+      A~ 0; B[:,i]: n^3 + 2n^2 + n; C: 2n^2."""
+    ext = dict(a=256, b=256, c=256, i=32, j=32)
+    vs = {v.name: v for v in family.enumerate_family("abc=ija,jbic")}
+    assert ac.kernel_distances(vs["i'c-gemm"], ext) == {"A": 0, "B": 84156416, "C": 18890752}
+    assert ac.kernel_distances(vs["ci'-gemm"], ext) == {"A": 0, "B": 84156416, "C": 16384}
+    blind = {r.tensor: ac.access_distance(r, regions(vs["ci'-gemm"]), vs["ci'-gemm"].loops, ext)
+             for r in regions(vs["ci'-gemm"])}
+    assert blind["C"] == 0 and blind["A"] != 0
+    n = 64
+    v = {x.name: x for x in family.enumerate_family("a=iaj,ji")}["i'-gemv"]
+    assert ac.kernel_distances(v, dict(a=n, i=n, j=n)) == {"A": 0, "B": n ** 3 + 2 * n ** 2 + n, "C": 2 * n * n}
+
+
+def test_copy_member_first_iteration_and_setup():
+    """ci'-gemm's first iteration of loop i (weight 1/32; loop c's 1/8192 share
+    has no class of its own): the walk starts at loop i with M = {A[:,:,:],
+    A~, B[:,:,:,c], C[:,:,c]} (262,144 + 8,192 + 262,144 + 65,536 = 598,016):
+    A~ does not vary with c (598,016), B and C vary with c and reach the root
+    (84,156,416).  Its steady setup (cache of 10^9 elements, no cut) lists B,
+    C and A~ by distance: B 8,192, remote 84,156,416 - 16,384 - 65,536,
+    C 65,536, remote 16,384 - 0 - 8,192, A~ 8,192 (A~ is never prefetched: no
+    loop changes it)."""
+    ext = dict(a=256, b=256, c=256, i=32, j=32)
+    v = {x.name: x for x in family.enumerate_family("abc=ija,jbic")}["ci'-gemm"]
+    assert ac.kernel_distances(v, ext, start=1) == {"A": 598016, "B": 84156416, "C": 84156416}
+    cls = ac.predict_member(v, ext, 1e9, 16, stage=5)
+    first = [c for c in cls if c.label.startswith("first")]
+    assert [c.label for c in first] == ["first@i"] and first[0].weight == 1 / 32
+    st = ac.predict_member(v, ext, 1e9, 16, stage=2)[0].setup
+    assert [list(e) for e in st] == [["op", "B", 8192], ["remote", None, 84156416 - 16384 - 65536],
+                                     ["op", "C", 65536], ["remote", None, 16384 - 8192], ["op", "A", 8192]]
