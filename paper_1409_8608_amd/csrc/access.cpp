@@ -24,31 +24,142 @@ static bool depends(const Operand& op, char loop, const std::string& joined) {
     return false;
 }
 
-// Walk outwards from the kernel (or, for a first-iteration class, from loop
-// position `start` with that loop and every loop inside it already joined).
-// Case 1: the operand does not change across the loop -> stop.  Case 2: it does
-// -> join all kernel operands along the loop and go up.  Case 3: root -> stop.
-// The distance is the size of the joined operands (empty set -> 0), plus the
-// caller's root gap in case 3: the paper assumes the contraction runs again
-// and again with nothing in between, a caller who knows the surrounding
-// program states what is accessed in between.
+// The walk over the member's program (Section 3.2: the back-traversal covers
+// any combination of loops and kernels).  The program of a member: its loops
+// in order; at the head of the body of loop position l (-1: before all loops)
+// the copies the member takes at level l (X~ := X[slice]), then the next loop
+// (the kernel in the innermost body), then the copies of C back (X[slice] :=
+// X~).  The kernel works on the buffer X~ of a copied operand, which no loop
+// changes.  Regions are numbered 0..2 (A, B, C) and 3..5 (their buffers).
+namespace {
+
+struct Reg {
+    int id;                            // 0..2 operand, 3..5 the buffer of operand id - 3
+    const Operand* op;                 // the operand (its letters; a buffer keeps the kept axes)
+    std::string joined;                // loops it is joined along
+};
+
+bool copied(const Variant& v, int t) {
+    for (auto& c : v.copies)
+        if (c.first == t) return true;
+    return false;
+}
+
+int64_t reg_size(const Spec& s, const Reg& r) {
+    if (r.id < 3) return region_size(s, *r.op, r.joined);
+    int64_t n = 1;                     // a buffer: the slice's kept axes
+    for (size_t ax = 0; ax < r.op->letters.size(); ++ax)
+        if (!r.op->fixed[ax]) n *= s.e(r.op->letters[ax]);
+    return n;
+}
+
+bool reg_varies(const Reg& r, char loop) {
+    if (r.id >= 3) return false;       // one buffer for every iteration
+    for (size_t ax = 0; ax < r.op->letters.size(); ++ax)
+        if (r.op->fixed[ax] && r.op->letters[ax] == loop && !has(r.joined, loop)) return true;
+    return false;
+}
+
+// The set M: per region id, the loops it is joined along (a region merged
+// with another of its tensor is joined along the loops either is joined along:
+// their union for the nested regions a walk meets).
+struct RegionSet {
+    bool in[6] = {false, false, false, false, false, false};
+    std::string joined[6];
+    void add(int id, const std::string& j) {
+        if (!in[id]) {
+            in[id] = true;
+            joined[id] = j;
+        } else {
+            for (char ch : j)
+                if (!has(joined[id], ch)) joined[id] += ch;
+        }
+    }
+    int64_t size(const Spec& s, const Variant& v) const {
+        int64_t n = 0;
+        for (int id = 0; id < 6; ++id)
+            if (in[id]) n += reg_size(s, Reg{id, &v.ops[id % 3], joined[id]});
+        return n;
+    }
+};
+
+// Regions of the copies at level l: copy-ins at the head of the body, copy-outs
+// (of C) at its end.
+void copy_regions(const Variant& v, int l, bool outs, std::vector<int>& ids) {
+    for (auto& c : v.copies)
+        if (c.second == l && (!outs || c.first == 2)) {
+            ids.push_back(c.first);
+            ids.push_back(c.first + 3);
+        }
+}
+
+// Every region the body at level l and everything inside it access, joined
+// along `joined` (which holds the loops from l + 1 inward, and l itself when
+// the whole loop is meant).
+void add_body(const Variant& v, int l, const std::string& joined, RegionSet& M) {
+    const int L = (int)v.loops.size();
+    for (int q = l; q < L; ++q) {
+        std::vector<int> ids;
+        copy_regions(v, q, false, ids);
+        for (int id : ids) M.add(id, joined);
+    }
+    for (int t = 0; t < 3; ++t) M.add(copied(v, t) ? t + 3 : t, joined);
+}
+
+}  // namespace
+
+// Access distance of kernel operand `tensor` (a copied operand: its buffer).
+// The walk starts at the kernel, or, for a first-iteration class, at loop
+// position `start` with M holding that loop's whole body joined along it and
+// the loops inside it (Section 3.5).  Case 1: the operand does not change
+// across the loop -> the statements after the current position in that body
+// (previous iteration) are walked back from its end, and the walk stops.
+// Case 2: it does -> the whole loop, joined along it, goes into M, and the
+// walk goes up.  An earlier statement of a body that touches the operand's
+// tensor stops the walk.  Case 3: the root -> the caller's root gap is added:
+// the paper assumes the contraction runs again and again with nothing in
+// between, a caller who knows the surrounding program states what is accessed
+// in between.
 int64_t access_distance(const Spec& s, const Variant& v, int tensor, int start, int64_t root_gap) {
-    std::string joined;
-    int pos = (int)v.loops.size() - 1;
+    const int L = (int)v.loops.size();
+    RegionSet M;
+    Reg op{copied(v, tensor) ? tensor + 3 : tensor, &v.ops[tensor], ""};
+    int level = L - 1;                 // body holding the current node
     if (start >= 0) {
-        joined = v.loops.substr(start);
-        pos = start - 1;
+        std::string inner = v.loops.substr(start);
+        add_body(v, start, inner, M);
+        op.joined = inner;
+        level = start - 1;
     }
-    for (; pos >= 0; --pos) {
-        char loop = v.loops[pos];
-        if (!depends(v.ops[tensor], loop, joined)) break;
-        joined += loop;
+    auto touches = [&](int id) { return id == op.id; };   // a statement on the operand's tensor
+    for (;;) {
+        // earlier statements of this body: its copy-ins (the current node
+        // follows them)
+        {
+            std::vector<int> ids;
+            copy_regions(v, level, false, ids);
+            for (int q = (int)ids.size() / 2 - 1; q >= 0; --q) {
+                if (touches(ids[2 * q]) || touches(ids[2 * q + 1])) return M.size(s, v);
+                M.add(ids[2 * q], "");
+                M.add(ids[2 * q + 1], "");
+            }
+        }
+        if (level < 0) return M.size(s, v) + root_gap;   // case 3
+        const char loop = v.loops[level];
+        if (!reg_varies(op, loop)) {       // case 1: the tail of the previous iteration
+            std::vector<int> ids;
+            copy_regions(v, level, true, ids);
+            for (int q = (int)ids.size() / 2 - 1; q >= 0; --q) {
+                if (touches(ids[2 * q]) || touches(ids[2 * q + 1])) break;
+                M.add(ids[2 * q], "");
+                M.add(ids[2 * q + 1], "");
+            }
+            return M.size(s, v);
+        }
+        add_body(v, level, v.loops.substr(level), M);    // case 2
+        op.joined += loop;
+        --level;
     }
-    const int64_t gap = pos < 0 ? root_gap : 0;
-    if (joined.empty()) return gap;
-    int64_t d = 0;
-    for (int t = 0; t < 3; ++t) d += region_size(s, v.ops[t], joined);
-    return d + gap;
 }
 
 // 1: the innermost loop indexes the operand's first axis (cache-line sharing);
@@ -134,7 +245,8 @@ std::vector<BenchClass> bench_classes(const Spec& s, const Variant& v, int stage
     for (int t = 0; t < 3; ++t) {
         size[t] = region_size(s, v.ops[t], "");
         dist[t] = access_distance(s, v, t, -1, gap[t]);
-        kind[t] = stage >= 3 ? prefetch_kind(s, v, t, line_elems) : 0;
+        // the kernel reads a copied operand from its buffer, which no loop changes
+        kind[t] = stage >= 3 && !copied(v, t) ? prefetch_kind(s, v, t, line_elems) : 0;
     }
     // Operands in the order of the access-distance list (ties: A, B, C); the
     // prefetch distances of Section 3.3 are folded into that list, so equal

@@ -111,19 +111,25 @@ def _regions(v):
     return [ac.Region(o.tensor, o.letters, o.fixed) for o in v.operands]
 
 
-@pytest.mark.parametrize("spec", SPECS)
+def _dist(v, ext, t, gaps=None):
+    """The oracle's distance of kernel operand t over the member's whole program."""
+    return ac.kernel_distances(v, ext, root_gaps=gaps)["ABC"[t]]
+
+
+@pytest.mark.parametrize("spec", SPECS + ["bac=ai,ibc"])
 @pytest.mark.parametrize("stage", [1, 2, 3, 4, 5])
 def test_symbolic_prediction_matches_oracle(spec, stage):
+    """Every member's distances and benchmark classes through the ABI equal the
+    oracle's walk over the member's program (copies of A, B and C included)."""
     ext = {ch: n for ch, n in zip("abcdij", (400, 30, 20, 12, 8, 6))}
     ext = {ch: ext[ch] for ch in set(spec) if ch.isalpha()}
     h = tc.tc_plan(spec, ext)
     for v in family.enumerate_family(spec):
         idx = v.number - 1
-        ops = _regions(v)
-        for t, r in enumerate(ops):
-            assert tc.tc_access_distance(h, idx, t) == ac.access_distance(r, ops, v.loops, ext), (v.name, t)
+        for t in range(3):
+            assert tc.tc_access_distance(h, idx, t) == _dist(v, ext, t), (v.name, t)
         for cache, line in ((786432.0, 8), (5000.0, 16)):
-            want = ac.predict_classes(ops, v.loops, ext, cache, line, stage=stage)
+            want = ac.predict_member(v, ext, cache, line, stage=stage)
             got = tc.tc_bench_classes(h, idx, stage, cache, line)
             assert [g["label"] for g in got] == [w.label for w in want], v.name
             for g, w in zip(got, want):
@@ -254,12 +260,10 @@ def test_root_gap_matches_oracle(spec, stage):
     tc.tc_set_root_gap(h, [gaps["A"], gaps["B"], gaps["C"]])
     for v in family.enumerate_family(spec):
         idx = v.number - 1
-        ops = _regions(v)
-        for t, r in enumerate(ops):
-            want = ac.access_distance(r, ops, v.loops, ext, root_gap=gaps[r.tensor])
-            assert tc.tc_access_distance(h, idx, t) == want, (v.name, t)
+        for t in range(3):
+            assert tc.tc_access_distance(h, idx, t) == _dist(v, ext, t, gaps), (v.name, t)
         for cache, line in ((786432.0, 8), (5000.0, 16)):
-            want = ac.predict_classes(ops, v.loops, ext, cache, line, stage=stage, root_gaps=gaps)
+            want = ac.predict_member(v, ext, cache, line, stage=stage, root_gaps=gaps)
             got = tc.tc_bench_classes(h, idx, stage, cache, line)
             assert [g["label"] for g in got] == [w.label for w in want], v.name
             for g, w in zip(got, want):
@@ -267,9 +271,8 @@ def test_root_gap_matches_oracle(spec, stage):
                 assert [tuple(e) for e in g["setup"]] == [tuple(e) for e in w.setup], (v.name, g["label"])
     tc.tc_set_root_gap(h, None)       # back to the paper's assumption
     v = family.enumerate_family(spec)[-1]
-    ops = _regions(v)
-    for t, r in enumerate(ops):
-        assert tc.tc_access_distance(h, v.number - 1, t) == ac.access_distance(r, ops, v.loops, ext)
+    for t in range(3):
+        assert tc.tc_access_distance(h, v.number - 1, t) == _dist(v, ext, t)
     with pytest.raises(tc.TcError) as e:
         tc.tc_set_root_gap(h, [0, -1, 0])
     assert e.value.name == "TC_E_EXTENT"
@@ -300,14 +303,13 @@ def test_chain_root_gaps_match_oracle():
             gap = want[j][t] // eb
             # an operand reused across every loop of every member (A of the
             # first contraction) never reaches the root: its gap has no effect
-            reachable += any(ac.access_distance(_regions(v)[t], _regions(v), v.loops, ex, root_gap=1) !=
-                             ac.access_distance(_regions(v)[t], _regions(v), v.loops, ex) for v in fam)
+            one = {"ABC"[t]: 1}
+            reachable += any(_dist(v, ex, t, one) != _dist(v, ex, t) for v in fam)
             for v in fam:
-                ops = _regions(v)
-                if ac.access_distance(ops[t], ops, v.loops, ex, root_gap=1) == ac.access_distance(ops[t], ops, v.loops, ex):
+                if _dist(v, ex, t, one) == _dist(v, ex, t):
                     continue                  # this member's walk stops before the root
-                assert tc.tc_access_distance(plans[j], v.number - 1, t) == \
-                    ac.access_distance(ops[t], ops, v.loops, ex, root_gap=gap), (sp, v.name, t)
+                assert tc.tc_access_distance(plans[j], v.number - 1, t) == _dist(v, ex, t, {"ABC"[t]: gap}), \
+                    (sp, v.name, t)
                 checked += 1
                 break
     assert checked == reachable >= 7
