@@ -320,19 +320,28 @@ def forms(args, torch, tc, wl):
     for dt in (("f64", "f32") if "batched" in chosen else ()):
         out[f"batched_{dt}"] = batched(args, torch, tc, wl, dt)
         print(f"# batched {dt} done", file=sys.stderr, flush=True)
+    if "batched" in chosen:
+        # the batched mixed-precision form: FP64 data, split-BF16 products
+        out["batched_bf16x3"] = batched(args, torch, tc, wl, "f64", compute="bf16x3",
+                                        sequential_ms=out["batched_f64"]["sequential_ms"])
+        print("# batched bf16x3 done", file=sys.stderr, flush=True)
     if "complex" in chosen:
         out.update(complex_forms(args, torch, tc, wl))
         print("# complex done", file=sys.stderr, flush=True)
     if "batched_f32" in out and "batched_f64" in out:
         out["batched_f32"]["factor_vs_sequential_fp64"] = round(
             out["batched_f64"]["sequential_ms"] / out["batched_f32"]["batched_tuned_ms"], 3)
+    if "batched_bf16x3" in out:
+        out["batched_bf16x3"]["factor_vs_sequential_fp64"] = out["batched_bf16x3"]["speedup_vs_sequential"]
     return out
 
 
-def batched(args, torch, tc, wl, dtype):
+def batched(args, torch, tc, wl, dtype, compute="native", sequential_ms=None):
     """4096 contractions of the four batch patterns, uneven extents: one
     tc_contract per member on one stream versus one graph replay (before and
-    after tuning).  Device data from a seeded torch generator (uniform[-1,1])."""
+    after tuning).  Device data from a seeded torch generator (uniform[-1,1]).
+    With compute="bf16x3" every member runs split-BF16 tiles in the graph and
+    the sequential FP64 time of the native run is given."""
     import numpy as np
     shapes, redraws = wl.batch_shapes(4096)
     tdt = torch.float64 if dtype == "f64" else torch.float32
@@ -342,7 +351,7 @@ def batched(args, torch, tc, wl, dtype):
     plans, As, Bs, Cs = [], [], [], []
     flops = bytes_ = 0
     for it in shapes:
-        p = tc.Plan(it["spec"], it["ext"], dtype)
+        p = tc.Plan(it["spec"], it["ext"], dtype, compute=compute)
         plans.append(p)
         A = tc.empty_fortran(p.shape("A"), tdt).uniform_(-1, 1, generator=gen)
         B = tc.empty_fortran(p.shape("B"), tdt).uniform_(-1, 1, generator=gen)
@@ -356,8 +365,13 @@ def batched(args, torch, tc, wl, dtype):
     def seq():
         for p, A, B, C in zip(plans, As, Bs, Cs):
             p.contract(A, B, C)
-    seq_ms, seq_wall = _events_time(seq, 2, 1, torch)
+    if sequential_ms is None:
+        seq_ms, seq_wall = _events_time(seq, 2, 1, torch)
+    else:
+        seq_ms, seq_wall = sequential_ms, None
+    t0 = time.perf_counter()
     batch = tc.Batch(plans)
+    create_s = time.perf_counter() - t0
     bound = batch.bind(As, Bs, Cs)        # operands checked once; each replay is one library call
     run = lambda: batch.run(bound)
     bat_ms, _ = _events_time(run, 5, 3, torch)
@@ -378,18 +392,23 @@ def batched(args, torch, tc, wl, dtype):
         it = shapes[t]
         ref = _einsum_ref(it["spec"], As[t].double().cpu().numpy(), Bs[t].double().cpu().numpy())
         worst = max(worst, _normwise(Cs[t].double().cpu().numpy(), ref))
-    peak = FP64_PEAK_TFS if dtype == "f64" else FP32_PEAK_TFS
-    bound_ms = max(flops / (peak * 1e12), bytes_ / (HBM_PEAK_GBS * 1e9)) * 1e3
+    peak = BF16_PEAK_TFS if compute == "bf16x3" else FP64_PEAK_TFS if dtype == "f64" else FP32_PEAK_TFS
+    executed = flops * (6 if compute != "native" else 1)     # six products in the split form
+    bound_ms = max(executed / (peak * 1e12), bytes_ / (HBM_PEAK_GBS * 1e9)) * 1e3
     rec = dict(workload="4096 contractions from {abc=ai,ibc; abc=ija,jbic; ab=iaj,jbi; abcd=ai,ibcd}, free extents "
-                        "logU[8,256], contracted logU[4,64], largest operand <= 2^24 elements, uniform[-1,1]",
+                        "logU[8,256], contracted logU[4,64], largest operand <= 2^24 elements, uniform[-1,1]"
+                        + ("" if compute == "native" else f", {compute} products on FP64 data"),
                redraws=redraws, gflop=round(flops / 1e9, 2), gbytes=round(bytes_ / 1e9, 2),
-               sequential_ms=round(seq_ms, 3), sequential_wall_ms=round(seq_wall, 3),
-               batched_ms=round(bat_ms, 3), batched_tuned_ms=round(tuned_ms, 3), tune_s=round(tune_s, 2),
+               sequential_ms=round(seq_ms, 3), create_s=round(create_s, 2),
+               batched_ms=round(bat_ms, 3), batched_tuned_ms=round(tuned_ms, 3),
                speedup_vs_sequential=round(seq_ms / tuned_ms, 3),
-               tuner=dict(top_k=2, candidates="(fused view | gemm members with all loops free) x 3 tile shapes",
+               tiles=info["tiles"], groups=info["groups"], normwise_err_sampled_max=worst,
+               tune_s=round(tune_s, 2),
+               tuner=dict(top_k=2, candidates=("(fused view | gemm members with all loops free) x 3 tile shapes"
+                                               if compute == "native" else "fused view x 3 tile shapes"),
                           members_on_family_variants=on_members, score_s=round(score_s, 2),
                           score={k: (round(v, 4) if isinstance(v, float) else v) for k, v in score.items()}),
-               tiles=info["tiles"], groups=info["groups"], normwise_err_sampled_max=worst,
+               **({} if seq_wall is None else dict(sequential_wall_ms=round(seq_wall, 3))),
                gflops=round(flops / (tuned_ms * 1e-3) / 1e9, 1),
                roofline=dict(bound="max(mfma, hbm)", lower_bound_ms=round(bound_ms, 3),
                              frac=round(bound_ms / tuned_ms, 4)))

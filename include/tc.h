@@ -309,14 +309,21 @@ tc_status tc_predict(tc_plan_t plan, tc_prediction* out, int capacity, int* n_ou
 
 /* Build a batch of n independent contractions (not in the paper: many
  * contractions in one launch; its tuner is seeded as Section 3 predicts).
- * Plans stay owned by the caller and must outlive the batch; each needs the
- * native compute mode, a non-empty C and a contracted extent > 0.  Every
- * contraction becomes matrix-core tiles (128x128 outputs, 64x64 when M or N is
- * at most 64, 32x128 when M is at most 32); work lists of (contraction, tile)
- * pairs, longest tiles first, go to device memory once, and the HIP graph that
- * tc_batch_contract replays is captured here: pointer staging from pinned host
- * memory, counter reset, one persistent kernel per group on up to four graph
- * branches.  Errors: TC_E_NULL, TC_E_UNSUPPORTED, TC_E_NOMEM, TC_E_HIP. */
+ * Plans stay owned by the caller and must outlive the batch; each needs real
+ * storage, a non-empty C and a contracted extent > 0.  Every native or
+ * TC_BF16X3 contraction becomes matrix-core tiles (128x128 outputs, 64x64 when
+ * M or N is at most 64, 32x128 when M is at most 32); a TC_BF16X3 member's
+ * tiles split its operands into three per-row / per-column scaled BF16 terms
+ * and multiply six term products on BF16 matrix cores (the split-precision
+ * form of tc_contract, with the scales and terms formed inside the tile).
+ * Work lists of (contraction, tile) pairs, longest tiles first, go to device
+ * memory once, and the HIP graph that tc_batch_contract replays is captured
+ * here: pointer staging from pinned host memory, counter reset, one
+ * persistent kernel per group on up to four graph branches.  A TC_FP8X3
+ * member runs its plan's own split and product launches in a branch, on the
+ * plan's workspace: such a plan may appear once per batch and needs at most
+ * 8192 contracted positions (TC_E_UNSUPPORTED otherwise).
+ * Errors: TC_E_NULL, TC_E_UNSUPPORTED, TC_E_NOMEM, TC_E_HIP. */
 tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n);
 
 /* Choose each member's candidate -- a loop/kernel variant (the fused GEMM
@@ -377,13 +384,16 @@ tc_status tc_batch_score(tc_batch_t batch, int sample, uint64_t seed, tc_tune_sc
 
 /* The candidate member `member` runs with: its variant (TC_VARIANT_FUSED or a
  * 0-based family member of its plan), tile shape (0: 128x128, 1: 64x64,
- * 2: 32x128) and how many candidates it has.  Any output pointer may be NULL. */
+ * 2: 32x128) and how many candidates it has (a TC_BF16X3 member: the fused
+ * view with three shapes; a TC_FP8X3 member: TC_VARIANT_FUSED, shape -1 and
+ * no candidates).  Any output pointer may be NULL. */
 tc_status tc_batch_choice(tc_batch_t batch, int member, int* variant, int* shape, int* n_candidates);
 
 /* Make member `member` run candidate (variant, shape) -- variant
  * TC_VARIANT_FUSED or a family member of its plan that is a candidate (see
  * tc_batch_tune), shape 0..2 -- and capture the graph again.  Allocates
- * (work lists).  Errors: TC_E_NULL, TC_E_VARIANT, TC_E_NOMEM, TC_E_HIP. */
+ * (work lists).  A TC_FP8X3 member has no candidates (TC_E_VARIANT).
+ * Errors: TC_E_NULL, TC_E_VARIANT, TC_E_NOMEM, TC_E_HIP. */
 tc_status tc_batch_set_choice(tc_batch_t batch, int member, int variant, int shape);
 
 /* Members, work items (tiles), persistent-kernel groups and the within-5%

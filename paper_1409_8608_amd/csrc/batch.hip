@@ -17,6 +17,13 @@
 // groups spread over up to four graph branches.  tc_batch_contract only writes
 // the staging buffer and replays the graph.
 //
+// Split-precision members: a TC_BF16X3 plan runs as split-BF16 tiles of the
+// same persistent kernel (FP64 or FP32 operands split into three BF16 terms
+// in the tile, with per-row and per-column power-of-two scales found by a
+// first sweep over K; its candidates are the fused view with the three
+// shapes), in groups of its own.  A TC_FP8X3 plan runs its plan's own
+// launches (split passes and scaled FP8 products) in a graph branch.
+//
 // tc_batch_tune chooses each contraction's candidate the way Section 3
 // predicts a family member: micro-benchmarks of the kernel, run after the
 // cache set-up the member meets, composed by invocation counts.  In a batch a
@@ -65,6 +72,7 @@ struct Cand {
 
 struct BatchGroup {
     bool f64;
+    bool x3;            // split-BF16 tiles
     int shape;
     bool ak, bk;
     std::vector<int2> work;
@@ -83,7 +91,8 @@ std::map<std::string, std::pair<int, int>> g_tune_cache;
 
 std::string signature(const tc_plan_s* p) {
     const Spec& s = p->spec;
-    std::string k = std::to_string((int)s.dtype) + "|" + s.a + "," + s.b + "=" + s.c + "|";
+    std::string k = std::to_string((int)s.dtype) + "/" + std::to_string((int)s.compute) + "|" + s.a + "," + s.b +
+                    "=" + s.c + "|";
     for (char ch : s.base) k += std::to_string(s.e(ch)) + ",";
     for (int t = 0; t < 3; ++t) {
         k += "|";
@@ -96,7 +105,9 @@ std::string signature(const tc_plan_s* p) {
 
 struct tc_batch_s {
     std::vector<tc_plan_s*> plans;
-    std::vector<std::vector<Cand>> cands;   // per member
+    std::vector<char> split;                // member runs the split-FP8 form (its plan's own launches)
+    std::vector<char> x3;                   // member runs split-BF16 tiles
+    std::vector<std::vector<Cand>> cands;   // per member (none for a split-FP8 member)
     std::vector<int> choice;                // index into cands[c]
     std::vector<int> deflt;                 // the untuned default's index
     std::vector<std::vector<double>> est;   // seed estimates (seconds), filled by tuning
@@ -157,6 +168,7 @@ static bool batchable_member(const VariantPlan& vp) {
 static MfmaArgs make_item(const tc_batch_s* b, int c, const Cand& cd) {
     tc_plan_s* p = b->plans[c];
     MfmaArgs a{};
+    if (b->split[c]) return a;            // no tiles: the split-FP8 form runs its own launches
     if (cd.variant == TC_VARIANT_FUSED) {
         const GemmView& gv = p->gv;
         a.m.n = (int)gv.m.size();
@@ -202,7 +214,7 @@ static tc_status build_groups(tc_batch_s* b) {
     free_groups(b);
     const int n = (int)b->plans.size();
     b->items.resize(n);
-    for (int c = 0; c < n; ++c) b->items[c] = make_item(b, c, b->cands[c][b->choice[c]]);
+    for (int c = 0; c < n; ++c) b->items[c] = b->split[c] ? MfmaArgs{} : make_item(b, c, b->cands[c][b->choice[c]]);
     std::map<int, int> gid;   // key -> group index
     std::vector<std::vector<std::pair<int64_t, int2>>> lists;
     int ncu = 256;
@@ -212,15 +224,18 @@ static tc_status build_groups(tc_batch_s* b) {
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
     }
     for (int c = 0; c < n; ++c) {
+        if (b->split[c]) continue;
         MfmaArgs& a = b->items[c];
         const bool f64 = b->plans[c]->spec.dtype == TC_F64;
+        const bool x3 = b->x3[c];
         const bool ak = mfma_kmajor_a(a), bk = mfma_kmajor_b(a);
         const int sh = b->cands[c][b->choice[c]].shape;
-        const int key = (f64 ? 16 : 0) | (sh << 2) | (ak ? 2 : 0) | (bk ? 1 : 0);   // sh in 0..3
+        const int key = (x3 ? 32 : 0) | (f64 ? 16 : 0) | (sh << 2) | (ak ? 2 : 0) | (bk ? 1 : 0);   // sh in 0..3
         if (!gid.count(key)) {
             gid[key] = (int)b->groups.size();
             BatchGroup g;
             g.f64 = f64;
+            g.x3 = x3;
             g.shape = sh;
             g.ak = ak;
             g.bk = bk;
@@ -241,7 +256,7 @@ static tc_status build_groups(tc_batch_s* b) {
         if (e != hipSuccess) return fail(TC_E_NOMEM, "hipMalloc batch work list");
         e = hipMemcpy(g.d_work, g.work.data(), sizeof(int2) * g.work.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "upload batch work list");
-        int occ = mfma_batch_occupancy(g.f64, g.shape, g.ak, g.bk);
+        int occ = g.x3 ? x3_batch_occupancy(g.f64, g.shape, g.ak, g.bk) : mfma_batch_occupancy(g.f64, g.shape, g.ak, g.bk);
         g.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)g.work.size(), (int64_t)occ * ncu));
     }
     hipError_t e = hipMalloc(&b->d_counters, sizeof(int) * std::max<size_t>(1, b->groups.size()));
@@ -258,22 +273,40 @@ static tc_status capture(tc_batch_s* b) {
     if (e != hipSuccess) return hip_fail(e, "begin capture");
     hipLaunchKernelGGL(k_stage, dim3((n + 255) / 256), dim3(256), 0, b->cap, b->h_ptrs, b->d_ptrs, n);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, b->cap, b->d_counters, (int)b->groups.size());
-    // the groups are independent: up to four branches of the graph, so that one
-    // group's tail overlaps the next group's blocks
-    const int nb = (int)std::min<size_t>(4, b->groups.size());
+    // the groups (and the split-FP8 members) are independent: up to four
+    // branches of the graph, so that one group's tail overlaps the next group's
+    // blocks
+    std::vector<int> splits;
+    for (int c = 0; c < n; ++c)
+        if (b->split[c]) splits.push_back(c);
+    const size_t jobs = b->groups.size() + splits.size();
+    const int nb = (int)std::min<size_t>(4, jobs);
     if (nb > 1 && e == hipSuccess) e = hipEventRecord(b->fork, b->cap);
     for (int q = 1; q < nb && e == hipSuccess; ++q) e = hipStreamWaitEvent(b->side[q - 1], b->fork, 0);
-    for (size_t gi = 0; gi < b->groups.size() && e == hipSuccess; ++gi) {
-        BatchGroup& g = b->groups[gi];
-        const int q = (int)(gi % nb);
-        hipStream_t st = q == 0 ? b->cap : b->side[q - 1];
-        hipError_t le = launch_mfma_batch(g.f64, g.shape, g.ak, g.bk, b->d_items, b->d_ptrs, g.d_work,
-                                          (int)g.work.size(), b->d_counters + gi, g.grid, st);
-        if (le != hipSuccess) e = le;
+    tc_status st = TC_OK;
+    for (size_t j = 0; j < jobs && e == hipSuccess && !st; ++j) {
+        const int q = (int)(j % nb);
+        hipStream_t sq = q == 0 ? b->cap : b->side[q - 1];
+        if (j < b->groups.size()) {
+            BatchGroup& g = b->groups[j];
+            hipError_t le = (g.x3 ? launch_x3_batch : launch_mfma_batch)(g.f64, g.shape, g.ak, g.bk, b->d_items,
+                                                                         b->d_ptrs, g.d_work, (int)g.work.size(),
+                                                                         b->d_counters + j, g.grid, sq);
+            if (le != hipSuccess) e = le;
+        } else {
+            const int c = splits[j - b->groups.size()];
+            st = run_split_batched(b->plans[c], b->d_ptrs + c, sq);
+        }
     }
-    for (int q = 1; q < nb && e == hipSuccess; ++q) {
+    for (int q = 1; q < nb && e == hipSuccess && !st; ++q) {
         e = hipEventRecord(b->join[q - 1], b->side[q - 1]);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[q - 1], 0);
+    }
+    if (st) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(b->cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        return st;
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
@@ -324,7 +357,7 @@ struct Timer {
     }
     // the previous call gave this member all three operands (an alpha = 0
     // member may have left A and B out: it is not timed)
-    bool usable(int c) const { return b->h_ptrs[c].A && b->h_ptrs[c].B && b->h_ptrs[c].C; }
+    bool usable(int c) const { return !b->split[c] && b->h_ptrs[c].A && b->h_ptrs[c].B && b->h_ptrs[c].C; }
     MfmaArgs item(int c, const Cand& cd) {
         MfmaArgs a = make_item(b, c, cd);
         const BatchPtrs& pt = b->h_ptrs[c];
@@ -343,7 +376,7 @@ struct Timer {
         for (int r = 0; r <= reps; ++r) {
             hipError_t e = launch_touch(scratch, scratch_bytes, sink, st);
             if (e == hipSuccess) e = hipEventRecord(t0, st);
-            if (e == hipSuccess) e = launch_mfma_shape(f64, cd.shape, a, st);
+            if (e == hipSuccess) e = (b->x3[c] ? launch_x3_shape : launch_mfma_shape)(f64, cd.shape, a, st);
             if (e == hipSuccess) e = hipEventRecord(t1, st);
             if (e == hipSuccess) e = hipEventSynchronize(t1);
             float ms = 0;
@@ -367,7 +400,7 @@ static int kbucket(int64_t kpad) {
 // bucket, operand layouts, C unit-stride along m
 static std::string bench_key(const tc_batch_s* b, int c, const Cand& cd, const MfmaArgs& a) {
     const bool cm1 = a.m.n > 0 && a.m.d[0].sC == 1;
-    return std::to_string((int)b->plans[c]->spec.dtype) + "/" + std::to_string(cd.shape) + "/" +
+    return std::to_string((int)b->plans[c]->spec.dtype) + (b->x3[c] ? "x/" : "/") + std::to_string(cd.shape) + "/" +
            std::to_string(kbucket(cd.kpad)) + "/" + std::to_string((int)mfma_kmajor_a(a)) +
            std::to_string((int)mfma_kmajor_b(a)) + std::to_string((int)cm1);
 }
@@ -392,7 +425,8 @@ static tc_status seed_estimates(tc_batch_s* b, Timer& tm) {
         double t;
         hipError_t e = tm.time(c, cd, 10, &t);            // Section 3: median of ten
         if (e != hipSuccess) return hip_fail(e, "tuning micro-benchmark");
-        const int64_t wave = (int64_t)mfma_batch_occupancy(f64, cd.shape, mfma_kmajor_a(a), mfma_kmajor_b(a)) * tm.ncu;
+        const int64_t wave = (int64_t)(b->x3[c] ? x3_batch_occupancy : mfma_batch_occupancy)(
+                                 f64, cd.shape, mfma_kmajor_a(a), mfma_kmajor_b(a)) * tm.ncu;
         per_tile[kv.first] = t / (double)std::max<int64_t>(a.ntiles, wave);
     }
     b->est.assign(n, {});
@@ -425,10 +459,6 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
             delete b;
             return fail(TC_E_NULL, "a plan is NULL");
         }
-        if (p->spec.compute != TC_NATIVE) {
-            delete b;
-            return fail(TC_E_UNSUPPORTED, "batches run the native compute mode");
-        }
         if (p->spec.is_complex()) {
             delete b;
             return fail(TC_E_UNSUPPORTED, "batches take real plans");
@@ -438,6 +468,29 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
             return fail(TC_E_UNSUPPORTED, "batch members need a non-empty C and contracted extent");
         }
         b->plans.push_back(p);
+        b->x3.push_back(p->spec.compute == TC_BF16X3);
+        if (p->spec.compute == TC_FP8X3) {
+            // the split-FP8 form (per-slice scaled FP8 terms on matrix cores)
+            // runs its plan's own launches in the graph, on the plan's
+            // workspace: a plan can be one such member only
+            for (int q = 0; q < c; ++q)
+                if (plans[q] == p) {
+                    delete b;
+                    return fail(TC_E_UNSUPPORTED, "a split-FP8 plan is listed twice (its workspace is per plan)");
+                }
+            if (!p->d_split) {
+                delete b;
+                return fail(TC_E_UNSUPPORTED, "split-FP8 member without its workspace (plan built with no GPU)");
+            }
+            if (split_positions(p) > 8192) {
+                delete b;
+                return fail(TC_E_UNSUPPORTED, "FP8 split form takes at most 8192 contracted positions");
+            }
+            b->split.push_back(1);
+            b->cands.emplace_back();
+            continue;
+        }
+        b->split.push_back(0);
         std::vector<Cand> cs;
         auto add_variant = [&](int v, const std::vector<GtDim>& kd, bool swap) {
             std::vector<int64_t> tab = build_ktab(kd, BATCH_BK);
@@ -448,8 +501,8 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
         add_variant(TC_VARIANT_FUSED, p->gv.k, p->gv.swapped);
         // gemm members keep the one contracted index: only specs with a single
         // contracted index (and no batch or trace index) have members whose
-        // loops are all free
-        if (p->spec.contracted.size() == 1 && !p->spec.general()) {
+        // loops are all free (split-BF16 members: the fused view only)
+        if (p->spec.contracted.size() == 1 && !p->spec.general() && !b->x3.back()) {
             for (int v = 0; v < (int)p->fam().size(); ++v) {
                 const VariantPlan& vp = p->vplans()[v];
                 if (batchable_member(vp)) add_variant(v, {vp.body.kb}, false);
@@ -462,6 +515,11 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
         e = hipMemcpy(b->d_ktab, tab_all.data(), sizeof(int64_t) * tab_all.size(), hipMemcpyHostToDevice);
     // default: the fused view with the default shape, or the tuning cache's choice
     for (int c = 0; c < n && e == hipSuccess; ++c) {
+        if (b->split[c]) {
+            b->deflt.push_back(-1);
+            b->choice.push_back(-1);
+            continue;
+        }
         int d = 0;
         const MfmaArgs a0 = make_item(b, c, b->cands[c][0]);
         for (int j = 0; j < (int)b->cands[c].size(); ++j)
@@ -541,7 +599,9 @@ tc_status tc_batch_contract(tc_batch_t b, const void* const* A, const void* cons
         if (e != hipSuccess) return hip_fail(e, "wait for previous batch");
     }
     for (int c = 0; c < n; ++c) {
-        const bool sw = b->cands[c][b->choice[c]].swap;
+        // each member's operands in its kernels' order (the split-FP8 form and the
+        // fused view take A and B in GEMM-view order)
+        const bool sw = b->split[c] ? b->plans[c]->gv.swapped : b->cands[c][b->choice[c]].swap;
         b->h_ptrs[c].A = sw ? B[c] : A[c];
         b->h_ptrs[c].B = sw ? A[c] : B[c];
         b->h_ptrs[c].C = C[c];
@@ -568,8 +628,9 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
     const int n = (int)b->plans.size();
     // the tuned members' staging entries: the previous call's pointers (in
     // candidate-independent order) and alpha; C := alpha * contract(A, B)
+    auto swapped = [&](int c) { return !b->split[c] && b->cands[c][b->choice[c]].swap; };
     for (int c = 0; c < n; ++c)
-        if (b->cands[c][b->choice[c]].swap) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
+        if (swapped(c)) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
     Timer tm{b, nullptr};
     tc_status st = tm.open();
     if (!st) st = seed_estimates(b, tm);
@@ -583,7 +644,7 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
         // member's kernel order
         std::vector<BatchPtrs> keep(b->h_ptrs, b->h_ptrs + n);
         for (int c = 0; c < n; ++c)
-            if (b->cands[c][b->choice[c]].swap) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
+            if (swapped(c)) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
         hipError_t err = hipGraphLaunch(b->exec, tm.st);   // warm-up
         if (err == hipSuccess) err = hipEventRecord(tm.t0, tm.st);
         for (int r = 0; r < 5 && err == hipSuccess; ++r) err = hipGraphLaunch(b->exec, tm.st);
@@ -654,11 +715,13 @@ tc_status tc_batch_tune(tc_batch_t b, int top_k) {
     if (!st) st = use(kept);
     // staging back in each kept choice's kernel order
     for (int c = 0; c < n; ++c)
-        if (b->cands[c][b->choice[c]].swap) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
+        if (swapped(c)) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
     if (!st) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         for (int c = 0; c < n; ++c)
-            g_tune_cache[signature(b->plans[c])] = {b->cands[c][b->choice[c]].variant, b->cands[c][b->choice[c]].shape};
+            if (!b->split[c])
+                g_tune_cache[signature(b->plans[c])] = {b->cands[c][b->choice[c]].variant,
+                                                        b->cands[c][b->choice[c]].shape};
     }
     return st;
 }
@@ -674,8 +737,9 @@ tc_status tc_batch_score(tc_batch_t b, int sample, uint64_t seed, tc_tune_score*
     Timer tm{b, nullptr};
     tc_status st = tm.open();
     // the staging entries in A, B order for the timer
+    auto swapped = [&](int c) { return !b->split[c] && b->cands[c][b->choice[c]].swap; };
     for (int c = 0; c < n; ++c)
-        if (b->cands[c][b->choice[c]].swap) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
+        if (swapped(c)) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
     if (!st && b->est.empty()) st = seed_estimates(b, tm);
     std::vector<int> members;
     for (int c = 0; c < n; ++c)
@@ -710,7 +774,7 @@ tc_status tc_batch_score(tc_batch_t b, int sample, uint64_t seed, tc_tune_score*
         }
     }
     for (int c = 0; c < n; ++c)
-        if (b->cands[c][b->choice[c]].swap) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
+        if (swapped(c)) std::swap(b->h_ptrs[c].A, b->h_ptrs[c].B);
     if (st) return st;
     const double m = (double)members.size();
     out->n_sampled = (int)members.size();
@@ -746,6 +810,7 @@ tc_status tc_batch_info(tc_batch_t b, int* n_members, int64_t* n_tiles, int* n_g
 tc_status tc_batch_set_choice(tc_batch_t b, int member, int variant, int shape) {
     if (!b) return fail(TC_E_NULL, "batch is NULL");
     if (member < 0 || member >= (int)b->plans.size()) return fail(TC_E_VARIANT, "member out of range");
+    if (b->split[member]) return fail(TC_E_VARIANT, "a split-FP8 member has no tile candidates");
     int j = -1;
     for (int q = 0; q < (int)b->cands[member].size(); ++q)
         if (b->cands[member][q].variant == variant && b->cands[member][q].shape == shape) j = q;
@@ -765,6 +830,12 @@ tc_status tc_batch_set_choice(tc_batch_t b, int member, int variant, int shape) 
 tc_status tc_batch_choice(tc_batch_t b, int member, int* variant, int* shape, int* n_candidates) {
     if (!b) return fail(TC_E_NULL, "batch is NULL");
     if (member < 0 || member >= (int)b->plans.size()) return fail(TC_E_VARIANT, "member out of range");
+    if (b->split[member]) {                   // the split-FP8 form: its own launches
+        if (variant) *variant = TC_VARIANT_FUSED;
+        if (shape) *shape = -1;
+        if (n_candidates) *n_candidates = 0;
+        return TC_OK;
+    }
     const Cand& cd = b->cands[member][b->choice[member]];
     if (variant) *variant = cd.variant;
     if (shape) *shape = cd.shape;

@@ -83,6 +83,9 @@ __device__ __forceinline__ int64_t grp_off(const GtDims& g, int64_t i, int slot)
 
 struct SplitArgs {
     const void* X;
+    // batches: X, and whether to run at all (alpha != 0), come from the
+    // member's staged pointers at run time (X unused)
+    const BatchPtrs* bp;
     GtDims rows;          // the side's free dims (slot selects the stride)
     int slot;             // 0: A side (sA); 1: B side (sB)
     const int64_t* koff;  // Kp element offsets of the side's operand, -1 for padding
@@ -120,7 +123,8 @@ __device__ __forceinline__ uint32_t pack2(double lo, double hi) {
 template <typename T, int CPT, bool VEC>
 __global__ __launch_bounds__(256) void k_split(SplitArgs a) {
     __shared__ double red[4];
-    const T* X = (const T*)a.X;
+    if (a.bp && a.bp->alpha == 0.0) return;   // a batch member with alpha = 0 reads neither input
+    const T* X = (const T*)(a.bp ? (a.slot == 0 ? a.bp->A : a.bp->B) : a.X);
     // neighbouring slices on one XCD: their stage-image rows share cache
     // lines, which then fill in one L2
     const int64_t row = xcd_item(blockIdx.x, a.nrows);
@@ -199,7 +203,8 @@ __global__ __launch_bounds__(256) void k_split(SplitArgs a) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_split_long(SplitArgs a) {
     __shared__ double red[4];
-    const T* X = (const T*)a.X;
+    if (a.bp && a.bp->alpha == 0.0) return;   // a batch member with alpha = 0 reads neither input
+    const T* X = (const T*)(a.bp ? (a.slot == 0 ? a.bp->A : a.bp->B) : a.X);
     const int64_t row = blockIdx.x;
     const int tid = threadIdx.x;
     const int64_t base = grp_off(a.rows, row, a.slot);
@@ -287,7 +292,8 @@ __device__ __forceinline__ uint32_t pack4_e4m3(const double* t) {
 template <typename T, int CPT, bool VEC>
 __global__ __launch_bounds__(256) void k_split8(SplitArgs a) {
     __shared__ double red[4];
-    const T* X = (const T*)a.X;
+    if (a.bp && a.bp->alpha == 0.0) return;   // a batch member with alpha = 0 reads neither input
+    const T* X = (const T*)(a.bp ? (a.slot == 0 ? a.bp->A : a.bp->B) : a.X);
     const int64_t row = xcd_item(blockIdx.x, a.nrows);
     const int tid = threadIdx.x;
     const int64_t base = grp_off(a.rows, row, a.slot);
@@ -360,6 +366,7 @@ __global__ __launch_bounds__(256) void k_split8(SplitArgs a) {
 }
 
 struct X3Args {
+    const BatchPtrs* bp;  // batches: C, alpha and beta from the member's staged entry (C, alpha, beta unused)
     const uint16_t* tA;   // stage images of A's terms (panel_off layout)
     const uint16_t* tB;   // stage images of B's terms
     const int32_t* eA;
@@ -421,7 +428,9 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
     }
     __syncthreads();
 
-    const int64_t ktiles = a.Kp / SPLIT_BK;
+    const double alpha = a.bp ? a.bp->alpha : a.alpha, beta_d = a.bp ? a.bp->beta : a.beta;
+    // alpha = 0 (a batch member): no stage is loaded; the epilogue writes beta * C
+    const int64_t ktiles = alpha == 0.0 ? 0 : a.Kp / SPLIT_BK;
     // A's stage kt: the images of row tiles 2 mt and 2 mt + 1; B's: row tile nt
     const char* gA = (const char*)a.tA + 2 * mt * ktiles * XSTAGE;
     const char* gB = (const char*)a.tB + nt * ktiles * XSTAGE;
@@ -524,8 +533,8 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
     }
     __builtin_amdgcn_s_waitcnt(wait_vm(0));   // the trailing reload lands before the block exits
 
-    T* C = (T*)a.C;
-    const T beta = (T)a.beta;
+    T* C = (T*)(a.bp ? a.bp->C : a.C);
+    const T beta = (T)beta_d;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -539,10 +548,10 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
                 const int64_t cm = sCm[ml];
                 if (cm < 0) continue;
                 // the two FP32 partials add exactly in FP64
-                const double v = a.alpha * ldexp((double)big[i][j][q] + (double)small[i][j][q], sEm[ml] + sEn[nl]);
+                const double v = alpha * ldexp((double)big[i][j][q] + (double)small[i][j][q], sEm[ml] + sEn[nl]);
                 T* cp = C + cn + cm;
                 T out = (T)v;
-                if (a.beta != 0.0) out += beta * (*cp);
+                if (beta_d != 0.0) out += beta * (*cp);
                 *cp = out;
             }
         }
@@ -594,7 +603,8 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3_8(X3Args a) {
     }
     __syncthreads();
 
-    const int64_t ktiles = a.Kp / F8_BK;
+    const double alpha = a.bp ? a.bp->alpha : a.alpha, beta_d = a.bp ? a.bp->beta : a.beta;
+    const int64_t ktiles = alpha == 0.0 ? 0 : a.Kp / F8_BK;
     const char* gA = (const char*)a.tA + 2 * mt * ktiles * XSTAGE;
     const char* gB = (const char*)a.tB + nt * ktiles * XSTAGE;
     const uint32_t loff = (uint32_t)lane * 16u;
@@ -688,8 +698,8 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3_8(X3Args a) {
     }
     __builtin_amdgcn_s_waitcnt(wait_vm(0));
 
-    T* C = (T*)a.C;
-    const T beta = (T)a.beta;
+    T* C = (T*)(a.bp ? a.bp->C : a.C);
+    const T beta = (T)beta_d;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -702,10 +712,10 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3_8(X3Args a) {
                 const int ml = wm * 64 + j * 32 + (lane & 31);
                 const int64_t cm = sCm[ml];
                 if (cm < 0) continue;
-                const double v = a.alpha * ldexp((double)big[i][j][q] + (double)small[i][j][q], sEm[ml] + sEn[nl]);
+                const double v = alpha * ldexp((double)big[i][j][q] + (double)small[i][j][q], sEm[ml] + sEn[nl]);
                 T* cp = C + cn + cm;
                 T out = (T)v;
-                if (a.beta != 0.0) out += beta * (*cp);
+                if (beta_d != 0.0) out += beta * (*cp);
                 *cp = out;
             }
         }
@@ -814,8 +824,26 @@ static void launch_split8(const SplitArgs& s, int64_t nch, bool vec, dim3 grid, 
     }
 }
 
+// The split form's launches: the two split passes and the product.  With `bp`
+// (a batch member) the operands, alpha and beta are read from the member's
+// staged entry when the kernels run, and the split passes take element loads
+// (the pointers' alignment is not known ahead).
+static tc_status launch_split_form(tc_plan_s* p, const void* A, const void* B, void* C, double alpha,
+                                   double beta, const BatchPtrs* bp, hipStream_t st);
+
 tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
                     hipStream_t st) {
+    return launch_split_form(p, A, B, C, alpha, beta, nullptr, st);
+}
+
+int64_t split_positions(const tc_plan_s* p) { return p->d_split ? p->split_layout[L_KT] : 0; }
+
+tc_status run_split_batched(tc_plan_s* p, const BatchPtrs* bp, hipStream_t st) {
+    return launch_split_form(p, nullptr, nullptr, nullptr, 0.0, 0.0, bp, st);
+}
+
+static tc_status launch_split_form(tc_plan_s* p, const void* A, const void* B, void* C, double alpha,
+                                   double beta, const BatchPtrs* bp, hipStream_t st) {
     const GemmView& gv = p->gv;
     const bool f64 = p->spec.dtype == TC_F64;
     const bool fp8 = p->spec.compute == TC_FP8X3;
@@ -832,6 +860,7 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
     for (int side = 0; side < 2; ++side) {
         SplitArgs s{};
         s.X = side == 0 ? A : B;
+        s.bp = bp;
         const std::vector<GtDim>& g = side == 0 ? gv.m : gv.n;
         s.rows.n = (int)g.size();
         for (int d = 0; d < s.rows.n; ++d) s.rows.d[d] = g[d];
@@ -845,7 +874,7 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
         if (s.nrows <= 0 || L[L_KT] == 0) continue;   // no K: the exponents stay 0, the terms empty
         if (s.nrows > 0x7fffffff) return fail(TC_E_EXTENT, "too many slices for one launch");
         const dim3 grid((unsigned)s.nrows), blk(256);
-        const bool vec = L[side == 0 ? L_VA : L_VB] != 0 && ((uintptr_t)s.X) % 16 == 0;
+        const bool vec = !bp && L[side == 0 ? L_VA : L_VB] != 0 && ((uintptr_t)s.X) % 16 == 0;
         if (fp8) {
             const int64_t nch = s.Kt / 16;   // chunks of sixteen positions (Kt is a multiple of 64)
             if (f64) launch_split8<double>(s, nch, vec, grid, blk, st);
@@ -859,6 +888,7 @@ tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double 
         if (e != hipSuccess) return hip_fail(e, "split kernel launch");
     }
     X3Args x{};
+    x.bp = bp;
     x.tA = tA; x.tB = tB;
     x.eA = eA; x.eB = eB;
     x.C = C;

@@ -28,7 +28,7 @@ bool mfma_a_first(int64_t M, int64_t N);
 int64_t mfma_split_plan(bool f64, int64_t M, int64_t N, int64_t Kpad, int64_t* slice_tiles, int64_t* ws_bytes,
                         int64_t ws_cap = 64LL << 20);
 
-// Batches: tile shape 0 = 128x128, 1 = 64x64; persistent kernel over a work
+// Batches: tile shape 0 = 128x128, 1 = 64x64, 2 = 32x128; persistent kernel over a work
 // list of (contraction, tile) pairs taken off an atomic counter.
 void mfma_tiles_shape(int shape, MfmaArgs& a);
 bool mfma_kmajor_a(const MfmaArgs& a);
@@ -37,6 +37,11 @@ hipError_t launch_mfma_batch(bool f64, int shape, bool ak, bool bk, const MfmaAr
                              const int2* work, int nwork, int* counter, int grid, hipStream_t st);
 int mfma_batch_occupancy(bool f64, int shape, bool ak, bool bk);
 hipError_t launch_mfma_shape(bool f64, int shape, MfmaArgs& a, hipStream_t st);
+// The same for split-BF16 tiles (FP64 or FP32 storage; one pass, no split K).
+hipError_t launch_x3_batch(bool f64, int shape, bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs,
+                           const int2* work, int nwork, int* counter, int grid, hipStream_t st);
+int x3_batch_occupancy(bool f64, int shape, bool ak, bool bk);
+hipError_t launch_x3_shape(bool f64, int shape, MfmaArgs& a, hipStream_t st);
 
 // Strided copy (copy statements of the family) and C := beta*C prologue.
 hipError_t launch_copy(bool f64, CopyArgs& a, hipStream_t st);

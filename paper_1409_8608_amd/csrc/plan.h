@@ -116,6 +116,11 @@ tc_status run_variant(tc_plan_s* p, int v, const void* A, const void* B, void* C
 tc_status prepare_split(tc_plan_s* p);
 tc_status run_split(tc_plan_s* p, const void* A, const void* B, void* C, double alpha, double beta,
                     hipStream_t st);
+// The same launches for a batch member whose operands (GEMM-view order),
+// alpha and beta are read from its staged entry `bp` when the kernels run.
+tc_status run_split_batched(tc_plan_s* p, const BatchPtrs* bp, hipStream_t st);
+// contracted positions of a split plan's term tables (0 before its workspace exists)
+int64_t split_positions(const tc_plan_s* p);
 void release_plan_device(tc_plan_s* p);
 
 // complex storage (complex.hip)

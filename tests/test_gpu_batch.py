@@ -107,10 +107,15 @@ def test_batch_errors():
     with pytest.raises(tc.TcError) as e:
         tc.tc_batch_tune(tc.Batch([p]).handle, 2)
     assert e.value.name == "TC_E_UNSUPPORTED"
-    ps = tc.Plan("ab=ai,ib", dict(a=8, b=8, i=8), "f64", compute="bf16x3")
+    ps = tc.Plan("ab=ai,ib", dict(a=8, b=8, i=8), "f64", compute="fp8x3")
     with pytest.raises(tc.TcError) as e:
-        tc.Batch([ps])
+        tc.Batch([ps, p, ps])                # a split-FP8 plan's workspace serves one member
     assert e.value.name == "TC_E_UNSUPPORTED"
+    with pytest.raises(tc.TcError) as e:
+        tc.Batch([ps]).set_choice(0, tc.TC_VARIANT_FUSED, 0)   # no tile candidates
+    assert e.value.name == "TC_E_VARIANT"
+    pb = tc.Plan("ab=ai,ib", dict(a=8, b=8, i=8), "f64", compute="bf16x3")
+    assert tc.Batch([pb, p, pb]).info()["members"] == 3   # split-BF16 tiles use no plan workspace
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -243,3 +248,113 @@ def test_batch_every_candidate_exact(dtype):
     with pytest.raises(tc.TcError) as e:
         batch.set_choice(2, 0, 0)                 # abc=ija,jbic has no member candidates
     assert e.value.name == "TC_E_VARIANT"
+
+
+def test_batch_split_precision_members():
+    """Split-precision members (BF16 and FP8 terms, FP64 and FP32 storage) in
+    one graph with native members: integer data exact (single-term integers,
+    exact partial sums); real data within the split forms' bounds against the
+    oracle (split-BF16 tiles: componentwise within the FP32-accumulation bound
+    of the oracle's exactly accumulated split result, and FP32 level against
+    FP64); alpha = 0 with absent inputs; two replays with new operands."""
+    import torch
+    from gpu_util import split_bound
+    from oracle import split as osplit
+    cases = [("ab=iaj,jbi", dict(a=70, b=90, i=12, j=10), "f64", "bf16x3"),
+             ("abc=ija,jbic", dict(a=40, b=33, c=7, i=5, j=11), "f32", "bf16x3"),
+             ("abcd=ai,ibcd", dict(a=17, b=5, c=6, d=7, i=300), "f64", "fp8x3"),
+             ("abc=ai,ibc", dict(a=37, b=9, c=5, i=3), "f64", "native"),
+             ("ab=iaj,jbi", dict(a=50, b=45, i=8, j=8), "f64", "bf16x3")]
+    plans = [tc.Plan(sp, ex, dt, compute=cm) for sp, ex, dt, cm in cases]
+    batch = tc.Batch(plans)
+    assert [batch.choice(t)["candidates"] for t in range(len(cases))] == [3, 3, 0, 9, 3]
+    rng = np.random.default_rng(31)
+    for rep, integer in enumerate((True, False)):
+        host, dev = [], []
+        for (sp, ex, dt, cm), p in zip(cases, plans):
+            tdt = torch.float64 if dt == "f64" else torch.float32
+            A, B, C0 = wl.tensors(sp, ex, rng, integer=integer, with_c=True)
+            if dt == "f32":
+                A, B, C0 = (x.astype(np.float32).astype(np.float64) for x in (A, B, C0))
+            host.append((A, B, C0))
+            dev.append([tc.to_device_fortran(A, tdt), tc.to_device_fortran(B, tdt), tc.to_device_fortran(C0, tdt)])
+        alphas = [1.5, -2.0, 0.5, 1.0, 0.0]
+        betas = [0.0, 1.0, -1.0, 0.5, 2.0]
+        dev[4][0] = dev[4][1] = None                      # alpha = 0: A and B are not read
+        batch.contract([d[0] for d in dev], [d[1] for d in dev], [d[2] for d in dev], alphas, betas)
+        torch.cuda.synchronize()
+        for t, ((sp, ex, dt, cm), (A, B, C0), d, al, be) in enumerate(zip(cases, host, dev, alphas, betas)):
+            got = d[2].double().cpu().numpy()
+            ref = oracle.contract(sp, ex, A, B, C=np.array(C0, order="F"), alpha=al, beta=be)
+            if integer or al == 0.0 or cm == "native":
+                if integer or al == 0.0:
+                    np.testing.assert_array_equal(got, ref, err_msg=f"member {t} replay {rep}")
+                else:
+                    assert oracle.normwise_rel_err(got, ref) <= 1e-12
+                continue
+            absAB = oracle.contract(sp, ex, np.abs(A), np.abs(B))
+            if cm == "bf16x3":
+                sa_, sb_, sc_ = oracle.split_spec(sp)
+                K = int(np.prod([ex[ch] for ch in sa_ if ch not in sc_]))
+                ref_split = osplit.contract_split(sp, ex, A, B, C=np.array(C0, order="F"), alpha=al, beta=be)
+                assert np.all(np.abs(got - ref_split) <= abs(al) * split_bound(K) * absAB
+                              + 2.0 ** -50 * np.abs(ref_split)), (t, rep)
+                assert oracle.normwise_rel_err(got, ref) <= 1e-5, (t, rep)
+            else:                                         # FP8 terms: within 2^-9 |A||B|
+                assert np.all(np.abs(got - ref) <= abs(al) * 2.0 ** -9 * absAB + 2.0 ** -50 * np.abs(ref)), (t, rep)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_bf16x3_tiles_wide_range(dtype):
+    """Split-BF16 tiles on operands whose slices span many binades (FP64:
+    per-slice scales 2^-300 .. 2^300, far outside BF16's and FP32's range, so
+    only the per-row and per-column scaling keeps the terms representable;
+    FP32: 2^-60 .. 2^60), every tile shape and both operand layouts, several
+    K tiles and ragged edges: componentwise within the FP32-accumulation bound
+    of the oracle's exactly accumulated split result (and, for FP32 storage,
+    normwise at FP32 level)."""
+    import torch
+    from gpu_util import split_bound
+    from oracle import split as osplit
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    span = 300 if dtype == "f64" else 60
+    cases = [("ab=iaj,jbi", dict(a=130, b=70, i=7, j=9)),
+             ("abc=ija,jbic", dict(a=33, b=20, c=3, i=6, j=5)),
+             ("abc=ai,ibc", dict(a=150, b=17, c=4, i=37)),
+             ("abcd=ai,ibcd", dict(a=40, b=9, c=3, d=2, i=20)),
+             ("ba=ai,ib", dict(a=19, b=140, i=50))]
+    rng = np.random.default_rng(77)
+    plans, host, dev = [], [], []
+    for sp, ex in cases:
+        sa, sb, sc = oracle.split_spec(sp)
+        A = np.array(rng.uniform(-1, 1, [ex[c] for c in sa]), order="F")
+        B = np.array(rng.uniform(-1, 1, [ex[c] for c in sb]), order="F")
+        for X, lets in ((A, sa), (B, sb)):
+            shp = [X.shape[ax] if ch in sc else 1 for ax, ch in enumerate(lets)]
+            X *= np.exp2(rng.integers(-span, span + 1, shp).astype(np.float64))
+        if dtype == "f32":
+            A, B = A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
+        p = tc.Plan(sp, ex, dtype, compute="bf16x3")
+        plans.append(p)
+        host.append((A, B))
+        dev.append((tc.to_device_fortran(A, tdt), tc.to_device_fortran(B, tdt), tc.empty_fortran(p.shape("C"), tdt)))
+    batch = tc.Batch(plans)
+    for shape in range(3):
+        for t in range(len(cases)):
+            batch.set_choice(t, tc.TC_VARIANT_FUSED, shape)
+        for d in dev:
+            d[2].fill_(float("nan"))
+        batch.contract([d[0] for d in dev], [d[1] for d in dev], [d[2] for d in dev],
+                       [1.0] * len(cases), [0.0] * len(cases))
+        torch.cuda.synchronize()
+        for t, ((sp, ex), (A, B), d) in enumerate(zip(cases, host, dev)):
+            got = d[2].double().cpu().numpy()
+            sa, sb, sc = oracle.split_spec(sp)
+            K = int(np.prod([ex[c] for c in sa if c not in sc]))
+            ref_split = osplit.contract_split(sp, ex, A, B)
+            absAB = oracle.contract(sp, ex, np.abs(A), np.abs(B))
+            # FP32 storage rounds the result once more
+            tol = split_bound(K) * absAB + (2.0 ** -24 if dtype == "f32" else 2.0 ** -52) * np.abs(ref_split)
+            assert np.all(np.abs(got - ref_split) <= tol), (sp, shape)
+            if dtype == "f32":   # FP64 entries span 2^+-600: their squares overflow a norm
+                assert oracle.normwise_rel_err(got, oracle.contract(sp, ex, A, B)) <= 1e-5, (sp, shape)
