@@ -482,19 +482,25 @@ def precision(args, torch, tc, wl):
     rows = np.sort(rng.choice(4096, 24, replace=False))
     cols = np.sort(rng.choice(4096, 24, replace=False))
     ref = _einsum_ref(w["spec"], w["A"][:, rows, :], w["B"][:, cols, :])
+    absab = _einsum_ref(w["spec"], np.abs(w["A"][:, rows, :]), np.abs(w["B"][:, cols, :]))
     dA = tc.to_device_fortran(w["A"], torch.float64)
     dB = tc.to_device_fortran(w["B"], torch.float64)
     base_ms = None
     # FP64 plain, FP32 plain (FP32-rounded inputs, FP32 matrix cores), and the
-    # split-BF16 and split-FP8 forms on the FP64 inputs; errors against an
-    # FP64 einsum of the sampled slices
-    for name, dtype, compute, peak in (("fp64", "f64", "native", FP64_PEAK_TFS),
-                                       ("fp32", "f32", "native", FP32_PEAK_TFS),
-                                       ("bf16x3", "f64", "bf16x3", BF16_PEAK_TFS),
-                                       ("fp8x3", "f64", "fp8x3", FP8_PEAK_TFS)):
+    # split-BF16 (six term products; ablations with three and nine) and
+    # split-FP8 forms on the FP64 inputs; normwise and componentwise
+    # (max |C - ref| / (|A||B|)) errors against an FP64 einsum of the sampled
+    # slices
+    for name, dtype, compute, peak, nprod in (("fp64", "f64", "native", FP64_PEAK_TFS, 1),
+                                              ("fp32", "f32", "native", FP32_PEAK_TFS, 1),
+                                              ("bf16x3", "f64", "bf16x3", BF16_PEAK_TFS, 6),
+                                              ("bf16x3_p3", "f64", "bf16x3", BF16_PEAK_TFS, 3),
+                                              ("bf16x3_p9", "f64", "bf16x3", BF16_PEAK_TFS, 9),
+                                              ("fp8x3", "f64", "fp8x3", FP8_PEAK_TFS, 6)):
         tdt = torch.float64 if dtype == "f64" else torch.float32
         xA, xB = (dA, dB) if dtype == "f64" else (dA.to(tdt), dB.to(tdt))
-        plan = tc.Plan(w["spec"], w["ext"], dtype, compute=compute)
+        plan = tc.Plan(w["spec"], w["ext"], dtype, compute=compute,
+                       products=nprod if compute == "bf16x3" else None)
         plan.prepare()
         dC = tc.empty_fortran(plan.shape("C"), tdt)
         fn = lambda: plan.contract(xA, xB, dC)
@@ -502,13 +508,15 @@ def precision(args, torch, tc, wl):
         ms, _ = _events_time(fn, FORM_STEPS, FORM_WARMUP, torch)
         got = dC[torch.as_tensor(rows, device="cuda")][:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
         err = _normwise(got, ref)
+        cerr = float(np.max(np.abs(got - ref) / absab))
         tfs = fl / (ms * 1e-3) / 1e12
-        executed = fl * (6 if compute != "native" else 1)
+        executed = fl * nprod
         rec = dict(workload="C_ab = A_iaj B_jbi, a=b=4096, i=j=64, normal(0,1) x logU[1e-3,1e3] per slice",
                    ms=round(ms, 4), effective_gflops=round(tfs * 1e3, 1), normwise_err_sampled=err,
+                   componentwise_err_sampled=cerr, term_products=nprod if compute != "native" else None,
                    roofline=dict(bound="mfma", achieved=round(executed / (ms * 1e-3) / 1e12, 2), peak=peak,
                                  unit="TFLOP/s", frac=round(executed / (ms * 1e-3) / 1e12 / peak, 4),
-                                 counts="executed MFMA flops (6 products for the split forms)"))
+                                 counts="executed MFMA flops (one per term product for the split forms)"))
         if base_ms is None:
             base_ms = ms
         else:

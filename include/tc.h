@@ -224,6 +224,14 @@ tc_status tc_contract(tc_plan_t plan, const void* A, const void* B, void* C,
 tc_status tc_contract_complex(tc_plan_t plan, const void* A, const void* B, void* C,
                               double alpha_re, double alpha_im, double beta_re, double beta_im, void* stream);
 
+/* Term products kept by a TC_BF16X3 plan (the library's split-precision
+ * form; not in the paper): 6 (every t_A,p t_B,q with p + q <= 4, the default),
+ * or, as ablations, 3 (p + q <= 3: about 2^-16 of |A||B| dropped) or 9 (all).
+ * Host only; takes effect at the next tc_contract.  A batch takes only plans
+ * with 6.  Errors: TC_E_NULL, TC_E_UNSUPPORTED (not a TC_BF16X3 plan, or a
+ * count other than 3, 6, 9). */
+tc_status tc_set_split_products(tc_plan_t plan, int products);
+
 /* Copy the split terms of the last tc_contract of a TC_BF16X3 or TC_FP8X3
  * plan to host memory, for bit-exact checks of the quantisation (the
  * library's split-precision form; not in the paper).  side 0 = A,

@@ -29,7 +29,7 @@ EXPORTS = ("tc_plan", "tc_plan_destroy", "tc_variant_count", "tc_variant_get", "
            "tc_predict", "tc_batch_create", "tc_batch_tune", "tc_batch_contract", "tc_batch_destroy",
            "tc_batch_info", "tc_split_terms", "tc_status_str", "tc_last_error", "tc_set_root_gap",
            "tc_chain_root_gaps", "tc_contract_noalloc", "tc_batch_score", "tc_batch_choice",
-           "tc_batch_set_choice")
+           "tc_batch_set_choice", "tc_set_split_products")
 
 
 class TcError(RuntimeError):
@@ -112,6 +112,7 @@ def _load():
         "tc_batch_info": [P, ctypes.POINTER(ctypes.c_int), I64P, ctypes.POINTER(ctypes.c_int),
                           ctypes.POINTER(ctypes.c_double)],
         "tc_split_terms": [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_int32), I64P, I64P],
+        "tc_set_split_products": [P, ctypes.c_int],
         "tc_set_root_gap": [P, I64P],
         "tc_chain_root_gaps": [ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int), ctypes.c_int],
     }
@@ -407,7 +408,7 @@ class Plan:
     in spec order (missing -> Fortran order)."""
 
     def __init__(self, spec: str, extents: dict, dtype: str = "f64", strides: dict | None = None,
-                 compute: str = "native"):
+                 compute: str = "native", products: int | None = None):
         self.spec = spec
         self.extents = dict(extents)
         self.dtype = dtype
@@ -417,6 +418,8 @@ class Plan:
         self.handle = tc_plan(spec, self.extents, strides.get("A"), strides.get("B"), strides.get("C"),
                               DTYPES[dtype],
                               dict(native=TC_NATIVE, bf16x3=TC_BF16X3, fp8x3=TC_FP8X3)[compute])
+        if products is not None:         # split-BF16 term products: 6, or the ablations 3 and 9
+            _check(lib.tc_set_split_products(self.handle, int(products)))
 
     def _fortran(self, t):
         letters = self.letters["ABC".index(t)]

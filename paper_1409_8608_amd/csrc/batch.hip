@@ -467,6 +467,10 @@ tc_status tc_batch_create(tc_batch_t* out, const tc_plan_t* plans, int n) {
             delete b;
             return fail(TC_E_UNSUPPORTED, "batch members need a non-empty C and contracted extent");
         }
+        if (p->spec.compute == TC_BF16X3 && p->split_products != 6) {
+            delete b;
+            return fail(TC_E_UNSUPPORTED, "batch split-BF16 tiles keep six term products");
+        }
         b->plans.push_back(p);
         b->x3.push_back(p->spec.compute == TC_BF16X3);
         if (p->spec.compute == TC_FP8X3) {

@@ -10,7 +10,8 @@
 //    ready-made LDS images: for every 128-row tile and 32-wide K stage, one
 //    contiguous 24 KB block [term][row][four 16-byte chunks], the chunks of
 //    each row permuted by xswz so that fragment reads hit distinct banks.
-// 2. k_x3: C tile = sum over the six term products t_A,p t_B,q with p+q <= 4.
+// 2. k_x3: C tile = sum over the six term products t_A,p t_B,q with p+q <= 4
+//    (ablations: the three with p+q <= 3, or all nine).
 //    Stages are copied HBM -> LDS by the DMA form of the global load (no
 //    registers in between), double-buffered.  The leading product t_A1 t_B1
 //    and the five small products accumulate in two FP32 accumulators over all
@@ -390,9 +391,11 @@ constexpr int kWaitLgkm0 = 15 | (3 << 14) | (7 << 4);
 // three terms: two stage images of A, one of B, 72 KB) arrives in LDS by DMA
 // while the previous stage is multiplied; each wave copies six 1 KB pieces of
 // A and three of B per stage.  Work per stage and wave: 96 MFMAs against 24
-// fragment reads of 16 bytes per lane.
-template <typename T>
+// fragment reads of 16 bytes per lane.  NP: term products kept (6: p+q <= 4;
+// ablations 3: p+q <= 3, and 9: all).
+template <typename T, int NP = 6>
 __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
+    static_assert(NP == 3 || NP == 6 || NP == 9, "3, 6 or 9 term products");
     constexpr int NVA = 2 * XSTAGE / 16, NVB = XSTAGE / 16;   // uint4 per A / B stage
     constexpr int PA = 2 * XSTAGE / XPIECE / XWAVES;          // DMA pieces per wave: 6 of A
     constexpr int PB = XSTAGE / XPIECE / XWAVES;              // and 3 of B
@@ -491,6 +494,21 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
     // step and run out of registers).
     auto compute = [&](const uint4* sa, const uint4* sb) {
         bf8 b1[4], b2[4], b3[4], a1[4], a2[4], a3[4];
+        if constexpr (NP == 3) {
+            // t_A1 t_B1, then t_A1 t_B2 and t_A2 t_B1
+            load_b(sb, 0, b1);
+            load_a(sa, 0, a1);
+            load_b(sb, 1, b2);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(big, b1, a1);
+            __builtin_amdgcn_sched_barrier(0);
+            load_a(sa, 1, a2);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(small, b2, a1);
+            mma(small, b1, a2);
+            __builtin_amdgcn_sched_barrier(0);
+            return;
+        }
         load_b(sb, 0, b1);
         load_a(sa, 0, a1);
         load_b(sb, 2, b3);
@@ -510,6 +528,11 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
         mma(small, b2, a2);    // t_A2 t_B2
         __builtin_amdgcn_sched_barrier(0);
         mma(small, b1, a3);    // t_A3 t_B1
+        if constexpr (NP == 9) {
+            mma(small, b3, a2);    // t_A2 t_B3
+            mma(small, b2, a3);    // t_A3 t_B2
+            mma(small, b3, a3);    // t_A3 t_B3
+        }
         __builtin_amdgcn_sched_barrier(0);
     };
     // Stage kt sits in (sa, sb); stage kt + 1 goes into (na, nb), which every
@@ -905,6 +928,12 @@ static tc_status launch_split_form(tc_plan_s* p, const void* A, const void* B, v
     if (fp8) {
         if (f64) hipLaunchKernelGGL(k_x3_8<double>, xg, xb, 0, st, x);
         else hipLaunchKernelGGL(k_x3_8<float>, xg, xb, 0, st, x);
+    } else if (p->split_products == 3) {
+        if (f64) hipLaunchKernelGGL((k_x3<double, 3>), xg, xb, 0, st, x);
+        else hipLaunchKernelGGL((k_x3<float, 3>), xg, xb, 0, st, x);
+    } else if (p->split_products == 9) {
+        if (f64) hipLaunchKernelGGL((k_x3<double, 9>), xg, xb, 0, st, x);
+        else hipLaunchKernelGGL((k_x3<float, 9>), xg, xb, 0, st, x);
     } else {
         if (f64) hipLaunchKernelGGL(k_x3<double>, xg, xb, 0, st, x);
         else hipLaunchKernelGGL(k_x3<float>, xg, xb, 0, st, x);
@@ -914,6 +943,17 @@ static tc_status launch_split_form(tc_plan_s* p, const void* A, const void* B, v
 }
 
 }  // namespace tc
+
+extern "C" tc_status tc_set_split_products(tc_plan_t p, int products) {
+    using namespace tc;
+    if (!p) return fail(TC_E_NULL, "plan is NULL");
+    if (p->spec.compute != TC_BF16X3) return fail(TC_E_UNSUPPORTED, "term-product count applies to TC_BF16X3 plans");
+    if (products != 3 && products != 6 && products != 9)
+        return fail(TC_E_UNSUPPORTED, "term products: 3 (p+q <= 3), 6 (p+q <= 4) or 9 (all)");
+    p->split_products = products;
+    if (p->real) p->real->split_products = products;
+    return TC_OK;
+}
 
 extern "C" tc_status tc_split_terms(tc_plan_t p, int side, void* terms, int32_t* exps, int64_t* rows,
                                     int64_t* kp) {

@@ -64,6 +64,7 @@ struct tc_plan_s {
     std::vector<int64_t> h_ktab;
     int h_kvec = 0;
     // split-precision buffers (one allocation)
+    int split_products = 6;          // BF16 term products kept: 6 (p+q <= 4), or 3 / 9 (ablations)
     void* d_split = nullptr;
     int64_t split_bytes = 0;
     int64_t split_layout[16] = {0};

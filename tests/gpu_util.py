@@ -51,15 +51,15 @@ def check(spec, ext, A, B, got, dtype="f64", C0=None, alpha=1.0, beta=0.0, exact
     return err
 
 
-def split_bound(K: int) -> float:
+def split_bound(K: int, small: int = 5) -> float:
     """Componentwise bound, relative to (|A||B|)_c, between the device's
     split-BF16 result and the oracle's exactly accumulated split result.
     The leading product t_A1 t_B1 accumulates in FP32 over all K positions:
     (K + 8) u with u = 2^-24, each product rounded into the sum in the worst
-    case.  The five small products (together at most 2^-7 of the leading one
-    per position) accumulate in a second FP32 sum: 5 K u 2^-7.  2^-22 covers
-    the FP64 combine and the unscaling."""
-    return (K + 8) * 2.0 ** -24 + 5 * K * 2.0 ** -31 + 2.0 ** -22
+    case.  The `small` other products (five by default; each at most about
+    2^-7 of the leading one per position) accumulate in a second FP32 sum:
+    small K u 2^-7.  2^-22 covers the FP64 combine and the unscaling."""
+    return (K + 8) * 2.0 ** -24 + small * K * 2.0 ** -31 + 2.0 ** -22
 
 
 def split_bound_fp8(K: int) -> float:

@@ -73,6 +73,53 @@ def test_split_terms_bit_exact_and_result(spec, ext):
             np.testing.assert_array_equal(d, o)
 
 
+@pytest.mark.parametrize("products", [3, 9])
+@pytest.mark.parametrize("spec,ext", [
+    ("ab=iaj,jbi", dict(a=300, b=140, i=24, j=17)),
+    ("abc=ija,jbic", dict(a=40, b=33, c=7, i=5, j=11)),
+])
+def test_split_product_ablations(spec, ext, products):
+    """The ablations of the split-BF16 form: three term products (p + q <= 3)
+    and all nine.  Componentwise within the FP32-accumulation bound of the
+    oracle's exactly accumulated split result with the same products; the
+    three-product form is BF16x2 level (about 2^-16 |A||B|), the nine-product
+    form at least as accurate as the six-product one.  Batches refuse them."""
+    rng = np.random.default_rng(19)
+    sa, sb, sc = oracle.split_spec(spec)
+    A = np.array(rng.standard_normal([ext[c] for c in sa]), order="F")
+    B = np.array(rng.standard_normal([ext[c] for c in sb]), order="F")
+    fa = [ax for ax, ch in enumerate(sa) if ch in sc]
+    A *= np.exp(rng.uniform(np.log(1e-3), np.log(1e3), [A.shape[ax] if ax in fa else 1 for ax in range(A.ndim)]))
+    pairs = [(p, q) for p in (1, 2, 3) for q in (1, 2, 3) if products == 9 or p + q <= 3]
+    p = tc.Plan(spec, ext, "f64", compute="bf16x3", products=products)
+    got = run(p, A, B)
+    ref_split = sp.contract_split(spec, ext, A, B, pairs=pairs)
+    ref = oracle.contract(spec, ext, A, B)
+    absAB = oracle.contract(spec, ext, np.abs(A), np.abs(B))
+    K = int(np.prod([ext[c] for c in sa if c not in sc]))
+    assert np.all(np.abs(got - ref_split) <= split_bound(K, small=len(pairs) - 1) * absAB)
+    err = np.max(np.abs(got - ref) / absAB)
+    if products == 3:
+        assert 2.0 ** -22 < err <= 2.0 ** -14
+    else:
+        p6 = tc.Plan(spec, ext, "f64", compute="bf16x3")
+        err6 = np.max(np.abs(run(p6, A, B) - ref) / absAB)
+        assert err <= err6 * 1.05 + 2.0 ** -40
+        assert oracle.normwise_rel_err(got, ref) <= 1e-5
+    with pytest.raises(tc.TcError) as e:
+        tc.Batch([p])
+    assert e.value.name == "TC_E_UNSUPPORTED"
+
+
+def test_split_products_errors():
+    with pytest.raises(tc.TcError) as e:
+        tc.Plan("ab=ai,ib", dict(a=8, b=8, i=8), "f64", compute="bf16x3", products=4)
+    assert e.value.name == "TC_E_UNSUPPORTED"
+    with pytest.raises(tc.TcError) as e:
+        tc.Plan("ab=ai,ib", dict(a=8, b=8, i=8), "f64", compute="fp8x3", products=3)
+    assert e.value.name == "TC_E_UNSUPPORTED"
+
+
 @pytest.mark.parametrize("K", [6000, 9000])
 def test_split_long_contraction(K):
     """Long contracted extents: 4096 < K <= 8192 keeps each slice in

@@ -88,6 +88,33 @@ def test_split_contraction_error_bound():
     assert np.max(np.abs(got1 - ref) / absAB) > 1e-4
 
 
+def test_split_product_ablations():
+    """The term-product ablations of the split form.  With all nine products
+    the split of FP32-representable operands is exact (three 8-bit terms hold
+    24 bits), so the result is the plain contraction up to FP64 rounding.
+    Keeping only p + q <= 3 drops t1 t3, t3 t1 and t2 t2, each at most about
+    2^-16 of |a||b| (|t2| <= 2^-8 |x|, |t3| <= 2^-16 |x| after rounding to
+    nearest), so the error is below 2^-14 |A||B|, and for random data far
+    above the six-product error."""
+    rng = np.random.default_rng(12)
+    spec, ext = "ab=iaj,jbi", dict(a=18, b=21, i=5, j=9)
+    A = np.array(rng.standard_normal((5, 18, 9)) * np.exp(rng.uniform(-6, 6, (1, 18, 1))), order="F")
+    B = np.array(rng.standard_normal((9, 21, 5)) * np.exp(rng.uniform(-6, 6, (1, 21, 1))), order="F")
+    A32, B32 = (x.astype(np.float32).astype(np.float64) for x in (A, B))
+    all9 = [(p, q) for p in (1, 2, 3) for q in (1, 2, 3)]
+    p3 = [(p, q) for p in (1, 2) for q in (1, 2) if p + q <= 3]
+    assert sorted(p3) == [(1, 1), (1, 2), (2, 1)] and len(sp.PAIRS) == 6
+    ref32 = oracle.contract(spec, ext, A32, B32)
+    abs32 = oracle.contract(spec, ext, np.abs(A32), np.abs(B32))
+    got9 = sp.contract_split(spec, ext, A32, B32, pairs=all9)
+    assert np.all(np.abs(got9 - ref32) <= 2.0 ** -50 * abs32)
+    ref = oracle.contract(spec, ext, A, B)
+    absAB = oracle.contract(spec, ext, np.abs(A), np.abs(B))
+    e3 = np.max(np.abs(sp.contract_split(spec, ext, A, B, pairs=p3) - ref) / absAB)
+    e6 = np.max(np.abs(sp.contract_split(spec, ext, A, B) - ref) / absAB)
+    assert e3 <= 2.0 ** -14 and e3 > 2.0 ** -20 and e6 < 2.0 ** -22
+
+
 def test_split_integer_exact():
     """Small integers are exact in one BF16 (or E4M3) term: the split form
     equals the plain contraction bit for bit."""
