@@ -1,9 +1,10 @@
 // Split-precision contraction on BF16 matrix cores (gfx950
 // v_mfma_f32_16x16x32_bf16).
 //
-// 1. k_split: one block per slice (one row m of A's GEMM view, or one column n
-//    of B's), reading the slice once.  FP64 absmax over the slice -> exponent
-//    e = floor(log2(max)); the
+// 1. k_split2 (both operands in one launch; k_split_long past 8192
+//    positions): one block per slice (one row m of A's GEMM view, or one
+//    column n of B's), reading the slice once.  FP64 absmax over the slice ->
+//    exponent e = floor(log2(max)); the
 //    scaled values x = v * 2^-e (exact) are split into three BF16 terms by
 //    round-to-nearest-even, t1 = rn(x), t2 = rn(x - t1), t3 = rn(x - t1 - t2),
 //    in the K order of the plan's offset table.  The terms are written as
@@ -117,90 +118,8 @@ __device__ __forceinline__ uint32_t pack2(double lo, double hi) {
     return (uint32_t)bf16_bits(lo) | ((uint32_t)bf16_bits(hi) << 16);
 }
 
-// One block per slice.  Thread t owns the chunks t, t + 256, ... of eight
-// consecutive K positions (CPT of them): it loads their values once, keeps
-// them in registers through the block-wide max, then writes each chunk's three
-// terms as one 16-byte store per term.
-template <typename T, int CPT, bool VEC>
-__global__ __launch_bounds__(256) void k_split(SplitArgs a) {
-    __shared__ double red[4];
-    if (a.bp && a.bp->alpha == 0.0) return;   // a batch member with alpha = 0 reads neither input
-    const T* X = (const T*)(a.bp ? (a.slot == 0 ? a.bp->A : a.bp->B) : a.X);
-    // neighbouring slices on one XCD: their stage-image rows share cache
-    // lines, which then fill in one L2
-    const int64_t row = xcd_item(blockIdx.x, a.nrows);
-    const int tid = threadIdx.x;
-    const int64_t base = grp_off(a.rows, row, a.slot);
-    const int64_t nch = a.Kt / 8;
-    double v[CPT][8];
-    double amax = 0.0;
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int64_t ch = tid + 256 * c;
-        const bool in = ch < nch;
-        const int64_t* ko = a.koff + 8 * (in ? ch : 0);
-        if (VEC) {
-            // the host checked: every chunk is eight consecutive, 16-byte
-            // aligned elements (or eight padding entries)
-            typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
-            constexpr int W = 16 / sizeof(T);
-            const int64_t o = ko[0];
-            const bool ok = in && o >= 0;
-            const v16* p = (const v16*)(X + base + (ok ? o : 0));
-#pragma unroll
-            for (int q = 0; q < 8 / W; ++q) {
-                const v16 t = p[q];
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    v[c][q * W + w] = ok ? (double)t[w] : 0.0;
-                    amax = fmax(amax, fabs(v[c][q * W + w]));
-                }
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int64_t o = ko[e];
-                const bool ok = in && o >= 0;
-                const double x = (double)X[base + (ok ? o : 0)];
-                v[c][e] = ok ? x : 0.0;
-                amax = fmax(amax, fabs(v[c][e]));
-            }
-        }
-    }
-    for (int s = 32; s > 0; s >>= 1) amax = fmax(amax, __shfl_xor(amax, s));
-    if ((tid & 63) == 0) red[tid >> 6] = amax;
-    __syncthreads();
-    amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    int e = 0;
-    if (amax > 0.0) {
-        int E;
-        frexp(amax, &E);
-        e = E - 1;
-    }
-    if (tid == 0) a.exps[row] = e;
-    constexpr int64_t TS = XR * SPLIT_BK;   // elements between the terms of one stage image
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int64_t ch = tid + 256 * c;
-        if (ch >= nch) break;
-        double t1[8], t2[8], t3[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const double x = ldexp(v[c][q], -e);
-            t1[q] = rn_bf16(x);
-            const double rest = x - t1[q];
-            t2[q] = rn_bf16(rest);
-            t3[q] = rn_bf16(rest - t2[q]);
-        }
-        uint4* out = (uint4*)(a.panels + panel_off(row, 8 * ch, 0, a.Kp));
-        out[0] = make_uint4(pack2(t1[0], t1[1]), pack2(t1[2], t1[3]), pack2(t1[4], t1[5]), pack2(t1[6], t1[7]));
-        out[TS / 8] = make_uint4(pack2(t2[0], t2[1]), pack2(t2[2], t2[3]), pack2(t2[4], t2[5]), pack2(t2[6], t2[7]));
-        out[2 * TS / 8] =
-            make_uint4(pack2(t3[0], t3[1]), pack2(t3[2], t3[3]), pack2(t3[4], t3[5]), pack2(t3[6], t3[7]));
-    }
-}
-
-// Any K: two passes over the slice, the second re-reading it (from cache).
+// BF16 terms for any K: two passes over the slice, the second re-reading it
+// (from cache); one block per slice.
 template <typename T>
 __global__ __launch_bounds__(256) void k_split_long(SplitArgs a) {
     __shared__ double red[4];
@@ -238,6 +157,168 @@ __global__ __launch_bounds__(256) void k_split_long(SplitArgs a) {
         t[0] = bf16_bits(r1);
         t[TS] = bf16_bits(r2);
         t[2 * TS] = bf16_bits(r3);
+    }
+}
+
+// Both operands' split in one launch (up to 8192 positions per slice): blocks
+// 0 .. nrows(A) - 1 take A's slices, the rest B's (one slice per block, the
+// slices handed to XCDs in contiguous ranges: neighbouring slices share
+// stage-image cache lines, which then fill in one L2).  A side reads its
+// slice in one of three ways:
+//   mode 0: every chunk of eight positions is eight consecutive aligned
+//     elements; consecutive threads load consecutive 16-byte pieces (two FP64
+//     or four FP32 positions), so a wave's load covers whole chunks, and each
+//     thread stores its piece's terms (4 or 8 bytes per term);
+//   mode 1: within a chunk the valid positions are a prefix, at offsets o0 +
+//     e * cstride (one table entry per chunk: o0 * 16 + count); a thread takes
+//     a chunk, without a table entry per position;
+//   mode 2: one table entry per position.
+struct SplitSide {
+    const void* X;
+    GtDims rows;
+    int slot;
+    int mode;
+    const int64_t* koff;
+    const int64_t* cinfo;   // mode 1: per chunk o0 * 16 + count
+    int64_t cstride;        // mode 1: element stride between a chunk's positions
+    int64_t nrows;
+    uint16_t* panels;
+    int32_t* exps;
+};
+
+struct Split2Args {
+    SplitSide s[2];
+    const BatchPtrs* bp;
+    int64_t Kp, Kt;
+};
+
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_split2(Split2Args a) {
+    __shared__ double red[4];
+    if (a.bp && a.bp->alpha == 0.0) return;   // a batch member with alpha = 0 reads neither input
+    const int64_t nA = a.s[0].nrows;
+    const int64_t item = xcd_item(blockIdx.x, nA + a.s[1].nrows);
+    const int side = item < nA ? 0 : 1;
+    const SplitSide& S = a.s[side];
+    const int64_t row = side == 0 ? item : item - nA;
+    const T* X = (const T*)(a.bp ? (S.slot == 0 ? a.bp->A : a.bp->B) : S.X);
+    const int tid = threadIdx.x;
+    const int64_t base = grp_off(S.rows, row, S.slot);
+    const int64_t nch = a.Kt / 8;
+    constexpr int W = 16 / (int)sizeof(T), P = 8 / W;   // elements per 16-byte piece, pieces per chunk
+    typedef T vW __attribute__((ext_vector_type(W)));
+    double v[CPT * 8];
+    double amax = 0.0;
+    const int mode = S.mode;
+    if (mode == 0) {
+#pragma unroll
+        for (int q = 0; q < CPT * P; ++q) {
+            const int64_t pc = tid + 256 * q, ch = pc / P;
+            const bool in = ch < nch;
+            const int64_t o = S.koff[8 * (in ? ch : 0)];
+            const bool ok = in && o >= 0;
+            const vW t = *(const vW*)(X + base + (ok ? o + W * (pc % P) : 0));
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                v[q * W + w] = ok ? (double)t[w] : 0.0;
+                amax = fmax(amax, fabs(v[q * W + w]));
+            }
+        }
+    } else if (mode == 1) {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int64_t ch = tid + 256 * c;
+            const int64_t info = ch < nch ? S.cinfo[ch] : 0;
+            const int64_t o0 = info >> 4;
+            const int cnt = (int)(info & 15);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const bool ok = e < cnt;
+                const double x = (double)X[base + (ok ? o0 + e * S.cstride : 0)];
+                v[c * 8 + e] = ok ? x : 0.0;
+                amax = fmax(amax, fabs(v[c * 8 + e]));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int64_t ch = tid + 256 * c;
+            const bool in = ch < nch;
+            const int64_t* ko = S.koff + 8 * (in ? ch : 0);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t o = ko[e];
+                const bool ok = in && o >= 0;
+                const double x = (double)X[base + (ok ? o : 0)];
+                v[c * 8 + e] = ok ? x : 0.0;
+                amax = fmax(amax, fabs(v[c * 8 + e]));
+            }
+        }
+    }
+    for (int s = 32; s > 0; s >>= 1) amax = fmax(amax, __shfl_xor(amax, s));
+    if ((tid & 63) == 0) red[tid >> 6] = amax;
+    __syncthreads();
+    amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    int e = 0;
+    if (amax > 0.0) {
+        int E;
+        frexp(amax, &E);
+        e = E - 1;
+    }
+    if (tid == 0) S.exps[row] = e;
+    constexpr int64_t TS = XR * SPLIT_BK;   // elements between the terms of one stage image
+    if (mode == 0) {
+#pragma unroll
+        for (int q = 0; q < CPT * P; ++q) {
+            const int64_t pc = tid + 256 * q, ch = pc / P;
+            if (ch >= nch) break;
+            uint32_t w1[W / 2], w2[W / 2], w3[W / 2];
+#pragma unroll
+            for (int h = 0; h < W / 2; ++h) {
+                double t1[2], t2[2], t3[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const double x = ldexp(v[q * W + 2 * h + u], -e);
+                    t1[u] = rn_bf16(x);
+                    const double rest = x - t1[u];
+                    t2[u] = rn_bf16(rest);
+                    t3[u] = rn_bf16(rest - t2[u]);
+                }
+                w1[h] = pack2(t1[0], t1[1]);
+                w2[h] = pack2(t2[0], t2[1]);
+                w3[h] = pack2(t3[0], t3[1]);
+            }
+            uint16_t* out = S.panels + panel_off(row, 8 * ch + W * (pc % P), 0, a.Kp);
+            if constexpr (W == 2) {
+                *(uint32_t*)out = w1[0];
+                *(uint32_t*)(out + TS) = w2[0];
+                *(uint32_t*)(out + 2 * TS) = w3[0];
+            } else {
+                *(uint2*)out = make_uint2(w1[0], w1[1]);
+                *(uint2*)(out + TS) = make_uint2(w2[0], w2[1]);
+                *(uint2*)(out + 2 * TS) = make_uint2(w3[0], w3[1]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int64_t ch = tid + 256 * c;
+            if (ch >= nch) break;
+            double t1[8], t2[8], t3[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double x = ldexp(v[c * 8 + q], -e);
+                t1[q] = rn_bf16(x);
+                const double rest = x - t1[q];
+                t2[q] = rn_bf16(rest);
+                t3[q] = rn_bf16(rest - t2[q]);
+            }
+            uint4* out = (uint4*)(S.panels + panel_off(row, 8 * ch, 0, a.Kp));
+            out[0] = make_uint4(pack2(t1[0], t1[1]), pack2(t1[2], t1[3]), pack2(t1[4], t1[5]), pack2(t1[6], t1[7]));
+            out[TS / 8] = make_uint4(pack2(t2[0], t2[1]), pack2(t2[2], t2[3]), pack2(t2[4], t2[5]), pack2(t2[6], t2[7]));
+            out[2 * TS / 8] =
+                make_uint4(pack2(t3[0], t3[1]), pack2(t3[2], t3[3]), pack2(t3[4], t3[5]), pack2(t3[6], t3[7]));
+        }
     }
 }
 
@@ -747,7 +828,9 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3_8(X3Args a) {
 // ---------------------------------------------------------------------------
 // Workspace layout inside p->d_split: K offsets of A | of B | terms A | terms B |
 // exps A | exps B
-enum { L_KOA = 0, L_KOB, L_TA, L_TB, L_EA, L_EB, L_KP, L_RA, L_RB, L_KT, L_VA, L_VB };
+// | chunk tables of A | of B (affine chunks, BF16 form)
+enum { L_KOA = 0, L_KOB, L_TA, L_TB, L_EA, L_EB, L_KP, L_RA, L_RB, L_KT, L_VA, L_VB,
+       L_CIA, L_CIB, L_CSA, L_CSB, L_AFA, L_AFB };
 
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -780,6 +863,8 @@ tc_status prepare_split(tc_plan_s* p) {
     L[L_TB] = off;   off += round_up(3 * RB * Kp * tb, 256);
     L[L_EA] = off;   off += round_up(RA * 4, 256);
     L[L_EB] = off;   off += round_up(RB * 4, 256);
+    L[L_CIA] = off;  off += round_up(std::max<int64_t>(1, Kt / 8) * 8, 256);
+    L[L_CIB] = off;  off += round_up(std::max<int64_t>(1, Kt / 8) * 8, 256);
     L[L_KP] = Kp; L[L_RA] = RA; L[L_RB] = RB; L[L_KT] = Kt;
     // Chunk-vector reads for a side: every chunk of eight positions is eight
     // consecutive elements (or eight padding entries), starting at an element
@@ -800,6 +885,28 @@ tc_status prepare_split(tc_plan_s* p) {
         for (const GtDim& d : g) vec = vec && (side == 0 ? d.sA : d.sB) % W == 0;
         L[side == 0 ? L_VA : L_VB] = vec ? 1 : 0;
     }
+    // Affine chunks: in every chunk of eight positions the valid entries are a
+    // prefix at offsets o0 + e * s, with one s for the whole side.
+    std::vector<int64_t> cinfo[2];
+    for (int side = 0; side < 2; ++side) {
+        bool aff = Kt > 0 && !fp8;
+        int64_t stride = 0;
+        cinfo[side].assign((size_t)std::max<int64_t>(1, Kt / 8), 0);
+        for (int64_t c = 0; aff && c < Kt / 8; ++c) {
+            const int64_t* k = ko[side].data() + 8 * c;
+            int cnt = 0;
+            while (cnt < 8 && k[cnt] >= 0) ++cnt;
+            for (int e = cnt; aff && e < 8; ++e) aff = k[e] < 0;
+            if (cnt >= 2) {
+                if (stride == 0) stride = k[1] - k[0];
+                for (int e = 1; aff && e < cnt; ++e) aff = k[e] == k[0] + e * stride;
+            }
+            aff = aff && (cnt == 0 || (k[0] >= 0 && k[0] < (INT64_C(1) << 58)));
+            cinfo[side][c] = cnt == 0 ? 0 : k[0] * 16 + cnt;
+        }
+        L[side == 0 ? L_AFA : L_AFB] = aff ? 1 : 0;
+        L[side == 0 ? L_CSA : L_CSB] = stride;
+    }
     hipError_t e = hipMalloc(&p->d_split, (size_t)std::max<int64_t>(off, 256));
     if (e != hipSuccess) {
         p->d_split = nullptr;
@@ -811,26 +918,17 @@ tc_status prepare_split(tc_plan_s* p) {
     for (int side = 0; side < 2 && e == hipSuccess && Kp > 0; ++side)
         e = hipMemcpy((char*)p->d_split + L[side == 0 ? L_KOA : L_KOB], ko[side].data(), (size_t)(Kp * 8),
                       hipMemcpyHostToDevice);
+    for (int side = 0; side < 2 && e == hipSuccess && Kt > 0; ++side)
+        e = hipMemcpy((char*)p->d_split + L[side == 0 ? L_CIA : L_CIB], cinfo[side].data(),
+                      cinfo[side].size() * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "split workspace set-up");
     return TC_OK;
 }
 
+// BF16 terms of slices longer than k_split2 takes (more than 8192 positions).
 template <typename T>
-static void launch_split(const SplitArgs& s, int64_t nch, bool vec, dim3 grid, dim3 blk, hipStream_t st) {
-    if (nch > 1024) {
-        hipLaunchKernelGGL(k_split_long<T>, grid, blk, 0, st, s);
-        return;
-    }
-    const int cpt = nch <= 256 ? 1 : nch <= 512 ? 2 : 4;
-    if (vec) {
-        if (cpt == 1) hipLaunchKernelGGL((k_split<T, 1, true>), grid, blk, 0, st, s);
-        else if (cpt == 2) hipLaunchKernelGGL((k_split<T, 2, true>), grid, blk, 0, st, s);
-        else hipLaunchKernelGGL((k_split<T, 4, true>), grid, blk, 0, st, s);
-    } else {
-        if (cpt == 1) hipLaunchKernelGGL((k_split<T, 1, false>), grid, blk, 0, st, s);
-        else if (cpt == 2) hipLaunchKernelGGL((k_split<T, 2, false>), grid, blk, 0, st, s);
-        else hipLaunchKernelGGL((k_split<T, 4, false>), grid, blk, 0, st, s);
-    }
+static void launch_split_long(const SplitArgs& s, dim3 grid, dim3 blk, hipStream_t st) {
+    hipLaunchKernelGGL(k_split_long<T>, grid, blk, 0, st, s);
 }
 
 // FP8 terms for up to 8192 contracted positions (k_split8 keeps a slice in
@@ -880,7 +978,49 @@ static tc_status launch_split_form(tc_plan_s* p, const void* A, const void* B, v
     int32_t* eA = (int32_t*)(w + L[L_EA]);
     int32_t* eB = (int32_t*)(w + L[L_EB]);
     hipError_t e;
+    if (!fp8 && L[L_KT] > 0 && L[L_KT] / 8 <= 1024) {
+        // both sides in one launch
+        Split2Args s2{};
+        s2.bp = bp;
+        s2.Kp = Kp;
+        s2.Kt = L[L_KT];
+        for (int side = 0; side < 2; ++side) {
+            SplitSide& S = s2.s[side];
+            S.X = side == 0 ? A : B;
+            const std::vector<GtDim>& g = side == 0 ? gv.m : gv.n;
+            S.rows.n = (int)g.size();
+            for (int d = 0; d < S.rows.n; ++d) S.rows.d[d] = g[d];
+            S.slot = side;
+            S.koff = (const int64_t*)(w + L[side == 0 ? L_KOA : L_KOB]);
+            S.cinfo = (const int64_t*)(w + L[side == 0 ? L_CIA : L_CIB]);
+            S.cstride = L[side == 0 ? L_CSA : L_CSB];
+            S.nrows = std::max<int64_t>(0, side == 0 ? gv.M : gv.N);
+            S.panels = side == 0 ? tA : tB;
+            S.exps = side == 0 ? eA : eB;
+            const bool vec = !bp && L[side == 0 ? L_VA : L_VB] != 0 && ((uintptr_t)S.X) % 16 == 0;
+            S.mode = vec ? 0 : L[side == 0 ? L_AFA : L_AFB] ? 1 : 2;
+        }
+        const int64_t blocks = s2.s[0].nrows + s2.s[1].nrows;
+        if (blocks > 0x7fffffff) return fail(TC_E_EXTENT, "too many slices for one launch");
+        if (blocks > 0) {
+            const int64_t nch = s2.Kt / 8;
+            const int cpt = nch <= 256 ? 1 : nch <= 512 ? 2 : 4;
+            const dim3 grid((unsigned)blocks), blk(256);
+            if (f64) {
+                if (cpt == 1) hipLaunchKernelGGL((k_split2<double, 1>), grid, blk, 0, st, s2);
+                else if (cpt == 2) hipLaunchKernelGGL((k_split2<double, 2>), grid, blk, 0, st, s2);
+                else hipLaunchKernelGGL((k_split2<double, 4>), grid, blk, 0, st, s2);
+            } else {
+                if (cpt == 1) hipLaunchKernelGGL((k_split2<float, 1>), grid, blk, 0, st, s2);
+                else if (cpt == 2) hipLaunchKernelGGL((k_split2<float, 2>), grid, blk, 0, st, s2);
+                else hipLaunchKernelGGL((k_split2<float, 4>), grid, blk, 0, st, s2);
+            }
+            e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail(e, "split kernel launch");
+        }
+    }
     for (int side = 0; side < 2; ++side) {
+        if (!fp8 && L[L_KT] > 0 && L[L_KT] / 8 <= 1024) break;   // done above
         SplitArgs s{};
         s.X = side == 0 ? A : B;
         s.bp = bp;
@@ -903,9 +1043,8 @@ static tc_status launch_split_form(tc_plan_s* p, const void* A, const void* B, v
             if (f64) launch_split8<double>(s, nch, vec, grid, blk, st);
             else launch_split8<float>(s, nch, vec, grid, blk, st);
         } else {
-            const int64_t nch = s.Kt / 8;    // chunks of eight positions
-            if (f64) launch_split<double>(s, nch, vec, grid, blk, st);
-            else launch_split<float>(s, nch, vec, grid, blk, st);
+            if (f64) launch_split_long<double>(s, grid, blk, st);
+            else launch_split_long<float>(s, grid, blk, st);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "split kernel launch");

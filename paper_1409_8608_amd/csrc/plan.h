@@ -67,7 +67,7 @@ struct tc_plan_s {
     int split_products = 6;          // BF16 term products kept: 6 (p+q <= 4), or 3 / 9 (ablations)
     void* d_split = nullptr;
     int64_t split_bytes = 0;
-    int64_t split_layout[16] = {0};
+    int64_t split_layout[24] = {0};
 
 private:
     std::vector<tc::Variant> fam_;
