@@ -13,11 +13,13 @@ namespace tc {
 
 // SPLIT: the launch may split K (the split path costs registers, so launches
 // that never split use the kernel without it).
-template <typename T, int BM, int BN, int BK, int AMODE, int BMODE, bool SPLIT>
-__global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
+// NW: waves per block (4, or 8 = two per SIMD).
+template <typename T, int BM, int BN, int BK, int AMODE, int BMODE, bool SPLIT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_mfma(MfmaArgs a) {
     const int64_t S = SPLIT && a.kslices > 1 ? a.kslices : 1;
     const int64_t t = xcd_tile(blockIdx.x, a.ntiles * S);
-    mfma_tile<T, BM, BN, BK, AMODE, BMODE, SPLIT>(a, a.A, a.B, a.C, a.alpha, a.beta, t % a.ntiles, t / a.ntiles);
+    mfma_tile<T, BM, BN, BK, AMODE, BMODE, SPLIT, true, false, NW>(a, a.A, a.B, a.C, a.alpha, a.beta, t % a.ntiles,
+                                                                   t / a.ntiles);
 }
 
 // Split-K reduction: output (m, n) is the sum of its slices' partials, in
@@ -99,29 +101,36 @@ static int load_mode(const MfmaArgs& a, bool f64, int slot) {
 
 // Chunk loads need a whole number of 16-byte chunks per thread; a tile side
 // too small for that stages element by element.
-template <typename T, int ROWS>
+template <typename T, int ROWS, int NT>
 constexpr int fit_mode(int m) {
-    return (m == LD_KVEC && (ROWS * kBK / 256) % (16 / (int)sizeof(T)) != 0) ? LD_KSCAL : m;
+    return (m == LD_KVEC && (ROWS * kBK / NT) % (16 / (int)sizeof(T)) != 0) ? LD_KSCAL : m;
 }
 
-template <typename T, int BM, int BN, bool SPLIT = false>
+// Waves per block of the one-shot 128 x 128 launches: eight, two per SIMD, so
+// that one wave's MFMAs run while the other waits at a step barrier or issues
+// its loads (with four, one wave per SIMD, the matrix pipe idled whenever the
+// wave did anything else).
+constexpr int kNW = 8;
+
+template <typename T, int BM, int BN, bool SPLIT = false, int NW = 4>
 static hipError_t tile_dispatch(const MfmaArgs& a, int am, int bm, hipStream_t st) {
     const int64_t S = SPLIT && a.kslices > 1 ? a.kslices : 1;
     if (a.ntiles <= 0) return hipSuccess;
     if (a.ntiles * S > 0x7fffffff) return hipErrorInvalidConfiguration;
-    dim3 g((unsigned)(a.ntiles * S)), b(256);
-    constexpr int A0 = fit_mode<T, BM>(0), A1 = fit_mode<T, BM>(1), A2 = fit_mode<T, BM>(2);
-    constexpr int B0 = fit_mode<T, BN>(0), B1 = fit_mode<T, BN>(1), B2 = fit_mode<T, BN>(2);
+    dim3 g((unsigned)(a.ntiles * S)), b(64 * NW);
+    constexpr int NT = 64 * NW;
+    constexpr int A0 = fit_mode<T, BM, NT>(0), A1 = fit_mode<T, BM, NT>(1), A2 = fit_mode<T, BM, NT>(2);
+    constexpr int B0 = fit_mode<T, BN, NT>(0), B1 = fit_mode<T, BN, NT>(1), B2 = fit_mode<T, BN, NT>(2);
     switch (am * 3 + bm) {
-        case 0: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B0, SPLIT>), g, b, 0, st, a); break;
-        case 1: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B1, SPLIT>), g, b, 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B2, SPLIT>), g, b, 0, st, a); break;
-        case 3: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B0, SPLIT>), g, b, 0, st, a); break;
-        case 4: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B1, SPLIT>), g, b, 0, st, a); break;
-        case 5: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B2, SPLIT>), g, b, 0, st, a); break;
-        case 6: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B0, SPLIT>), g, b, 0, st, a); break;
-        case 7: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B1, SPLIT>), g, b, 0, st, a); break;
-        default: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B2, SPLIT>), g, b, 0, st, a); break;
+        case 0: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B0, SPLIT, NW>), g, b, 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B1, SPLIT, NW>), g, b, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A0, B2, SPLIT, NW>), g, b, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B0, SPLIT, NW>), g, b, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B1, SPLIT, NW>), g, b, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A1, B2, SPLIT, NW>), g, b, 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B0, SPLIT, NW>), g, b, 0, st, a); break;
+        case 7: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B1, SPLIT, NW>), g, b, 0, st, a); break;
+        default: hipLaunchKernelGGL((k_mfma<T, BM, BN, kBK, A2, B2, SPLIT, NW>), g, b, 0, st, a); break;
     }
     return hipGetLastError();
 }
@@ -129,9 +138,10 @@ static hipError_t tile_dispatch(const MfmaArgs& a, int am, int bm, hipStream_t s
 hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st) {
     int am = load_mode(a, f64, 0), bm = load_mode(a, f64, 1);
     if (a.kslices <= 1)
-        return f64 ? tile_dispatch<double, kBM, kBN>(a, am, bm, st) : tile_dispatch<float, kBM, kBN>(a, am, bm, st);
-    hipError_t e = f64 ? tile_dispatch<double, kBM, kBN, true>(a, am, bm, st)
-                       : tile_dispatch<float, kBM, kBN, true>(a, am, bm, st);
+        return f64 ? tile_dispatch<double, kBM, kBN, false, kNW>(a, am, bm, st)
+                   : tile_dispatch<float, kBM, kBN, false, kNW>(a, am, bm, st);
+    hipError_t e = f64 ? tile_dispatch<double, kBM, kBN, true, kNW>(a, am, bm, st)
+                       : tile_dispatch<float, kBM, kBN, true, kNW>(a, am, bm, st);
     if (e != hipSuccess || a.ntiles <= 0) return e;
     if (a.nbatch != 1 || a.npass != 1 || a.mode != 0 || !a.ws) return hipErrorInvalidValue;
     const int64_t total = a.M * a.N;
@@ -232,10 +242,12 @@ int mfma_batch_occupancy(bool f64, int shape, bool ak, bool bk) {
 }
 
 // One-shot launch with a chosen tile shape (used to time tuning candidates).
+// Four waves per block, as the persistent batch kernel.
 hipError_t launch_mfma_shape(bool f64, int shape, MfmaArgs& a, hipStream_t st) {
-    if (shape == 0) return launch_mfma(f64, a, st);
     mfma_tiles_shape(shape, a);
     int am = load_mode(a, f64, 0), bm = load_mode(a, f64, 1);
+    if (shape == 0)
+        return f64 ? tile_dispatch<double, 128, 128>(a, am, bm, st) : tile_dispatch<float, 128, 128>(a, am, bm, st);
     if (shape == 1)
         return f64 ? tile_dispatch<double, 64, 64>(a, am, bm, st) : tile_dispatch<float, 64, 64>(a, am, bm, st);
     return f64 ? tile_dispatch<double, 32, 128>(a, am, bm, st) : tile_dispatch<float, 32, 128>(a, am, bm, st);

@@ -181,22 +181,25 @@ __device__ __forceinline__ int xtile_at(int r, int k) {
 }
 
 template <typename T, int BM, int BN, int BK, int AMODE, int BMODE, bool SPLIT = false, bool DEEP = true,
-          bool X3 = false>
+          bool X3 = false, int NW = 4>
 __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, const void* Bp, void* Cp,
                                           double alpha_d, double beta_d, int64_t tile, int64_t slice) {
     typedef typename Mfma<T>::acc_t acc_t;
-    constexpr int EA = BM * BK / 256, EB = BN * BK / 256;   // elements per thread per tile
+    constexpr int NT = 64 * NW;                             // threads per block
+    constexpr int EA = BM * BK / NT, EB = BN * BK / NT;     // elements per thread per tile
     constexpr bool A_KMAJ = AMODE != LD_MMAJ, B_KMAJ = BMODE != LD_MMAJ;
     constexpr bool AV = AMODE == LD_KVEC, BV = BMODE == LD_KVEC;
     constexpr int VEC = 16 / (int)sizeof(T), CPR = BK / VEC;  // chunk width, chunks per row
     constexpr int CA = EA / VEC, CB = EB / VEC;              // chunks per thread (vector loads)
     typedef T vT __attribute__((ext_vector_type(VEC)));
-    static_assert((!AV || EA % VEC == 0) && (!BV || EB % VEC == 0) && 256 % CPR == 0, "vector staging shape");
-    // four waves, 2 x 2 over the tile, or 1 x 4 along n for tiles of 32 rows
-    constexpr int WM = BM >= 64 ? 2 : 1, WN = 4 / WM;
+    static_assert((!AV || EA % VEC == 0) && (!BV || EB % VEC == 0) && NT % CPR == 0, "vector staging shape");
+    // four waves, 2 x 2 over the tile, or 1 x 4 along n for tiles of 32 rows;
+    // eight waves (two per SIMD), 2 x 4
+    static_assert(NW == 4 || (NW == 8 && BM >= 64 && !X3), "eight waves take tiles of at least 64 rows");
+    constexpr int WM = BM >= 64 ? 2 : 1, WN = NW / WM;
     constexpr int FM = BM / WM / 16, FN = BN / WN / 16;    // 16x16 blocks per wave
-    static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
-    static_assert(BM % (256 / BK) == 0 && BN % (256 / BK) == 0, "M/N-major staging needs rows in 16s");
+    static_assert(EA >= 1 && EB >= 1, "tile too small for the block's threads");
+    static_assert(BM % (NT / BK) == 0 && BN % (NT / BK) == 0, "M/N-major staging needs whole row groups");
     static_assert(BK == 16, "the LDS layout holds 16 positions per row");
     static_assert(!X3 || (!AV && !BV && !SPLIT), "X3 tiles stage element by element and do not split K");
     __shared__ __attribute__((aligned(16))) T As[X3 ? 1 : 2][X3 ? 1 : BM * BK];
@@ -235,21 +238,21 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     // per-block offset tables: A/C offsets of the tile's rows (m) and B/C
     // offsets of its columns (n); -1 marks rows/columns past the edge
     __shared__ int64_t sAm[BM], sCm[BM], sBn[BN], sCn[BN];
-    for (int i = tid; i < BM; i += 256) {
+    for (int i = tid; i < BM; i += NT) {
         int64_t m = m_base + i;
         bool ok = m < a.M;
         sAm[i] = ok ? group_off<0>(a.m, m) : -1;
         sCm[i] = ok ? group_off<2>(a.m, m) : -1;
     }
-    for (int i = tid; i < BN; i += 256) {
+    for (int i = tid; i < BN; i += NT) {
         int64_t n = n_base + i;
         bool ok = n < a.N;
         sBn[i] = ok ? group_off<1>(a.n, n) : -1;
         sCn[i] = ok ? group_off<2>(a.n, n) : -1;
     }
     if constexpr (X3) {
-        for (int i = tid; i < BM; i += 256) sEA[i] = -1023;
-        for (int i = tid; i < BN; i += 256) sEB[i] = -1023;
+        for (int i = tid; i < BM; i += NT) sEA[i] = -1023;
+        for (int i = tid; i < BN; i += NT) sEB[i] = -1023;
     }
     lds_barrier();
 
@@ -268,7 +271,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     // beta * C (zeros without reading C when beta = 0)
     const int64_t ktiles = alpha_d == 0.0 ? 0 : kt_count;
     const int64_t* ktab0 = SPLIT ? a.ktab + 2 * k_first * BK : a.ktab;
-    constexpr int RT = 256 / BK;
+    constexpr int RT = NT / BK;
 
     if constexpr (X3) {
         // Sweep 1: the largest exponent of each of the tile's rows of A and
@@ -285,7 +288,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             const int64_t kb = kt0[2 * (B_KMAJ ? tid % BK : tid / RT) + 1];
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
-                const int idx = tid + 256 * e;
+                const int idx = tid + NT * e;
                 const int64_t om = sAm[A_KMAJ ? idx / BK : tid % RT + RT * e];
                 const bool ok = (om >= 0) & (ka >= 0);
                 const double v = (double)Ag[bA + (ok ? om + ka : 0)];
@@ -293,7 +296,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             }
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
-                const int idx = tid + 256 * e;
+                const int idx = tid + NT * e;
                 const int64_t on = sBn[B_KMAJ ? idx / BK : tid % RT + RT * e];
                 const bool ok = (on >= 0) & (kb >= 0);
                 const double v = (double)Bg[bB + (ok ? on + kb : 0)];
@@ -302,20 +305,20 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         }
 #pragma unroll
         for (int e = 0; e < EA; ++e) {
-            const int idx = tid + 256 * e;
+            const int idx = tid + NT * e;
             atomicMax(&sEA[A_KMAJ ? idx / BK : tid % RT + RT * e], ea[e]);
         }
 #pragma unroll
         for (int e = 0; e < EB; ++e) {
-            const int idx = tid + 256 * e;
+            const int idx = tid + NT * e;
             atomicMax(&sEB[B_KMAJ ? idx / BK : tid % RT + RT * e], eb[e]);
         }
         lds_barrier();
-        for (int i = tid; i < BM; i += 256) {
+        for (int i = tid; i < BM; i += NT) {
             sEA[i] = min(max(sEA[i], -1022), 1023);
             sSA[i] = pow2d(-sEA[i]);
         }
-        for (int i = tid; i < BN; i += 256) {
+        for (int i = tid; i < BN; i += NT) {
             sEB[i] = min(max(sEB[i], -1022), 1023);
             sSB[i] = pow2d(-sEB[i]);
         }
@@ -356,7 +359,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         // loads still in flight.  In K-major loading a thread always handles
         // the same k of a tile (one entry); in M/N-major loading EA/EB.
         // Every thread handles one K position per tile: tid % BK along K
-        // (K-major) or tid / RT with RT = 256 / BK threads on consecutive
+        // (K-major) or tid / RT with RT = NT / BK threads on consecutive
         // rows (M/N-major, rows tid % RT + RT * e), so one table entry each.
         constexpr int TA = 1, TB = 1;
         int64_t tA[2][TA], tB[2][TB];
@@ -381,7 +384,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 // 16-byte chunks: chunk q = row q / CPR, positions VEC * (q % CPR) ..
 #pragma unroll
                 for (int e = 0; e < CA; ++e) {
-                    const int64_t om = sAm[(tid + 256 * e) / CPR];
+                    const int64_t om = sAm[(tid + NT * e) / CPR];
                     const bool ok = (om >= 0) & (tA[ts][0] >= 0) & live;
                     va[sl][e] = *(const vT*)(Ag + bA + pA + (ok ? om + tA[ts][0] : 0));
                     ma |= (uint32_t)ok << e;
@@ -389,7 +392,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             } else {
 #pragma unroll
                 for (int e = 0; e < EA; ++e) {
-                    const int idx = tid + 256 * e;
+                    const int idx = tid + NT * e;
                     const int64_t om = sAm[A_KMAJ ? idx / BK : tid % RT + RT * e];
                     const int64_t ko = tA[ts][0];
                     const bool ok = (om >= 0) & (ko >= 0) & live;
@@ -400,7 +403,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             if constexpr (BV) {
 #pragma unroll
                 for (int e = 0; e < CB; ++e) {
-                    const int64_t on = sBn[(tid + 256 * e) / CPR];
+                    const int64_t on = sBn[(tid + NT * e) / CPR];
                     const bool ok = (on >= 0) & (tB[ts][0] >= 0) & live;
                     vb[sl][e] = *(const vT*)(Bg + bB + pB + (ok ? on + tB[ts][0] : 0));
                     mb |= (uint32_t)ok << e;
@@ -408,7 +411,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             } else {
 #pragma unroll
                 for (int e = 0; e < EB; ++e) {
-                    const int idx = tid + 256 * e;
+                    const int idx = tid + NT * e;
                     const int64_t on = sBn[B_KMAJ ? idx / BK : tid % RT + RT * e];
                     const int64_t ko = tB[ts][0];
                     const bool ok = (on >= 0) & (ko >= 0) & live;
@@ -433,14 +436,14 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 };
 #pragma unroll
                 for (int e = 0; e < EA; ++e) {
-                    const int idx = tid + 256 * e;
+                    const int idx = tid + NT * e;
                     const int r = A_KMAJ ? idx / BK : tid % RT + RT * e, k = A_KMAJ ? idx % BK : tid / RT;
                     const double x = (okA[sl] >> e) & 1 ? (double)ra[sl][e] * sSA[r] : 0.0;
                     put(Xa[buf], BM, r, k, x);
                 }
 #pragma unroll
                 for (int e = 0; e < EB; ++e) {
-                    const int idx = tid + 256 * e;
+                    const int idx = tid + NT * e;
                     const int r = B_KMAJ ? idx / BK : tid % RT + RT * e, k = B_KMAJ ? idx % BK : tid / RT;
                     const double x = (okB[sl] >> e) & 1 ? (double)rb[sl][e] * sSB[r] : 0.0;
                     put(Xb[buf], BN, r, k, x);
@@ -450,13 +453,13 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             if constexpr (AV) {
 #pragma unroll
                 for (int e = 0; e < CA; ++e) {
-                    const int q = tid + 256 * e;
+                    const int q = tid + NT * e;
                     *(vT*)&As[buf][tile_at<T>(q / CPR, VEC * (q % CPR))] = (okA[sl] >> e) & 1 ? va[sl][e] : vT(0);
                 }
             } else {
 #pragma unroll
                 for (int e = 0; e < EA; ++e) {
-                    const int idx = tid + 256 * e;
+                    const int idx = tid + NT * e;
                     As[buf][tile_at<T>(A_KMAJ ? idx / BK : tid % RT + RT * e, A_KMAJ ? idx % BK : tid / RT)] =
                         (okA[sl] >> e) & 1 ? ra[sl][e] : (T)0;
                 }
@@ -464,13 +467,13 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             if constexpr (BV) {
 #pragma unroll
                 for (int e = 0; e < CB; ++e) {
-                    const int q = tid + 256 * e;
+                    const int q = tid + NT * e;
                     *(vT*)&Bs[buf][tile_at<T>(q / CPR, VEC * (q % CPR))] = (okB[sl] >> e) & 1 ? vb[sl][e] : vT(0);
                 }
             } else {
 #pragma unroll
                 for (int e = 0; e < EB; ++e) {
-                    const int idx = tid + 256 * e;
+                    const int idx = tid + NT * e;
                     Bs[buf][tile_at<T>(B_KMAJ ? idx / BK : tid % RT + RT * e, B_KMAJ ? idx % BK : tid / RT)] =
                         (okB[sl] >> e) & 1 ? rb[sl][e] : (T)0;
                 }
