@@ -195,17 +195,25 @@ void mfma_tiles_shape(int shape, MfmaArgs& a) {
 bool mfma_kmajor_a(const MfmaArgs& a) { return k_major(a.m, 0); }
 bool mfma_kmajor_b(const MfmaArgs& a) { return k_major(a.n, 1); }
 
+// Waves per block of the persistent kernel's 128 x 128 tiles (the FP64 form
+// needs all 256 VGPRs with four; see kNW).
+constexpr int kBNW = 8;
+
+template <int BM>
+constexpr int batch_nw() { return BM == 128 ? kBNW : 4; }
+
 template <typename T, int BM, int BN>
 static hipError_t batch_dispatch(bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs, const int2* work,
                                  int nwork, int* counter, int grid, hipStream_t st) {
-    dim3 g(grid), b(256);
+    constexpr int NW = batch_nw<BM>();
+    dim3 g(grid), b(64 * NW);
     // runs of up to 16 items when the list is long (at least about 64 runs
     // per block); short lists of costly tiles keep single items for balance
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)nwork / ((int64_t)grid * 64)));
-    if (ak && bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 1>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
-    else if (ak) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 0>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
-    else if (bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 1>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
-    else hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 0>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+    if (ak && bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 1, false, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+    else if (ak) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 0, false, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+    else if (bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 1, false, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+    else hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 0, false, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
     return hipGetLastError();
 }
 
@@ -224,12 +232,13 @@ hipError_t launch_mfma_batch(bool f64, int shape, bool ak, bool bk, const MfmaAr
 // Resident blocks per CU of the persistent kernel (occupancy query).
 template <typename T, int BM, int BN>
 static int occ_of(bool ak, bool bk) {
+    constexpr int NW = batch_nw<BM>();
     int n = 0;
     hipError_t e;
-    if (ak && bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 1, 1>, 256, 0);
-    else if (ak) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 1, 0>, 256, 0);
-    else if (bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 0, 1>, 256, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 0, 0>, 256, 0);
+    if (ak && bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 1, 1, false, NW>, 64 * NW, 0);
+    else if (ak) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 1, 0, false, NW>, 64 * NW, 0);
+    else if (bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 0, 1, false, NW>, 64 * NW, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kBK, 0, 0, false, NW>, 64 * NW, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
@@ -241,13 +250,14 @@ int mfma_batch_occupancy(bool f64, int shape, bool ak, bool bk) {
                       : shape == 1 ? occ_of<float, 64, 64>(ak, bk) : occ_of<float, 32, 128>(ak, bk);
 }
 
-// One-shot launch with a chosen tile shape (used to time tuning candidates).
-// Four waves per block, as the persistent batch kernel.
+// One-shot launch with a chosen tile shape (used to time tuning candidates),
+// with the persistent batch kernel's waves per block.
 hipError_t launch_mfma_shape(bool f64, int shape, MfmaArgs& a, hipStream_t st) {
     mfma_tiles_shape(shape, a);
     int am = load_mode(a, f64, 0), bm = load_mode(a, f64, 1);
     if (shape == 0)
-        return f64 ? tile_dispatch<double, 128, 128>(a, am, bm, st) : tile_dispatch<float, 128, 128>(a, am, bm, st);
+        return f64 ? tile_dispatch<double, 128, 128, false, kBNW>(a, am, bm, st)
+                   : tile_dispatch<float, 128, 128, false, kBNW>(a, am, bm, st);
     if (shape == 1)
         return f64 ? tile_dispatch<double, 64, 64>(a, am, bm, st) : tile_dispatch<float, 64, 64>(a, am, bm, st);
     return f64 ? tile_dispatch<double, 32, 128>(a, am, bm, st) : tile_dispatch<float, 32, 128>(a, am, bm, st);

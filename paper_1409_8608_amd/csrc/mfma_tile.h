@@ -666,9 +666,9 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
 // items (contraction, tile) off an atomic counter until the list is
 // exhausted, so every block exits once the counter passes nwork.  Claiming a
 // run per atomic keeps the single counter from serialising the many small
-// tiles of a large batch.  X3: the split-BF16 tiles.
-template <typename T, int BM, int BN, int BK, int AMODE, int BMODE, bool X3 = false>
-__global__ __launch_bounds__(256) void k_mfma_batch(const MfmaArgs* __restrict__ items,
+// tiles of a large batch.  X3: the split-BF16 tiles.  NW: waves per block.
+template <typename T, int BM, int BN, int BK, int AMODE, int BMODE, bool X3 = false, int NW = 4>
+__global__ __launch_bounds__(64 * NW) void k_mfma_batch(const MfmaArgs* __restrict__ items,
                                                     const BatchPtrs* __restrict__ ptrs,
                                                     const int2* __restrict__ work, int nwork, int chunk,
                                                     int* counter) {
@@ -684,8 +684,8 @@ __global__ __launch_bounds__(256) void k_mfma_batch(const MfmaArgs* __restrict__
             const BatchPtrs& pt = ptrs[wi.x];
             // batch tiles have short K: one step of loads in flight (the
             // two-deep prefetch costs registers these kernels do not have)
-            mfma_tile<T, BM, BN, BK, AMODE, BMODE, false, false, X3>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha,
-                                                                      pt.beta, wi.y, 0);
+            mfma_tile<T, BM, BN, BK, AMODE, BMODE, false, false, X3, NW>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha,
+                                                                          pt.beta, wi.y, 0);
             lds_barrier();   // the tile's LDS tables and s_w are reused by the next item
         }
     }
