@@ -16,17 +16,22 @@ namespace {
 
 constexpr int kXBK = 16;
 
+// waves per block: eight (two per SIMD) for the 128 x 128 tiles, whose four-wave
+// form takes all 256 VGPRs
+template <int BM>
+constexpr int x3_nw() { return BM == 128 ? 8 : 4; }
+
 template <typename T, int BM, int BN, int AMODE, int BMODE>
-__global__ __launch_bounds__(256) void k_mfma_x3(MfmaArgs a) {
+__global__ __launch_bounds__(64 * x3_nw<BM>()) void k_mfma_x3(MfmaArgs a) {
     const int64_t t = xcd_tile(blockIdx.x, a.ntiles);
-    mfma_tile<T, BM, BN, kXBK, AMODE, BMODE, false, false, true>(a, a.A, a.B, a.C, a.alpha, a.beta, t, 0);
+    mfma_tile<T, BM, BN, kXBK, AMODE, BMODE, false, false, true, x3_nw<BM>()>(a, a.A, a.B, a.C, a.alpha, a.beta, t, 0);
 }
 
 template <typename T, int BM, int BN>
 hipError_t one_shot(const MfmaArgs& a, bool ak, bool bk, hipStream_t st) {
     if (a.ntiles <= 0) return hipSuccess;
     if (a.ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-    dim3 g((unsigned)a.ntiles), b(256);
+    dim3 g((unsigned)a.ntiles), b(64 * x3_nw<BM>());
     if (ak && bk) hipLaunchKernelGGL((k_mfma_x3<T, BM, BN, 1, 1>), g, b, 0, st, a);
     else if (ak) hipLaunchKernelGGL((k_mfma_x3<T, BM, BN, 1, 0>), g, b, 0, st, a);
     else if (bk) hipLaunchKernelGGL((k_mfma_x3<T, BM, BN, 0, 1>), g, b, 0, st, a);
@@ -37,28 +42,30 @@ hipError_t one_shot(const MfmaArgs& a, bool ak, bool bk, hipStream_t st) {
 template <typename T, int BM, int BN>
 hipError_t persistent(bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs, const int2* work, int nwork,
                       int* counter, int grid, hipStream_t st) {
-    dim3 g(grid), b(256);
+    constexpr int NW = x3_nw<BM>();
+    dim3 g(grid), b(64 * NW);
     // runs of up to 16 items when the list is long (as the native batch kernel)
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)nwork / ((int64_t)grid * 64)));
     if (ak && bk)
-        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 1, 1, true>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 1, 1, true, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
     else if (ak)
-        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 1, 0, true>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 1, 0, true, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
     else if (bk)
-        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 0, 1, true>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 0, 1, true, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
     else
-        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 0, 0, true>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 0, 0, true, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
     return hipGetLastError();
 }
 
 template <typename T, int BM, int BN>
 int occupancy(bool ak, bool bk) {
+    constexpr int NW = x3_nw<BM>();
     int n = 0;
     hipError_t e;
-    if (ak && bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kXBK, 1, 1, true>, 256, 0);
-    else if (ak) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kXBK, 1, 0, true>, 256, 0);
-    else if (bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kXBK, 0, 1, true>, 256, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kXBK, 0, 0, true>, 256, 0);
+    if (ak && bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kXBK, 1, 1, true, NW>, 64 * NW, 0);
+    else if (ak) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kXBK, 1, 0, true, NW>, 64 * NW, 0);
+    else if (bk) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kXBK, 0, 1, true, NW>, 64 * NW, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mfma_batch<T, BM, BN, kXBK, 0, 0, true, NW>, 64 * NW, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
