@@ -249,7 +249,7 @@ tc_status prepare_plan(tc_plan_s* p) {
     int BK = mfma_bk(f64);
     if (p->selected == TC_VARIANT_FUSED || p->selected == TC_VARIANT_PREDICTED) {
         if (!use_stream_kernel(s, p->gv) && !p->ktab_ready) {
-            std::vector<int64_t> tab = build_ktab(p->gv.k, BK, 4, mfma_a_first(p->gv.M, p->gv.N), 4);
+            std::vector<int64_t> tab = build_ktab(p->gv.k, BK, 4, mfma_a_first(f64, p->gv.M, p->gv.N, p->gv.K), 4);
             p->kpad = (int64_t)tab.size() / 2;
             p->kvec = ktab_vec_flags(tab, f64 ? 2 : 4);
             tc_status st = upload(&p->d_ktab, &p->ktab_cap, tab);

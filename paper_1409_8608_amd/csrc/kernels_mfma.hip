@@ -45,15 +45,24 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(MfmaArgs a) {
 }
 
 
-// Tile shape per storage type.  FP64: 128x128x16 (64 accumulators per lane in
-// 16 MFMA blocks per wave); FP32: 128x128x16 as well.
-constexpr int kBM = 128, kBN = 128, kBK = 16;
+// Tile shape of the one-shot launches (eight waves per block): 128 x 128 x 16,
+// each wave 64 x 32; FP32 with at least 2048 summed positions 256 x 128 x 16,
+// each wave 64 x 64, which halves the barriers and stagings per MFMA (FP32
+// MFMAs take half as long as FP64's).  Measured on MI355X: 4096^2 x 4096 FP32
+// 1.690 -> 1.395 ms with the wide tile; 256^3 x 1024 0.374 -> 0.446 ms, so short
+// contractions keep 128 x 128.
+constexpr int kBK = 16;
+constexpr int kBMW = 256;   // rows of the wide FP32 tile
+static bool wide_tile(bool f64, int64_t kpad) { return !f64 && kpad >= 2048; }
+static int64_t tile_m(bool f64, int64_t kpad) { return wide_tile(f64, kpad) ? kBMW : 128; }
+constexpr int64_t kTileN = 128;
 
 int mfma_bk(bool) { return kBK; }
 
-void mfma_tiles(bool, MfmaArgs& a) {
-    a.mt = (a.M + kBM - 1) / kBM;
-    a.nt = (a.N + kBN - 1) / kBN;
+void mfma_tiles(bool f64, MfmaArgs& a) {
+    const int64_t bm = tile_m(f64, a.Kpad);
+    a.mt = (a.M + bm - 1) / bm;
+    a.nt = (a.N + kTileN - 1) / kTileN;
     a.ntiles = a.mt * a.nt * a.nbatch;
 }
 
@@ -63,10 +72,11 @@ void mfma_tiles(bool, MfmaArgs& a) {
 // with more distinct rows in that set walks its contiguous contracted index
 // fastest (its cache lines are reused on consecutive K tiles); the other
 // reuses its lines every 4 tiles (super-blocks of 4 blocks).
-bool mfma_a_first(int64_t M, int64_t N) {
-    const int64_t mt = (M + kBM - 1) / kBM, nt = (N + kBN - 1) / kBN;
+bool mfma_a_first(bool f64, int64_t M, int64_t N, int64_t K) {
+    const int64_t bm = tile_m(f64, K), bn = kTileN;
+    const int64_t mt = (M + bm - 1) / bm, nt = (N + bn - 1) / bn;
     const int64_t R = std::max<int64_t>(1, std::min<int64_t>((mt * nt + 7) / 8, 64));
-    return std::min(mt, R) * kBM > (R + mt - 1) / mt * kBN;
+    return std::min(mt, R) * bm > (R + mt - 1) / mt * bn;
 }
 
 // Lanes go along K for an operand whose free group is not unit-stride.
@@ -138,40 +148,46 @@ static hipError_t tile_dispatch(const MfmaArgs& a, int am, int bm, hipStream_t s
 hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st) {
     int am = load_mode(a, f64, 0), bm = load_mode(a, f64, 1);
     if (a.kslices <= 1)
-        return f64 ? tile_dispatch<double, kBM, kBN, false, kNW>(a, am, bm, st)
-                   : tile_dispatch<float, kBM, kBN, false, kNW>(a, am, bm, st);
-    hipError_t e = f64 ? tile_dispatch<double, kBM, kBN, true, kNW>(a, am, bm, st)
-                       : tile_dispatch<float, kBM, kBN, true, kNW>(a, am, bm, st);
+        return f64 ? tile_dispatch<double, 128, 128, false, kNW>(a, am, bm, st)
+               : wide_tile(f64, a.Kpad) ? tile_dispatch<float, kBMW, 128, false, kNW>(a, am, bm, st)
+                                        : tile_dispatch<float, 128, 128, false, kNW>(a, am, bm, st);
+    hipError_t e = f64 ? tile_dispatch<double, 128, 128, true, kNW>(a, am, bm, st)
+                   : wide_tile(f64, a.Kpad) ? tile_dispatch<float, kBMW, 128, true, kNW>(a, am, bm, st)
+                                            : tile_dispatch<float, 128, 128, true, kNW>(a, am, bm, st);
     if (e != hipSuccess || a.ntiles <= 0) return e;
     if (a.nbatch != 1 || a.npass != 1 || a.mode != 0 || !a.ws) return hipErrorInvalidValue;
     const int64_t total = a.M * a.N;
     dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536))), b(256);
-    if (f64) hipLaunchKernelGGL((k_splitk_reduce<double, kBM, kBN>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_splitk_reduce<float, kBM, kBN>), g, b, 0, st, a);
+    if (f64) hipLaunchKernelGGL((k_splitk_reduce<double, 128, 128>), g, b, 0, st, a);
+    else if (wide_tile(f64, a.Kpad)) hipLaunchKernelGGL((k_splitk_reduce<float, kBMW, 128>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_splitk_reduce<float, 128, 128>), g, b, 0, st, a);
     return hipGetLastError();
 }
 
 // Split-K choice for a fused M x N x Kpad launch (one batch, one pass): none
 // while the output tiles fill about two waves of resident blocks, or when K is
 // short; else enough slices of at least 8 K tiles to fill them, with the
-// workspace (slices x tiles x 128 x 128 elements) at most ws_cap bytes.
+// workspace (slices x tiles x tile elements) at most ws_cap bytes.
 // Returns the slice count and sets the tiles per slice and the workspace bytes.
 int64_t mfma_split_plan(bool f64, int64_t M, int64_t N, int64_t Kpad, int64_t* slice_tiles, int64_t* ws_bytes,
                         int64_t ws_cap) {
-    const int64_t ntiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    const int64_t bm = tile_m(f64, Kpad), bn = kTileN;
+    const int64_t ntiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
     const int64_t ktiles = Kpad / kBK;
-    const int64_t fill = f64 ? 256 : 512;   // resident blocks of the two tile kernels on 256 CUs
+    // resident blocks of the eight-wave tile kernels on 256 CUs: one per CU,
+    // two for the FP32 128 x 128 form
+    const int64_t fill = (f64 || bm == kBMW) ? 256 : 512;
     const int64_t esize = f64 ? 8 : 4;
     *slice_tiles = ktiles;
     *ws_bytes = 0;
     if (ntiles <= 0 || ntiles >= fill || ktiles < 16) return 1;
     int64_t S = std::min<int64_t>((2 * fill + ntiles - 1) / ntiles, ktiles / 8);
-    S = std::min<int64_t>(S, ws_cap / (ntiles * kBM * kBN * esize));
+    S = std::min<int64_t>(S, ws_cap / (ntiles * bm * bn * esize));
     if (S < 2) return 1;
     const int64_t per = (ktiles + S - 1) / S;
     S = (ktiles + per - 1) / per;
     *slice_tiles = per;
-    *ws_bytes = S * ntiles * kBM * kBN * esize;
+    *ws_bytes = S * ntiles * bm * bn * esize;
     return S;
 }
 

@@ -23,7 +23,7 @@ hipError_t launch_simt(bool f64, SimtArgs& a, hipStream_t st);
 hipError_t launch_mfma(bool f64, MfmaArgs& a, hipStream_t st);
 void mfma_tiles(bool f64, MfmaArgs& a);
 int mfma_bk(bool f64);
-bool mfma_a_first(int64_t M, int64_t N);
+bool mfma_a_first(bool f64, int64_t M, int64_t N, int64_t K);
 // ws_cap: largest workspace the caller can give (bytes)
 int64_t mfma_split_plan(bool f64, int64_t M, int64_t N, int64_t Kpad, int64_t* slice_tiles, int64_t* ws_bytes,
                         int64_t ws_cap = 64LL << 20);

@@ -194,9 +194,9 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     typedef T vT __attribute__((ext_vector_type(VEC)));
     static_assert((!AV || EA % VEC == 0) && (!BV || EB % VEC == 0) && NT % CPR == 0, "vector staging shape");
     // four waves, 2 x 2 over the tile, or 1 x 4 along n for tiles of 32 rows;
-    // eight waves (two per SIMD), 2 x 4
+    // eight waves (two per SIMD), 2 x 4, or 4 x 2 for tiles of 256 rows
     static_assert(NW == 4 || (NW == 8 && BM >= 64), "eight waves take tiles of at least 64 rows");
-    constexpr int WM = BM >= 64 ? 2 : 1, WN = NW / WM;
+    constexpr int WM = (NW == 8 && BM >= 256) ? 4 : BM >= 64 ? 2 : 1, WN = NW / WM;
     constexpr int FM = BM / WM / 16, FN = BN / WN / 16;    // 16x16 blocks per wave
     static_assert(EA >= 1 && EB >= 1, "tile too small for the block's threads");
     static_assert(BM % (NT / BK) == 0 && BN % (NT / BK) == 0, "M/N-major staging needs whole row groups");

@@ -82,7 +82,7 @@ extern "C" tc_status tc_contract_noalloc(tc_plan_t p, const void* A, const void*
                                           std::to_string((long long)TC_NOALLOC_SCRATCH_BYTES) + " bytes");
     const int BK = mfma_bk(f64);
     if (p->h_ktab.empty()) {
-        p->h_ktab = build_ktab(gv.k, BK, 4, mfma_a_first(gv.M, gv.N), 4);
+        p->h_ktab = build_ktab(gv.k, BK, 4, mfma_a_first(f64, gv.M, gv.N, gv.K), 4);
         p->h_kvec = ktab_vec_flags(p->h_ktab, f64 ? 2 : 4);
     }
     const int64_t tab_bytes = (int64_t)(p->h_ktab.size() * sizeof(int64_t));
