@@ -1,8 +1,9 @@
 """GPU prediction (Section 3 on the device): every member gets a finite
 prediction for each of the five stages, the member picked by the prediction
-computes the right contraction, and the scoring against measured times is
-printed.  Absolute predicted times are not pinned by anything (the paper has
-no GPU numbers); the tests check consistency, the bench reports accuracy."""
+computes the right contraction, its measured time is within 1.25x of the
+measured fastest (among the family members alone and with the fused kernel),
+and the predicted and measured rankings agree (Spearman >= 0.8).  Absolute
+predicted times are not pinned by anything (the paper has no GPU numbers)."""
 import numpy as np
 import pytest
 
@@ -63,10 +64,17 @@ def test_predict_and_select(spec, ext):
     best = int(np.argmin(meas))
     pick = int(np.argmin(pred))
     rho = spearman(pred, meas)
+    # the family alone (Section 3 ranks members; the fused kernel is the library's own)
+    fam_pick, fam_best = int(np.argmin(pred[:n])), int(np.argmin(meas[:n]))
     print(f"\n{spec}: spearman {rho:.3f}; predicted-best measured {meas[pick]*1e6:.1f} us vs best "
-          f"{meas[best]*1e6:.1f} us; stage rho " +
+          f"{meas[best]*1e6:.1f} us; family pick {meas[fam_pick]*1e6:.1f} us vs family best "
+          f"{meas[fam_best]*1e6:.1f} us; stage rho " +
           " ".join(f"{spearman([q['stage_s'][s] for q in preds], meas):.2f}" for s in range(5)))
-    assert rho > 0.0
+    # measured on MI355X: rank correlation 0.98 and the exact fastest picked on
+    # both shapes; the bounds leave room for timing noise
+    assert rho >= 0.8
+    assert meas[fam_pick] <= 1.25 * meas[fam_best]
+    assert meas[pick] <= 1.25 * meas[best]
 
 
 def test_predict_with_chain_root_gaps():
