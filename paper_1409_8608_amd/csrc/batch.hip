@@ -9,11 +9,14 @@
 // view with a default shape (or the tuning cache's choice for a contraction
 // seen before), writes one static descriptor per contraction to device memory,
 // builds work lists of (contraction, tile) pairs, one per (storage type, tile
-// shape, operand layout) group, ordered longest-first by the estimated cost of
-// a tile (contracted length x tile area), and captures a graph: a staging
+// shape, operand layout) group, cut into eight ranges of whole contractions
+// balanced by estimated cost (contracted length x tile area x tiles), one per
+// XCD so that a contraction's tiles share one L2, each range longest tiles
+// first, and captures a graph: a staging
 // kernel that copies the call's pointers and scalars from pinned host memory,
 // a kernel that zeroes the work counters (no memset nodes), and one persistent
-// kernel per group whose blocks take tiles off the group's counter, the
+// kernel per group whose blocks take tiles off their XCD's range counter (and
+// then off the other ranges' counters), the
 // groups spread over up to four graph branches.  tc_batch_contract only writes
 // the staging buffer and replays the graph.
 //
@@ -75,8 +78,9 @@ struct BatchGroup {
     bool x3;            // split-BF16 tiles
     int shape;
     bool ak, bk;
-    std::vector<int2> work;
-    int2* d_work = nullptr;
+    std::vector<int2> work;   // eight per-XCD ranges of whole contractions
+    int xstart[9] = {0};      // range offsets
+    int2* d_work = nullptr;   // the list, then the nine offsets
     int grid = 1;
 };
 
@@ -216,7 +220,7 @@ static tc_status build_groups(tc_batch_s* b) {
     b->items.resize(n);
     for (int c = 0; c < n; ++c) b->items[c] = b->split[c] ? MfmaArgs{} : make_item(b, c, b->cands[c][b->choice[c]]);
     std::map<int, int> gid;   // key -> group index
-    std::vector<std::vector<std::pair<int64_t, int2>>> lists;
+    std::vector<std::vector<int>> gmembers;   // members of each group
     int ncu = 256;
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
@@ -240,26 +244,49 @@ static tc_status build_groups(tc_batch_s* b) {
             g.ak = ak;
             g.bk = bk;
             b->groups.push_back(g);
-            lists.emplace_back();
+            gmembers.emplace_back();
         }
-        const int64_t cost = a.Kpad * (sh == 0 ? 128 * 128 : sh == 1 ? 64 * 64 : 32 * 128);
-        for (int64_t t = 0; t < a.ntiles; ++t) lists[gid[key]].push_back({cost, int2{c, (int)t}});
+        gmembers[gid[key]].push_back(c);
     }
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-        auto& L = lists[gi];
-        std::stable_sort(L.begin(), L.end(), [](const std::pair<int64_t, int2>& x, const std::pair<int64_t, int2>& y) {
-            return x.first > y.first;
-        });
         BatchGroup& g = b->groups[gi];
-        for (auto& e : L) g.work.push_back(e.second);
-        hipError_t e = hipMalloc(&g.d_work, sizeof(int2) * std::max<size_t>(1, g.work.size()));
+        // Members go whole to the XCD with the least estimated work so far,
+        // largest members first (cost of a tile: contracted length x tile
+        // area); each range then lists its members longest tiles first, a
+        // member's tiles together.
+        auto tile_cost = [&](int c) {
+            const int sh = b->cands[c][b->choice[c]].shape;
+            return b->items[c].Kpad * (sh == 0 ? 128 * 128 : sh == 1 ? 64 * 64 : 32 * 128);
+        };
+        std::vector<int> ms = gmembers[gi];
+        std::stable_sort(ms.begin(), ms.end(), [&](int x, int y) {
+            return tile_cost(x) * b->items[x].ntiles > tile_cost(y) * b->items[y].ntiles;
+        });
+        std::vector<int> xm[8];
+        int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int c : ms) {
+            const int x = (int)(std::min_element(load, load + 8) - load);
+            xm[x].push_back(c);
+            load[x] += tile_cost(c) * b->items[c].ntiles;
+        }
+        for (int x = 0; x < 8; ++x) {
+            std::stable_sort(xm[x].begin(), xm[x].end(), [&](int p, int q) { return tile_cost(p) > tile_cost(q); });
+            g.xstart[x] = (int)g.work.size();
+            for (int c : xm[x])
+                for (int64_t t = 0; t < b->items[c].ntiles; ++t) g.work.push_back(int2{c, (int)t});
+        }
+        g.xstart[8] = (int)g.work.size();
+        const size_t list_bytes = sizeof(int2) * g.work.size();
+        hipError_t e = hipMalloc(&g.d_work, list_bytes + sizeof(g.xstart));
         if (e != hipSuccess) return fail(TC_E_NOMEM, "hipMalloc batch work list");
-        e = hipMemcpy(g.d_work, g.work.data(), sizeof(int2) * g.work.size(), hipMemcpyHostToDevice);
+        e = hipMemcpy(g.d_work, g.work.data(), list_bytes, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((char*)g.d_work + list_bytes, g.xstart, sizeof(g.xstart), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "upload batch work list");
         int occ = g.x3 ? x3_batch_occupancy(g.f64, g.shape, g.ak, g.bk) : mfma_batch_occupancy(g.f64, g.shape, g.ak, g.bk);
         g.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)g.work.size(), (int64_t)occ * ncu));
     }
-    hipError_t e = hipMalloc(&b->d_counters, sizeof(int) * std::max<size_t>(1, b->groups.size()));
+    hipError_t e = hipMalloc(&b->d_counters, sizeof(int) * 8 * std::max<size_t>(1, b->groups.size()));
     if (e != hipSuccess) return fail(TC_E_NOMEM, "hipMalloc batch counters");
     e = hipMemcpy(b->d_items, b->items.data(), sizeof(MfmaArgs) * b->items.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "upload batch descriptors");
@@ -272,7 +299,8 @@ static tc_status capture(tc_batch_s* b) {
     hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "begin capture");
     hipLaunchKernelGGL(k_stage, dim3((n + 255) / 256), dim3(256), 0, b->cap, b->h_ptrs, b->d_ptrs, n);
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, b->cap, b->d_counters, (int)b->groups.size());
+    const int ncount = 8 * (int)b->groups.size();   // eight per-XCD counters per group
+    hipLaunchKernelGGL(k_zero, dim3(std::max(1, (ncount + 63) / 64)), dim3(64), 0, b->cap, b->d_counters, ncount);
     // the groups (and the split-FP8 members) are independent: up to four
     // branches of the graph, so that one group's tail overlaps the next group's
     // blocks
@@ -289,9 +317,10 @@ static tc_status capture(tc_batch_s* b) {
         hipStream_t sq = q == 0 ? b->cap : b->side[q - 1];
         if (j < b->groups.size()) {
             BatchGroup& g = b->groups[j];
+            const int* xs = (const int*)((const char*)g.d_work + sizeof(int2) * g.work.size());
             hipError_t le = (g.x3 ? launch_x3_batch : launch_mfma_batch)(g.f64, g.shape, g.ak, g.bk, b->d_items,
-                                                                         b->d_ptrs, g.d_work, (int)g.work.size(),
-                                                                         b->d_counters + j, g.grid, sq);
+                                                                         b->d_ptrs, g.d_work, xs, (int)g.work.size(),
+                                                                         b->d_counters + 8 * j, g.grid, sq);
             if (le != hipSuccess) e = le;
         } else {
             const int c = splits[j - b->groups.size()];

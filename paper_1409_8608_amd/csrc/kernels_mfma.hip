@@ -220,29 +220,29 @@ constexpr int batch_nw() { return BM == 128 ? kBNW : 4; }
 
 template <typename T, int BM, int BN>
 static hipError_t batch_dispatch(bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs, const int2* work,
-                                 int nwork, int* counter, int grid, hipStream_t st) {
+                                 const int* xstart, int nwork, int* counter, int grid, hipStream_t st) {
     constexpr int NW = batch_nw<BM>();
     dim3 g(grid), b(64 * NW);
     // runs of up to 16 items when the list is long (at least about 64 runs
     // per block); short lists of costly tiles keep single items for balance
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)nwork / ((int64_t)grid * 64)));
-    if (ak && bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 1, false, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
-    else if (ak) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 0, false, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
-    else if (bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 1, false, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
-    else hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 0, false, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+    if (ak && bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 1, false, NW>), g, b, 0, st, items, ptrs, work, xstart, chunk, counter);
+    else if (ak) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 1, 0, false, NW>), g, b, 0, st, items, ptrs, work, xstart, chunk, counter);
+    else if (bk) hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 1, false, NW>), g, b, 0, st, items, ptrs, work, xstart, chunk, counter);
+    else hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kBK, 0, 0, false, NW>), g, b, 0, st, items, ptrs, work, xstart, chunk, counter);
     return hipGetLastError();
 }
 
 hipError_t launch_mfma_batch(bool f64, int shape, bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs,
-                             const int2* work, int nwork, int* counter, int grid, hipStream_t st) {
+                             const int2* work, const int* xstart, int nwork, int* counter, int grid, hipStream_t st) {
     if (nwork <= 0) return hipSuccess;
     if (f64)
-        return shape == 0   ? batch_dispatch<double, 128, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
-               : shape == 1 ? batch_dispatch<double, 64, 64>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
-                            : batch_dispatch<double, 32, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st);
-    return shape == 0   ? batch_dispatch<float, 128, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
-           : shape == 1 ? batch_dispatch<float, 64, 64>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
-                        : batch_dispatch<float, 32, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st);
+        return shape == 0   ? batch_dispatch<double, 128, 128>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st)
+               : shape == 1 ? batch_dispatch<double, 64, 64>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st)
+                            : batch_dispatch<double, 32, 128>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st);
+    return shape == 0   ? batch_dispatch<float, 128, 128>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st)
+           : shape == 1 ? batch_dispatch<float, 64, 64>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st)
+                        : batch_dispatch<float, 32, 128>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st);
 }
 
 // Resident blocks per CU of the persistent kernel (occupancy query).

@@ -40,20 +40,20 @@ hipError_t one_shot(const MfmaArgs& a, bool ak, bool bk, hipStream_t st) {
 }
 
 template <typename T, int BM, int BN>
-hipError_t persistent(bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs, const int2* work, int nwork,
-                      int* counter, int grid, hipStream_t st) {
+hipError_t persistent(bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs, const int2* work,
+                      const int* xstart, int nwork, int* counter, int grid, hipStream_t st) {
     constexpr int NW = x3_nw<BM>();
     dim3 g(grid), b(64 * NW);
     // runs of up to 16 items when the list is long (as the native batch kernel)
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)nwork / ((int64_t)grid * 64)));
     if (ak && bk)
-        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 1, 1, true, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 1, 1, true, NW>), g, b, 0, st, items, ptrs, work, xstart, chunk, counter);
     else if (ak)
-        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 1, 0, true, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 1, 0, true, NW>), g, b, 0, st, items, ptrs, work, xstart, chunk, counter);
     else if (bk)
-        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 0, 1, true, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 0, 1, true, NW>), g, b, 0, st, items, ptrs, work, xstart, chunk, counter);
     else
-        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 0, 0, true, NW>), g, b, 0, st, items, ptrs, work, nwork, chunk, counter);
+        hipLaunchKernelGGL((k_mfma_batch<T, BM, BN, kXBK, 0, 0, true, NW>), g, b, 0, st, items, ptrs, work, xstart, chunk, counter);
     return hipGetLastError();
 }
 
@@ -85,15 +85,15 @@ hipError_t launch_x3_shape(bool f64, int shape, MfmaArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_x3_batch(bool f64, int shape, bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs,
-                           const int2* work, int nwork, int* counter, int grid, hipStream_t st) {
+                           const int2* work, const int* xstart, int nwork, int* counter, int grid, hipStream_t st) {
     if (nwork <= 0) return hipSuccess;
     if (f64)
-        return shape == 0   ? persistent<double, 128, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
-               : shape == 1 ? persistent<double, 64, 64>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
-                            : persistent<double, 32, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st);
-    return shape == 0   ? persistent<float, 128, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
-           : shape == 1 ? persistent<float, 64, 64>(ak, bk, items, ptrs, work, nwork, counter, grid, st)
-                        : persistent<float, 32, 128>(ak, bk, items, ptrs, work, nwork, counter, grid, st);
+        return shape == 0   ? persistent<double, 128, 128>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st)
+               : shape == 1 ? persistent<double, 64, 64>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st)
+                            : persistent<double, 32, 128>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st);
+    return shape == 0   ? persistent<float, 128, 128>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st)
+           : shape == 1 ? persistent<float, 64, 64>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st)
+                        : persistent<float, 32, 128>(ak, bk, items, ptrs, work, xstart, nwork, counter, grid, st);
 }
 
 int x3_batch_occupancy(bool f64, int shape, bool ak, bool bk) {

@@ -29,17 +29,18 @@ int64_t mfma_split_plan(bool f64, int64_t M, int64_t N, int64_t Kpad, int64_t* s
                         int64_t ws_cap = 64LL << 20);
 
 // Batches: tile shape 0 = 128x128, 1 = 64x64, 2 = 32x128; persistent kernel over a work
-// list of (contraction, tile) pairs taken off an atomic counter.
+// list of (contraction, tile) pairs in eight per-XCD ranges (xstart: nine
+// offsets), taken off eight atomic counters.
 void mfma_tiles_shape(int shape, MfmaArgs& a);
 bool mfma_kmajor_a(const MfmaArgs& a);
 bool mfma_kmajor_b(const MfmaArgs& a);
 hipError_t launch_mfma_batch(bool f64, int shape, bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs,
-                             const int2* work, int nwork, int* counter, int grid, hipStream_t st);
+                             const int2* work, const int* xstart, int nwork, int* counter, int grid, hipStream_t st);
 int mfma_batch_occupancy(bool f64, int shape, bool ak, bool bk);
 hipError_t launch_mfma_shape(bool f64, int shape, MfmaArgs& a, hipStream_t st);
 // The same for split-BF16 tiles (FP64 or FP32 storage; one pass, no split K).
 hipError_t launch_x3_batch(bool f64, int shape, bool ak, bool bk, const MfmaArgs* items, const BatchPtrs* ptrs,
-                           const int2* work, int nwork, int* counter, int grid, hipStream_t st);
+                           const int2* work, const int* xstart, int nwork, int* counter, int grid, hipStream_t st);
 int x3_batch_occupancy(bool f64, int shape, bool ak, bool bk);
 hipError_t launch_x3_shape(bool f64, int shape, MfmaArgs& a, hipStream_t st);
 

@@ -664,31 +664,43 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     }
 }
 
-// Persistent form for batches: blocks take runs of `chunk` consecutive work
-// items (contraction, tile) off an atomic counter until the list is
-// exhausted, so every block exits once the counter passes nwork.  Claiming a
-// run per atomic keeps the single counter from serialising the many small
-// tiles of a large batch.  X3: the split-BF16 tiles.  NW: waves per block.
+// Persistent form for batches.  A group's work list of (contraction, tile)
+// items is cut into eight ranges, one per XCD, each holding whole
+// contractions, so that the tiles of one contraction run on one XCD and share
+// its L2.  Block b runs on XCD b % 8 (the hardware deals blocks round-robin)
+// and takes runs of `chunk` consecutive items off its range's counter; when
+// its range is exhausted it takes items from the other ranges in turn, and it
+// exits once all eight counters have passed their ranges' ends.  Claiming a
+// run per atomic keeps the counters from serialising the many small tiles of
+// a large batch.  xstart: the nine range offsets (xstart[8] = list length);
+// counter: eight counters, zero at launch.  X3: the split-BF16 tiles.  NW:
+// waves per block.
 template <typename T, int BM, int BN, int BK, int AMODE, int BMODE, bool X3 = false, int NW = 4>
 __global__ __launch_bounds__(64 * NW) void k_mfma_batch(const MfmaArgs* __restrict__ items,
-                                                    const BatchPtrs* __restrict__ ptrs,
-                                                    const int2* __restrict__ work, int nwork, int chunk,
-                                                    int* counter) {
+                                                      const BatchPtrs* __restrict__ ptrs,
+                                                      const int2* __restrict__ work, const int* __restrict__ xstart,
+                                                      int chunk, int* counter) {
     __shared__ int s_w;
-    for (;;) {
-        if (threadIdx.x == 0) s_w = atomicAdd(counter, chunk);
-        lds_barrier();
-        const int w0 = s_w;
-        if (w0 >= nwork) break;
-        const int w1 = min(w0, nwork - chunk) + chunk;
-        for (int w = w0; w < w1; ++w) {
-            const int2 wi = work[w];
-            const BatchPtrs& pt = ptrs[wi.x];
-            // batch tiles have short K: one step of loads in flight (the
-            // two-deep prefetch costs registers these kernels do not have)
-            mfma_tile<T, BM, BN, BK, AMODE, BMODE, false, false, X3, NW>(items[wi.x], pt.A, pt.B, pt.C, pt.alpha,
-                                                                          pt.beta, wi.y, 0);
-            lds_barrier();   // the tile's LDS tables and s_w are reused by the next item
+    const int x0 = blockIdx.x % 8;
+    for (int d = 0; d < 8; ++d) {
+        const int x = (x0 + d) & 7;
+        const int lo = xstart[x], n = xstart[x + 1] - lo;
+        for (;;) {
+            if (threadIdx.x == 0) s_w = atomicAdd(counter + x, chunk);
+            lds_barrier();
+            const int w0 = s_w;
+            lds_barrier();   // every thread has read s_w before thread 0 claims again
+            if (w0 >= n) break;
+            const int w1 = min(w0 + chunk, n);
+            for (int w = w0; w < w1; ++w) {
+                const int2 wi = work[lo + w];
+                const BatchPtrs& pt = ptrs[wi.x];
+                // batch tiles have short K: one step of loads in flight (the
+                // two-deep prefetch costs registers these kernels do not have)
+                mfma_tile<T, BM, BN, BK, AMODE, BMODE, false, false, X3, NW>(items[wi.x], pt.A, pt.B, pt.C,
+                                                                              pt.alpha, pt.beta, wi.y, 0);
+                lds_barrier();   // the tile's LDS tables are reused by the next item
+            }
         }
     }
 }
