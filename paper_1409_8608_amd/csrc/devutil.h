@@ -7,6 +7,14 @@
 
 namespace tc {
 
+// Global-memory view of a pointer.  Where a kernel reads its pointers from
+// memory (a batch's device table, an argument struct indexed at run time) the
+// compiler cannot tell the address space and issues flat loads and stores;
+// those also count against the LDS wait counter, so every LDS barrier would
+// wait for all memory operations in flight.  Every operand, table and
+// workspace the kernels touch is device memory.
+template <typename T> using gmem = T __attribute__((address_space(1)));
+
 // rem := rem / ext, returns rem % ext; 32-bit arithmetic when it fits
 __device__ __forceinline__ int64_t divmod(int64_t& rem, int64_t ext) {
     if ((uint64_t)rem <= 0xffffffffull && (uint64_t)ext <= 0xffffffffull) {

@@ -26,6 +26,7 @@
 #include <cstring>
 #include <vector>
 
+#include "devutil.h"
 #include "launch.h"
 #include "plan.h"
 
@@ -114,6 +115,9 @@ __device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t total) {
     return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ uint32_t pack2(double lo, double hi) {
     return (uint32_t)bf16_bits(lo) | ((uint32_t)bf16_bits(hi) << 16);
 }
@@ -124,13 +128,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_split_long(SplitArgs a) {
     __shared__ double red[4];
     if (a.bp && a.bp->alpha == 0.0) return;   // a batch member with alpha = 0 reads neither input
-    const T* X = (const T*)(a.bp ? (a.slot == 0 ? a.bp->A : a.bp->B) : a.X);
+    const gmem<T>* X = (const gmem<T>*)(a.bp ? (a.slot == 0 ? a.bp->A : a.bp->B) : a.X);
+    const gmem<int64_t>* koff = (const gmem<int64_t>*)a.koff;
     const int64_t row = blockIdx.x;
     const int tid = threadIdx.x;
     const int64_t base = grp_off(a.rows, row, a.slot);
     double amax = 0.0;
     for (int64_t k = tid; k < a.Kt; k += 256) {
-        const int64_t o = a.koff[k];
+        const int64_t o = koff[k];
         const double v = o >= 0 ? (double)X[base + o] : 0.0;
         amax = fmax(amax, fabs(v));
     }
@@ -144,16 +149,16 @@ __global__ __launch_bounds__(256) void k_split_long(SplitArgs a) {
         frexp(amax, &E);
         e = E - 1;
     }
-    if (tid == 0) a.exps[row] = e;
+    if (tid == 0) ((gmem<int32_t>*)a.exps)[row] = e;
     constexpr int64_t TS = XR * SPLIT_BK;
     for (int64_t k = tid; k < a.Kt; k += 256) {
-        const int64_t o = a.koff[k];
+        const int64_t o = koff[k];
         const double x = o >= 0 ? ldexp((double)X[base + o], -e) : 0.0;
         const double r1 = rn_bf16(x);
         const double rest = x - r1;
         const double r2 = rn_bf16(rest);
         const double r3 = rn_bf16(rest - r2);
-        uint16_t* t = a.panels + panel_off(row, k, 0, a.Kp);
+        gmem<uint16_t>* t = (gmem<uint16_t>*)a.panels + panel_off(row, k, 0, a.Kp);
         t[0] = bf16_bits(r1);
         t[TS] = bf16_bits(r2);
         t[2 * TS] = bf16_bits(r3);
@@ -201,7 +206,10 @@ __global__ __launch_bounds__(256) void k_split2(Split2Args a) {
     const int side = item < nA ? 0 : 1;
     const SplitSide& S = a.s[side];
     const int64_t row = side == 0 ? item : item - nA;
-    const T* X = (const T*)(a.bp ? (S.slot == 0 ? a.bp->A : a.bp->B) : S.X);
+    const gmem<T>* X = (const gmem<T>*)(a.bp ? (S.slot == 0 ? a.bp->A : a.bp->B) : S.X);
+    const gmem<int64_t>* koff = (const gmem<int64_t>*)S.koff;
+    const gmem<int64_t>* cinfo = (const gmem<int64_t>*)S.cinfo;
+    gmem<uint16_t>* panels = (gmem<uint16_t>*)S.panels;
     const int tid = threadIdx.x;
     const int64_t base = grp_off(S.rows, row, S.slot);
     const int64_t nch = a.Kt / 8;
@@ -215,9 +223,9 @@ __global__ __launch_bounds__(256) void k_split2(Split2Args a) {
         for (int q = 0; q < CPT * P; ++q) {
             const int64_t pc = tid + 256 * q, ch = pc / P;
             const bool in = ch < nch;
-            const int64_t o = S.koff[8 * (in ? ch : 0)];
+            const int64_t o = koff[8 * (in ? ch : 0)];
             const bool ok = in && o >= 0;
-            const vW t = *(const vW*)(X + base + (ok ? o + W * (pc % P) : 0));
+            const vW t = *(const gmem<vW>*)(X + base + (ok ? o + W * (pc % P) : 0));
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 v[q * W + w] = ok ? (double)t[w] : 0.0;
@@ -228,7 +236,7 @@ __global__ __launch_bounds__(256) void k_split2(Split2Args a) {
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int64_t ch = tid + 256 * c;
-            const int64_t info = ch < nch ? S.cinfo[ch] : 0;
+            const int64_t info = ch < nch ? cinfo[ch] : 0;
             const int64_t o0 = info >> 4;
             const int cnt = (int)(info & 15);
 #pragma unroll
@@ -244,7 +252,7 @@ __global__ __launch_bounds__(256) void k_split2(Split2Args a) {
         for (int c = 0; c < CPT; ++c) {
             const int64_t ch = tid + 256 * c;
             const bool in = ch < nch;
-            const int64_t* ko = S.koff + 8 * (in ? ch : 0);
+            const gmem<int64_t>* ko = koff + 8 * (in ? ch : 0);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int64_t o = ko[e];
@@ -265,7 +273,7 @@ __global__ __launch_bounds__(256) void k_split2(Split2Args a) {
         frexp(amax, &E);
         e = E - 1;
     }
-    if (tid == 0) S.exps[row] = e;
+    if (tid == 0) ((gmem<int32_t>*)S.exps)[row] = e;
     constexpr int64_t TS = XR * SPLIT_BK;   // elements between the terms of one stage image
     if (mode == 0) {
 #pragma unroll
@@ -288,15 +296,15 @@ __global__ __launch_bounds__(256) void k_split2(Split2Args a) {
                 w2[h] = pack2(t2[0], t2[1]);
                 w3[h] = pack2(t3[0], t3[1]);
             }
-            uint16_t* out = S.panels + panel_off(row, 8 * ch + W * (pc % P), 0, a.Kp);
+            gmem<uint16_t>* out = panels + panel_off(row, 8 * ch + W * (pc % P), 0, a.Kp);
             if constexpr (W == 2) {
-                *(uint32_t*)out = w1[0];
-                *(uint32_t*)(out + TS) = w2[0];
-                *(uint32_t*)(out + 2 * TS) = w3[0];
+                *(gmem<uint32_t>*)out = w1[0];
+                *(gmem<uint32_t>*)(out + TS) = w2[0];
+                *(gmem<uint32_t>*)(out + 2 * TS) = w3[0];
             } else {
-                *(uint2*)out = make_uint2(w1[0], w1[1]);
-                *(uint2*)(out + TS) = make_uint2(w2[0], w2[1]);
-                *(uint2*)(out + 2 * TS) = make_uint2(w3[0], w3[1]);
+                *(gmem<u32x2>*)out = u32x2{w1[0], w1[1]};
+                *(gmem<u32x2>*)(out + TS) = u32x2{w2[0], w2[1]};
+                *(gmem<u32x2>*)(out + 2 * TS) = u32x2{w3[0], w3[1]};
             }
         }
     } else {
@@ -313,11 +321,11 @@ __global__ __launch_bounds__(256) void k_split2(Split2Args a) {
                 t2[q] = rn_bf16(rest);
                 t3[q] = rn_bf16(rest - t2[q]);
             }
-            uint4* out = (uint4*)(S.panels + panel_off(row, 8 * ch, 0, a.Kp));
-            out[0] = make_uint4(pack2(t1[0], t1[1]), pack2(t1[2], t1[3]), pack2(t1[4], t1[5]), pack2(t1[6], t1[7]));
-            out[TS / 8] = make_uint4(pack2(t2[0], t2[1]), pack2(t2[2], t2[3]), pack2(t2[4], t2[5]), pack2(t2[6], t2[7]));
+            gmem<u32x4>* out = (gmem<u32x4>*)(panels + panel_off(row, 8 * ch, 0, a.Kp));
+            out[0] = u32x4{pack2(t1[0], t1[1]), pack2(t1[2], t1[3]), pack2(t1[4], t1[5]), pack2(t1[6], t1[7])};
+            out[TS / 8] = u32x4{pack2(t2[0], t2[1]), pack2(t2[2], t2[3]), pack2(t2[4], t2[5]), pack2(t2[6], t2[7])};
             out[2 * TS / 8] =
-                make_uint4(pack2(t3[0], t3[1]), pack2(t3[2], t3[3]), pack2(t3[4], t3[5]), pack2(t3[6], t3[7]));
+                u32x4{pack2(t3[0], t3[1]), pack2(t3[2], t3[3]), pack2(t3[4], t3[5]), pack2(t3[6], t3[7])};
         }
     }
 }
@@ -375,7 +383,8 @@ template <typename T, int CPT, bool VEC>
 __global__ __launch_bounds__(256) void k_split8(SplitArgs a) {
     __shared__ double red[4];
     if (a.bp && a.bp->alpha == 0.0) return;   // a batch member with alpha = 0 reads neither input
-    const T* X = (const T*)(a.bp ? (a.slot == 0 ? a.bp->A : a.bp->B) : a.X);
+    const gmem<T>* X = (const gmem<T>*)(a.bp ? (a.slot == 0 ? a.bp->A : a.bp->B) : a.X);
+    const gmem<int64_t>* koff = (const gmem<int64_t>*)a.koff;
     const int64_t row = xcd_item(blockIdx.x, a.nrows);
     const int tid = threadIdx.x;
     const int64_t base = grp_off(a.rows, row, a.slot);
@@ -386,7 +395,7 @@ __global__ __launch_bounds__(256) void k_split8(SplitArgs a) {
     for (int c = 0; c < CPT; ++c) {
         const int64_t ch = tid + 256 * c;
         const bool in = ch < nch;
-        const int64_t* ko = a.koff + 16 * (in ? ch : 0);
+        const gmem<int64_t>* ko = koff + 16 * (in ? ch : 0);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (VEC) {
@@ -394,7 +403,7 @@ __global__ __launch_bounds__(256) void k_split8(SplitArgs a) {
                 constexpr int W = 16 / sizeof(T);
                 const int64_t o = ko[8 * h];
                 const bool ok = in && o >= 0;
-                const v16* p = (const v16*)(X + base + (ok ? o : 0));
+                const gmem<v16>* p = (const gmem<v16>*)(X + base + (ok ? o : 0));
 #pragma unroll
                 for (int q = 0; q < 8 / W; ++q) {
                     const v16 t = p[q];
@@ -424,9 +433,9 @@ __global__ __launch_bounds__(256) void k_split8(SplitArgs a) {
         frexp(amax, &E);
         e = E - 1;
     }
-    if (tid == 0) a.exps[row] = e;
+    if (tid == 0) ((gmem<int32_t>*)a.exps)[row] = e;
     constexpr int64_t TS = XR * F8_BK;   // bytes between the terms of one stage image
-    uint8_t* pan = (uint8_t*)a.panels;
+    gmem<uint8_t>* pan = (gmem<uint8_t>*)a.panels;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int64_t ch = tid + 256 * c;
@@ -440,10 +449,10 @@ __global__ __launch_bounds__(256) void k_split8(SplitArgs a) {
             t2[q] = rn_e4m3(ldexp(r1, 4));
             t3[q] = rn_e4m3(ldexp(r1 - ldexp(t2[q], -4), 8));
         }
-        uint4* out = (uint4*)(pan + panel_off8(row, 16 * ch, 0, a.Kp));
-        out[0] = make_uint4(pack4_e4m3(t1), pack4_e4m3(t1 + 4), pack4_e4m3(t1 + 8), pack4_e4m3(t1 + 12));
-        out[TS / 16] = make_uint4(pack4_e4m3(t2), pack4_e4m3(t2 + 4), pack4_e4m3(t2 + 8), pack4_e4m3(t2 + 12));
-        out[2 * TS / 16] = make_uint4(pack4_e4m3(t3), pack4_e4m3(t3 + 4), pack4_e4m3(t3 + 8), pack4_e4m3(t3 + 12));
+        gmem<u32x4>* out = (gmem<u32x4>*)(pan + panel_off8(row, 16 * ch, 0, a.Kp));
+        out[0] = u32x4{pack4_e4m3(t1), pack4_e4m3(t1 + 4), pack4_e4m3(t1 + 8), pack4_e4m3(t1 + 12)};
+        out[TS / 16] = u32x4{pack4_e4m3(t2), pack4_e4m3(t2 + 4), pack4_e4m3(t2 + 8), pack4_e4m3(t2 + 12)};
+        out[2 * TS / 16] = u32x4{pack4_e4m3(t3), pack4_e4m3(t3 + 4), pack4_e4m3(t3 + 8), pack4_e4m3(t3 + 12)};
     }
 }
 
@@ -637,7 +646,7 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
     }
     __builtin_amdgcn_s_waitcnt(wait_vm(0));   // the trailing reload lands before the block exits
 
-    T* C = (T*)(a.bp ? a.bp->C : a.C);
+    gmem<T>* C = (gmem<T>*)(a.bp ? a.bp->C : a.C);
     const T beta = (T)beta_d;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -653,7 +662,7 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3(X3Args a) {
                 if (cm < 0) continue;
                 // the two FP32 partials add exactly in FP64
                 const double v = alpha * ldexp((double)big[i][j][q] + (double)small[i][j][q], sEm[ml] + sEn[nl]);
-                T* cp = C + cn + cm;
+                gmem<T>* cp = C + cn + cm;
                 T out = (T)v;
                 if (beta_d != 0.0) out += beta * (*cp);
                 *cp = out;
@@ -802,7 +811,7 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3_8(X3Args a) {
     }
     __builtin_amdgcn_s_waitcnt(wait_vm(0));
 
-    T* C = (T*)(a.bp ? a.bp->C : a.C);
+    gmem<T>* C = (gmem<T>*)(a.bp ? a.bp->C : a.C);
     const T beta = (T)beta_d;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -817,7 +826,7 @@ __global__ __launch_bounds__(64 * XWAVES) void k_x3_8(X3Args a) {
                 const int64_t cm = sCm[ml];
                 if (cm < 0) continue;
                 const double v = alpha * ldexp((double)big[i][j][q] + (double)small[i][j][q], sEm[ml] + sEn[nl]);
-                T* cp = C + cn + cm;
+                gmem<T>* cp = C + cn + cm;
                 T out = (T)v;
                 if (beta_d != 0.0) out += beta * (*cp);
                 *cp = out;

@@ -40,6 +40,7 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "devutil.h"
 #include "gett.h"
 
 namespace tc {
@@ -211,9 +212,9 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     __shared__ int sEA[X3 ? BM : 1], sEB[X3 ? BN : 1];
     __shared__ double sSA[X3 ? BM : 1], sSB[X3 ? BN : 1];
 
-    const T* __restrict__ Ag = (const T*)Ap;
-    const T* __restrict__ Bg = (const T*)Bp;
-    T* Cg = (T*)Cp;
+    const gmem<T>* __restrict__ Ag = (const gmem<T>*)Ap;
+    const gmem<T>* __restrict__ Bg = (const gmem<T>*)Bp;
+    gmem<T>* Cg = (gmem<T>*)Cp;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     const int wm = wid % WM, wn = wid / WM;
@@ -270,7 +271,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     // alpha = 0 reads neither A nor B: no K tiles, so the epilogue writes
     // beta * C (zeros without reading C when beta = 0)
     const int64_t ktiles = alpha_d == 0.0 ? 0 : kt_count;
-    const int64_t* ktab0 = SPLIT ? a.ktab + 2 * k_first * BK : a.ktab;
+    const gmem<int64_t>* ktab0 = (const gmem<int64_t>*)(SPLIT ? a.ktab + 2 * k_first * BK : a.ktab);
     constexpr int RT = NT / BK;
 
     if constexpr (X3) {
@@ -283,7 +284,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
 #pragma unroll
         for (int e = 0; e < EB; ++e) eb[e] = -1023;
         for (int64_t kt = 0; kt < ktiles; ++kt) {
-            const int64_t* kt0 = ktab0 + 2 * kt * BK;
+            const gmem<int64_t>* kt0 = ktab0 + 2 * kt * BK;
             const int64_t ka = kt0[2 * (A_KMAJ ? tid % BK : tid / RT)];
             const int64_t kb = kt0[2 * (B_KMAJ ? tid % BK : tid / RT) + 1];
 #pragma unroll
@@ -367,7 +368,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         int64_t tA[2][TA], tB[2][TB];
         auto tload = [&](int64_t kt, auto ts_c) {
             constexpr int ts = decltype(ts_c)::value;
-            const int64_t* kt0 = ktab0 + 2 * kt * BK;
+            const gmem<int64_t>* kt0 = ktab0 + 2 * kt * BK;
 #pragma unroll
             for (int e = 0; e < TA; ++e)
                 tA[ts][e] = kt0[2 * (AV ? VEC * (tid % CPR) : A_KMAJ ? tid % BK : tid / RT)];
@@ -388,7 +389,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 for (int e = 0; e < CA; ++e) {
                     const int64_t om = sAm[(tid + NT * e) / CPR];
                     const bool ok = (om >= 0) & (tA[ts][0] >= 0) & live;
-                    va[sl][e] = *(const vT*)(Ag + bA + pA + (ok ? om + tA[ts][0] : 0));
+                    va[sl][e] = *(const gmem<vT>*)(Ag + bA + pA + (ok ? om + tA[ts][0] : 0));
                     ma |= (uint32_t)ok << e;
                 }
             } else {
@@ -407,7 +408,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 for (int e = 0; e < CB; ++e) {
                     const int64_t on = sBn[(tid + NT * e) / CPR];
                     const bool ok = (on >= 0) & (tB[ts][0] >= 0) & live;
-                    vb[sl][e] = *(const vT*)(Bg + bB + pB + (ok ? on + tB[ts][0] : 0));
+                    vb[sl][e] = *(const gmem<vT>*)(Bg + bB + pB + (ok ? on + tB[ts][0] : 0));
                     mb |= (uint32_t)ok << e;
                 }
             } else {
@@ -609,7 +610,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                         const int ml = wm * (BM / WM) + j * 16 + (lane & 15);
                         const int64_t cm = sCm[ml];
                         if (cm < 0) continue;
-                        T* cp = Cg + bC + cn + cm;
+                        gmem<T>* cp = Cg + bC + cn + cm;
                         double v = alpha_d * ldexp((double)big[i][j][q] + (double)small[i][j][q], sEA[ml] + en);
                         if (beta_d != 0.0) v += beta_d * (double)(*cp);
                         *cp = (T)v;
@@ -621,7 +622,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             if constexpr (SPLIT) if (a.kslices > 1) {
                 // split K: raw partial tile to the workspace (rows and columns past
                 // the edge hold zeros and are never read)
-                T* wsp = (T*)a.ws + (slice * a.ntiles + tile) * (int64_t)(BM * BN);
+                gmem<T>* wsp = (gmem<T>*)a.ws + (slice * a.ntiles + tile) * (int64_t)(BM * BN);
 #pragma unroll
                 for (int i = 0; i < FN; ++i)
 #pragma unroll
@@ -642,7 +643,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                     for (int j = 0; j < FM; ++j) {
                         const int64_t cm = sCm[wm * (BM / WM) + j * 16 + (lane & 15)];
                         if (cm < 0) continue;
-                        T* cp = Cg + bC + cn + cm;
+                        gmem<T>* cp = Cg + bC + cn + cm;
                         T v = alpha * acc[i][j][q];
                         if (a.mode == 1) v = *cp + v;
                         else if (beta_d != 0.0) v += beta * (*cp);
