@@ -29,4 +29,20 @@ __device__ __forceinline__ int64_t divmod(int64_t& rem, int64_t ext) {
     return m;
 }
 
+// Round-to-nearest-even to 8 significant bits with an unbounded exponent
+// (the value 2^E rint(m 2^8) for x = m 2^E, 1/2 <= |m| < 1), on the FP64 bit
+// pattern: the 45 low fraction bits are dropped after adding half an ulp of
+// the kept part (less one when its last bit is 0, so that ties go to even); a
+// carry moves into the exponent, as it should.  A subnormal x is scaled by 2^64
+// first (exact) and the result scaled back (exact: its lowest bit is not below
+// x's).  Zero keeps its sign.
+__device__ __forceinline__ double rn8(double x) {
+    const bool sub = __builtin_fabs(x) < 0x1p-1022;
+    uint64_t u = (uint64_t)__double_as_longlong(sub ? x * 0x1p64 : x);
+    u += 0xFFFFFFFFFFFull + ((u >> 45) & 1);
+    u &= ~0x1FFFFFFFFFFFull;
+    const double r = __longlong_as_double((long long)u);
+    return sub ? r * 0x1p-64 : r;
+}
+
 }  // namespace tc

@@ -58,11 +58,7 @@ __host__ __device__ __forceinline__ int xswz(int r, int c) { return c ^ ((r >> 1
 
 // Round-to-nearest-even to an 8-bit significand, unbounded exponent (the
 // values stay far inside BF16's range after the per-slice scaling).
-__device__ __forceinline__ double rn_bf16(double x) {
-    int E;
-    double m = frexp(x, &E);
-    return ldexp(rint(ldexp(m, 8)), E - 8);
-}
+__device__ __forceinline__ double rn_bf16(double x) { return rn8(x); }
 
 __device__ __forceinline__ uint16_t bf16_bits(double t) {
     // t has at most 8 significant bits and a float exponent: exact in FP32,

@@ -152,17 +152,6 @@ __device__ __forceinline__ double pow2d(int k) {
     return __longlong_as_double((long long)u);
 }
 
-// Round-to-nearest-even to 8 significant bits, on the FP64 bit pattern: the
-// 45 low fraction bits are dropped after adding half an ulp of the kept part
-// (less one when its last bit is 0, so that ties go to even); a carry moves
-// into the exponent, as it should.
-__device__ __forceinline__ double rne8(double x) {
-    uint64_t u = (uint64_t)__double_as_longlong(x);
-    u += 0xFFFFFFFFFFFull + ((u >> 45) & 1);
-    u &= ~0x1FFFFFFFFFFFull;
-    return __longlong_as_double((long long)u);
-}
-
 // floor(log2 |x|) of a normal x (zero and subnormals give -1023, which the
 // scale clamps to -1022)
 __device__ __forceinline__ int expo2(double x) {
@@ -428,10 +417,11 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         auto sstore = [&](int buf, auto slot_c) {
             constexpr int sl = decltype(slot_c)::value;
             if constexpr (X3) {
-                // scale, split into three terms, one plane per term
+                // scale, split into three terms (round-to-nearest-even at 8
+                // significant bits), one plane per term
                 auto put = [&](uint16_t* plane, int rows, int r, int k, double x) {
-                    const double t1 = rne8(x), r1 = x - t1;
-                    const double t2 = rne8(r1), t3 = rne8(r1 - t2);
+                    const double t1 = rn8(x), r1 = x - t1;
+                    const double t2 = rn8(r1), t3 = rn8(r1 - t2);
                     const int at = xtile_at(r, k);
                     plane[at] = bf16_of(t1);
                     plane[rows * BK + at] = bf16_of(t2);
