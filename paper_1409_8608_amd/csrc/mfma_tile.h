@@ -263,6 +263,11 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
     const gmem<int64_t>* ktab0 = (const gmem<int64_t>*)(SPLIT ? a.ktab + 2 * k_first * BK : a.ktab);
     constexpr int RT = NT / BK;
 
+    // X3 with a single K tile (at most 16 summed positions): sweep 1's
+    // operand values and masks, which the staging step then takes instead of
+    // loading the same tile again
+    T xa[X3 ? EA : 1], xb[X3 ? EB : 1];
+    uint32_t xmA = 0, xmB = 0;
     if constexpr (X3) {
         // Sweep 1: the largest exponent of each of the tile's rows of A and
         // columns of B over all of K (a thread's element slots keep their row
@@ -281,16 +286,18 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 const int idx = tid + NT * e;
                 const int64_t om = sAm[A_KMAJ ? idx / BK : tid % RT + RT * e];
                 const bool ok = (om >= 0) & (ka >= 0);
-                const double v = (double)Ag[bA + (ok ? om + ka : 0)];
-                if (ok) ea[e] = max(ea[e], expo2(v));
+                xa[e] = Ag[bA + (ok ? om + ka : 0)];
+                if (ok) ea[e] = max(ea[e], expo2((double)xa[e]));
+                xmA = (xmA & ~(1u << e)) | ((uint32_t)ok << e);
             }
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
                 const int idx = tid + NT * e;
                 const int64_t on = sBn[B_KMAJ ? idx / BK : tid % RT + RT * e];
                 const bool ok = (on >= 0) & (kb >= 0);
-                const double v = (double)Bg[bB + (ok ? on + kb : 0)];
-                if (ok) eb[e] = max(eb[e], expo2(v));
+                xb[e] = Bg[bB + (ok ? on + kb : 0)];
+                if (ok) eb[e] = max(eb[e], expo2((double)xb[e]));
+                xmB = (xmB & ~(1u << e)) | ((uint32_t)ok << e);
             }
         }
 #pragma unroll
@@ -539,8 +546,18 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
             // Loads leave the prologue in the order a step leaves them (the
             // table of tile NS - 1, then the operands of tile 1 for FP32), so
             // the wait counts at the loop entry match the steady state.
-            tload(0, S0{});
-            gload(S0{}, S0{}, true);
+            if (X3 && ktiles == 1) {
+                // the tile sweep 1 loaded (same table entries, same masks)
+#pragma unroll
+                for (int e = 0; e < EA; ++e) ra[0][e] = xa[e];
+#pragma unroll
+                for (int e = 0; e < EB; ++e) rb[0][e] = xb[e];
+                okA[0] = xmA;
+                okB[0] = xmB;
+            } else {
+                tload(0, S0{});
+                gload(S0{}, S0{}, true);
+            }
             sstore(0, S0{});
             tload(std::min<int64_t>(1, last), S1{});
             if (NS == 3) {
