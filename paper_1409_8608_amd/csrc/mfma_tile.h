@@ -277,10 +277,14 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
         for (int e = 0; e < EA; ++e) ea[e] = -1023;
 #pragma unroll
         for (int e = 0; e < EB; ++e) eb[e] = -1023;
+        // each tile's K-table entries are requested one tile ahead, before
+        // the operands of the tile in hand
+        const int ia = 2 * (A_KMAJ ? tid % BK : tid / RT), ib = 2 * (B_KMAJ ? tid % BK : tid / RT) + 1;
+        int64_t ka = ktiles > 0 ? ktab0[ia] : 0, kb = ktiles > 0 ? ktab0[ib] : 0;
         for (int64_t kt = 0; kt < ktiles; ++kt) {
-            const gmem<int64_t>* kt0 = ktab0 + 2 * kt * BK;
-            const int64_t ka = kt0[2 * (A_KMAJ ? tid % BK : tid / RT)];
-            const int64_t kb = kt0[2 * (B_KMAJ ? tid % BK : tid / RT) + 1];
+            const gmem<int64_t>* kt1 = ktab0 + 2 * std::min<int64_t>(kt + 1, ktiles - 1) * BK;
+            const int64_t na = kt1[ia], nb = kt1[ib];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
                 const int idx = tid + NT * e;
@@ -299,6 +303,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, const void* Ap, con
                 if (ok) eb[e] = max(eb[e], expo2((double)xb[e]));
                 xmB = (xmB & ~(1u << e)) | ((uint32_t)ok << e);
             }
+            ka = na;
+            kb = nb;
         }
 #pragma unroll
         for (int e = 0; e < EA; ++e) {
